@@ -1,0 +1,183 @@
+/*
+ * stpci.h -- C ABI of the MI355X categorical STP-DAS configuration-interaction
+ * library (libstpci.so).
+ *
+ * The library computes sigma = H c for a CI Hamiltonian over a categorically
+ * compressed small-tensor-product distributed-active-space (STP-DAS)
+ * wavefunction, and runs the Davidson eigensolver that calls it.  The
+ * operations follow the Methods section of arXiv:2505.20375: the categorical
+ * vector C = (+)_B C^B (Results, categorical compression), the sigma build of
+ * Eqs. sigmaL / sigmaL1e / sigmaL2e, the Davidson solver with the
+ * preconditioner of Eq. sparsePreconditioner, and the residual-based
+ * convergence test.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Hamiltonian.  H = e_core + sum_pq h_pq a+_p a_q
+ *                 + 1/2 sum_pqrs (pq|rs) a+_p a+_r a_s a_q,
+ *   with two-electron integrals in chemists' (Mulliken) order,
+ *   g[p][q][r][s] = (pq|rs).  h must be Hermitian; g must satisfy
+ *   (pq|rs) = (rs|pq) and (pq|rs) = conj((qp|sr)).
+ * Space.  The M spin-orbitals are split into n_sub contiguous subspaces
+ *   (distributed active spaces) of sizes sub_size[k]; a determinant belongs to
+ *   the space when its electron count in subspace k lies in the inclusive
+ *   window [win_lo[k], win_hi[k]].  A category is one occupation tuple
+ *   (n_1..n_K) of the space.  Determinant |b> = a+_{i1}...a+_{iN}|0>,
+ *   i1 < ... < iN (bit p of b set <=> spin-orbital p occupied).
+ * Vector layout.  A CI vector is the concatenation of one dense block per
+ *   category, categories in lexicographic order of (n_1..n_K); inside a block
+ *   the element of local strings (s_1..s_K) sits at row-major position
+ *   sum_k rank(s_k) * stride_k (subspace 1 slowest), rank = colexicographic
+ *   rank of the local occupation mask among masks of equal popcount (the
+ *   ascending order of the mask values).  n_vec vectors are stored one after
+ *   the other ([n_vec][n_dets]).  Complex values are interleaved (re, im)
+ *   doubles, the layout of torch.complex128.
+ * Memory.  Host arrays passed in are copied; the caller keeps ownership.
+ *   Device pointers (suffix _dev) are caller-owned HIP device allocations on
+ *   the context's device; the library never frees them.  The context owns its
+ *   tables, integrals, solver vectors and workspace and frees them in
+ *   stpci_destroy.
+ * Streams.  All device work of a context runs in order on the stream given
+ *   to stpci_create (NULL: the default stream).  Calls returning results to
+ *   host memory synchronise that stream; stpci_sigma does not.
+ * Errors.  Every call returns a status; nothing aborts, throws or exits
+ *   across the ABI.  stpci_last_error() describes the last failure on a
+ *   context.  A context is used by one host thread at a time.
+ */
+#ifndef STPCI_H
+#define STPCI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stpci_ctx stpci_ctx;
+
+typedef enum {
+    STPCI_OK = 0,
+    STPCI_EINVAL = -1,   /* invalid argument: shape, symmetry, empty space, NULL pointer */
+    STPCI_ENOMEM = -2,   /* device memory budget exceeded or allocation failed */
+    STPCI_EHIP = -3,     /* a HIP runtime call failed */
+    STPCI_ENOCONV = -4,  /* Davidson reached max_iter (results hold the last iterate) */
+    STPCI_ESTATE = -5    /* call order: integrals/space missing, or host-only context */
+} stpci_status;
+
+typedef enum { STPCI_REAL64 = 0, STPCI_COMPLEX128 = 1 } stpci_scalar;
+
+/* Arithmetic of the category-block contractions (sigma build).  The Davidson
+ * residual, orthogonalisation and subspace problem are always FP64. */
+typedef enum { STPCI_FP64 = 0, STPCI_FP32 = 1 } stpci_precision;
+
+/* Create a context on HIP device `hip_device` issuing work on `hip_stream`
+ * (a hipStream_t, NULL for the default stream).  hip_device = -1 creates a
+ * host-only context: space and table queries work, device calls return
+ * STPCI_ESTATE. */
+stpci_status stpci_create(stpci_ctx** out, int hip_device, void* hip_stream);
+
+/* Free every allocation made by the context.  NULL-safe. */
+void stpci_destroy(stpci_ctx* ctx);
+
+/* Text of the last error on ctx (valid until the next call on ctx). */
+const char* stpci_last_error(const stpci_ctx* ctx);
+
+/* Set the Hamiltonian (the inputs h'_pq and g_pqrs of Eqs. sigmaL1e/sigmaL2e
+ * are derived from it: h'_pq = h_pq - 1/2 sum_r (pr|rq)).
+ * n_orb: number of spin-orbitals, or of spatial orbitals when spin_free = 1
+ *   (then the space is built over 2*n_orb spin-orbitals, alpha block first,
+ *   with h_so = h (x) 1 and (ps qs'|rt st') = (pq|rs) d_ss' d_tt').
+ * h: [n_orb][n_orb], g: [n_orb]^4 in the scalar type given.
+ * Returns STPCI_EINVAL if h is not Hermitian or g breaks the symmetries
+ * above (tolerance 1e-12 relative to the largest element). */
+stpci_status stpci_set_integrals(stpci_ctx* ctx, int n_orb, stpci_scalar scalar, int spin_free,
+                                 const void* h, const void* g, double e_core);
+
+/* Set the distributed-active-space partition and the occupation windows
+ * (Results: STP-DAS partition and categories).  n_sub <= 8, each subspace at
+ * most 32 spin-orbitals, at most 64 in total.  An empty space is
+ * STPCI_EINVAL.  The partition must cover the spin-orbitals of the
+ * integrals (checked when both are set). */
+stpci_status stpci_set_space(stpci_ctx* ctx, int n_elec, int n_sub, const int* sub_size, const int* win_lo,
+                             const int* win_hi);
+
+/* Space summary.  Any output pointer may be NULL.
+ * n_dets: determinants; n_cat: categories; bytes_per_vec: bytes of one CI
+ * vector; w_sigma_macs: multiply-adds of one sigma build in the resolution
+ * over intermediate determinants, W1 + W2 with W1 = sum_B |B| deg(B),
+ * W2 = sum_C |C| deg(C)^2 (deg = one-electron moves into the space);
+ * nnz_h: nonzero couplings <L|H|K> allowed between space determinants. */
+stpci_status stpci_space_info(const stpci_ctx* ctx, int64_t* n_dets, int* n_cat, int64_t* bytes_per_vec,
+                              double* w_sigma_macs, double* nnz_h);
+
+/* Algorithmic work of one sigma build for one vector, split as in the
+ * two-electron resolution: w1 = sum_B |B| deg(B) one-electron multiply-adds
+ * (Eq. sigmaL1e), w2 = sum_C |C| deg(C)^2 two-electron multiply-adds over the
+ * intermediate categories C (Eq. sigmaL2e), n_intermediate = number of
+ * intermediate determinants, max_deg = largest move count of a determinant.
+ * Any output may be NULL. */
+stpci_status stpci_work_counts(const stpci_ctx* ctx, double* w1, double* w2, int64_t* n_intermediate,
+                               int* max_deg);
+
+/* Category `cat` (0-based, lexicographic): occupation tuple occ[n_sub],
+ * offset of its block in the vector, and its number of determinants. */
+stpci_status stpci_category(const stpci_ctx* ctx, int cat, int* occ, int64_t* offset, int64_t* n_dets);
+
+/* Global occupation bitstring of the determinant at vector address addr. */
+stpci_status stpci_address_to_det(const stpci_ctx* ctx, int64_t addr, uint64_t* occ_bits);
+
+/* sigma_dev = H c_dev for n_vec vectors (Eq. sigmaL: one-electron part
+ * Eq. sigmaL1e plus two-electron part Eq. sigmaL2e, the latter resolved over
+ * every intermediate determinant one move away from the space, including
+ * occupations outside the windows).  Device pointers, [n_vec][n_dets] in the
+ * scalar type of the integrals; c_dev and sigma_dev must not overlap.
+ * Asynchronous on the context stream. */
+stpci_status stpci_sigma(stpci_ctx* ctx, const void* c_dev, void* sigma_dev, int n_vec, stpci_precision prec);
+
+/* diag_dev[i] = <i|H|i> (real, n_dets doubles).  The solver itself never
+ * stores the diagonal; this call exists for checks. */
+stpci_status stpci_diagonal(stpci_ctx* ctx, double* diag_dev);
+
+/* Davidson options.  k: roots; max_iter: iterations; max_subspace: expansion
+ * vectors kept before a restart from the Ritz vectors (0: automatic);
+ * tol_residual: stop when every ||H x - E x|| <= tol_residual; eps_drop: the
+ * epsilon of Eq. sparsePreconditioner (0: traditional Davidson update with
+ * the 1e-12 guard); precision: sigma arithmetic inside the iteration;
+ * refine_tol_energy: with precision != FP64, energies are refined with FP64
+ * sigma products until they change by less than this; guess_dev: k starting
+ * vectors ([k][n_dets], device) or NULL for unit vectors at the k lowest
+ * diagonal elements. */
+typedef struct {
+    int k;
+    int max_iter;
+    int max_subspace;
+    double tol_residual;
+    double eps_drop;
+    stpci_precision precision;
+    double refine_tol_energy;
+    const void* guess_dev;
+} stpci_dav_opts;
+
+/* Lowest k eigenpairs (Results: Davidson with residual-norm convergence).
+ * energies, resid: host arrays of k doubles (Ritz values and residual norms);
+ * vecs_dev: device [k][n_dets] for the Ritz vectors or NULL; n_iter: host int
+ * or NULL.  Returns STPCI_ENOCONV when max_iter is reached. */
+stpci_status stpci_davidson(stpci_ctx* ctx, const stpci_dav_opts* opts, double* energies, double* resid,
+                            void* vecs_dev, int* n_iter);
+
+/* Per-iteration record of the last Davidson run: iteration count, and for
+ * iteration i < cap the Ritz values energies[i*k + j] and residual norms
+ * resid[i*k + j].  Either array may be NULL. */
+stpci_status stpci_dav_history(const stpci_ctx* ctx, int* n_iter, int cap, double* energies, double* resid);
+
+/* Kernel timing with HIP events on the context stream.  enable != 0 starts
+ * recording every kernel launch of the sigma build; stpci_kernel_time
+ * returns, for kernel `name` ("sigma1e", "sigma2e"), the number of recorded
+ * launches and their summed duration in milliseconds (synchronises). */
+stpci_status stpci_profile(stpci_ctx* ctx, int enable);
+stpci_status stpci_kernel_time(stpci_ctx* ctx, const char* name, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STPCI_H */

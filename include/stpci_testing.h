@@ -1,0 +1,32 @@
+/*
+ * stpci_testing.h -- test hooks of libstpci (not part of the solver API).
+ */
+#ifndef STPCI_TESTING_H
+#define STPCI_TESTING_H
+
+#include "stpci.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Eigen-decomposition of a Hermitian n x n matrix with the host Jacobi
+ * solver that the Davidson driver uses for its projected problem.
+ * A: host [n][n] complex (interleaved), read only; w: n eigenvalues
+ * ascending; V: [n][n] complex, eigenvectors as columns.  Host memory only;
+ * returns STPCI_EINVAL for n < 1 or NULL pointers. */
+stpci_status stpci_test_heev(int n, const double* A, double* w, double* V);
+
+/* Run, on the host, the move enumeration and sign/address arithmetic that the
+ * sigma kernels use, for up to max_dets_per_cat determinants of every
+ * intermediate category (evenly spaced), and verify each move against the
+ * global sign rule and the address-to-determinant map.  n_checked: moves
+ * checked; n_bad: moves whose target address is outside the space, holds the
+ * wrong determinant, or carries the wrong sign. */
+stpci_status stpci_test_moves(const stpci_ctx* ctx, int64_t max_dets_per_cat, int64_t* n_checked,
+                              int64_t* n_bad);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STPCI_TESTING_H */

@@ -1,0 +1,220 @@
+"""Python binding of libstpci (MI355X categorical STP-DAS CI: sigma build and Davidson).
+
+Argument marshalling only: every step of the sigma build and of the Davidson
+iteration runs in the library's HIP kernels and its C++ driver.  PyTorch
+supplies device memory (tensor data pointers) and the stream.  Importing this
+package fails loudly when the compiled library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstpci.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libstpci.so is not built; run `python paper_2505_20375_amd/build.py` "
+                      "(or __graft_entry__.build()) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
+REAL64, COMPLEX128 = 0, 1
+FP64, FP32 = 0, 1
+_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", ENOCONV: "ENOCONV", ESTATE: "ESTATE"}
+
+
+class DavOpts(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("max_iter", ctypes.c_int), ("max_subspace", ctypes.c_int),
+                ("tol_residual", ctypes.c_double), ("eps_drop", ctypes.c_double), ("precision", ctypes.c_int),
+                ("refine_tol_energy", ctypes.c_double), ("guess_dev", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_IP = ctypes.POINTER(ctypes.c_int)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_DP = ctypes.POINTER(ctypes.c_double)
+_SIGS = {
+    "stpci_create": ([ctypes.POINTER(_P), _I, _P], _I),
+    "stpci_destroy": ([_P], None),
+    "stpci_last_error": ([_P], ctypes.c_char_p),
+    "stpci_set_integrals": ([_P, _I, _I, _I, _P, _P, _D], _I),
+    "stpci_set_space": ([_P, _I, _I, _IP, _IP, _IP], _I),
+    "stpci_space_info": ([_P, _I64P, _IP, _I64P, _DP, _DP], _I),
+    "stpci_category": ([_P, _I, _IP, _I64P, _I64P], _I),
+    "stpci_work_counts": ([_P, _DP, _DP, _I64P, _IP], _I),
+    "stpci_address_to_det": ([_P, _I64, ctypes.POINTER(ctypes.c_uint64)], _I),
+    "stpci_sigma": ([_P, _P, _P, _I, _I], _I),
+    "stpci_diagonal": ([_P, _P], _I),
+    "stpci_davidson": ([_P, ctypes.POINTER(DavOpts), _DP, _DP, _P, _IP], _I),
+    "stpci_dav_history": ([_P, _IP, _I, _DP, _DP], _I),
+    "stpci_profile": ([_P, _I], _I),
+    "stpci_kernel_time": ([_P, ctypes.c_char_p, _I64P, _DP], _I),
+    "stpci_test_heev": ([_I, _P, _P, _P], _I),
+    "stpci_test_moves": ([_P, _I64, _I64P, _I64P], _I),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class StpciError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def _iarr(xs):
+    a = (ctypes.c_int * len(xs))(*[int(x) for x in xs])
+    return a
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or an int)."""
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class SpaceInfo:
+    n_dets: int
+    n_cat: int
+    bytes_per_vec: int
+    w_sigma_macs: float
+    nnz_h: float
+
+
+class Context:
+    """One CI problem on one device (device=-1: host-only, no GPU calls)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        h = _P()
+        if device >= 0 and stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        st = _lib.stpci_create(ctypes.byref(h), int(device), _P(stream) if stream else None)
+        if st != OK:
+            raise StpciError(st, "stpci_create failed (device %d)" % device)
+        self._h = h
+        self.device = device
+        self.cplx = True
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.stpci_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, st):
+        if st != OK:
+            raise StpciError(st, _lib.stpci_last_error(self._h).decode())
+        return st
+
+    # -- problem definition -------------------------------------------------
+    def set_integrals(self, h, g, spin_free=False, e_core=0.0):
+        cplx = np.iscomplexobj(h) or np.iscomplexobj(g)
+        dt = np.complex128 if cplx else np.float64
+        h = np.ascontiguousarray(h, dtype=dt)
+        g = np.ascontiguousarray(g, dtype=dt)
+        n = h.shape[0]
+        self._check(_lib.stpci_set_integrals(self._h, n, COMPLEX128 if cplx else REAL64, int(bool(spin_free)),
+                                             h.ctypes.data_as(_P), g.ctypes.data_as(_P), float(e_core)))
+        self.cplx = bool(cplx)
+
+    def set_space(self, n_elec, sub, lo=None, hi=None):
+        lo = list(lo) if lo is not None else [0] * len(sub)
+        hi = list(hi) if hi is not None else list(sub)
+        self._check(_lib.stpci_set_space(self._h, int(n_elec), len(sub), _iarr(sub), _iarr(lo), _iarr(hi)))
+        self.n_sub = len(sub)
+
+    def space_info(self) -> SpaceInfo:
+        nd, nb = ctypes.c_int64(), ctypes.c_int64()
+        nc = ctypes.c_int()
+        w, z = ctypes.c_double(), ctypes.c_double()
+        self._check(_lib.stpci_space_info(self._h, ctypes.byref(nd), ctypes.byref(nc), ctypes.byref(nb),
+                                          ctypes.byref(w), ctypes.byref(z)))
+        return SpaceInfo(nd.value, nc.value, nb.value, w.value, z.value)
+
+    def work_counts(self):
+        """(w1, w2, intermediate determinants, max moves per determinant)."""
+        w1, w2 = ctypes.c_double(), ctypes.c_double()
+        ni, md = ctypes.c_int64(), ctypes.c_int()
+        self._check(_lib.stpci_work_counts(self._h, ctypes.byref(w1), ctypes.byref(w2), ctypes.byref(ni),
+                                           ctypes.byref(md)))
+        return w1.value, w2.value, ni.value, md.value
+
+    def category(self, i):
+        occ = (ctypes.c_int * 8)()
+        off, n = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.stpci_category(self._h, int(i), occ, ctypes.byref(off), ctypes.byref(n)))
+        return tuple(occ[:self.n_sub]), off.value, n.value
+
+    def address_to_det(self, addr) -> int:
+        b = ctypes.c_uint64()
+        self._check(_lib.stpci_address_to_det(self._h, int(addr), ctypes.byref(b)))
+        return b.value
+
+    # -- device work ----------------------------------------------------------
+    def sigma(self, c, out, n_vec=1, precision=FP64):
+        self._check(_lib.stpci_sigma(self._h, _ptr(c), _ptr(out), int(n_vec), int(precision)))
+
+    def diagonal(self, out):
+        self._check(_lib.stpci_diagonal(self._h, _ptr(out)))
+
+    def davidson(self, k=1, tol=1e-8, max_iter=100, max_subspace=0, eps_drop=0.0, precision=FP64,
+                 refine_tol_energy=1e-8, guess=None, vecs=None, allow_noconv=False):
+        o = DavOpts(int(k), int(max_iter), int(max_subspace), float(tol), float(eps_drop), int(precision),
+                    float(refine_tol_energy), _ptr(guess).value if guess is not None else None)
+        e = (ctypes.c_double * k)()
+        r = (ctypes.c_double * k)()
+        it = ctypes.c_int()
+        st = _lib.stpci_davidson(self._h, ctypes.byref(o), e, r, _ptr(vecs) if vecs is not None else None,
+                                 ctypes.byref(it))
+        if st != OK and not (allow_noconv and st == ENOCONV):
+            self._check(st)
+        return np.array(e[:]), np.array(r[:]), it.value, st
+
+    def history(self):
+        n = ctypes.c_int()
+        self._check(_lib.stpci_dav_history(self._h, ctypes.byref(n), 0, None, None))
+        return n.value
+
+    def test_moves(self, max_dets_per_cat=1 << 40):
+        """Host check of the kernels' move arithmetic: (moves checked, moves wrong)."""
+        n, b = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.stpci_test_moves(self._h, int(max_dets_per_cat), ctypes.byref(n), ctypes.byref(b)))
+        return n.value, b.value
+
+    def profile(self, enable=True):
+        self._check(_lib.stpci_profile(self._h, int(bool(enable))))
+
+    def kernel_time(self, name):
+        n, t = ctypes.c_int64(), ctypes.c_double()
+        self._check(_lib.stpci_kernel_time(self._h, name.encode(), ctypes.byref(n), ctypes.byref(t)))
+        return n.value, t.value
+
+
+def heev(A):
+    """Host Jacobi eigensolver used by the Davidson driver (exposed for tests)."""
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    w = np.zeros(n)
+    V = np.zeros((n, n), dtype=np.complex128)
+    st = _lib.stpci_test_heev(n, A.ctypes.data_as(_P), w.ctypes.data_as(_P), V.ctypes.data_as(_P))
+    if st != OK:
+        raise StpciError(st, "heev failed")
+    return w, V
+
+
+EXPORTED = sorted(_SIGS)

@@ -1,0 +1,427 @@
+// C ABI of libstpci: context, integrals, space, sigma, diagonal, profiling.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <sstream>
+
+#include "ctx.hpp"
+#include "kernels.hpp"
+
+using namespace stp;
+
+stpci_ctx::~stpci_ctx() {
+    if (!host_only) {
+        (void)hipSetDevice(device);
+        for (auto& e : events) {
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+        for (DevBuf* b : {&d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
+                          &d_hp, &d_gT, &d_hd, &d_JK, &d_V, &d_W, &d_X, &d_R, &d_T, &d_partial, &d_small, &d_topv,
+                          &d_topi})
+            b->free_();
+    }
+}
+
+namespace stp {
+
+stpci_status set_err(stpci_ctx* c, stpci_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+stpci_status hip_check(stpci_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return STPCI_OK;
+    std::ostringstream o;
+    o << what << ": " << hipGetErrorString(e);
+    return set_err(c, e == hipErrorOutOfMemory ? STPCI_ENOMEM : STPCI_EHIP, o.str());
+}
+
+size_t scalar_bytes(const stpci_ctx* c) { return c->cplx ? 16 : 8; }
+
+stpci_status ensure(stpci_ctx* c, DevBuf& b, size_t bytes, const char* what) {
+    if (b.bytes >= bytes && b.p) return STPCI_OK;
+    b.free_();
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        std::ostringstream o;
+        o << "device allocation of " << bytes << " bytes for " << what << " failed";
+        return set_err(c, STPCI_ENOMEM, o.str());
+    }
+    b.bytes = bytes;
+    return STPCI_OK;
+}
+
+template <class T>
+static stpci_status upload(stpci_ctx* c, DevBuf& b, const std::vector<T>& v, const char* what) {
+    size_t bytes = v.size() * sizeof(T);
+    stpci_status s = ensure(c, b, bytes, what);
+    if (s) return s;
+    if (bytes) return hip_check(c, hipMemcpy(b.p, v.data(), bytes, hipMemcpyHostToDevice), what);
+    return STPCI_OK;
+}
+
+stpci_status prepare(stpci_ctx* c) {
+    if (c->host_only) return set_err(c, STPCI_ESTATE, "host-only context has no device");
+    if (!c->have_ints) return set_err(c, STPCI_ESTATE, "integrals not set");
+    if (!c->have_space) return set_err(c, STPCI_ESTATE, "space not set");
+    if (c->prepared) return STPCI_OK;
+    if (c->hs.sp.M != c->M) {
+        std::ostringstream o;
+        o << "space covers " << c->hs.sp.M << " spin-orbitals but the integrals have " << c->M;
+        return set_err(c, STPCI_EINVAL, o.str());
+    }
+    stpci_status s;
+    if ((s = hip_check(c, hipSetDevice(c->device), "hipSetDevice"))) return s;
+    HostSpace& H = c->hs;
+    if ((s = upload(c, c->d_cats, H.cats, "categories"))) return s;
+    if ((s = upload(c, c->d_tabs, H.tabs, "string tables"))) return s;
+    if ((s = upload(c, c->d_bits, H.bits, "string masks"))) return s;
+    if ((s = upload(c, c->d_ann, H.ann, "annihilation table"))) return s;
+    if ((s = upload(c, c->d_cre, H.cre, "creation table"))) return s;
+    if ((s = upload(c, c->d_work_cat, H.work_cat, "work categories"))) return s;
+    if ((s = upload(c, c->d_work_begin, H.work_begin, "work offsets"))) return s;
+    if ((s = upload(c, c->d_space_begin, H.space_begin, "space offsets"))) return s;
+    if ((s = upload(c, c->d_hp, c->hprime, "h'"))) return s;
+    if ((s = upload(c, c->d_gT, c->gT, "two-electron integrals"))) return s;
+    if ((s = upload(c, c->d_hd, c->hd, "diagonal integrals"))) return s;
+    if ((s = upload(c, c->d_JK, c->JK, "Coulomb-exchange integrals"))) return s;
+    DevSpace& D = c->dev;
+    D.sp = H.sp;
+    D.cats = (const Cat*)c->d_cats.p;
+    D.tabs = (const StrTab*)c->d_tabs.p;
+    D.bits = (const uint32_t*)c->d_bits.p;
+    D.ann = (const int32_t*)c->d_ann.p;
+    D.cre = (const int32_t*)c->d_cre.p;
+    D.work_cat = (const int32_t*)c->d_work_cat.p;
+    D.work_begin = (const int64_t*)c->d_work_begin.p;
+    D.space_begin = (const int64_t*)c->d_space_begin.p;
+    c->prepared = true;
+    return STPCI_OK;
+}
+
+static void record(stpci_ctx* c, int kind, bool start) {
+    if (!c->profile) return;
+    if (start) {
+        KernelEvent e{kind, nullptr, nullptr};
+        (void)hipEventCreate(&e.a);
+        (void)hipEventCreate(&e.b);
+        (void)hipEventRecord(e.a, c->stream);
+        c->events.push_back(e);
+    } else {
+        (void)hipEventRecord(c->events.back().b, c->stream);
+    }
+}
+
+stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, stpci_precision prec) {
+    if (prec != STPCI_FP64) return set_err(c, STPCI_EINVAL, "unsupported sigma precision");
+    if (c->hs.max_deg > MAXDEG) return set_err(c, STPCI_EINVAL, "a determinant has more moves than MAXDEG");
+    record(c, 0, true);
+    hipError_t e = launch_sigma1e(c->dev, c->cplx, c->d_hp.p, cin, sout, n_vec, c->stream);
+    record(c, 0, false);
+    if (e != hipSuccess) return hip_check(c, e, "sigma1e launch");
+    record(c, 1, true);
+    e = launch_sigma2e_v0(c->dev, c->cplx, c->d_gT.p, cin, sout, n_vec, c->stream);
+    record(c, 1, false);
+    if (e != hipSuccess) return hip_check(c, e, "sigma2e launch");
+    return STPCI_OK;
+}
+
+}  // namespace stp
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+stpci_status stpci_create(stpci_ctx** out, int hip_device, void* hip_stream) {
+    if (!out) return STPCI_EINVAL;
+    *out = nullptr;
+    stpci_ctx* c = new (std::nothrow) stpci_ctx();
+    if (!c) return STPCI_ENOMEM;
+    if (hip_device >= 0) {
+        int n = 0;
+        hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess || hip_device >= n) {
+            (void)hipGetLastError();
+            delete c;
+            return STPCI_EHIP;
+        }
+        if (hipSetDevice(hip_device) != hipSuccess) {
+            delete c;
+            return STPCI_EHIP;
+        }
+        c->device = hip_device;
+        c->host_only = false;
+        c->stream = (hipStream_t)hip_stream;
+    }
+    *out = c;
+    return STPCI_OK;
+}
+
+void stpci_destroy(stpci_ctx* ctx) { delete ctx; }
+
+const char* stpci_last_error(const stpci_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+stpci_status stpci_set_integrals(stpci_ctx* c, int n_orb, stpci_scalar scalar, int spin_free, const void* h,
+                                 const void* g, double e_core) {
+    if (!c) return STPCI_EINVAL;
+    if (!h || !g) return set_err(c, STPCI_EINVAL, "h and g must be non-NULL");
+    if (scalar != STPCI_REAL64 && scalar != STPCI_COMPLEX128) return set_err(c, STPCI_EINVAL, "unknown scalar type");
+    const int M = spin_free ? 2 * n_orb : n_orb;
+    if (n_orb < 1 || M > MMAX) return set_err(c, STPCI_EINVAL, "n_orb out of range");
+    const bool cplx = scalar == STPCI_COMPLEX128;
+    const int n = n_orb;
+    auto hin = [&](int p, int q, double& re, double& im) {
+        const double* a = (const double*)h;
+        if (cplx) { re = a[2 * (p * n + q)]; im = a[2 * (p * n + q) + 1]; }
+        else { re = a[p * n + q]; im = 0.0; }
+    };
+    auto gin = [&](int p, int q, int r, int s, double& re, double& im) {
+        const double* a = (const double*)g;
+        size_t i = (((size_t)p * n + q) * n + r) * n + s;
+        if (cplx) { re = a[2 * i]; im = a[2 * i + 1]; }
+        else { re = a[i]; im = 0.0; }
+    };
+    // validation on the given (spatial or spin-orbital) arrays
+    double hmax = 0, gmax = 0, hbad = 0, gbad = 0;
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q) {
+            double a, b, x, y;
+            hin(p, q, a, b);
+            hin(q, p, x, y);
+            hmax = std::max(hmax, std::hypot(a, b));
+            hbad = std::max(hbad, std::hypot(a - x, b + y));
+        }
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q)
+            for (int r = 0; r < n; ++r)
+                for (int s = 0; s < n; ++s) {
+                    double a, b, x, y, u, v;
+                    gin(p, q, r, s, a, b);
+                    gin(r, s, p, q, x, y);
+                    gin(q, p, s, r, u, v);
+                    gmax = std::max(gmax, std::hypot(a, b));
+                    gbad = std::max(gbad, std::hypot(a - x, b - y));
+                    gbad = std::max(gbad, std::hypot(a - u, b + v));
+                }
+    if (!(std::isfinite(hmax) && std::isfinite(gmax)))
+        return set_err(c, STPCI_EINVAL, "integrals contain non-finite values");
+    if (hbad > 1e-12 * std::max(1.0, hmax)) return set_err(c, STPCI_EINVAL, "h is not Hermitian");
+    if (gbad > 1e-12 * std::max(1.0, gmax))
+        return set_err(c, STPCI_EINVAL, "g violates (pq|rs) = (rs|pq) or (pq|rs) = conj((qp|sr))");
+
+    // spin-orbital arrays (interleaved when complex)
+    const int w = cplx ? 2 : 1;
+    std::vector<double> H((size_t)M * M * w, 0.0), G((size_t)M * M * M * M * w, 0.0);
+    auto spat = [&](int P, int& p, int& sp) { sp = spin_free ? P / n : 0; p = spin_free ? P % n : P; };
+    for (int P = 0; P < M; ++P)
+        for (int Q = 0; Q < M; ++Q) {
+            int p, q, sp, sq;
+            spat(P, p, sp);
+            spat(Q, q, sq);
+            if (sp != sq) continue;
+            double a, b;
+            hin(p, q, a, b);
+            H[((size_t)P * M + Q) * w] = a;
+            if (cplx) H[((size_t)P * M + Q) * w + 1] = b;
+        }
+    for (int P = 0; P < M; ++P)
+        for (int Q = 0; Q < M; ++Q)
+            for (int R = 0; R < M; ++R)
+                for (int S = 0; S < M; ++S) {
+                    int p, q, r, s, sp, sq, sr, ss;
+                    spat(P, p, sp); spat(Q, q, sq); spat(R, r, sr); spat(S, s, ss);
+                    if (sp != sq || sr != ss) continue;
+                    double a, b;
+                    gin(p, q, r, s, a, b);
+                    size_t i = ((((size_t)P * M + Q) * M + R) * M + S) * w;
+                    G[i] = a;
+                    if (cplx) G[i + 1] = b;
+                }
+    c->M = M;
+    c->cplx = cplx;
+    c->e_core = e_core;
+    c->h.swap(H);
+    c->g.swap(G);
+    // derived arrays
+    const size_t MM = (size_t)M * M;
+    c->hprime.assign(MM * w, 0.0);
+    for (int p = 0; p < M; ++p)
+        for (int q = 0; q < M; ++q)
+            for (int k = 0; k < w; ++k) {
+                double v = c->h[((size_t)p * M + q) * w + k];
+                for (int r = 0; r < M; ++r) v -= 0.5 * c->g[((((size_t)p * M + r) * M + r) * M + q) * w + k];
+                c->hprime[((size_t)p * M + q) * w + k] = v;
+            }
+    c->gT.assign(MM * MM * w, 0.0);
+    for (int xp = 0; xp < M; ++xp)
+        for (int yp = 0; yp < M; ++yp)
+            for (int y = 0; y < M; ++y)
+                for (int x = 0; x < M; ++x) {
+                    size_t src = ((((size_t)xp * M + yp) * M + y) * M + x) * w;
+                    size_t dst = (((size_t)y * M + x) * MM + ((size_t)yp * M + xp)) * w;
+                    for (int k = 0; k < w; ++k) c->gT[dst + k] = c->g[src + k];
+                }
+    c->hd.assign(M, 0.0);
+    c->JK.assign(MM, 0.0);
+    for (int i = 0; i < M; ++i) {
+        c->hd[i] = c->h[((size_t)i * M + i) * w];
+        for (int j = 0; j < M; ++j) {
+            double J = c->g[((((size_t)i * M + i) * M + j) * M + j) * w];
+            double Kx = c->g[((((size_t)i * M + j) * M + j) * M + i) * w];
+            c->JK[(size_t)i * M + j] = J - Kx;
+        }
+    }
+    c->have_ints = true;
+    c->prepared = false;
+    return STPCI_OK;
+}
+
+stpci_status stpci_set_space(stpci_ctx* c, int n_elec, int n_sub, const int* sub_size, const int* win_lo,
+                             const int* win_hi) {
+    if (!c) return STPCI_EINVAL;
+    if (!sub_size || !win_lo || !win_hi) return set_err(c, STPCI_EINVAL, "NULL partition array");
+    std::string err;
+    stp::HostSpace hs;
+    try {
+        if (!hs.build(n_elec, n_sub, sub_size, win_lo, win_hi, err)) return set_err(c, STPCI_EINVAL, err);
+    } catch (const std::bad_alloc&) {
+        return set_err(c, STPCI_ENOMEM, "host memory exhausted while building string tables");
+    }
+    c->hs = std::move(hs);
+    c->have_space = true;
+    c->prepared = false;
+    return STPCI_OK;
+}
+
+stpci_status stpci_space_info(const stpci_ctx* c, int64_t* n_dets, int* n_cat, int64_t* bytes_per_vec,
+                              double* w_sigma_macs, double* nnz_h) {
+    if (!c) return STPCI_EINVAL;
+    if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
+    const HostSpace& H = c->hs;
+    if (n_dets) *n_dets = H.sp.ndets;
+    if (n_cat) *n_cat = H.sp.nspace;
+    if (bytes_per_vec) *bytes_per_vec = H.sp.ndets * (int64_t)(c->have_ints ? scalar_bytes(c) : 16);
+    if (w_sigma_macs) *w_sigma_macs = H.W1 + H.W2;
+    if (nnz_h) *nnz_h = H.nnz;
+    return STPCI_OK;
+}
+
+stpci_status stpci_work_counts(const stpci_ctx* c, double* w1, double* w2, int64_t* n_inter, int* max_deg) {
+    if (!c) return STPCI_EINVAL;
+    if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
+    if (w1) *w1 = c->hs.W1;
+    if (w2) *w2 = c->hs.W2;
+    if (n_inter) *n_inter = c->hs.sp.nwork_dets;
+    if (max_deg) *max_deg = c->hs.max_deg;
+    return STPCI_OK;
+}
+
+static bool host_to_bits(const void* u, int64_t a, uint64_t* b) {
+    return static_cast<const HostSpace*>(u)->address_to_det(a, b);
+}
+
+stpci_status stpci_test_moves(const stpci_ctx* c, int64_t max_dets_per_cat, int64_t* n_checked, int64_t* n_bad) {
+    if (!c || !n_checked || !n_bad) return STPCI_EINVAL;
+    if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
+    const HostSpace& H = c->hs;
+    DevSpace D{};
+    D.sp = H.sp;
+    D.cats = H.cats.data();
+    D.tabs = H.tabs.data();
+    D.bits = H.bits.data();
+    D.ann = H.ann.data();
+    D.cre = H.cre.data();
+    D.work_cat = H.work_cat.data();
+    D.work_begin = H.work_begin.data();
+    D.space_begin = H.space_begin.data();
+    *n_bad = check_moves_host(D, max_dets_per_cat, n_checked, host_to_bits, &H);
+    return STPCI_OK;
+}
+
+stpci_status stpci_category(const stpci_ctx* c, int cat, int* occ, int64_t* offset, int64_t* n_dets) {
+    if (!c) return STPCI_EINVAL;
+    if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
+    if (cat < 0 || cat >= c->hs.sp.nspace) return set_err(const_cast<stpci_ctx*>(c), STPCI_EINVAL, "bad category");
+    const Cat& C = c->hs.cats[cat];
+    if (occ)
+        for (int k = 0; k < c->hs.sp.K; ++k) occ[k] = C.occ[k];
+    if (offset) *offset = C.offset;
+    if (n_dets) *n_dets = C.size;
+    return STPCI_OK;
+}
+
+stpci_status stpci_address_to_det(const stpci_ctx* c, int64_t addr, uint64_t* bits) {
+    if (!c || !bits) return STPCI_EINVAL;
+    if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
+    if (!c->hs.address_to_det(addr, bits)) return set_err(const_cast<stpci_ctx*>(c), STPCI_EINVAL, "bad address");
+    return STPCI_OK;
+}
+
+stpci_status stpci_sigma(stpci_ctx* c, const void* c_dev, void* sigma_dev, int n_vec, stpci_precision prec) {
+    if (!c) return STPCI_EINVAL;
+    if (!c_dev || !sigma_dev || n_vec < 1) return set_err(c, STPCI_EINVAL, "bad sigma arguments");
+    stpci_status s = prepare(c);
+    if (s) return s;
+    if ((s = hip_check(c, hipSetDevice(c->device), "hipSetDevice"))) return s;
+    size_t bytes = (size_t)c->hs.sp.ndets * scalar_bytes(c) * n_vec;
+    const char* a = (const char*)c_dev;
+    const char* b = (const char*)sigma_dev;
+    if (a < b + bytes && b < a + bytes) return set_err(c, STPCI_EINVAL, "c_dev and sigma_dev overlap");
+    return sigma_impl(c, c_dev, sigma_dev, n_vec, prec);
+}
+
+stpci_status stpci_diagonal(stpci_ctx* c, double* diag_dev) {
+    if (!c) return STPCI_EINVAL;
+    if (!diag_dev) return set_err(c, STPCI_EINVAL, "NULL diag_dev");
+    stpci_status s = prepare(c);
+    if (s) return s;
+    return hip_check(c, launch_diag(c->dev, (const double*)c->d_hd.p, (const double*)c->d_JK.p, c->e_core,
+                                    diag_dev, c->stream),
+                     "diag launch");
+}
+
+stpci_status stpci_profile(stpci_ctx* c, int enable) {
+    if (!c) return STPCI_EINVAL;
+    if (c->host_only) return set_err(c, STPCI_ESTATE, "host-only context");
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& e : c->events) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    c->events.clear();
+    c->profile = enable != 0;
+    return STPCI_OK;
+}
+
+stpci_status stpci_kernel_time(stpci_ctx* c, const char* name, int64_t* launches, double* total_ms) {
+    if (!c || !name) return STPCI_EINVAL;
+    int kind = -1;
+    if (!std::strcmp(name, "sigma1e")) kind = 0;
+    if (!std::strcmp(name, "sigma2e")) kind = 1;
+    if (kind < 0) return set_err(c, STPCI_EINVAL, "unknown kernel name");
+    if (c->host_only) return set_err(c, STPCI_ESTATE, "host-only context");
+    stpci_status s = hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
+    if (s) return s;
+    int64_t n = 0;
+    double t = 0;
+    for (auto& e : c->events) {
+        if (e.kind != kind) continue;
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+            t += ms;
+            ++n;
+        }
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = t;
+    return STPCI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal state of one stpci context.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/stpci.h"
+#include "space.hpp"
+
+namespace stp {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void free_() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+struct KernelEvent {
+    int kind;  // 0 sigma1e, 1 sigma2e
+    hipEvent_t a, b;
+};
+
+struct DavRecord {
+    std::vector<double> e, r;
+};
+
+}  // namespace stp
+
+struct stpci_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    bool host_only = true;
+    std::string err;
+
+    // integrals (spin-orbital basis)
+    bool have_ints = false;
+    bool cplx = true;
+    int M = 0;
+    double e_core = 0.0;
+    std::vector<double> h, g;      // interleaved if complex
+    std::vector<double> hprime;    // h' = h - 1/2 sum_r (pr|rq)
+    std::vector<double> gT;        // gT[(y*M + x)*M*M + (y'*M + x')] = (x' y' | y x)
+    std::vector<double> hd, JK;    // Re h_ii ; (ii|jj) - (ij|ji)
+
+    // space
+    bool have_space = false;
+    stp::HostSpace hs;
+
+    // device copies
+    bool prepared = false;
+    stp::DevBuf d_cats, d_tabs, d_bits, d_ann, d_cre, d_work_cat, d_work_begin, d_space_begin;
+    stp::DevBuf d_hp, d_gT, d_hd, d_JK;
+    stp::DevSpace dev{};
+
+    // Davidson workspace
+    stp::DevBuf d_V, d_W, d_X, d_R, d_T, d_partial, d_small, d_topv, d_topi;
+    std::vector<stp::DavRecord> history;
+    int hist_k = 0;
+
+    // profiling
+    bool profile = false;
+    std::vector<stp::KernelEvent> events;
+
+    ~stpci_ctx();
+};
+
+namespace stp {
+stpci_status set_err(stpci_ctx* c, stpci_status s, const std::string& msg);
+stpci_status hip_check(stpci_ctx* c, hipError_t e, const char* what);
+stpci_status prepare(stpci_ctx* c);
+stpci_status ensure(stpci_ctx* c, DevBuf& b, size_t bytes, const char* what);
+stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, stpci_precision prec);
+size_t scalar_bytes(const stpci_ctx* c);
+}  // namespace stp

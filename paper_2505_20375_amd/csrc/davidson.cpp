@@ -1,0 +1,353 @@
+// Davidson eigensolver driver (Results: Rayleigh-Ritz with the residual
+// r = HC - EC appended after preconditioning, convergence on ||r||;
+// preconditioner of Eq. sparsePreconditioner with the 1e-12 guard).
+// Vectors stay on the device; only the small projected problem (at most 64 x
+// 64) is solved on the host with a cyclic complex Jacobi method.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <numeric>
+#include <sstream>
+
+#include "ctx.hpp"
+#include "kernels.hpp"
+
+using namespace stp;
+using cplx = std::complex<double>;
+
+namespace stp {
+
+// Eigen-decomposition of a Hermitian n x n matrix A (row-major), eigenvalues
+// ascending in w, eigenvectors as columns of V (row-major n x n).
+void jacobi_heev(int n, std::vector<cplx> A, std::vector<double>& w, std::vector<cplx>& V) {
+    V.assign((size_t)n * n, cplx(0, 0));
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    auto a = [&](int i, int j) -> cplx& { return A[(size_t)i * n + j]; };
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0, tot = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double x = std::norm(a(i, j));
+                tot += x;
+                if (i != j) off += x;
+            }
+        if (off <= 1e-30 * std::max(tot, 1e-300)) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                cplx apq = a(p, q);
+                double r = std::abs(apq);
+                if (r < 1e-300) continue;
+                cplx ph = apq / r;  // e^{i phi}
+                double app = a(p, p).real(), aqq = a(q, q).real();
+                double tau = (aqq - app) / (2.0 * r);
+                double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                double cs = 1.0 / std::sqrt(1.0 + t * t), sn = t * cs;
+                // J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] on (p, q)
+                cplx Jpp = cs, Jpq = sn, Jqp = -sn * std::conj(ph), Jqq = cs * std::conj(ph);
+                for (int k = 0; k < n; ++k) {  // columns: A <- A J
+                    cplx akp = a(k, p), akq = a(k, q);
+                    a(k, p) = akp * Jpp + akq * Jqp;
+                    a(k, q) = akp * Jpq + akq * Jqq;
+                }
+                for (int k = 0; k < n; ++k) {  // rows: A <- J^H A
+                    cplx apk = a(p, k), aqk = a(q, k);
+                    a(p, k) = std::conj(Jpp) * apk + std::conj(Jqp) * aqk;
+                    a(q, k) = std::conj(Jpq) * apk + std::conj(Jqq) * aqk;
+                }
+                a(p, q) = 0;
+                a(q, p) = 0;
+                a(p, p) = a(p, p).real();
+                a(q, q) = a(q, q).real();
+                for (int k = 0; k < n; ++k) {
+                    cplx vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = vkp * Jpp + vkq * Jqp;
+                    V[(size_t)k * n + q] = vkp * Jpq + vkq * Jqq;
+                }
+            }
+    }
+    std::vector<int> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int i, int j) { return a(i, i).real() < a(j, j).real(); });
+    w.resize(n);
+    std::vector<cplx> Vs((size_t)n * n);
+    for (int jj = 0; jj < n; ++jj) {
+        w[jj] = a(ord[jj], ord[jj]).real();
+        for (int i = 0; i < n; ++i) Vs[(size_t)i * n + jj] = V[(size_t)i * n + ord[jj]];
+    }
+    V.swap(Vs);
+}
+
+}  // namespace stp
+
+namespace {
+
+// layout of the small device workspace
+constexpr size_t kYOff = 0;                 // Ritz coefficients, up to 64 x 16 complex
+constexpr size_t kThetaOff = 64 * 16 * 16;  // Ritz values, 64 doubles
+constexpr size_t kDotsOff = kThetaOff + 64 * 8;
+constexpr size_t kCoefOff = kDotsOff + 64 * 16;
+constexpr size_t kSmallBytes = kCoefOff + 64 * 16;
+
+struct Dav {
+    stpci_ctx* c;
+    int64_t N;
+    size_t sb;     // scalar bytes
+    bool cx;
+    hipStream_t st;
+
+    char* vec(DevBuf& b, int i) { return (char*)b.p + (size_t)i * N * sb; }
+
+    stpci_status hip(hipError_t e, const char* w) { return hip_check(c, e, w); }
+
+    // out[i] = <A_i | w> for i < m  (host result)
+    stpci_status dots(const void* A, int m, const void* w, std::vector<cplx>& out) {
+        char* small = (char*)c->d_small.p + kDotsOff;
+        stpci_status s = hip(launch_dots(cx, A, N, m, w, N, c->d_partial.p, small, st), "dots");
+        if (s) return s;
+        std::vector<double> buf((size_t)m * (cx ? 2 : 1));
+        if ((s = hip(hipMemcpyAsync(buf.data(), small, buf.size() * 8, hipMemcpyDeviceToHost, st), "dots copy")))
+            return s;
+        if ((s = hip(hipStreamSynchronize(st), "sync"))) return s;
+        out.resize(m);
+        for (int i = 0; i < m; ++i) out[i] = cx ? cplx(buf[2 * i], buf[2 * i + 1]) : cplx(buf[i], 0.0);
+        return STPCI_OK;
+    }
+
+    // upload a small coefficient matrix Y (m x k, row-major) into d_small + off
+    stpci_status put_small(const std::vector<cplx>& Y, size_t byte_off) {
+        std::vector<double> buf(Y.size() * (cx ? 2 : 1));
+        for (size_t i = 0; i < Y.size(); ++i) {
+            if (cx) { buf[2 * i] = Y[i].real(); buf[2 * i + 1] = Y[i].imag(); }
+            else buf[i] = Y[i].real();
+        }
+        return hip(hipMemcpyAsync((char*)c->d_small.p + byte_off, buf.data(), buf.size() * 8,
+                                  hipMemcpyHostToDevice, st),
+                   "small upload");
+    }
+
+    stpci_status norm(const void* x, double& n) {
+        std::vector<cplx> d;
+        stpci_status s = dots(x, 1, x, d);
+        n = std::sqrt(std::max(0.0, d[0].real()));
+        return s;
+    }
+
+    // x <- x - A coef  (coef: m entries)
+    stpci_status subtract(const void* A, int m, const std::vector<cplx>& coef, void* x) {
+        stpci_status s = put_small(coef, kCoefOff);
+        if (s) return s;
+        return hip(launch_combine(cx, A, nullptr, N, m, (char*)c->d_small.p + kCoefOff, 1, nullptr, x, nullptr, N,
+                                  2, st),
+                   "cgs");
+    }
+};
+
+}  // namespace
+
+extern "C" stpci_status stpci_test_heev(int n, const double* A, double* w, double* V) {
+    if (n < 1 || !A || !w || !V) return STPCI_EINVAL;
+    std::vector<cplx> M((size_t)n * n);
+    for (size_t i = 0; i < M.size(); ++i) M[i] = cplx(A[2 * i], A[2 * i + 1]);
+    std::vector<double> ww;
+    std::vector<cplx> VV;
+    jacobi_heev(n, M, ww, VV);
+    for (int i = 0; i < n; ++i) w[i] = ww[i];
+    for (size_t i = 0; i < VV.size(); ++i) { V[2 * i] = VV[i].real(); V[2 * i + 1] = VV[i].imag(); }
+    return STPCI_OK;
+}
+
+extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, double* energies, double* resid,
+                                       void* vecs_dev, int* n_iter) {
+    if (!c || !o || !energies || !resid) return STPCI_EINVAL;
+    stpci_status s = prepare(c);
+    if (s) return s;
+    if ((s = hip_check(c, hipSetDevice(c->device), "hipSetDevice"))) return s;
+    const int64_t N = c->hs.sp.ndets;
+    int k = o->k;
+    if (k < 1 || k > 16 || k > N) return set_err(c, STPCI_EINVAL, "k must be in [1, min(16, n_dets)]");
+    if (o->precision != STPCI_FP64) return set_err(c, STPCI_EINVAL, "precision not supported by this solver");
+    int mmax = o->max_subspace > 0 ? o->max_subspace : std::max(8 * k, 16);
+    mmax = (int)std::min<int64_t>(std::min(mmax, 64), N);
+    if (mmax < 2 * k && N >= 2 * k) mmax = 2 * k;
+    mmax = std::max(mmax, k);
+    const int max_iter = o->max_iter > 0 ? o->max_iter : 100;
+    const double tol = o->tol_residual > 0 ? o->tol_residual : 1e-8;
+
+    Dav d{c, N, scalar_bytes(c), c->cplx, c->stream};
+    const size_t vb = (size_t)N * d.sb;
+    if ((s = ensure(c, c->d_V, vb * mmax, "Davidson V"))) return s;
+    if ((s = ensure(c, c->d_W, vb * mmax, "Davidson W"))) return s;
+    if ((s = ensure(c, c->d_X, vb * k, "Ritz vectors"))) return s;
+    if ((s = ensure(c, c->d_R, vb * k, "residuals"))) return s;
+    if ((s = ensure(c, c->d_T, vb * k, "corrections"))) return s;
+    if ((s = ensure(c, c->d_partial, (size_t)dots_blocks(N) * 64 * 16, "dot partials"))) return s;
+    if ((s = ensure(c, c->d_small, kSmallBytes, "small workspace"))) return s;
+    const size_t theta_off = kThetaOff;
+
+    // initial guess
+    if (o->guess_dev) {
+        if ((s = d.hip(hipMemcpyAsync(c->d_V.p, o->guess_dev, vb * k, hipMemcpyDeviceToDevice, c->stream), "guess")))
+            return s;
+        // orthonormalise the guess (CGS2)
+        for (int i = 0; i < k; ++i) {
+            for (int pass = 0; pass < 2 && i > 0; ++pass) {
+                std::vector<cplx> coef;
+                if ((s = d.dots(c->d_V.p, i, d.vec(c->d_V, i), coef))) return s;
+                if ((s = d.subtract(c->d_V.p, i, coef, d.vec(c->d_V, i)))) return s;
+            }
+            double nr;
+            if ((s = d.norm(d.vec(c->d_V, i), nr))) return s;
+            if (nr < 1e-14) return set_err(c, STPCI_EINVAL, "guess vectors are linearly dependent");
+            if ((s = d.hip(launch_scale(d.cx, d.vec(c->d_V, i), 1.0 / nr, N, c->stream), "scale"))) return s;
+        }
+    } else {
+        int nb = topk_blocks(c->dev);
+        if ((s = ensure(c, c->d_topv, (size_t)nb * k * 8, "top-k values"))) return s;
+        if ((s = ensure(c, c->d_topi, (size_t)nb * k * 8, "top-k indices"))) return s;
+        if ((s = d.hip(launch_diag_topk(c->dev, (const double*)c->d_hd.p, (const double*)c->d_JK.p, c->e_core, k,
+                                        (double*)c->d_topv.p, (int64_t*)c->d_topi.p, c->stream),
+                       "top-k")))
+            return s;
+        std::vector<double> tv((size_t)nb * k);
+        std::vector<int64_t> ti((size_t)nb * k);
+        (void)hipMemcpyAsync(tv.data(), c->d_topv.p, tv.size() * 8, hipMemcpyDeviceToHost, c->stream);
+        (void)hipMemcpyAsync(ti.data(), c->d_topi.p, ti.size() * 8, hipMemcpyDeviceToHost, c->stream);
+        if ((s = d.hip(hipStreamSynchronize(c->stream), "sync"))) return s;
+        std::vector<int> ord(tv.size());
+        std::iota(ord.begin(), ord.end(), 0);
+        std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+            return tv[a] < tv[b] || (tv[a] == tv[b] && ti[a] < ti[b]);
+        });
+        for (int i = 0; i < k; ++i)
+            if ((s = d.hip(launch_unit(d.cx, d.vec(c->d_V, i), N, ti[ord[i]], c->stream), "unit"))) return s;
+    }
+    if ((s = sigma_impl(c, c->d_V.p, c->d_W.p, k, STPCI_FP64))) return s;
+
+    std::vector<cplx> G((size_t)64 * 64, cplx(0, 0));
+    auto Gat = [&](int i, int j) -> cplx& { return G[(size_t)i * 64 + j]; };
+    int m = k;
+    for (int j = 0; j < m; ++j) {
+        std::vector<cplx> col;
+        if ((s = d.dots(c->d_V.p, m, d.vec(c->d_W, j), col))) return s;
+        for (int i = 0; i < m; ++i) Gat(i, j) = col[i];
+    }
+    c->history.clear();
+    c->hist_k = k;
+    std::vector<double> theta(k, 0.0), rn(k, 0.0);
+    int it = 0;
+    bool converged = false;
+    for (it = 1; it <= max_iter; ++it) {
+        std::vector<cplx> A((size_t)m * m);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) A[(size_t)i * m + j] = 0.5 * (Gat(i, j) + std::conj(Gat(j, i)));
+        std::vector<double> w;
+        std::vector<cplx> Y;
+        jacobi_heev(m, A, w, Y);
+        std::vector<cplx> Yk((size_t)m * k);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < k; ++j) Yk[(size_t)i * k + j] = Y[(size_t)i * m + j];
+        for (int j = 0; j < k; ++j) theta[j] = w[j];
+        if ((s = d.put_small(Yk, kYOff))) return s;
+        if ((s = d.hip(hipMemcpyAsync((char*)c->d_small.p + theta_off, theta.data(), k * 8, hipMemcpyHostToDevice,
+                                      c->stream),
+                       "theta")))
+            return s;
+        if ((s = d.hip(launch_combine(d.cx, c->d_V.p, c->d_W.p, N, m, c->d_small.p, k,
+                                      (const double*)((char*)c->d_small.p + theta_off), c->d_X.p, c->d_R.p, N, 1,
+                                      c->stream),
+                       "ritz")))
+            return s;
+        for (int j = 0; j < k; ++j)
+            if ((s = d.norm(d.vec(c->d_R, j), rn[j]))) return s;
+        c->history.push_back(DavRecord{theta, rn});
+        converged = true;
+        for (int j = 0; j < k; ++j) converged = converged && rn[j] <= tol;
+        if (converged) break;
+        if (it == max_iter) break;
+        // corrections for unconverged roots
+        int nt = 0;
+        for (int j = 0; j < k; ++j) {
+            if (rn[j] <= tol) continue;
+            if ((s = d.hip(launch_precond(c->dev, d.cx, (const double*)c->d_hd.p, (const double*)c->d_JK.p,
+                                          c->e_core, d.vec(c->d_R, j), d.vec(c->d_T, nt), theta[j], 1e-12,
+                                          c->stream),
+                           "precond")))
+                return s;
+            ++nt;
+        }
+        // thick restart from the Ritz vectors when the space would overflow
+        if (m + nt > mmax) {
+            // W Y -> R (residuals are no longer needed), then V <- X, W <- W Y
+            if ((s = d.hip(launch_combine(d.cx, c->d_W.p, nullptr, N, m, c->d_small.p, k, nullptr, c->d_R.p,
+                                          nullptr, N, 0, c->stream),
+                           "restart WY")))
+                return s;
+            if ((s = d.hip(hipMemcpyAsync(c->d_V.p, c->d_X.p, vb * k, hipMemcpyDeviceToDevice, c->stream), "restart V")))
+                return s;
+            if ((s = d.hip(hipMemcpyAsync(c->d_W.p, c->d_R.p, vb * k, hipMemcpyDeviceToDevice, c->stream), "restart W")))
+                return s;
+            std::fill(G.begin(), G.end(), cplx(0, 0));
+            for (int j = 0; j < k; ++j) Gat(j, j) = theta[j];
+            m = k;
+        }
+        int added = 0;
+        for (int t = 0; t < nt; ++t) {
+            void* tv = d.vec(c->d_T, t);
+            double n0;
+            if ((s = d.norm(tv, n0))) return s;
+            if (n0 == 0.0) continue;
+            for (int pass = 0; pass < 2; ++pass) {
+                std::vector<cplx> coef;
+                if ((s = d.dots(c->d_V.p, m + added, tv, coef))) return s;
+                if ((s = d.subtract(c->d_V.p, m + added, coef, tv))) return s;
+            }
+            double nr;
+            if ((s = d.norm(tv, nr))) return s;
+            if (nr < 1e-10 * std::max(1.0, n0) || m + added >= mmax) continue;
+            if ((s = d.hip(launch_scale(d.cx, tv, 1.0 / nr, N, c->stream), "normalise"))) return s;
+            if ((s = d.hip(hipMemcpyAsync(d.vec(c->d_V, m + added), tv, vb, hipMemcpyDeviceToDevice, c->stream),
+                           "append")))
+                return s;
+            ++added;
+        }
+        if (added == 0) break;  // no new direction: stagnation
+        if ((s = sigma_impl(c, d.vec(c->d_V, m), d.vec(c->d_W, m), added, STPCI_FP64))) return s;
+        for (int j = m; j < m + added; ++j) {
+            std::vector<cplx> col;
+            if ((s = d.dots(c->d_V.p, m + added, d.vec(c->d_W, j), col))) return s;
+            for (int i = 0; i < m + added; ++i) {
+                Gat(i, j) = col[i];
+                Gat(j, i) = std::conj(col[i]);
+            }
+        }
+        m += added;
+    }
+    for (int j = 0; j < k; ++j) {
+        energies[j] = theta[j];
+        resid[j] = rn[j];
+    }
+    if (vecs_dev) {
+        if ((s = d.hip(hipMemcpyAsync(vecs_dev, c->d_X.p, vb * k, hipMemcpyDeviceToDevice, c->stream), "vecs out")))
+            return s;
+    }
+    if ((s = d.hip(hipStreamSynchronize(c->stream), "sync"))) return s;
+    if (n_iter) *n_iter = std::min(it, max_iter);
+    return converged ? STPCI_OK : set_err(c, STPCI_ENOCONV, "Davidson did not converge");
+}
+
+extern "C" stpci_status stpci_dav_history(const stpci_ctx* c, int* n_iter, int cap, double* energies,
+                                          double* resid) {
+    if (!c) return STPCI_EINVAL;
+    int n = (int)c->history.size();
+    if (n_iter) *n_iter = n;
+    int k = c->hist_k;
+    for (int i = 0; i < std::min(n, cap); ++i)
+        for (int j = 0; j < k; ++j) {
+            if (energies) energies[i * k + j] = c->history[i].e[j];
+            if (resid) resid[i * k + j] = c->history[i].r[j];
+        }
+    return STPCI_OK;
+}

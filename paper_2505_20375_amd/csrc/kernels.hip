@@ -1,0 +1,590 @@
+// HIP kernels of the categorical STP-DAS sigma build and the Davidson vector
+// algebra, written for gfx950 (64-wide wavefronts).
+//
+// sigma = 1e-sigma + 2e-sigma (Eq. sigmaL):
+//   1e: sigma_L += sum_pq h'_pq <L|E_pq|K> C_K          (Eq. sigmaL1e)
+//   2e: sigma_L += 1/2 sum_J sum_pqrs <L|E_pq|J> (pq|rs) <J|E_rs|K> C_K   (Eq. sigmaL2e)
+// with h'_pq = h_pq - 1/2 sum_r (pr|rq).  A "move" from a determinant D is
+// the pair (x created, y annihilated) of E_xy applied to D; its target is the
+// determinant reached and its sign that of E_xy D.  For an intermediate J the
+// moves (x, y) give
+//   D side:  K = E_xy J,  <J|E_rs|K> = sign  with (r, s) = (y, x)
+//   E side:  L = E_xy J,  <L|E_pq|J> = sign  with (p, q) = (x, y)
+// so the 2e update of J is e = G_J d with G_J[m', m] = (x' y' | y x) over
+// the moves m', m of J, followed by sigma[target(m')] += 1/2 sign(m') e[m'].
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace stp {
+
+struct cd {
+    double x, y;
+};
+
+template <bool CPLX>
+struct VT;
+template <>
+struct VT<false> {
+    using T = double;
+    static __device__ __forceinline__ T zero() { return 0.0; }
+    static __device__ __forceinline__ T mad(T a, T b, T c) { return fma(a, b, c); }
+    static __device__ __forceinline__ T scale(T a, double s) { return a * s; }
+    static __device__ __forceinline__ T add(T a, T b) { return a + b; }
+    static __device__ __forceinline__ T sub(T a, T b) { return a - b; }
+    static __device__ __forceinline__ T conjmul(T a, T b) { return a * b; }
+    static __device__ __forceinline__ void atomic_add(T* p, T v) { unsafeAtomicAdd(p, v); }
+    static __device__ __forceinline__ double re(T a) { return a; }
+    static __device__ __forceinline__ double abs2(T a) { return a * a; }
+};
+template <>
+struct VT<true> {
+    using T = cd;
+    static __device__ __forceinline__ T zero() { return cd{0.0, 0.0}; }
+    static __device__ __forceinline__ T mad(T a, T b, T c) {
+        c.x = fma(a.x, b.x, c.x);
+        c.x = fma(-a.y, b.y, c.x);
+        c.y = fma(a.x, b.y, c.y);
+        c.y = fma(a.y, b.x, c.y);
+        return c;
+    }
+    static __device__ __forceinline__ T scale(T a, double s) { return cd{a.x * s, a.y * s}; }
+    static __device__ __forceinline__ T add(T a, T b) { return cd{a.x + b.x, a.y + b.y}; }
+    static __device__ __forceinline__ T sub(T a, T b) { return cd{a.x - b.x, a.y - b.y}; }
+    // conj(a) * b
+    static __device__ __forceinline__ T conjmul(T a, T b) {
+        return cd{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+    }
+    static __device__ __forceinline__ void atomic_add(T* p, T v) {
+        unsafeAtomicAdd(&p->x, v.x);
+        unsafeAtomicAdd(&p->y, v.y);
+    }
+    static __device__ __forceinline__ double re(T a) { return a.x; }
+    static __device__ __forceinline__ double abs2(T a) { return a.x * a.x + a.y * a.y; }
+};
+
+// ---------------------------------------------------------------------------
+// string / move machinery
+// ---------------------------------------------------------------------------
+struct Det {
+    int64_t r[KMAX];   // local ranks
+    uint32_t s[KMAX];  // local occupation masks
+};
+
+__host__ __device__ __forceinline__ void decode(const DevSpace& S, const Cat& C, int64_t j, Det& d) {
+    const int K = S.sp.K;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        if (k < K) {
+            int64_t r = (j / C.stride[k]) % C.count[k];
+            d.r[k] = r;
+            d.s[k] = S.bits[S.tabs[C.tab[k]].bits_off + r];
+        }
+    }
+}
+
+__host__ __device__ __forceinline__ int nth_set(uint32_t v, int i) {
+    for (int t = 0; t < i; ++t) v &= v - 1u;
+    return __builtin_ctz(v);
+}
+
+__host__ __device__ __forceinline__ uint32_t lowmask(int m) { return (m >= 32) ? 0xffffffffu : ((1u << m) - 1u); }
+
+// Apply the move of class `cls` (local orbitals lx in xs, ly in ys) to d.
+// Returns the vector address of the target and its sign.
+__host__ __device__ __forceinline__ int64_t apply_move(const DevSpace& S, const Cat& C, int cls, int xs, int ys, int lx,
+                                              int ly, const Det& d, int& sign) {
+    const int K = S.sp.K;
+    const Cat& T = S.cats[C.cls_target[cls]];
+    int sg = 1;
+    int64_t rx = d.r[xs], ry = d.r[ys];
+    if (xs == ys) {
+        if (lx != ly) {
+            const StrTab& t0 = S.tabs[C.tab[ys]];
+            int32_t a = S.ann[t0.ann_off + d.r[ys] * t0.m + ly];
+            int64_t r1 = (a < 0 ? -a : a) - 1;
+            if (a < 0) sg = -sg;
+            const StrTab& t1 = S.tabs[t0.tab_dn];
+            int32_t b = S.cre[t1.cre_off + r1 * t1.m + lx];
+            rx = (b < 0 ? -b : b) - 1;
+            if (b < 0) sg = -sg;
+            ry = rx;
+        }
+    } else {
+        const StrTab& ty = S.tabs[C.tab[ys]];
+        int32_t a = S.ann[ty.ann_off + d.r[ys] * ty.m + ly];
+        ry = (a < 0 ? -a : a) - 1;
+        if (a < 0) sg = -sg;
+        const StrTab& tx = S.tabs[C.tab[xs]];
+        int32_t b = S.cre[tx.cre_off + d.r[xs] * tx.m + lx];
+        rx = (b < 0 ? -b : b) - 1;
+        if (b < 0) sg = -sg;
+        if (C.cls_phase[cls]) sg = -sg;
+    }
+    int64_t addr = T.offset;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        if (k < K) {
+            int64_t r = (k == xs) ? rx : ((k == ys) ? ry : d.r[k]);
+            addr += r * T.stride[k];
+        }
+    }
+    sign = sg;
+    return addr;
+}
+
+// Move of slot `slot` of category C for determinant d.
+__host__ __device__ __forceinline__ void slot_move(const DevSpace& S, const Cat& C, const Det& d, int slot, int& cls,
+                                          int& xs, int& ys, int& lx, int& ly) {
+    const int K = S.sp.K;
+    int c = 0;
+    while (C.cls_begin[c + 1] <= slot) ++c;
+    cls = c;
+    int code = C.cls_code[c];
+    xs = code / K;
+    ys = code - xs * K;
+    int t = slot - C.cls_begin[c];
+    int w = C.cls_width[c];
+    int i = t / w, jx = t - i * w;
+    ly = nth_set(d.s[ys], i);
+    int mx = S.sp.sub_m[xs];
+    int nvirt = mx - C.occ[xs];
+    lx = (jx < nvirt) ? nth_set(~d.s[xs] & lowmask(mx), jx) : ly;
+}
+
+__host__ __device__ __forceinline__ int find_segment(const int64_t* begin, int n, int64_t x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// 1e sigma: owner-computes over target determinants (writes every sigma_L)
+// ---------------------------------------------------------------------------
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_sigma1e(DevSpace S, const typename VT<CPLX>::T* __restrict__ hp,
+                                                 const typename VT<CPLX>::T* __restrict__ c,
+                                                 typename VT<CPLX>::T* __restrict__ sigma, int n_vec) {
+    using V = VT<CPLX>;
+    using T = typename V::T;
+    const int64_t nd = S.sp.ndets;
+    const int M = S.sp.M;
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < nd; L += (int64_t)gridDim.x * blockDim.x) {
+        int a = find_segment(S.space_begin, S.sp.nspace, L);
+        const Cat& A = S.cats[a];
+        Det d;
+        decode(S, A, L - A.offset, d);
+        for (int v = 0; v < n_vec; ++v) {
+            const T* cv = c + (int64_t)v * nd;
+            T acc = V::zero();
+            for (int slot = 0; slot < A.deg; ++slot) {
+                int cls, xs, ys, lx, ly, sg;
+                slot_move(S, A, d, slot, cls, xs, ys, lx, ly);
+                int64_t t = apply_move(S, A, cls, xs, ys, lx, ly, d, sg);
+                int x = S.sp.sub_off[xs] + lx, y = S.sp.sub_off[ys] + ly;
+                // p = y, q = x
+                acc = V::mad(V::scale(hp[y * M + x], (double)sg), cv[t], acc);
+            }
+            sigma[(int64_t)v * nd + L] = acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2e sigma, reference form: one wavefront per intermediate determinant J.
+// ---------------------------------------------------------------------------
+constexpr int MAXDEG_V0 = MAXDEG;
+
+template <bool CPLX>
+__global__ __launch_bounds__(64) void k_sigma2e_v0(DevSpace S, const typename VT<CPLX>::T* __restrict__ gT,
+                                                   const typename VT<CPLX>::T* __restrict__ c,
+                                                   typename VT<CPLX>::T* __restrict__ sigma, int n_vec) {
+    using V = VT<CPLX>;
+    using T = typename V::T;
+    __shared__ T dsh[MAXDEG_V0];
+    __shared__ int64_t tgt[MAXDEG_V0];
+    __shared__ int32_t pr[MAXDEG_V0];
+    const int lane = threadIdx.x;
+    const int M = S.sp.M;
+    const int64_t MM = (int64_t)M * M;
+    const int64_t nd = S.sp.ndets;
+    for (int64_t J = blockIdx.x; J < S.sp.nwork_dets; J += gridDim.x) {
+        int w = find_segment(S.work_begin, S.sp.nwork, J);
+        const Cat& C = S.cats[S.work_cat[w]];
+        Det d;
+        decode(S, C, J - S.work_begin[w], d);
+        const int deg = C.deg;
+        for (int slot = lane; slot < deg; slot += 64) {
+            int cls, xs, ys, lx, ly, sg;
+            slot_move(S, C, d, slot, cls, xs, ys, lx, ly);
+            int64_t t = apply_move(S, C, cls, xs, ys, lx, ly, d, sg);
+            int x = S.sp.sub_off[xs] + lx, y = S.sp.sub_off[ys] + ly;
+            tgt[slot] = t;
+            pr[slot] = ((y * M + x) << 1) | (sg < 0 ? 1 : 0);
+        }
+        __syncthreads();
+        for (int v = 0; v < n_vec; ++v) {
+            const T* cv = c + (int64_t)v * nd;
+            for (int slot = lane; slot < deg; slot += 64) {
+                T val = cv[tgt[slot]];
+                dsh[slot] = (pr[slot] & 1) ? V::scale(val, -1.0) : val;
+            }
+            __syncthreads();
+            for (int row = lane; row < deg; row += 64) {
+                const int64_t prow = pr[row] >> 1;
+                T acc = V::zero();
+                for (int col = 0; col < deg; ++col) {
+                    const int64_t pc = pr[col] >> 1;
+                    acc = V::mad(gT[pc * MM + prow], dsh[col], acc);
+                }
+                double s = (pr[row] & 1) ? -0.5 : 0.5;
+                V::atomic_add(&sigma[(int64_t)v * nd + tgt[row]], V::scale(acc, s));
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal of H, computed on the fly (never stored by the solver):
+//   H_LL = e_core + sum_{i in L} h_ii + sum_{i<j in L} [(ii|jj) - (ij|ji)]
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double diag_elem(const DevSpace& S, const double* __restrict__ hd,
+                                            const double* __restrict__ JK, double e_core, int64_t L) {
+    int a = find_segment(S.space_begin, S.sp.nspace, L);
+    const Cat& A = S.cats[a];
+    Det d;
+    decode(S, A, L - A.offset, d);
+    int occ[MMAX];
+    int n = 0;
+    for (int k = 0; k < S.sp.K; ++k) {
+        uint32_t s = d.s[k];
+        while (s) {
+            occ[n++] = S.sp.sub_off[k] + __builtin_ctz(s);
+            s &= s - 1u;
+        }
+    }
+    const int M = S.sp.M;
+    double e = e_core;
+    for (int i = 0; i < n; ++i) {
+        e += hd[occ[i]];
+        const double* row = JK + occ[i] * M;
+        for (int j = i + 1; j < n; ++j) e += row[occ[j]];
+    }
+    return e;
+}
+
+__global__ __launch_bounds__(256) void k_diag(DevSpace S, const double* hd, const double* JK, double e_core,
+                                              double* out) {
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < S.sp.ndets;
+         L += (int64_t)gridDim.x * blockDim.x)
+        out[L] = diag_elem(S, hd, JK, e_core, L);
+}
+
+// Davidson preconditioner (Eq. sparsePreconditioner with eps = 0):
+//   t_i = r_i / (theta - H_ii) if |theta - H_ii| >= guard, else 0.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_precond(DevSpace S, const double* hd, const double* JK, double e_core,
+                                                 const typename VT<CPLX>::T* __restrict__ r,
+                                                 typename VT<CPLX>::T* __restrict__ t, double theta,
+                                                 double guard) {
+    using V = VT<CPLX>;
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < S.sp.ndets;
+         L += (int64_t)gridDim.x * blockDim.x) {
+        double den = theta - diag_elem(S, hd, JK, e_core, L);
+        t[L] = (fabs(den) >= guard) ? V::scale(r[L], 1.0 / den) : V::zero();
+    }
+}
+
+// Lowest-k diagonal entries (value, address), ties to the lower address.
+constexpr int TOPK = 16;
+__global__ __launch_bounds__(256) void k_diag_topk(DevSpace S, const double* hd, const double* JK, double e_core,
+                                                   int k, double* out_val, int64_t* out_idx) {
+    double bv[TOPK];
+    int64_t bi[TOPK];
+    for (int i = 0; i < TOPK; ++i) { bv[i] = 1e300; bi[i] = INT64_MAX; }
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < S.sp.ndets;
+         L += (int64_t)gridDim.x * blockDim.x) {
+        double e = diag_elem(S, hd, JK, e_core, L);
+        if (e < bv[k - 1] || (e == bv[k - 1] && L < bi[k - 1])) {
+            int p = k - 1;
+            while (p > 0 && (e < bv[p - 1] || (e == bv[p - 1] && L < bi[p - 1]))) {
+                bv[p] = bv[p - 1];
+                bi[p] = bi[p - 1];
+                --p;
+            }
+            bv[p] = e;
+            bi[p] = L;
+        }
+    }
+    __shared__ double sv[256 * TOPK];
+    __shared__ int64_t si[256 * TOPK];
+    for (int i = 0; i < k; ++i) { sv[threadIdx.x * k + i] = bv[i]; si[threadIdx.x * k + i] = bi[i]; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double rv[TOPK];
+        int64_t ri[TOPK];
+        for (int i = 0; i < k; ++i) { rv[i] = 1e300; ri[i] = INT64_MAX; }
+        for (int q = 0; q < (int)blockDim.x * k; ++q) {
+            double e = sv[q];
+            int64_t L = si[q];
+            if (e < rv[k - 1] || (e == rv[k - 1] && L < ri[k - 1])) {
+                int p = k - 1;
+                while (p > 0 && (e < rv[p - 1] || (e == rv[p - 1] && L < ri[p - 1]))) {
+                    rv[p] = rv[p - 1];
+                    ri[p] = ri[p - 1];
+                    --p;
+                }
+                rv[p] = e;
+                ri[p] = L;
+            }
+        }
+        for (int i = 0; i < k; ++i) { out_val[blockIdx.x * k + i] = rv[i]; out_idx[blockIdx.x * k + i] = ri[i]; }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Vector algebra (memory-bound; wavefront + block reductions, fixed order)
+// ---------------------------------------------------------------------------
+constexpr int DOTV = 8;   // vectors per launch row
+
+// partial[block][i] = sum over the block's range of conj(V_i) * w
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_dots(const typename VT<CPLX>::T* __restrict__ Vb, int64_t ld, int m,
+                                              const typename VT<CPLX>::T* __restrict__ w, int64_t n,
+                                              typename VT<CPLX>::T* __restrict__ partial) {
+    using V = VT<CPLX>;
+    using T = typename V::T;
+    const int i0 = blockIdx.y * DOTV;
+    T acc[DOTV];
+#pragma unroll
+    for (int i = 0; i < DOTV; ++i) acc[i] = V::zero();
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        T wv = w[e];
+#pragma unroll
+        for (int i = 0; i < DOTV; ++i)
+            if (i0 + i < m) acc[i] = V::add(acc[i], V::conjmul(Vb[(int64_t)(i0 + i) * ld + e], wv));
+    }
+    __shared__ T red[256];
+    for (int i = 0; i < DOTV; ++i) {
+        if (i0 + i >= m) break;
+        red[threadIdx.x] = acc[i];
+        __syncthreads();
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] = V::add(red[threadIdx.x], red[threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * m + i0 + i] = red[0];
+        __syncthreads();
+    }
+}
+
+template <bool CPLX>
+__global__ void k_reduce_partials(const typename VT<CPLX>::T* __restrict__ partial, int nblk, int m,
+                                  typename VT<CPLX>::T* __restrict__ out) {
+    using V = VT<CPLX>;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    typename V::T s = V::zero();
+    for (int b = 0; b < nblk; ++b) s = V::add(s, partial[(int64_t)b * m + i]);
+    out[i] = s;
+}
+
+// out_j = sum_i A_i * Y[i][j]  (+ beta_j * out_j when accumulate)   for j < k
+// optionally R_j = sum_i B_i * Y[i][j] - theta_j * out_j
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_combine(const typename VT<CPLX>::T* __restrict__ A,
+                                                 const typename VT<CPLX>::T* __restrict__ B, int64_t ld, int m,
+                                                 const typename VT<CPLX>::T* __restrict__ Y, int k,
+                                                 const double* __restrict__ theta,
+                                                 typename VT<CPLX>::T* __restrict__ X,
+                                                 typename VT<CPLX>::T* __restrict__ R, int64_t n, int mode) {
+    // mode 0: X = A Y ; mode 1: X = A Y, R = B Y - X theta ; mode 2: X -= A Y (Y: m x 1)
+    using V = VT<CPLX>;
+    using T = typename V::T;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        for (int j = 0; j < k; ++j) {
+            T xs = V::zero(), rs = V::zero();
+            for (int i = 0; i < m; ++i) {
+                T y = Y[i * k + j];
+                xs = V::mad(A[(int64_t)i * ld + e], y, xs);
+                if (mode == 1) rs = V::mad(B[(int64_t)i * ld + e], y, rs);
+            }
+            if (mode == 2) {
+                X[(int64_t)j * ld + e] = V::sub(X[(int64_t)j * ld + e], xs);
+            } else {
+                X[(int64_t)j * ld + e] = xs;
+                if (mode == 1) R[(int64_t)j * ld + e] = V::sub(rs, V::scale(xs, theta[j]));
+            }
+        }
+    }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_scale(typename VT<CPLX>::T* __restrict__ x, double s, int64_t n) {
+    using V = VT<CPLX>;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        x[e] = V::scale(x[e], s);
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_unit(typename VT<CPLX>::T* __restrict__ x, int64_t n, int64_t at) {
+    using V = VT<CPLX>;
+    typename V::T one = V::zero();
+    *reinterpret_cast<double*>(&one) = 1.0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        x[e] = (e == at) ? one : V::zero();
+}
+
+// ---------------------------------------------------------------------------
+// Host-side check of the move machinery used by the kernels: for every
+// checked determinant and every move slot, the target address must lie in the
+// space, hold the determinant E_xy D, and carry the sign of the global rule
+// (-1)^(#occupied below y in D) * (-1)^(#occupied below x in D - y).
+// ---------------------------------------------------------------------------
+int64_t check_moves_host(const DevSpace& S, int64_t max_dets_per_cat, int64_t* n_checked,
+                         bool (*to_bits)(const void*, int64_t, uint64_t*), const void* user) {
+    int64_t bad = 0, checked = 0;
+    const int K = S.sp.K;
+    for (int w = 0; w < S.sp.nwork; ++w) {
+        const Cat& C = S.cats[S.work_cat[w]];
+        int64_t step = C.size <= max_dets_per_cat ? 1 : C.size / max_dets_per_cat;
+        for (int64_t j = 0; j < C.size; j += step) {
+            Det d;
+            decode(S, C, j, d);
+            uint64_t Jb = 0;
+            for (int k = 0; k < K; ++k) Jb |= (uint64_t)d.s[k] << S.sp.sub_off[k];
+            for (int slot = 0; slot < C.deg; ++slot) {
+                int cls, xs, ys, lx, ly, sg;
+                slot_move(S, C, d, slot, cls, xs, ys, lx, ly);
+                int64_t t = apply_move(S, C, cls, xs, ys, lx, ly, d, sg);
+                ++checked;
+                int x = S.sp.sub_off[xs] + lx, y = S.sp.sub_off[ys] + ly;
+                uint64_t want = (Jb & ~(1ULL << y)) | (1ULL << x);
+                int par = __builtin_popcountll(Jb & ((1ULL << y) - 1ULL)) +
+                          __builtin_popcountll((Jb & ~(1ULL << y)) & ((1ULL << x) - 1ULL));
+                int want_sign = (par & 1) ? -1 : 1;
+                uint64_t got = 0;
+                if (t < 0 || t >= S.sp.ndets || !to_bits(user, t, &got) || got != want || sg != want_sign) ++bad;
+            }
+        }
+    }
+    if (n_checked) *n_checked = checked;
+    return bad;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static inline int grid_for(int64_t n, int block, int cap = 65536) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_sigma1e(const DevSpace& S, bool cplx, const void* hp, const void* c, void* sigma, int n_vec,
+                          hipStream_t st) {
+    int g = grid_for(S.sp.ndets, 256);
+    if (cplx)
+        hipLaunchKernelGGL(k_sigma1e<true>, dim3(g), dim3(256), 0, st, S, (const cd*)hp, (const cd*)c, (cd*)sigma,
+                           n_vec);
+    else
+        hipLaunchKernelGGL(k_sigma1e<false>, dim3(g), dim3(256), 0, st, S, (const double*)hp, (const double*)c,
+                           (double*)sigma, n_vec);
+    return hipGetLastError();
+}
+
+hipError_t launch_sigma2e_v0(const DevSpace& S, bool cplx, const void* gT, const void* c, void* sigma, int n_vec,
+                             hipStream_t st) {
+    int g = grid_for(S.sp.nwork_dets, 1, 1 << 20);
+    if (cplx)
+        hipLaunchKernelGGL(k_sigma2e_v0<true>, dim3(g), dim3(64), 0, st, S, (const cd*)gT, (const cd*)c,
+                           (cd*)sigma, n_vec);
+    else
+        hipLaunchKernelGGL(k_sigma2e_v0<false>, dim3(g), dim3(64), 0, st, S, (const double*)gT, (const double*)c,
+                           (double*)sigma, n_vec);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const DevSpace& S, const double* hd, const double* JK, double e_core, double* out,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_diag, dim3(grid_for(S.sp.ndets, 256)), dim3(256), 0, st, S, hd, JK, e_core, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond(const DevSpace& S, bool cplx, const double* hd, const double* JK, double e_core,
+                          const void* r, void* t, double theta, double guard, hipStream_t st) {
+    int g = grid_for(S.sp.ndets, 256);
+    if (cplx)
+        hipLaunchKernelGGL(k_precond<true>, dim3(g), dim3(256), 0, st, S, hd, JK, e_core, (const cd*)r, (cd*)t,
+                           theta, guard);
+    else
+        hipLaunchKernelGGL(k_precond<false>, dim3(g), dim3(256), 0, st, S, hd, JK, e_core, (const double*)r,
+                           (double*)t, theta, guard);
+    return hipGetLastError();
+}
+
+int topk_blocks(const DevSpace& S) { return grid_for(S.sp.ndets, 256, 1024); }
+
+hipError_t launch_diag_topk(const DevSpace& S, const double* hd, const double* JK, double e_core, int k,
+                            double* vals, int64_t* idx, hipStream_t st) {
+    hipLaunchKernelGGL(k_diag_topk, dim3(topk_blocks(S)), dim3(256), 0, st, S, hd, JK, e_core, k, vals, idx);
+    return hipGetLastError();
+}
+
+int dots_blocks(int64_t n) { return grid_for(n, 256, 1024); }
+
+hipError_t launch_dots(bool cplx, const void* Vb, int64_t ld, int m, const void* w, int64_t n, void* partial,
+                       void* out, hipStream_t st) {
+    int nb = dots_blocks(n);
+    dim3 grid(nb, (m + DOTV - 1) / DOTV);
+    if (cplx) {
+        hipLaunchKernelGGL(k_dots<true>, grid, dim3(256), 0, st, (const cd*)Vb, ld, m, (const cd*)w, n,
+                           (cd*)partial);
+        hipLaunchKernelGGL(k_reduce_partials<true>, dim3(1), dim3(64), 0, st, (const cd*)partial, nb, m, (cd*)out);
+    } else {
+        hipLaunchKernelGGL(k_dots<false>, grid, dim3(256), 0, st, (const double*)Vb, ld, m, (const double*)w, n,
+                           (double*)partial);
+        hipLaunchKernelGGL(k_reduce_partials<false>, dim3(1), dim3(64), 0, st, (const double*)partial, nb, m,
+                           (double*)out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(bool cplx, const void* A, const void* B, int64_t ld, int m, const void* Y, int k,
+                          const double* theta, void* X, void* R, int64_t n, int mode, hipStream_t st) {
+    int g = grid_for(n, 256, 8192);
+    if (cplx)
+        hipLaunchKernelGGL(k_combine<true>, dim3(g), dim3(256), 0, st, (const cd*)A, (const cd*)B, ld, m,
+                           (const cd*)Y, k, theta, (cd*)X, (cd*)R, n, mode);
+    else
+        hipLaunchKernelGGL(k_combine<false>, dim3(g), dim3(256), 0, st, (const double*)A, (const double*)B, ld, m,
+                           (const double*)Y, k, theta, (double*)X, (double*)R, n, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(bool cplx, void* x, double s, int64_t n, hipStream_t st) {
+    int g = grid_for(n, 256, 8192);
+    if (cplx)
+        hipLaunchKernelGGL(k_scale<true>, dim3(g), dim3(256), 0, st, (cd*)x, s, n);
+    else
+        hipLaunchKernelGGL(k_scale<false>, dim3(g), dim3(256), 0, st, (double*)x, s, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_unit(bool cplx, void* x, int64_t n, int64_t at, hipStream_t st) {
+    int g = grid_for(n, 256, 8192);
+    if (cplx)
+        hipLaunchKernelGGL(k_unit<true>, dim3(g), dim3(256), 0, st, (cd*)x, n, at);
+    else
+        hipLaunchKernelGGL(k_unit<false>, dim3(g), dim3(256), 0, st, (double*)x, n, at);
+    return hipGetLastError();
+}
+
+}  // namespace stp

@@ -1,0 +1,32 @@
+// Host-side launchers of the HIP kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+#include "stp_internal.hpp"
+
+namespace stp {
+
+hipError_t launch_sigma1e(const DevSpace& S, bool cplx, const void* hp, const void* c, void* sigma, int n_vec,
+                          hipStream_t st);
+hipError_t launch_sigma2e_v0(const DevSpace& S, bool cplx, const void* gT, const void* c, void* sigma, int n_vec,
+                             hipStream_t st);
+hipError_t launch_diag(const DevSpace& S, const double* hd, const double* JK, double e_core, double* out,
+                       hipStream_t st);
+hipError_t launch_precond(const DevSpace& S, bool cplx, const double* hd, const double* JK, double e_core,
+                          const void* r, void* t, double theta, double guard, hipStream_t st);
+int topk_blocks(const DevSpace& S);
+hipError_t launch_diag_topk(const DevSpace& S, const double* hd, const double* JK, double e_core, int k,
+                            double* vals, int64_t* idx, hipStream_t st);
+int dots_blocks(int64_t n);
+hipError_t launch_dots(bool cplx, const void* Vb, int64_t ld, int m, const void* w, int64_t n, void* partial,
+                       void* out, hipStream_t st);
+hipError_t launch_combine(bool cplx, const void* A, const void* B, int64_t ld, int m, const void* Y, int k,
+                          const double* theta, void* X, void* R, int64_t n, int mode, hipStream_t st);
+hipError_t launch_scale(bool cplx, void* x, double s, int64_t n, hipStream_t st);
+int64_t check_moves_host(const DevSpace& S, int64_t max_dets_per_cat, int64_t* n_checked,
+                         bool (*to_bits)(const void*, int64_t, uint64_t*), const void* user);
+hipError_t launch_unit(bool cplx, void* x, int64_t n, int64_t at, hipStream_t st);
+
+}  // namespace stp

@@ -1,0 +1,85 @@
+// Internal data layout shared by the host tables (space.cpp) and the HIP
+// kernels (kernels.hip).  Plain structs only; no HIP types.
+#pragma once
+#include <cstdint>
+
+namespace stp {
+
+constexpr int KMAX = 8;          // subspaces (distributed active spaces)
+constexpr int MMAX = 64;         // spin-orbitals in total
+constexpr int MSUB = 32;         // spin-orbitals per subspace (local strings are uint32 masks)
+constexpr int NCLS = KMAX * KMAX;
+constexpr int MAXDEG = 1024;    // moves per determinant handled by the per-determinant 2e kernel
+
+// A local string table: all strings of n electrons in an m-orbital subspace,
+// ranked in colexicographic order (= ascending value of the bit mask).
+// ann[rank*m + l]: a_l applied to the string, packed as sign*(rank'+1) in the
+// table `tab_dn` (n-1 electrons), 0 if l is empty.  cre[rank*m + l]: a+_l,
+// packed into table `tab_up` (n+1 electrons), 0 if l is occupied.  The sign is
+// (-1)^(number of occupied local orbitals below l).
+struct StrTab {
+    int32_t m, n;
+    int64_t count;
+    int64_t bits_off;   // into bits[]
+    int64_t ann_off;    // into ann[] (count*m entries) or -1
+    int64_t cre_off;    // into cre[] (count*m entries) or -1
+    int32_t tab_dn;     // table index of (m, n-1) or -1
+    int32_t tab_up;     // table index of (m, n+1) or -1
+};
+
+// One category: an occupation tuple (n_1..n_K).  Categories inside the space
+// own a dense block of the CI vector (row-major over the local ranks, subspace
+// 1 slowest); categories outside the space appear only as intermediates of
+// the two-electron resolution.
+//
+// Move classes: a move creates x in subspace xs and annihilates y in subspace
+// ys (x == y allowed when xs == ys).  Class c = xs*K + ys is usable when the
+// category reached, cat + e_xs - e_ys, lies in the space; its slots are
+// enumerated y-major: slot = i*width + j with y = i-th occupied orbital of
+// the ys string and x = j-th empty orbital of the xs string, or x = y for the
+// last j when xs == ys.
+struct Cat {
+    int32_t occ[KMAX];
+    int32_t tab[KMAX];          // string table of (subspace k, occ[k])
+    int64_t count[KMAX];        // strings per subspace
+    int64_t stride[KMAX];       // row-major strides over local ranks
+    int64_t size;               // number of determinants
+    int64_t offset;             // vector offset (space categories) or -1
+    int64_t jbegin;             // first index in the intermediate enumeration, -1 if none
+    int32_t in_space;
+    int32_t deg;                // moves into the space from one determinant
+    int32_t ncls;
+    int32_t cls_code[NCLS];     // xs*K + ys
+    int32_t cls_width[NCLS];    // (m_xs - n_xs) + (xs == ys)
+    int32_t cls_begin[NCLS + 1];
+    int32_t cls_target[NCLS];   // category index reached
+    int32_t cls_phase[NCLS];    // 0/1: parity of electrons passed between subspaces
+};
+
+struct Space {
+    int32_t K, M, N;
+    int32_t sub_off[KMAX];
+    int32_t sub_m[KMAX];
+    int32_t ncat;               // all categories (space first, then intermediates)
+    int32_t nspace;             // number of space categories
+    int32_t nwork;              // categories with deg > 0 (intermediates of the 2e sum)
+    int64_t ndets;              // determinants in the space
+    int64_t nwork_dets;         // determinants over all work categories
+};
+
+// Device view passed by value to kernels.
+struct DevSpace {
+    Space sp;
+    const Cat* cats;
+    const StrTab* tabs;
+    const uint32_t* bits;
+    const int32_t* ann;
+    const int32_t* cre;
+    const int32_t* work_cat;     // [nwork] category index
+    const int64_t* work_begin;   // [nwork + 1] prefix over sizes
+    const int64_t* space_begin;  // [nspace + 1] vector offsets
+};
+
+inline int packed_rank(int32_t v) { return (v < 0 ? -v : v) - 1; }
+
+}  // namespace stp

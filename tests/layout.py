@@ -1,0 +1,54 @@
+"""The documented CI-vector layout, written out independently of the library.
+
+Categories in lexicographic order of (n_1..n_K); inside a category, row-major
+over the local string ranks with subspace 1 slowest; the local rank of a
+string is its position among the masks of equal popcount sorted ascending.
+Used by the tests to move seeded vectors between the oracle's order
+(ascending bitstring) and the library's layout.
+"""
+import itertools
+
+import numpy as np
+
+
+def categories(n_elec, sub, lo, hi):
+    out = []
+    for t in itertools.product(*[range(max(l, 0), min(h, m) + 1) for m, l, h in zip(sub, lo, hi)]):
+        if sum(t) == n_elec:
+            out.append(t)
+    return sorted(out)
+
+
+def local_masks(m, n):
+    return sorted(sum(1 << i for i in c) for c in itertools.combinations(range(m), n))
+
+
+def layout_dets(n_elec, sub, lo=None, hi=None):
+    lo = list(lo) if lo is not None else [0] * len(sub)
+    hi = list(hi) if hi is not None else list(sub)
+    offs = np.cumsum([0] + list(sub))[:-1]
+    out = []
+    for t in categories(n_elec, sub, lo, hi):
+        lists = [local_masks(m, n) for m, n in zip(sub, t)]
+        for combo in itertools.product(*lists):
+            b = 0
+            for k, mk in enumerate(combo):
+                b |= int(mk) << int(offs[k])
+            out.append(b)
+    return np.array(out, dtype=np.uint64)
+
+
+class Perm:
+    """Maps vectors between oracle order (sorted dets) and library layout."""
+
+    def __init__(self, sorted_dets, lib_dets):
+        self.idx = np.searchsorted(sorted_dets, lib_dets)
+        assert np.all(sorted_dets[self.idx] == lib_dets)
+
+    def to_lib(self, x_oracle):
+        return x_oracle[self.idx]
+
+    def to_oracle(self, x_lib):
+        out = np.empty_like(x_lib)
+        out[self.idx] = x_lib
+        return out

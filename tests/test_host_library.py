@@ -1,0 +1,169 @@
+"""Host-side checks of libstpci (no GPU): exported symbols, space and table
+logic, work counts, layout, validation, and the host eigensolver."""
+import glob
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2505_20375_amd as stpci
+import synth
+from oracle import space as ospace
+from tests import layout
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for hdr in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(hdr).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b(stpci_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert "stpci_sigma" in names and "stpci_davidson" in names
+    for n in sorted(names):
+        assert hasattr(stpci._lib, n), n
+
+
+def host_ctx(n_elec, sub, lo=None, hi=None):
+    c = stpci.Context(device=-1)
+    c.set_space(n_elec, sub, lo, hi)
+    return c
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3p", "c3lit"])
+def test_space_sizes(name):
+    sp = synth.CONFIGS[name]["space"]
+    c = host_ctx(sp.n_elec, sp.sub, sp.lo, sp.hi)
+    info = c.space_info()
+    assert info.n_dets == sp.n_dets()
+    assert info.n_cat == len(sp.categories())
+    if name == "c3p":
+        assert info.n_dets == 1365867360 and info.n_cat == 10
+        assert info.w_sigma_macs == pytest.approx(3.80e11 + 1.144e14, rel=2e-3)
+    if name == "c2":
+        assert info.nnz_h == pytest.approx(2.566e9, rel=1e-3)
+
+
+@pytest.mark.parametrize("n,sub,lo,hi", [
+    (3, [8], None, None),
+    (4, [4, 6], [1, 1], [3, 3]),
+    (5, [4, 4, 4], [1, 1, 1], [2, 3, 2]),
+    (4, [4, 4, 4], None, None),
+    (8, [8, 8], [4, 4], [4, 4]),
+])
+def test_layout_and_address_to_det(n, sub, lo, hi):
+    c = host_ctx(n, sub, lo, hi)
+    ref = layout.layout_dets(n, sub, lo, hi)
+    info = c.space_info()
+    assert info.n_dets == len(ref)
+    got = np.array([c.address_to_det(i) for i in range(len(ref))], dtype=np.uint64)
+    assert np.array_equal(got, ref)
+    # same determinant set as the oracle's enumeration
+    assert np.array_equal(np.sort(got), ospace.enumerate_dets(n, sub, lo, hi))
+    cats = layout.categories(n, sub, lo or [0] * len(sub), hi or list(sub))
+    off = 0
+    for i, t in enumerate(cats):
+        occ, o, nd = c.category(i)
+        assert occ == t and o == off
+        assert nd == math.prod(math.comb(m, k) for m, k in zip(sub, t))
+        off += nd
+
+
+def brute_counts(n, sub, lo, hi):
+    """W1, W2 and structural nnz(H) by explicit enumeration of bitstrings."""
+    M = sum(sub)
+    lo = lo or [0] * len(sub)
+    hi = hi or list(sub)
+    dets = ospace.enumerate_dets(n, sub, lo, hi)
+    inset = set(int(b) for b in dets)
+    allN = ospace.enumerate_dets(n, [M])
+    W1 = W2 = 0
+    for J in allN:
+        J = int(J)
+        deg = 0
+        for y in range(M):
+            if not (J >> y) & 1:
+                continue
+            for x in range(M):
+                if x != y and (J >> x) & 1:
+                    continue
+                K = (J & ~(1 << y)) | (1 << x)
+                if K in inset:
+                    deg += 1
+        W2 += deg * deg
+        if J in inset:
+            W1 += deg
+    nnz = 0
+    for L in dets:
+        for K in dets:
+            if bin(int(L) ^ int(K)).count("1") <= 4:
+                nnz += 1
+    return W1, W2, nnz
+
+
+@pytest.mark.parametrize("n,sub,lo,hi", [
+    (3, [7], None, None),
+    (4, [4, 6], [1, 1], [3, 3]),
+    (4, [3, 3, 3], [1, 0, 1], [2, 2, 2]),
+])
+def test_work_counts_match_brute_force(n, sub, lo, hi):
+    c = host_ctx(n, sub, lo, hi)
+    info = c.space_info()
+    W1, W2, nnz = brute_counts(n, sub, lo, hi)
+    assert info.w_sigma_macs == W1 + W2
+    assert info.nnz_h == nnz
+
+
+def test_invalid_inputs_are_rejected():
+    c = stpci.Context(device=-1)
+    with pytest.raises(stpci.StpciError) as e:
+        c.set_space(9, [4, 4], [0, 0], [4, 4])  # 9 electrons cannot fit
+    assert e.value.status in (stpci.EINVAL,)
+    with pytest.raises(stpci.StpciError):
+        c.set_space(4, [4, 4], [3, 3], [4, 4])  # windows exclude every pattern
+    ints = synth.complex_integrals(4, 1)
+    bad = ints.h.copy()
+    bad[0, 1] += 0.1
+    with pytest.raises(stpci.StpciError) as e:
+        c.set_integrals(bad, ints.g)
+    assert e.value.status == stpci.EINVAL
+    g2 = ints.g.copy()
+    g2[0, 1, 2, 3] += 0.01
+    with pytest.raises(stpci.StpciError):
+        c.set_integrals(ints.h, g2)
+    c.set_integrals(ints.h, ints.g)
+    with pytest.raises(stpci.StpciError) as e:
+        c.sigma(0, 0)
+    # device calls on a host-only context report a state error, not a crash
+    assert e.value.status in (stpci.EINVAL, stpci.ESTATE)
+
+
+def test_host_eigensolver_matches_lapack():
+    rng = np.random.default_rng(0)
+    for n in (1, 2, 5, 17, 40):
+        Z = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+        A = Z + Z.conj().T
+        w, V = stpci.heev(A)
+        assert np.allclose(w, np.linalg.eigvalsh(A), atol=1e-11 * max(1, np.abs(A).max()))
+        assert np.allclose(A @ V, V * w, atol=1e-10 * max(1, np.abs(A).max()))
+        assert np.allclose(V.conj().T @ V, np.eye(n), atol=1e-12)
+
+
+@pytest.mark.parametrize("name,cap", [("T2", 1 << 40), ("T3", 1 << 40), ("T4", 1 << 40), ("T8", 1 << 40),
+                                      ("c1", 1 << 40), ("c2", 5000), ("c3p", 300)])
+def test_kernel_move_arithmetic_on_host(name, cap):
+    """The move enumeration, signs and target addresses that the sigma kernels
+    compute (same code, compiled for the host) agree with the global
+    fermion-sign rule and stay inside the space."""
+    sp = (synth.CONFIGS.get(name) or synth.TSPACES[name])["space"]
+    c = host_ctx(sp.n_elec, sp.sub, sp.lo, sp.hi)
+    n, bad = c.test_moves(cap)
+    assert n > 0 and bad == 0

@@ -20,6 +20,12 @@ if not os.path.exists(LIB_PATH):
     raise ImportError("libstpci.so is not built; run `python paper_2505_20375_amd/build.py` "
                       "(or __graft_entry__.build()) first")
 
+# PyTorch bundles its own HIP runtime (SONAME libamdhip64.so.7).  Loading
+# torch first makes libstpci's dependency resolve to that same runtime, so the
+# process holds exactly one HIP runtime shared by torch's allocations, streams
+# and this library's kernels.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5

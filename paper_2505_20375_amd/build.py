@@ -19,7 +19,8 @@ ARCH = os.environ.get("STPCI_ARCH", "gfx950")
 SOURCES = ["kernels.hip", "sigma2e.hip", "space.cpp", "capi.cpp", "davidson.cpp"]
 
 # gfx950 device code is built without packed FP32 instructions.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Code object v5 is loadable by the HIP runtime that PyTorch bundles.
+DEVICE_FLAGS = ["-mcode-object-version=5", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I" + CSRC,
           "-I" + os.path.join(os.path.dirname(HERE), "include")]
 
@@ -43,7 +44,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-mcode-object-version=5", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

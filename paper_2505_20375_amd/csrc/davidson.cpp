@@ -306,7 +306,8 @@ extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, do
             }
             double nr;
             if ((s = d.norm(tv, nr))) return s;
-            if (nr < 1e-10 * std::max(1.0, n0) || m + added >= mmax) continue;
+            // a direction that lost all but 1e-8 of its norm lies in the span (linear dependence)
+            if (nr < 1e-8 * n0 || m + added >= mmax) continue;
             if ((s = d.hip(launch_scale(d.cx, tv, 1.0 / nr, N, c->stream), "normalise"))) return s;
             if ((s = d.hip(hipMemcpyAsync(d.vec(c->d_V, m + added), tv, vb, hipMemcpyDeviceToDevice, c->stream),
                            "append")))

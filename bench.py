@@ -40,6 +40,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--solves", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calib-mb", type=float, default=0.0,
+                    help="only run a plain device copy of this many MB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -48,6 +50,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calib_mb > 0:
+        # a plain copy kernel of known size: reads and writes exactly n bytes per launch
+        n = int(args.copy_calib_mb * 2 ** 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(max(args.steps, 1)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8, "launches": max(args.steps, 1)}))
+        return
 
     import synth
     import paper_2505_20375_amd as stpci

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -19,7 +20,7 @@ stpci_ctx::~stpci_ctx() {
             (void)hipEventDestroy(e.a);
             (void)hipEventDestroy(e.b);
         }
-        for (DevBuf* b : {&d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
+        for (DevBuf* b : {&d_s2blocks, &d_ygroup, &d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
                           &d_hp, &d_gT, &d_hd, &d_JK, &d_V, &d_W, &d_X, &d_R, &d_T, &d_partial, &d_small, &d_topv,
                           &d_topi})
             b->free_();
@@ -92,6 +93,51 @@ stpci_status prepare(stpci_ctx* c) {
     if ((s = upload(c, c->d_gT, c->gT, "two-electron integrals"))) return s;
     if ((s = upload(c, c->d_hd, c->hd, "diagonal integrals"))) return s;
     if ((s = upload(c, c->d_JK, c->JK, "Coulomb-exchange integrals"))) return s;
+    // schedule of the tiled two-electron kernel
+    {
+        const char* kv = getenv("STPCI_SIGMA2E");
+        c->s2_kernel = 3;
+        if (kv && !strcmp(kv, "v0")) c->s2_kernel = 0;
+        if (kv && !strcmp(kv, "tiled")) c->s2_kernel = 1;
+        if (kv && !strcmp(kv, "wave")) c->s2_kernel = 2;
+        if (c->s2_kernel == 3 && !symtile_supported(H.max_deg, c->cplx)) c->s2_kernel = 1;
+        if (c->s2_kernel == 2 && !sigma_wave_supported(H.max_deg)) c->s2_kernel = 1;
+        int ngroups = 0;
+        if (const char* g = getenv("STPCI_S2_GROUPS")) ngroups = atoi(g);
+        if (ngroups <= 0) {
+            // integrals touched by one group of rows should fit a quarter of an XCD's L2 (4 MB)
+            double gbytes = (double)H.sp.M * H.sp.M * H.sp.M * H.sp.M * scalar_bytes(c);
+            ngroups = 1;
+            while (ngroups < 8 && gbytes / ngroups > 1.5e6) ngroups *= 2;
+        }
+        ngroups = std::max(1, std::min(ngroups, H.sp.M));
+        size_t budget = 60 * 1024;  // dynamic LDS per workgroup (the kernel adds ~1.3 KB static)
+        if (const char* b = getenv("STPCI_S2_LDS_KB")) budget = (size_t)atoi(b) * 1024;
+        const size_t per_move = 2 * scalar_bytes(c) + 8 + 4 + 4 + 4;
+        std::vector<Sigma2eBlock> blocks;
+        int max_tot = 0, max_nj = 0;
+        for (int w = 0; w < H.sp.nwork; ++w) {
+            const Cat& C = H.cats[H.work_cat[w]];
+            int nj = (int)std::max<int64_t>(1, (int64_t)(budget / (per_move * C.deg + DET_BYTES)));
+            nj = std::min(nj, 4096);
+            for (int64_t j0 = 0; j0 < C.size; j0 += nj) {
+                int cnt = (int)std::min<int64_t>(nj, C.size - j0);
+                blocks.push_back(Sigma2eBlock{H.work_cat[w], cnt, j0});
+                max_tot = std::max(max_tot, cnt * C.deg);
+                max_nj = std::max(max_nj, cnt);
+            }
+        }
+        std::vector<int32_t> yg(H.sp.M);
+        for (int o = 0; o < H.sp.M; ++o) yg[o] = (int32_t)((int64_t)o * ngroups / H.sp.M);
+        if ((s = upload(c, c->d_s2blocks, blocks, "sigma2e schedule"))) return s;
+        if ((s = upload(c, c->d_ygroup, yg, "row groups"))) return s;
+        c->s2.blocks = (const Sigma2eBlock*)c->d_s2blocks.p;
+        c->s2.ygroup = (const int32_t*)c->d_ygroup.p;
+        c->s2.nblocks = (int32_t)blocks.size();
+        c->s2.ngroups = ngroups;
+        c->s2.max_tot = max_tot;
+        c->s2.max_nj = max_nj;
+    }
     DevSpace& D = c->dev;
     D.sp = H.sp;
     D.cats = (const Cat*)c->d_cats.p;
@@ -122,12 +168,28 @@ static void record(stpci_ctx* c, int kind, bool start) {
 stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, stpci_precision prec) {
     if (prec != STPCI_FP64) return set_err(c, STPCI_EINVAL, "unsupported sigma precision");
     if (c->hs.max_deg > MAXDEG) return set_err(c, STPCI_EINVAL, "a determinant has more moves than MAXDEG");
+    hipError_t e;
+    if (c->s2_kernel >= 2) {
+        // one pass: zero sigma, then the fused one- and two-electron kernel
+        record(c, 1, true);
+        if (c->s2_kernel == 3)
+            e = launch_sigma_symtile(c->dev, c->hs.max_deg, c->cplx, c->d_gT.p, c->d_hp.p, cin, sout, n_vec,
+                                     c->stream);
+        else
+            e = launch_sigma_wave(c->dev, c->hs.max_deg, c->cplx, c->d_gT.p, c->d_hp.p, cin, sout, n_vec, c->stream);
+        record(c, 1, false);
+        if (e != hipSuccess) return hip_check(c, e, "sigma launch");
+        return STPCI_OK;
+    }
     record(c, 0, true);
-    hipError_t e = launch_sigma1e(c->dev, c->cplx, c->d_hp.p, cin, sout, n_vec, c->stream);
+    e = launch_sigma1e(c->dev, c->cplx, c->d_hp.p, cin, sout, n_vec, c->stream);
     record(c, 0, false);
     if (e != hipSuccess) return hip_check(c, e, "sigma1e launch");
     record(c, 1, true);
-    e = launch_sigma2e_v0(c->dev, c->cplx, c->d_gT.p, cin, sout, n_vec, c->stream);
+    if (c->s2_kernel == 0)
+        e = launch_sigma2e_v0(c->dev, c->cplx, c->d_gT.p, cin, sout, n_vec, c->stream);
+    else
+        e = launch_sigma2e_tiled(c->dev, c->s2, c->cplx, c->d_gT.p, cin, sout, n_vec, c->stream);
     record(c, 1, false);
     if (e != hipSuccess) return hip_check(c, e, "sigma2e launch");
     return STPCI_OK;

@@ -57,6 +57,11 @@ struct stpci_ctx {
     stp::DevBuf d_hp, d_gT, d_hd, d_JK;
     stp::DevSpace dev{};
 
+    // schedule of the tiled two-electron kernel
+    stp::DevBuf d_s2blocks, d_ygroup;
+    stp::Sigma2eSched s2{};
+    int s2_kernel = 2;   // 0: reference per-determinant kernel, 1: tiled, 2: fused wavefront-per-determinant
+
     // Davidson workspace
     stp::DevBuf d_V, d_W, d_X, d_R, d_T, d_partial, d_small, d_topv, d_topi;
     std::vector<stp::DavRecord> history;

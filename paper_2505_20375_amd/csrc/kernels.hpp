@@ -12,6 +12,17 @@ hipError_t launch_sigma1e(const DevSpace& S, bool cplx, const void* hp, const vo
                           hipStream_t st);
 hipError_t launch_sigma2e_v0(const DevSpace& S, bool cplx, const void* gT, const void* c, void* sigma, int n_vec,
                              hipStream_t st);
+size_t sigma2e_tiled_lds(const Sigma2eSched& P, int nv, bool cplx);
+hipError_t launch_sigma2e_tiled(const DevSpace& S, const Sigma2eSched& P, bool cplx, const void* gT, const void* c,
+                                void* sigma, int n_vec, hipStream_t st);
+bool sigma_wave_supported(int deg_max);
+bool symtile_supported(int deg_max, bool cplx);
+// sigma = H c in one pass, Hermitian 4x4 tiles per intermediate determinant
+hipError_t launch_sigma_symtile(const DevSpace& S, int deg_max, bool cplx, const void* gT, const void* hp,
+                                const void* c, void* sigma, int n_vec, hipStream_t st);
+// sigma = H c (one- and two-electron parts) in one pass over the intermediate determinants
+hipError_t launch_sigma_wave(const DevSpace& S, int deg_max, bool cplx, const void* gT, const void* hp,
+                             const void* c, void* sigma, int n_vec, hipStream_t st);
 hipError_t launch_diag(const DevSpace& S, const double* hd, const double* JK, double e_core, double* out,
                        hipStream_t st);
 hipError_t launch_precond(const DevSpace& S, bool cplx, const double* hd, const double* JK, double e_core,

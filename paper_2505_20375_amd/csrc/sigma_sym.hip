@@ -1,0 +1,266 @@
+// Fused sigma build, one wavefront per intermediate determinant, Hermitian
+// 4x4 tiles (the kernel the library uses by default).
+//
+// For an intermediate determinant J with moves m = (x created, y annihilated)
+// into the space (Eq. sigmaL2e resolved over J):
+//   d[m]       = sign(m) C[target(m)]
+//   G_J[m', m] = (x' y' | y x)            Hermitian in (m', m)
+//   e          = G_J d,   sigma[target(m')] += 1/2 sign(m') e[m'].
+// When J lies in the space the same d also yields the one-electron term of
+// Eq. sigmaL1e for L = J: sigma_J += sum_m h'_{y x} d[m].
+//
+// The moves of J are cut into blocks of 4 consecutive slots; the upper
+// triangle of 4x4 block pairs (b <= b') is split evenly over the 64 lanes.
+// A lane loads one 16-element tile of G_J (rows: 4 consecutive x' of one
+// annihilated orbital, so each column's 4 elements are adjacent in memory)
+// and uses every element for both vectors and, off the diagonal, twice:
+//   e[rows b]  += G[b, b'] d[b']          (kept in registers while b repeats)
+//   e[cols b'] += G[b, b']^H d[b]         (added to LDS with FP64 atomics).
+// Each integral element feeds 4 complex multiply-adds per vector pair, the
+// LDS traffic for d is one 4-vector per tile side, and all partial sums meet
+// in the wavefront's LDS slice before one atomic update of sigma per move.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "kernels.hpp"
+#include "stp_device.hpp"
+
+namespace stp {
+
+constexpr int ST_TILE = 4;
+
+// LDS index of (slot, vector): blocks of 4 slots are padded by 16 bytes so
+// that the lanes of a wavefront, which read blocks at a stride of one block,
+// start on different banks (a b128 read then touches each bank once per 16
+// lanes).
+template <int NV, int SB>
+__device__ __forceinline__ int st_idx(int slot, int v) {
+    constexpr int blk = ST_TILE * NV + 16 / SB;  // elements per padded block
+    return (slot >> 2) * blk + (slot & 3) * NV + v;
+}
+
+template <int NV, int SB>
+__host__ __device__ constexpr int st_elems(int deg_cap) {
+    return ((deg_cap + 3) >> 2) * (ST_TILE * NV + 16 / SB);
+}
+
+template <bool CPLX, int NV>
+__global__ __launch_bounds__(256) void k_sigma_symtile(DevSpace S, const typename VT<CPLX>::T* __restrict__ gT,
+                                                      const typename VT<CPLX>::T* __restrict__ hp,
+                                                      const typename VT<CPLX>::T* __restrict__ c,
+                                                      typename VT<CPLX>::T* __restrict__ sigma, int n_vec,
+                                                      int deg_cap) {
+    using V = VT<CPLX>;
+    using T = typename V::T;
+    constexpr int SB = sizeof(T);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const int ne = st_elems<NV, SB>(deg_cap);
+    const size_t slice = (size_t)2 * ne * SB + (size_t)deg_cap * 16;
+    unsigned char* base = smem + (size_t)wid * slice;
+    T* dsh = reinterpret_cast<T*>(base);                         // padded [slot][NV]
+    T* esh = dsh + ne;                                           // padded [slot][NV]
+    int64_t* tgt = reinterpret_cast<int64_t*>(esh + ne);
+    int32_t* coff = reinterpret_cast<int32_t*>(tgt + deg_cap);   // pair(m) * M^2
+    int32_t* rinf = coff + deg_cap;                              // pair(m) << 1 | negative sign
+    const int M = S.sp.M;
+    const int MM = M * M;
+    const int64_t nd = S.sp.ndets;
+    const int64_t total = S.sp.nwork_dets;
+    const int64_t nw = (int64_t)gridDim.x * wpb;
+    for (int64_t J = (int64_t)blockIdx.x * wpb + wid; J < total; J += nw) {
+        const int w = find_segment(S.work_begin, S.sp.nwork, J);
+        const Cat& C = S.cats[S.work_cat[w]];
+        const int64_t jloc = J - S.work_begin[w];
+        Det dt;
+        decode(S, C, jloc, dt);
+        const int deg = C.deg;
+
+        // ---- phase 1: moves, gathers, one-electron term
+        T one[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) one[v] = V::zero();
+        for (int slot = lane; slot < ((deg + 3) & ~3); slot += 64) {
+            if (slot >= deg) {  // zero the padding slots of the last block
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    dsh[st_idx<NV, SB>(slot, v)] = V::zero();
+                    esh[st_idx<NV, SB>(slot, v)] = V::zero();
+                }
+                continue;
+            }
+            int cls, xs, ys, lx, ly, sg;
+            slot_move(S, C, dt, slot, cls, xs, ys, lx, ly);
+            const int64_t t = apply_move(S, C, cls, xs, ys, lx, ly, dt, sg);
+            const int x = S.sp.sub_off[xs] + lx, y = S.sp.sub_off[ys] + ly;
+            const int pair = y * M + x;
+            tgt[slot] = t;
+            coff[slot] = pair * MM;
+            rinf[slot] = (pair << 1) | (sg < 0 ? 1 : 0);
+            const T hv = hp[y * M + x];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                T val = (v < n_vec) ? c[(int64_t)v * nd + t] : V::zero();
+                if (sg < 0) val = V::scale(val, -1.0);
+                dsh[st_idx<NV, SB>(slot, v)] = val;
+                esh[st_idx<NV, SB>(slot, v)] = V::zero();
+                one[v] = V::mad(hv, val, one[v]);
+            }
+        }
+        if (C.in_space) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const T s = wave_sum<CPLX>(one[v]);
+                if (lane == 0 && v < n_vec) V::atomic_add(&sigma[(int64_t)v * nd + C.offset + jloc], s);
+            }
+        }
+        wave_lds_sync();
+
+        // ---- phase 2: upper-triangle tiles of G_J
+        const int nb = (deg + ST_TILE - 1) / ST_TILE;
+        const int np = nb * (nb + 1) / 2;
+        const int p0 = (int)(((int64_t)lane * np) >> 6);
+        const int p1 = (int)(((int64_t)(lane + 1) * np) >> 6);
+        int b = 0, start = 0;
+        while (b < nb && start + (nb - b) <= p0) {
+            start += nb - b;
+            ++b;
+        }
+        int bp = b + (p0 - start);
+        int cur = -1;
+        int prow[ST_TILE];
+        T drow[ST_TILE][NV], erow[ST_TILE][NV];
+        for (int p = p0; p < p1; ++p) {
+            if (b != cur) {
+                if (cur >= 0) {
+#pragma unroll
+                    for (int r = 0; r < ST_TILE; ++r)
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) V::lds_add(&esh[st_idx<NV, SB>(cur * ST_TILE + r, v)], erow[r][v]);
+                }
+                cur = b;
+#pragma unroll
+                for (int r = 0; r < ST_TILE; ++r) {
+                    const int s = b * ST_TILE + r;
+                    // a padding row has d = 0 and adds zeros; its offset is kept in range
+                    prow[r] = (s < deg) ? (rinf[s] >> 1) : 0;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        drow[r][v] = dsh[st_idx<NV, SB>(s, v)];
+                        erow[r][v] = V::zero();
+                    }
+                }
+            }
+            const bool offdiag = (bp != b);
+#pragma unroll
+            for (int k = 0; k < ST_TILE; ++k) {
+                const int s = bp * ST_TILE + k;
+                if (s >= deg) break;
+                const int co = coff[s];
+                T dcol[NV], ecol[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    dcol[v] = dsh[st_idx<NV, SB>(s, v)];
+                    ecol[v] = V::zero();
+                }
+                T g[ST_TILE];
+#pragma unroll
+                for (int r = 0; r < ST_TILE; ++r) g[r] = gT[co + prow[r]];
+#pragma unroll
+                for (int r = 0; r < ST_TILE; ++r)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        erow[r][v] = V::mad(g[r], dcol[v], erow[r][v]);
+                        ecol[v] = V::cmad(g[r], drow[r][v], ecol[v]);
+                    }
+                if (offdiag) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) V::lds_add(&esh[st_idx<NV, SB>(s, v)], ecol[v]);
+                }
+            }
+            if (++bp == nb) {
+                ++b;
+                bp = b;
+            }
+        }
+        if (cur >= 0) {
+#pragma unroll
+            for (int r = 0; r < ST_TILE; ++r)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) V::lds_add(&esh[st_idx<NV, SB>(cur * ST_TILE + r, v)], erow[r][v]);
+        }
+        wave_lds_sync();
+
+        // ---- phase 3: one atomic update of sigma per move and vector
+        for (int slot = lane; slot < deg; slot += 64) {
+            const double s = (rinf[slot] & 1) ? -0.5 : 0.5;
+            const int64_t t = tgt[slot];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < n_vec) V::atomic_add(&sigma[(int64_t)v * nd + t], V::scale(esh[st_idx<NV, SB>(slot, v)], s));
+        }
+        wave_lds_sync();  // the next determinant reuses this wavefront's LDS slice
+    }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_fill_zero(typename VT<CPLX>::T* __restrict__ x, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        x[e] = VT<CPLX>::zero();
+}
+
+size_t symtile_slice_bytes(int deg_max, int nv, bool cplx) {
+    const int sb = cplx ? 16 : 8;
+    const size_t ne = (size_t)((deg_max + 3) >> 2) * (ST_TILE * nv + 16 / sb);
+    return 2 * ne * sb + (size_t)deg_max * 16;
+}
+
+bool symtile_supported(int deg_max, bool cplx) { return symtile_slice_bytes(deg_max, 2, cplx) <= 64 * 1024; }
+
+template <bool CPLX, int NV>
+static hipError_t launch_sym_nv(const DevSpace& S, int deg_max, const void* gT, const void* hp, const void* c,
+                                void* sigma, int nv, hipStream_t st) {
+    using T = typename VT<CPLX>::T;
+    const size_t per_wave = symtile_slice_bytes(deg_max, NV, CPLX);
+    int wpb = 4;
+    while (wpb > 1 && per_wave * wpb > 48 * 1024) wpb >>= 1;
+    const size_t lds = per_wave * wpb;
+    int64_t blocks = (S.sp.nwork_dets + wpb - 1) / wpb;
+    blocks = std::min<int64_t>(blocks, 256 * 64);
+    hipLaunchKernelGGL((k_sigma_symtile<CPLX, NV>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, S,
+                       (const T*)gT, (const T*)hp, (const T*)c, (T*)sigma, nv, deg_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_sigma_symtile(const DevSpace& S, int deg_max, bool cplx, const void* gT, const void* hp,
+                                const void* c, void* sigma, int n_vec, hipStream_t st) {
+    const int64_t n = S.sp.ndets * n_vec;
+    const int zg = (int)std::min<int64_t>(8192, (n + 255) / 256);
+    if (cplx)
+        hipLaunchKernelGGL(k_fill_zero<true>, dim3(zg), dim3(256), 0, st, (cd*)sigma, n);
+    else
+        hipLaunchKernelGGL(k_fill_zero<false>, dim3(zg), dim3(256), 0, st, (double*)sigma, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t sb = cplx ? 16 : 8;
+    for (int v0 = 0; v0 < n_vec; v0 += 2) {
+        const int nv = (n_vec - v0 >= 2) ? 2 : 1;
+        const int64_t off = (int64_t)v0 * S.sp.ndets;
+        const void* cc = (const char*)c + off * sb;
+        void* ss = (char*)sigma + off * sb;
+        if (cplx)
+            e = (nv == 2) ? launch_sym_nv<true, 2>(S, deg_max, gT, hp, cc, ss, 2, st)
+                          : launch_sym_nv<true, 1>(S, deg_max, gT, hp, cc, ss, 1, st);
+        else
+            e = (nv == 2) ? launch_sym_nv<false, 2>(S, deg_max, gT, hp, cc, ss, 2, st)
+                          : launch_sym_nv<false, 1>(S, deg_max, gT, hp, cc, ss, 1, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace stp

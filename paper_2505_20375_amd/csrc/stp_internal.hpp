@@ -9,7 +9,8 @@ constexpr int KMAX = 8;          // subspaces (distributed active spaces)
 constexpr int MMAX = 64;         // spin-orbitals in total
 constexpr int MSUB = 32;         // spin-orbitals per subspace (local strings are uint32 masks)
 constexpr int NCLS = KMAX * KMAX;
-constexpr int MAXDEG = 1024;    // moves per determinant handled by the per-determinant 2e kernel
+constexpr int MAXDEG = 1024;
+constexpr int DET_BYTES = 96;   // sizeof of the device-side decoded determinant (ranks + masks)    // moves per determinant handled by the per-determinant 2e kernel
 
 // A local string table: all strings of n electrons in an m-orbital subspace,
 // ranked in colexicographic order (= ascending value of the bit mask).
@@ -80,6 +81,22 @@ struct DevSpace {
     const int64_t* space_begin;  // [nspace + 1] vector offsets
 };
 
-inline int packed_rank(int32_t v) { return (v < 0 ? -v : v) - 1; }
+// Schedule of the tiled two-electron kernel: blocks of consecutive
+// determinants of one intermediate category, times groups of annihilated
+// orbitals y' (ygroup[orbital] = group id).
+struct Sigma2eBlock {
+    int32_t cat;
+    int32_t count;
+    int64_t j0;
+};
+
+struct Sigma2eSched {
+    const Sigma2eBlock* blocks;
+    const int32_t* ygroup;
+    int32_t nblocks;
+    int32_t ngroups;
+    int32_t max_tot;   // largest count * deg over the blocks
+    int32_t max_nj;    // largest count
+};
 
 }  // namespace stp

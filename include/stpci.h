@@ -170,9 +170,17 @@ stpci_status stpci_davidson(stpci_ctx* ctx, const stpci_dav_opts* opts, double* 
  * resid[i*k + j].  Either array may be NULL. */
 stpci_status stpci_dav_history(const stpci_ctx* ctx, int* n_iter, int cap, double* energies, double* resid);
 
+/* Sigma products spent by the last Davidson run, counted in vectors: with
+ * precision STPCI_FP32 the run first iterates with FP32 contractions to a
+ * residual of max(tol_residual, 1e-4), then refines from those Ritz vectors
+ * with FP64 contractions to tol_residual (the reported energies and residuals
+ * are always those of the FP64 phase). */
+stpci_status stpci_dav_stats(const stpci_ctx* ctx, int* sigma_fp64, int* sigma_fp32);
+
 /* Kernel timing with HIP events on the context stream.  enable != 0 starts
  * recording every kernel launch of the sigma build; stpci_kernel_time
- * returns, for kernel `name` ("sigma1e", "sigma2e"), the number of recorded
+ * returns, for kernel `name` ("sigma1e", "sigma2e" -- the whole fused pass
+ * when the one-electron term is folded in -- or "sigma_fp32"), the number of recorded
  * launches and their summed duration in milliseconds (synchronises). */
 stpci_status stpci_profile(stpci_ctx* ctx, int enable);
 stpci_status stpci_kernel_time(stpci_ctx* ctx, const char* name, int64_t* launches, double* total_ms);

@@ -61,6 +61,7 @@ _SIGS = {
     "stpci_diagonal": ([_P, _P], _I),
     "stpci_davidson": ([_P, ctypes.POINTER(DavOpts), _DP, _DP, _P, _IP], _I),
     "stpci_dav_history": ([_P, _IP, _I, _DP, _DP], _I),
+    "stpci_dav_stats": ([_P, _IP, _IP], _I),
     "stpci_profile": ([_P, _I], _I),
     "stpci_kernel_time": ([_P, ctypes.c_char_p, _I64P, _DP], _I),
     "stpci_test_heev": ([_I, _P, _P, _P], _I),
@@ -201,6 +202,12 @@ class Context:
         n, b = ctypes.c_int64(), ctypes.c_int64()
         self._check(_lib.stpci_test_moves(self._h, int(max_dets_per_cat), ctypes.byref(n), ctypes.byref(b)))
         return n.value, b.value
+
+    def dav_stats(self):
+        """(FP64 sigma vectors, FP32 sigma vectors) spent by the last Davidson run."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        self._check(_lib.stpci_dav_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def profile(self, enable=True):
         self._check(_lib.stpci_profile(self._h, int(bool(enable))))

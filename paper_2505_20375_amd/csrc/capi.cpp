@@ -20,7 +20,7 @@ stpci_ctx::~stpci_ctx() {
             (void)hipEventDestroy(e.a);
             (void)hipEventDestroy(e.b);
         }
-        for (DevBuf* b : {&d_s2blocks, &d_ygroup, &d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
+        for (DevBuf* b : {&d_gT32, &d_hp32, &d_s2blocks, &d_ygroup, &d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
                           &d_hp, &d_gT, &d_hd, &d_JK, &d_V, &d_W, &d_X, &d_R, &d_T, &d_partial, &d_small, &d_topv,
                           &d_topi})
             b->free_();
@@ -165,15 +165,35 @@ static void record(stpci_ctx* c, int kind, bool start) {
     }
 }
 
+static stpci_status ensure32(stpci_ctx* c) {
+    if (c->have32) return STPCI_OK;
+    stpci_status s;
+    if ((s = upload(c, c->d_gT32, c->gT32, "FP32 two-electron integrals"))) return s;
+    if ((s = upload(c, c->d_hp32, c->hp32, "FP32 h'"))) return s;
+    c->have32 = true;
+    return STPCI_OK;
+}
+
 stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, stpci_precision prec) {
-    if (prec != STPCI_FP64) return set_err(c, STPCI_EINVAL, "unsupported sigma precision");
+    if (prec != STPCI_FP64 && prec != STPCI_FP32) return set_err(c, STPCI_EINVAL, "unsupported sigma precision");
+    if (prec == STPCI_FP32) {
+        // category-block contraction in FP32 (FP32 accumulation); sigma accumulated in FP64
+        if (c->s2_kernel != 3) return set_err(c, STPCI_EINVAL, "FP32 contraction needs the tile kernel");
+        stpci_status s = ensure32(c);
+        if (s) return s;
+        record(c, 2, true);
+        hipError_t e = launch_sigma_symtile(c->dev, c->hs.max_deg, c->cplx, true, c->d_gT32.p, c->d_hp32.p, cin,
+                                            sout, n_vec, c->stream);
+        record(c, 2, false);
+        return e == hipSuccess ? STPCI_OK : hip_check(c, e, "FP32 sigma launch");
+    }
     if (c->hs.max_deg > MAXDEG) return set_err(c, STPCI_EINVAL, "a determinant has more moves than MAXDEG");
     hipError_t e;
     if (c->s2_kernel >= 2) {
         // one pass: zero sigma, then the fused one- and two-electron kernel
         record(c, 1, true);
         if (c->s2_kernel == 3)
-            e = launch_sigma_symtile(c->dev, c->hs.max_deg, c->cplx, c->d_gT.p, c->d_hp.p, cin, sout, n_vec,
+            e = launch_sigma_symtile(c->dev, c->hs.max_deg, c->cplx, false, c->d_gT.p, c->d_hp.p, cin, sout, n_vec,
                                      c->stream);
         else
             e = launch_sigma_wave(c->dev, c->hs.max_deg, c->cplx, c->d_gT.p, c->d_hp.p, cin, sout, n_vec, c->stream);
@@ -339,6 +359,9 @@ stpci_status stpci_set_integrals(stpci_ctx* c, int n_orb, stpci_scalar scalar, i
             c->JK[(size_t)i * M + j] = J - Kx;
         }
     }
+    c->gT32.assign(c->gT.begin(), c->gT.end());
+    c->hp32.assign(c->hprime.begin(), c->hprime.end());
+    c->have32 = false;
     c->have_ints = true;
     c->prepared = false;
     return STPCI_OK;
@@ -467,6 +490,7 @@ stpci_status stpci_kernel_time(stpci_ctx* c, const char* name, int64_t* launches
     int kind = -1;
     if (!std::strcmp(name, "sigma1e")) kind = 0;
     if (!std::strcmp(name, "sigma2e")) kind = 1;
+    if (!std::strcmp(name, "sigma_fp32")) kind = 2;
     if (kind < 0) return set_err(c, STPCI_EINVAL, "unknown kernel name");
     if (c->host_only) return set_err(c, STPCI_ESTATE, "host-only context");
     stpci_status s = hip_check(c, hipStreamSynchronize(c->stream), "stream sync");

@@ -27,6 +27,7 @@ struct KernelEvent {
 
 struct DavRecord {
     std::vector<double> e, r;
+    int precision = 0;
 };
 
 }  // namespace stp
@@ -46,6 +47,7 @@ struct stpci_ctx {
     std::vector<double> hprime;    // h' = h - 1/2 sum_r (pr|rq)
     std::vector<double> gT;        // gT[(y*M + x)*M*M + (y'*M + x')] = (x' y' | y x)
     std::vector<double> hd, JK;    // Re h_ii ; (ii|jj) - (ij|ji)
+    std::vector<float> gT32, hp32; // FP32 copies for the FP32 contraction
 
     // space
     bool have_space = false;
@@ -55,6 +57,8 @@ struct stpci_ctx {
     bool prepared = false;
     stp::DevBuf d_cats, d_tabs, d_bits, d_ann, d_cre, d_work_cat, d_work_begin, d_space_begin;
     stp::DevBuf d_hp, d_gT, d_hd, d_JK;
+    stp::DevBuf d_gT32, d_hp32;
+    bool have32 = false;
     stp::DevSpace dev{};
 
     // schedule of the tiled two-electron kernel
@@ -66,6 +70,7 @@ struct stpci_ctx {
     stp::DevBuf d_V, d_W, d_X, d_R, d_T, d_partial, d_small, d_topv, d_topi;
     std::vector<stp::DavRecord> history;
     int hist_k = 0;
+    int nsigma[2] = {0, 0};   // sigma builds of the last Davidson run: FP64, FP32 (vectors)
 
     // profiling
     bool profile = false;

@@ -85,8 +85,8 @@ void jacobi_heev(int n, std::vector<cplx> A, std::vector<double>& w, std::vector
 namespace {
 
 // layout of the small device workspace
-constexpr size_t kYOff = 0;                 // Ritz coefficients, up to 64 x 16 complex
-constexpr size_t kThetaOff = 64 * 16 * 16;  // Ritz values, 64 doubles
+constexpr size_t kYOff = 0;                 // Ritz coefficients, up to 64 x 32 complex
+constexpr size_t kThetaOff = 64 * 32 * 16;  // Ritz values, 64 doubles
 constexpr size_t kDotsOff = kThetaOff + 64 * 8;
 constexpr size_t kCoefOff = kDotsOff + 64 * 16;
 constexpr size_t kSmallBytes = kCoefOff + 64 * 16;
@@ -159,37 +159,46 @@ extern "C" stpci_status stpci_test_heev(int n, const double* A, double* w, doubl
     return STPCI_OK;
 }
 
-extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, double* energies, double* resid,
-                                       void* vecs_dev, int* n_iter) {
-    if (!c || !o || !energies || !resid) return STPCI_EINVAL;
-    stpci_status s = prepare(c);
-    if (s) return s;
-    if ((s = hip_check(c, hipSetDevice(c->device), "hipSetDevice"))) return s;
+// One Davidson run with sigma products of precision `prec`; starting vectors
+// from guess_dev ([k][n_dets]) or unit vectors at the lowest diagonal entries.
+// Appends its iterations to the context history.  On return energies/resid
+// hold the last Ritz values and residual norms and d_X the Ritz vectors.
+static stpci_status dav_core(stpci_ctx* c, const stpci_dav_opts* o, stpci_precision prec, const void* guess_dev,
+                             double tol, double* energies, double* resid, int* n_iter, bool* conv) {
+    stpci_status s;
     const int64_t N = c->hs.sp.ndets;
-    int k = o->k;
-    if (k < 1 || k > 16 || k > N) return set_err(c, STPCI_EINVAL, "k must be in [1, min(16, n_dets)]");
-    if (o->precision != STPCI_FP64) return set_err(c, STPCI_EINVAL, "precision not supported by this solver");
-    int mmax = o->max_subspace > 0 ? o->max_subspace : std::max(8 * k, 16);
+    const int k = o->k;
+    const int pidx = (prec == STPCI_FP32) ? 1 : 0;
+    const size_t vb = (size_t)N * scalar_bytes(c);
+    const int kr_max = std::min(2 * k, 32);   // Ritz vectors kept by a restart
+    int mmax = o->max_subspace > 0 ? o->max_subspace : std::max(8 * k, 32);
+    {
+        // expansion space bounded by the device memory left for V and W
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && vb > 0) {
+            const size_t have = c->d_V.bytes + c->d_W.bytes + c->d_X.bytes + c->d_R.bytes + c->d_T.bytes;
+            const double budget = 0.85 * (double)(fr + have) / (double)vb - 2.0 * kr_max - k;
+            if (budget / 2.0 < mmax) mmax = (int)std::max(budget / 2.0, (double)(2 * k));
+        }
+    }
     mmax = (int)std::min<int64_t>(std::min(mmax, 64), N);
     if (mmax < 2 * k && N >= 2 * k) mmax = 2 * k;
     mmax = std::max(mmax, k);
     const int max_iter = o->max_iter > 0 ? o->max_iter : 100;
-    const double tol = o->tol_residual > 0 ? o->tol_residual : 1e-8;
 
     Dav d{c, N, scalar_bytes(c), c->cplx, c->stream};
-    const size_t vb = (size_t)N * d.sb;
     if ((s = ensure(c, c->d_V, vb * mmax, "Davidson V"))) return s;
     if ((s = ensure(c, c->d_W, vb * mmax, "Davidson W"))) return s;
-    if ((s = ensure(c, c->d_X, vb * k, "Ritz vectors"))) return s;
-    if ((s = ensure(c, c->d_R, vb * k, "residuals"))) return s;
+    if ((s = ensure(c, c->d_X, vb * kr_max, "Ritz vectors"))) return s;
+    if ((s = ensure(c, c->d_R, vb * kr_max, "residuals"))) return s;
     if ((s = ensure(c, c->d_T, vb * k, "corrections"))) return s;
     if ((s = ensure(c, c->d_partial, (size_t)dots_blocks(N) * 64 * 16, "dot partials"))) return s;
     if ((s = ensure(c, c->d_small, kSmallBytes, "small workspace"))) return s;
     const size_t theta_off = kThetaOff;
 
     // initial guess
-    if (o->guess_dev) {
-        if ((s = d.hip(hipMemcpyAsync(c->d_V.p, o->guess_dev, vb * k, hipMemcpyDeviceToDevice, c->stream), "guess")))
+    if (guess_dev) {
+        if ((s = d.hip(hipMemcpyAsync(c->d_V.p, guess_dev, vb * k, hipMemcpyDeviceToDevice, c->stream), "guess")))
             return s;
         // orthonormalise the guess (CGS2)
         for (int i = 0; i < k; ++i) {
@@ -224,7 +233,8 @@ extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, do
         for (int i = 0; i < k; ++i)
             if ((s = d.hip(launch_unit(d.cx, d.vec(c->d_V, i), N, ti[ord[i]], c->stream), "unit"))) return s;
     }
-    if ((s = sigma_impl(c, c->d_V.p, c->d_W.p, k, STPCI_FP64))) return s;
+    if ((s = sigma_impl(c, c->d_V.p, c->d_W.p, k, prec))) return s;
+    c->nsigma[pidx] += k;
 
     std::vector<cplx> G((size_t)64 * 64, cplx(0, 0));
     auto Gat = [&](int i, int j) -> cplx& { return G[(size_t)i * 64 + j]; };
@@ -234,8 +244,6 @@ extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, do
         if ((s = d.dots(c->d_V.p, m, d.vec(c->d_W, j), col))) return s;
         for (int i = 0; i < m; ++i) Gat(i, j) = col[i];
     }
-    c->history.clear();
-    c->hist_k = k;
     std::vector<double> theta(k, 0.0), rn(k, 0.0);
     int it = 0;
     bool converged = false;
@@ -262,7 +270,7 @@ extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, do
             return s;
         for (int j = 0; j < k; ++j)
             if ((s = d.norm(d.vec(c->d_R, j), rn[j]))) return s;
-        c->history.push_back(DavRecord{theta, rn});
+        c->history.push_back(DavRecord{theta, rn, pidx});
         converged = true;
         for (int j = 0; j < k; ++j) converged = converged && rn[j] <= tol;
         if (converged) break;
@@ -278,20 +286,29 @@ extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, do
                 return s;
             ++nt;
         }
-        // thick restart from the Ritz vectors when the space would overflow
+        // thick restart when the space would overflow: keep the kr lowest Ritz
+        // vectors (V <- V Y_kr, W <- W Y_kr, G <- diag(theta_kr))
         if (m + nt > mmax) {
-            // W Y -> R (residuals are no longer needed), then V <- X, W <- W Y
-            if ((s = d.hip(launch_combine(d.cx, c->d_W.p, nullptr, N, m, c->d_small.p, k, nullptr, c->d_R.p,
+            const int kr = std::max(k, std::min(kr_max, mmax - nt));
+            std::vector<cplx> Yr((size_t)m * kr);
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j < kr; ++j) Yr[(size_t)i * kr + j] = Y[(size_t)i * m + j];
+            if ((s = d.put_small(Yr, kYOff))) return s;
+            if ((s = d.hip(launch_combine(d.cx, c->d_V.p, nullptr, N, m, c->d_small.p, kr, nullptr, c->d_X.p, nullptr,
+                                          N, 0, c->stream),
+                           "restart VY")))
+                return s;
+            if ((s = d.hip(launch_combine(d.cx, c->d_W.p, nullptr, N, m, c->d_small.p, kr, nullptr, c->d_R.p,
                                           nullptr, N, 0, c->stream),
                            "restart WY")))
                 return s;
-            if ((s = d.hip(hipMemcpyAsync(c->d_V.p, c->d_X.p, vb * k, hipMemcpyDeviceToDevice, c->stream), "restart V")))
+            if ((s = d.hip(hipMemcpyAsync(c->d_V.p, c->d_X.p, vb * kr, hipMemcpyDeviceToDevice, c->stream), "restart V")))
                 return s;
-            if ((s = d.hip(hipMemcpyAsync(c->d_W.p, c->d_R.p, vb * k, hipMemcpyDeviceToDevice, c->stream), "restart W")))
+            if ((s = d.hip(hipMemcpyAsync(c->d_W.p, c->d_R.p, vb * kr, hipMemcpyDeviceToDevice, c->stream), "restart W")))
                 return s;
             std::fill(G.begin(), G.end(), cplx(0, 0));
-            for (int j = 0; j < k; ++j) Gat(j, j) = theta[j];
-            m = k;
+            for (int j = 0; j < kr; ++j) Gat(j, j) = w[j];
+            m = kr;
         }
         int added = 0;
         for (int t = 0; t < nt; ++t) {
@@ -315,7 +332,8 @@ extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, do
             ++added;
         }
         if (added == 0) break;  // no new direction: stagnation
-        if ((s = sigma_impl(c, d.vec(c->d_V, m), d.vec(c->d_W, m), added, STPCI_FP64))) return s;
+        if ((s = sigma_impl(c, d.vec(c->d_V, m), d.vec(c->d_W, m), added, prec))) return s;
+        c->nsigma[pidx] += added;
         for (int j = m; j < m + added; ++j) {
             std::vector<cplx> col;
             if ((s = d.dots(c->d_V.p, m + added, d.vec(c->d_W, j), col))) return s;
@@ -330,13 +348,56 @@ extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, do
         energies[j] = theta[j];
         resid[j] = rn[j];
     }
-    if (vecs_dev) {
-        if ((s = d.hip(hipMemcpyAsync(vecs_dev, c->d_X.p, vb * k, hipMemcpyDeviceToDevice, c->stream), "vecs out")))
-            return s;
-    }
     if ((s = d.hip(hipStreamSynchronize(c->stream), "sync"))) return s;
-    if (n_iter) *n_iter = std::min(it, max_iter);
-    return converged ? STPCI_OK : set_err(c, STPCI_ENOCONV, "Davidson did not converge");
+    *n_iter = std::min(it, max_iter);
+    *conv = converged;
+    return STPCI_OK;
+}
+
+extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, double* energies, double* resid,
+                                       void* vecs_dev, int* n_iter) {
+    if (!c || !o || !energies || !resid) return STPCI_EINVAL;
+    stpci_status s = prepare(c);
+    if (s) return s;
+    if ((s = hip_check(c, hipSetDevice(c->device), "hipSetDevice"))) return s;
+    const int64_t N = c->hs.sp.ndets;
+    const int k = o->k;
+    if (k < 1 || k > 16 || k > N) return set_err(c, STPCI_EINVAL, "k must be in [1, min(16, n_dets)]");
+    if (o->precision != STPCI_FP64 && o->precision != STPCI_FP32)
+        return set_err(c, STPCI_EINVAL, "unknown precision");
+    const double tol = o->tol_residual > 0 ? o->tol_residual : 1e-8;
+    c->history.clear();
+    c->hist_k = k;
+    c->nsigma[0] = c->nsigma[1] = 0;
+    int it_total = 0, it = 0;
+    bool conv = false;
+    const void* guess = o->guess_dev;
+    if (o->precision == STPCI_FP32) {
+        // phase A: FP32 contraction until the residual reaches a tolerance the
+        // FP32 products can resolve; phase B refines from those Ritz vectors
+        // with FP64 products to the requested tolerance.
+        const double tol_a = std::max(tol, 1e-4);
+        if ((s = dav_core(c, o, STPCI_FP32, guess, tol_a, energies, resid, &it, &conv))) return s;
+        it_total += it;
+        guess = c->d_X.p;
+    }
+    if ((s = dav_core(c, o, STPCI_FP64, guess, tol, energies, resid, &it, &conv))) return s;
+    it_total += it;
+    if (vecs_dev) {
+        const size_t vb = (size_t)N * scalar_bytes(c) * k;
+        if ((s = hip_check(c, hipMemcpyAsync(vecs_dev, c->d_X.p, vb, hipMemcpyDeviceToDevice, c->stream), "vecs out")))
+            return s;
+        if ((s = hip_check(c, hipStreamSynchronize(c->stream), "sync"))) return s;
+    }
+    if (n_iter) *n_iter = it_total;
+    return conv ? STPCI_OK : set_err(c, STPCI_ENOCONV, "Davidson did not converge");
+}
+
+extern "C" stpci_status stpci_dav_stats(const stpci_ctx* c, int* sigma_fp64, int* sigma_fp32) {
+    if (!c) return STPCI_EINVAL;
+    if (sigma_fp64) *sigma_fp64 = c->nsigma[0];
+    if (sigma_fp32) *sigma_fp32 = c->nsigma[1];
+    return STPCI_OK;
 }
 
 extern "C" stpci_status stpci_dav_history(const stpci_ctx* c, int* n_iter, int cap, double* energies,

@@ -18,7 +18,8 @@ hipError_t launch_sigma2e_tiled(const DevSpace& S, const Sigma2eSched& P, bool c
 bool sigma_wave_supported(int deg_max);
 bool symtile_supported(int deg_max, bool cplx);
 // sigma = H c in one pass, Hermitian 4x4 tiles per intermediate determinant
-hipError_t launch_sigma_symtile(const DevSpace& S, int deg_max, bool cplx, const void* gT, const void* hp,
+// f32: integrals gT/hp are FP32 (complex FP32 when cplx); c and sigma stay FP64.
+hipError_t launch_sigma_symtile(const DevSpace& S, int deg_max, bool cplx, bool f32, const void* gT, const void* hp,
                                 const void* c, void* sigma, int n_vec, hipStream_t st);
 // sigma = H c (one- and two-electron parts) in one pass over the intermediate determinants
 hipError_t launch_sigma_wave(const DevSpace& S, int deg_max, bool cplx, const void* gT, const void* hp,

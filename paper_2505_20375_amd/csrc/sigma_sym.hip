@@ -46,13 +46,14 @@ __host__ __device__ constexpr int st_elems(int deg_cap) {
     return ((deg_cap + 3) >> 2) * (ST_TILE * NV + 16 / SB);
 }
 
-template <bool CPLX, int NV>
-__global__ __launch_bounds__(256) void k_sigma_symtile(DevSpace S, const typename VT<CPLX>::T* __restrict__ gT,
-                                                      const typename VT<CPLX>::T* __restrict__ hp,
+template <bool CPLX, bool F32, int NV>
+__global__ __launch_bounds__(256) void k_sigma_symtile(DevSpace S, const typename PT<CPLX, F32>::T* __restrict__ gT,
+                                                      const typename PT<CPLX, F32>::T* __restrict__ hp,
                                                       const typename VT<CPLX>::T* __restrict__ c,
                                                       typename VT<CPLX>::T* __restrict__ sigma, int n_vec,
                                                       int deg_cap) {
-    using V = VT<CPLX>;
+    using V = PT<CPLX, F32>;     // contraction arithmetic
+    using V64 = VT<CPLX>;        // vector storage and sigma accumulation
     using T = typename V::T;
     constexpr int SB = sizeof(T);
     extern __shared__ __align__(16) unsigned char smem[];
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(256) void k_sigma_symtile(DevSpace S, const typenam
             const T hv = hp[y * M + x];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                T val = (v < n_vec) ? c[(int64_t)v * nd + t] : V::zero();
+                T val = (v < n_vec) ? V::from64(c[(int64_t)v * nd + t]) : V::zero();
                 if (sg < 0) val = V::scale(val, -1.0);
                 dsh[st_idx<NV, SB>(slot, v)] = val;
                 esh[st_idx<NV, SB>(slot, v)] = V::zero();
@@ -114,8 +115,8 @@ __global__ __launch_bounds__(256) void k_sigma_symtile(DevSpace S, const typenam
         if (C.in_space) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const T s = wave_sum<CPLX>(one[v]);
-                if (lane == 0 && v < n_vec) V::atomic_add(&sigma[(int64_t)v * nd + C.offset + jloc], s);
+                const typename V64::T s = wave_sum<CPLX>(V::to64(one[v]));
+                if (lane == 0 && v < n_vec) V64::atomic_add(&sigma[(int64_t)v * nd + C.offset + jloc], s);
             }
         }
         wave_lds_sync();
@@ -201,7 +202,8 @@ __global__ __launch_bounds__(256) void k_sigma_symtile(DevSpace S, const typenam
             const int64_t t = tgt[slot];
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                if (v < n_vec) V::atomic_add(&sigma[(int64_t)v * nd + t], V::scale(esh[st_idx<NV, SB>(slot, v)], s));
+                if (v < n_vec)
+                    V64::atomic_add(&sigma[(int64_t)v * nd + t], V64::scale(V::to64(esh[st_idx<NV, SB>(slot, v)]), s));
         }
         wave_lds_sync();  // the next determinant reuses this wavefront's LDS slice
     }
@@ -213,54 +215,57 @@ __global__ __launch_bounds__(256) void k_fill_zero(typename VT<CPLX>::T* __restr
         x[e] = VT<CPLX>::zero();
 }
 
-size_t symtile_slice_bytes(int deg_max, int nv, bool cplx) {
-    const int sb = cplx ? 16 : 8;
+size_t symtile_slice_bytes(int deg_max, int nv, int sb) {
     const size_t ne = (size_t)((deg_max + 3) >> 2) * (ST_TILE * nv + 16 / sb);
     return 2 * ne * sb + (size_t)deg_max * 16;
 }
 
-bool symtile_supported(int deg_max, bool cplx) { return symtile_slice_bytes(deg_max, 2, cplx) <= 64 * 1024; }
+bool symtile_supported(int deg_max, bool cplx) { return symtile_slice_bytes(deg_max, 2, cplx ? 16 : 8) <= 64 * 1024; }
 
-template <bool CPLX, int NV>
+template <bool CPLX, bool F32, int NV>
 static hipError_t launch_sym_nv(const DevSpace& S, int deg_max, const void* gT, const void* hp, const void* c,
                                 void* sigma, int nv, hipStream_t st) {
-    using T = typename VT<CPLX>::T;
-    const size_t per_wave = symtile_slice_bytes(deg_max, NV, CPLX);
+    using T = typename PT<CPLX, F32>::T;
+    using T64 = typename VT<CPLX>::T;
+    const size_t per_wave = symtile_slice_bytes(deg_max, NV, (int)sizeof(T));
     int wpb = 4;
     while (wpb > 1 && per_wave * wpb > 48 * 1024) wpb >>= 1;
     const size_t lds = per_wave * wpb;
     int64_t blocks = (S.sp.nwork_dets + wpb - 1) / wpb;
     blocks = std::min<int64_t>(blocks, 256 * 64);
-    hipLaunchKernelGGL((k_sigma_symtile<CPLX, NV>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, S,
-                       (const T*)gT, (const T*)hp, (const T*)c, (T*)sigma, nv, deg_max);
+    hipLaunchKernelGGL((k_sigma_symtile<CPLX, F32, NV>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, S,
+                       (const T*)gT, (const T*)hp, (const T64*)c, (T64*)sigma, nv, deg_max);
     return hipGetLastError();
 }
 
-hipError_t launch_sigma_symtile(const DevSpace& S, int deg_max, bool cplx, const void* gT, const void* hp,
-                                const void* c, void* sigma, int n_vec, hipStream_t st) {
+template <bool CPLX, bool F32>
+static hipError_t launch_sym_all(const DevSpace& S, int deg_max, const void* gT, const void* hp, const void* c,
+                                 void* sigma, int n_vec, hipStream_t st) {
+    using T64 = typename VT<CPLX>::T;
     const int64_t n = S.sp.ndets * n_vec;
     const int zg = (int)std::min<int64_t>(8192, (n + 255) / 256);
-    if (cplx)
-        hipLaunchKernelGGL(k_fill_zero<true>, dim3(zg), dim3(256), 0, st, (cd*)sigma, n);
-    else
-        hipLaunchKernelGGL(k_fill_zero<false>, dim3(zg), dim3(256), 0, st, (double*)sigma, n);
+    hipLaunchKernelGGL(k_fill_zero<CPLX>, dim3(zg), dim3(256), 0, st, (T64*)sigma, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t sb = cplx ? 16 : 8;
     for (int v0 = 0; v0 < n_vec; v0 += 2) {
         const int nv = (n_vec - v0 >= 2) ? 2 : 1;
         const int64_t off = (int64_t)v0 * S.sp.ndets;
-        const void* cc = (const char*)c + off * sb;
-        void* ss = (char*)sigma + off * sb;
-        if (cplx)
-            e = (nv == 2) ? launch_sym_nv<true, 2>(S, deg_max, gT, hp, cc, ss, 2, st)
-                          : launch_sym_nv<true, 1>(S, deg_max, gT, hp, cc, ss, 1, st);
-        else
-            e = (nv == 2) ? launch_sym_nv<false, 2>(S, deg_max, gT, hp, cc, ss, 2, st)
-                          : launch_sym_nv<false, 1>(S, deg_max, gT, hp, cc, ss, 1, st);
+        const T64* cc = (const T64*)c + off;
+        T64* ss = (T64*)sigma + off;
+        e = (nv == 2) ? launch_sym_nv<CPLX, F32, 2>(S, deg_max, gT, hp, cc, ss, 2, st)
+                      : launch_sym_nv<CPLX, F32, 1>(S, deg_max, gT, hp, cc, ss, 1, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_sigma_symtile(const DevSpace& S, int deg_max, bool cplx, bool f32, const void* gT, const void* hp,
+                                const void* c, void* sigma, int n_vec, hipStream_t st) {
+    if (cplx)
+        return f32 ? launch_sym_all<true, true>(S, deg_max, gT, hp, c, sigma, n_vec, st)
+                   : launch_sym_all<true, false>(S, deg_max, gT, hp, c, sigma, n_vec, st);
+    return f32 ? launch_sym_all<false, true>(S, deg_max, gT, hp, c, sigma, n_vec, st)
+               : launch_sym_all<false, false>(S, deg_max, gT, hp, c, sigma, n_vec, st);
 }
 
 }  // namespace stp

@@ -68,6 +68,61 @@ struct VT<true> {
     static __device__ __forceinline__ double abs2(T a) { return a.x * a.x + a.y * a.y; }
 };
 
+struct alignas(8) cf {
+    float x, y;
+};
+
+// Compute-precision traits of the sigma contraction: T is the arithmetic type
+// of the integrals, gathered coefficients and partial sums; T64 the storage
+// type of the CI vectors (always FP64).
+template <bool CPLX, bool F32>
+struct PT;
+template <bool CPLX>
+struct PT<CPLX, false> : VT<CPLX> {
+    using T64 = typename VT<CPLX>::T;
+    static __device__ __forceinline__ typename VT<CPLX>::T from64(T64 a) { return a; }
+    static __device__ __forceinline__ T64 to64(typename VT<CPLX>::T a) { return a; }
+};
+template <>
+struct PT<false, true> {
+    using T = float;
+    using T64 = double;
+    static __device__ __forceinline__ T zero() { return 0.0f; }
+    static __device__ __forceinline__ T mad(T a, T b, T c) { return fmaf(a, b, c); }
+    static __device__ __forceinline__ T cmad(T a, T b, T c) { return fmaf(a, b, c); }
+    static __device__ __forceinline__ T scale(T a, double s) { return a * (float)s; }
+    static __device__ __forceinline__ void lds_add(T* p, T v) { atomicAdd(p, v); }
+    static __device__ __forceinline__ T from64(T64 a) { return (float)a; }
+    static __device__ __forceinline__ T64 to64(T a) { return (double)a; }
+};
+template <>
+struct PT<true, true> {
+    using T = cf;
+    using T64 = cd;
+    static __device__ __forceinline__ T zero() { return cf{0.0f, 0.0f}; }
+    static __device__ __forceinline__ T mad(T a, T b, T c) {
+        c.x = fmaf(a.x, b.x, c.x);
+        c.x = fmaf(-a.y, b.y, c.x);
+        c.y = fmaf(a.x, b.y, c.y);
+        c.y = fmaf(a.y, b.x, c.y);
+        return c;
+    }
+    static __device__ __forceinline__ T cmad(T a, T b, T c) {
+        c.x = fmaf(a.x, b.x, c.x);
+        c.x = fmaf(a.y, b.y, c.x);
+        c.y = fmaf(a.x, b.y, c.y);
+        c.y = fmaf(-a.y, b.x, c.y);
+        return c;
+    }
+    static __device__ __forceinline__ T scale(T a, double s) { return cf{a.x * (float)s, a.y * (float)s}; }
+    static __device__ __forceinline__ void lds_add(T* p, T v) {
+        atomicAdd(&p->x, v.x);
+        atomicAdd(&p->y, v.y);
+    }
+    static __device__ __forceinline__ T from64(T64 a) { return cf{(float)a.x, (float)a.y}; }
+    static __device__ __forceinline__ T64 to64(T a) { return cd{(double)a.x, (double)a.y}; }
+};
+
 // ---------------------------------------------------------------------------
 // string / move machinery
 // ---------------------------------------------------------------------------

@@ -40,6 +40,14 @@ class DavOpts(ctypes.Structure):
                 ("refine_tol_energy", ctypes.c_double), ("guess_dev", ctypes.c_void_p)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("n_orb", ctypes.c_int), ("scalar", ctypes.c_int), ("spin_free", ctypes.c_int),
+                ("h", ctypes.c_void_p), ("g", ctypes.c_void_p), ("e_core", ctypes.c_double),
+                ("n_elec", ctypes.c_int), ("n_sub", ctypes.c_int), ("sub_size", ctypes.POINTER(ctypes.c_int)),
+                ("win_lo", ctypes.POINTER(ctypes.c_int)), ("win_hi", ctypes.POINTER(ctypes.c_int)),
+                ("opts", ctypes.POINTER(DavOpts))]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _I64 = ctypes.c_int64
@@ -66,6 +74,15 @@ _SIGS = {
     "stpci_kernel_time": ([_P, ctypes.c_char_p, _I64P, _DP], _I),
     "stpci_test_heev": ([_I, _P, _P, _P], _I),
     "stpci_test_moves": ([_P, _I64, _I64P, _I64P], _I),
+    "stpci_server_create": ([ctypes.POINTER(_P), _I, _P, _I64, _I], _I),
+    "stpci_server_destroy": ([_P], None),
+    "stpci_server_last_error": ([_P], ctypes.c_char_p),
+    "stpci_server_submit": ([_P, ctypes.POINTER(Request), _IP], _I),
+    "stpci_server_cancel": ([_P, _I], _I),
+    "stpci_server_tick": ([_P, _IP, _IP], _I),
+    "stpci_server_result": ([_P, _I, _IP, _DP, _DP, _IP, _DP, _DP, _DP], _I),
+    "stpci_server_request_info": ([_P, _I, _I64P, _DP, _I64P, _IP], _I),
+    "stpci_server_stats": ([_P, _I64P, _I64P, _IP, _I64P, _I64P], _I),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -216,6 +233,101 @@ class Context:
         n, t = ctypes.c_int64(), ctypes.c_double()
         self._check(_lib.stpci_kernel_time(self._h, name.encode(), ctypes.byref(n), ctypes.byref(t)))
         return n.value, t.value
+
+
+QUEUED, ACTIVE, DONE, FAILED, CANCELLED = 0, 1, 2, 3, 4
+
+
+@dataclass
+class RequestResult:
+    state: int
+    energies: np.ndarray
+    resid: np.ndarray
+    n_iter: int
+    t_submit: float
+    t_admit: float
+    t_done: float
+    status: int
+
+
+class Server:
+    """Continuous-batching CI solve server on one device (see stpci_serve.h)."""
+
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 64 << 30, max_active: int = 32, stream=None):
+        h = _P()
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        st = _lib.stpci_server_create(ctypes.byref(h), int(device), _P(stream) if stream else None,
+                                      int(mem_budget_bytes), int(max_active))
+        if st != OK:
+            raise StpciError(st, "stpci_server_create failed (device %d)" % device)
+        self._h = h
+        self._k = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.stpci_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, st):
+        if st != OK:
+            raise StpciError(st, _lib.stpci_server_last_error(self._h).decode())
+        return st
+
+    def submit(self, h, g, n_elec, sub, lo=None, hi=None, k=1, tol=1e-8, max_iter=100, max_subspace=0,
+               precision=FP64, spin_free=False, e_core=0.0) -> int:
+        cplx = np.iscomplexobj(h) or np.iscomplexobj(g)
+        dt = np.complex128 if cplx else np.float64
+        h = np.ascontiguousarray(h, dtype=dt)
+        g = np.ascontiguousarray(g, dtype=dt)
+        lo = list(lo) if lo is not None else [0] * len(sub)
+        hi = list(hi) if hi is not None else list(sub)
+        o = DavOpts(int(k), int(max_iter), int(max_subspace), float(tol), 0.0, int(precision), 1e-8, None)
+        r = Request(h.shape[0], COMPLEX128 if cplx else REAL64, int(bool(spin_free)), h.ctypes.data_as(_P),
+                    g.ctypes.data_as(_P), float(e_core), int(n_elec), len(sub), _iarr(sub), _iarr(lo), _iarr(hi),
+                    ctypes.pointer(o))
+        rid = ctypes.c_int()
+        self._check(_lib.stpci_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
+        self._k[rid.value] = int(k)
+        return rid.value
+
+    def cancel(self, rid):
+        self._check(_lib.stpci_server_cancel(self._h, int(rid)))
+
+    def tick(self):
+        """One scheduling step; returns (requests still pending, requests retired now)."""
+        a, f = ctypes.c_int(), ctypes.c_int()
+        self._check(_lib.stpci_server_tick(self._h, ctypes.byref(a), ctypes.byref(f)))
+        return a.value, f.value
+
+    def result(self, rid) -> RequestResult:
+        k = self._k[rid]
+        e = (ctypes.c_double * k)()
+        r = (ctypes.c_double * k)()
+        state, it = ctypes.c_int(), ctypes.c_int()
+        ts, ta, td = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        st = _lib.stpci_server_result(self._h, int(rid), ctypes.byref(state), e, r, ctypes.byref(it),
+                                      ctypes.byref(ts), ctypes.byref(ta), ctypes.byref(td))
+        return RequestResult(state.value, np.array(e[:]), np.array(r[:]), it.value, ts.value, ta.value, td.value, st)
+
+    def request_info(self, rid):
+        """(n_dets, nnz(H), footprint bytes, sigma vectors used)."""
+        n, nz, fp, sv = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64(), ctypes.c_int()
+        self._check(_lib.stpci_server_request_info(self._h, int(rid), ctypes.byref(n), ctypes.byref(nz),
+                                                   ctypes.byref(fp), ctypes.byref(sv)))
+        return n.value, nz.value, fp.value, sv.value
+
+    def stats(self):
+        """dict(used, peak, peak_active, ticks, grouped_launches)."""
+        u, p, t, gl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        pa = ctypes.c_int()
+        self._check(_lib.stpci_server_stats(self._h, ctypes.byref(u), ctypes.byref(p), ctypes.byref(pa),
+                                            ctypes.byref(t), ctypes.byref(gl)))
+        return dict(used=u.value, peak=p.value, peak_active=pa.value, ticks=t.value, grouped_launches=gl.value)
 
 
 def heev(A):

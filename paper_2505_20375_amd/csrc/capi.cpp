@@ -102,6 +102,8 @@ stpci_status prepare(stpci_ctx* c) {
         if (kv && !strcmp(kv, "wave")) c->s2_kernel = 2;
         if (c->s2_kernel == 3 && !symtile_supported(H.max_deg, c->cplx)) c->s2_kernel = 1;
         if (c->s2_kernel == 2 && !sigma_wave_supported(H.max_deg)) c->s2_kernel = 1;
+    }
+    if (c->s2_kernel == 1) {
         int ngroups = 0;
         if (const char* g = getenv("STPCI_S2_GROUPS")) ngroups = atoi(g);
         if (ngroups <= 0) {
@@ -165,7 +167,7 @@ static void record(stpci_ctx* c, int kind, bool start) {
     }
 }
 
-static stpci_status ensure32(stpci_ctx* c) {
+stpci_status ensure32(stpci_ctx* c) {
     if (c->have32) return STPCI_OK;
     stpci_status s;
     if ((s = upload(c, c->d_gT32, c->gT32, "FP32 two-electron integrals"))) return s;

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime_api.h>
 
+#include <complex>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,20 @@ struct KernelEvent {
 struct DavRecord {
     std::vector<double> e, r;
     int precision = 0;
+};
+
+// State of one Davidson run (see davidson.cpp).
+struct DavState {
+    stpci_dav_opts opts{};
+    stpci_precision prec = STPCI_FP64;
+    double tol = 0, final_tol = 0;
+    int pidx = 0, kr_max = 0, mmax = 0, max_iter = 0;
+    int m = 0;    // vectors in V with their W known
+    int nv = 0;   // pending: W[m..m+nv) = H V[m..m+nv)
+    int it = 0, it_prev = 0;
+    bool converged = false, done = false, active = false;
+    std::vector<std::complex<double>> G;
+    std::vector<double> theta, rn;
 };
 
 }  // namespace stp
@@ -71,6 +86,7 @@ struct stpci_ctx {
     std::vector<stp::DavRecord> history;
     int hist_k = 0;
     int nsigma[2] = {0, 0};   // sigma builds of the last Davidson run: FP64, FP32 (vectors)
+    stp::DavState dav;
 
     // profiling
     bool profile = false;
@@ -85,5 +101,12 @@ stpci_status hip_check(stpci_ctx* c, hipError_t e, const char* what);
 stpci_status prepare(stpci_ctx* c);
 stpci_status ensure(stpci_ctx* c, DevBuf& b, size_t bytes, const char* what);
 stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, stpci_precision prec);
+stpci_status ensure32(stpci_ctx* c);  // upload the FP32 integral copies once
 size_t scalar_bytes(const stpci_ctx* c);
+// step-wise Davidson (davidson.cpp)
+stpci_status dav_begin(stpci_ctx* c, const stpci_dav_opts* o);
+int64_t dav_device_bytes(const stpci_ctx* c, const stpci_dav_opts& o);
+bool dav_pending(stpci_ctx* c, const void** in, void** out, int* n, stpci_precision* prec);
+stpci_status dav_step_after_sigma(stpci_ctx* c, int* finished);
+stpci_status dav_collect(stpci_ctx* c, double* energies, double* resid, void* vecs_dev, int* n_iter);
 }  // namespace stp

@@ -159,49 +159,78 @@ extern "C" stpci_status stpci_test_heev(int n, const double* A, double* w, doubl
     return STPCI_OK;
 }
 
-// One Davidson run with sigma products of precision `prec`; starting vectors
-// from guess_dev ([k][n_dets]) or unit vectors at the lowest diagonal entries.
-// Appends its iterations to the context history.  On return energies/resid
-// hold the last Ritz values and residual norms and d_X the Ritz vectors.
-static stpci_status dav_core(stpci_ctx* c, const stpci_dav_opts* o, stpci_precision prec, const void* guess_dev,
-                             double tol, double* energies, double* resid, int* n_iter, bool* conv) {
+// ---------------------------------------------------------------------------
+// Davidson as a state machine.  A run alternates two steps:
+//   pending  -> the sigma products the iteration needs next: W[m..m+nv) = H V[m..m+nv)
+//   advance  -> after those products: extend G = V^H W, Rayleigh-Ritz,
+//               residuals, convergence test, preconditioned corrections,
+//               CGS2, restart, which leaves the next pending products.
+// stpci_davidson drives it with its own sigma calls; the request server
+// drives many contexts at once and performs their sigma products in one
+// grouped launch.
+// ---------------------------------------------------------------------------
+static int subspace_request(const stpci_dav_opts& o) {
+    return o.max_subspace > 0 ? o.max_subspace : std::max(8 * o.k, 32);
+}
+
+// Expansion-space size for a request of mmax vectors (at most 64, at most N,
+// at least 2k where the space allows it).
+static int subspace_cap(int mmax, int k, int64_t N) {
+    mmax = (int)std::min<int64_t>(std::min(mmax, 64), N);
+    if (mmax < 2 * k && N >= 2 * k) mmax = 2 * k;
+    return std::max(mmax, k);
+}
+
+namespace stp {
+// Upper bound of the device bytes a Davidson run allocates (the expansion
+// space is only ever reduced below this when device memory is short).
+int64_t dav_device_bytes(const stpci_ctx* c, const stpci_dav_opts& o) {
+    const int64_t N = c->hs.sp.ndets;
+    const int64_t vb = N * (int64_t)scalar_bytes(c);
+    const int k = o.k, kr = std::min(2 * k, 32);
+    const int mmax = subspace_cap(subspace_request(o), k, N);
+    int64_t b = vb * (2LL * mmax + 2LL * kr + k);
+    b += (int64_t)dots_blocks(N) * 64 * 16 + (int64_t)kSmallBytes;
+    if (!o.guess_dev) b += 1024LL * k * 16;  // top-k partials: at most 1024 blocks
+    return b;
+}
+}  // namespace stp
+
+static stpci_status dav_start(stpci_ctx* c, stpci_precision prec, const void* guess_dev, double tol) {
+    DavState& D = c->dav;
+    const stpci_dav_opts& o = D.opts;
     stpci_status s;
     const int64_t N = c->hs.sp.ndets;
-    const int k = o->k;
-    const int pidx = (prec == STPCI_FP32) ? 1 : 0;
+    const int k = o.k;
+    D.prec = prec;
+    D.tol = tol;
+    D.pidx = (prec == STPCI_FP32) ? 1 : 0;
     const size_t vb = (size_t)N * scalar_bytes(c);
-    const int kr_max = std::min(2 * k, 32);   // Ritz vectors kept by a restart
-    int mmax = o->max_subspace > 0 ? o->max_subspace : std::max(8 * k, 32);
+    D.kr_max = std::min(2 * k, 32);
+    int mmax = subspace_request(o);
     {
         // expansion space bounded by the device memory left for V and W
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) == hipSuccess && vb > 0) {
             const size_t have = c->d_V.bytes + c->d_W.bytes + c->d_X.bytes + c->d_R.bytes + c->d_T.bytes;
-            const double budget = 0.85 * (double)(fr + have) / (double)vb - 2.0 * kr_max - k;
+            const double budget = 0.85 * (double)(fr + have) / (double)vb - 2.0 * D.kr_max - k;
             if (budget / 2.0 < mmax) mmax = (int)std::max(budget / 2.0, (double)(2 * k));
         }
     }
-    mmax = (int)std::min<int64_t>(std::min(mmax, 64), N);
-    if (mmax < 2 * k && N >= 2 * k) mmax = 2 * k;
-    mmax = std::max(mmax, k);
-    const int max_iter = o->max_iter > 0 ? o->max_iter : 100;
-
-    Dav d{c, N, scalar_bytes(c), c->cplx, c->stream};
-    if ((s = ensure(c, c->d_V, vb * mmax, "Davidson V"))) return s;
-    if ((s = ensure(c, c->d_W, vb * mmax, "Davidson W"))) return s;
-    if ((s = ensure(c, c->d_X, vb * kr_max, "Ritz vectors"))) return s;
-    if ((s = ensure(c, c->d_R, vb * kr_max, "residuals"))) return s;
+    D.mmax = subspace_cap(mmax, k, N);
+    D.max_iter = o.max_iter > 0 ? o.max_iter : 100;
+    if ((s = ensure(c, c->d_V, vb * D.mmax, "Davidson V"))) return s;
+    if ((s = ensure(c, c->d_W, vb * D.mmax, "Davidson W"))) return s;
+    if ((s = ensure(c, c->d_X, vb * D.kr_max, "Ritz vectors"))) return s;
+    if ((s = ensure(c, c->d_R, vb * D.kr_max, "residuals"))) return s;
     if ((s = ensure(c, c->d_T, vb * k, "corrections"))) return s;
     if ((s = ensure(c, c->d_partial, (size_t)dots_blocks(N) * 64 * 16, "dot partials"))) return s;
     if ((s = ensure(c, c->d_small, kSmallBytes, "small workspace"))) return s;
-    const size_t theta_off = kThetaOff;
-
-    // initial guess
+    Dav d{c, N, scalar_bytes(c), c->cplx, c->stream};
     if (guess_dev) {
         if ((s = d.hip(hipMemcpyAsync(c->d_V.p, guess_dev, vb * k, hipMemcpyDeviceToDevice, c->stream), "guess")))
             return s;
-        // orthonormalise the guess (CGS2)
-        for (int i = 0; i < k; ++i) {
+        for (int i = 0; i < k; ++i) {  // orthonormalise the guess (CGS2)
             for (int pass = 0; pass < 2 && i > 0; ++pass) {
                 std::vector<cplx> coef;
                 if ((s = d.dots(c->d_V.p, i, d.vec(c->d_V, i), coef))) return s;
@@ -233,164 +262,224 @@ static stpci_status dav_core(stpci_ctx* c, const stpci_dav_opts* o, stpci_precis
         for (int i = 0; i < k; ++i)
             if ((s = d.hip(launch_unit(d.cx, d.vec(c->d_V, i), N, ti[ord[i]], c->stream), "unit"))) return s;
     }
-    if ((s = sigma_impl(c, c->d_V.p, c->d_W.p, k, prec))) return s;
-    c->nsigma[pidx] += k;
-
-    std::vector<cplx> G((size_t)64 * 64, cplx(0, 0));
-    auto Gat = [&](int i, int j) -> cplx& { return G[(size_t)i * 64 + j]; };
-    int m = k;
-    for (int j = 0; j < m; ++j) {
-        std::vector<cplx> col;
-        if ((s = d.dots(c->d_V.p, m, d.vec(c->d_W, j), col))) return s;
-        for (int i = 0; i < m; ++i) Gat(i, j) = col[i];
-    }
-    std::vector<double> theta(k, 0.0), rn(k, 0.0);
-    int it = 0;
-    bool converged = false;
-    for (it = 1; it <= max_iter; ++it) {
-        std::vector<cplx> A((size_t)m * m);
-        for (int i = 0; i < m; ++i)
-            for (int j = 0; j < m; ++j) A[(size_t)i * m + j] = 0.5 * (Gat(i, j) + std::conj(Gat(j, i)));
-        std::vector<double> w;
-        std::vector<cplx> Y;
-        jacobi_heev(m, A, w, Y);
-        std::vector<cplx> Yk((size_t)m * k);
-        for (int i = 0; i < m; ++i)
-            for (int j = 0; j < k; ++j) Yk[(size_t)i * k + j] = Y[(size_t)i * m + j];
-        for (int j = 0; j < k; ++j) theta[j] = w[j];
-        if ((s = d.put_small(Yk, kYOff))) return s;
-        if ((s = d.hip(hipMemcpyAsync((char*)c->d_small.p + theta_off, theta.data(), k * 8, hipMemcpyHostToDevice,
-                                      c->stream),
-                       "theta")))
-            return s;
-        if ((s = d.hip(launch_combine(d.cx, c->d_V.p, c->d_W.p, N, m, c->d_small.p, k,
-                                      (const double*)((char*)c->d_small.p + theta_off), c->d_X.p, c->d_R.p, N, 1,
-                                      c->stream),
-                       "ritz")))
-            return s;
-        for (int j = 0; j < k; ++j)
-            if ((s = d.norm(d.vec(c->d_R, j), rn[j]))) return s;
-        c->history.push_back(DavRecord{theta, rn, pidx});
-        converged = true;
-        for (int j = 0; j < k; ++j) converged = converged && rn[j] <= tol;
-        if (converged) break;
-        if (it == max_iter) break;
-        // corrections for unconverged roots
-        int nt = 0;
-        for (int j = 0; j < k; ++j) {
-            if (rn[j] <= tol) continue;
-            if ((s = d.hip(launch_precond(c->dev, d.cx, (const double*)c->d_hd.p, (const double*)c->d_JK.p,
-                                          c->e_core, d.vec(c->d_R, j), d.vec(c->d_T, nt), theta[j], 1e-12,
-                                          c->stream),
-                           "precond")))
-                return s;
-            ++nt;
-        }
-        // thick restart when the space would overflow: keep the kr lowest Ritz
-        // vectors (V <- V Y_kr, W <- W Y_kr, G <- diag(theta_kr))
-        if (m + nt > mmax) {
-            const int kr = std::max(k, std::min(kr_max, mmax - nt));
-            std::vector<cplx> Yr((size_t)m * kr);
-            for (int i = 0; i < m; ++i)
-                for (int j = 0; j < kr; ++j) Yr[(size_t)i * kr + j] = Y[(size_t)i * m + j];
-            if ((s = d.put_small(Yr, kYOff))) return s;
-            if ((s = d.hip(launch_combine(d.cx, c->d_V.p, nullptr, N, m, c->d_small.p, kr, nullptr, c->d_X.p, nullptr,
-                                          N, 0, c->stream),
-                           "restart VY")))
-                return s;
-            if ((s = d.hip(launch_combine(d.cx, c->d_W.p, nullptr, N, m, c->d_small.p, kr, nullptr, c->d_R.p,
-                                          nullptr, N, 0, c->stream),
-                           "restart WY")))
-                return s;
-            if ((s = d.hip(hipMemcpyAsync(c->d_V.p, c->d_X.p, vb * kr, hipMemcpyDeviceToDevice, c->stream), "restart V")))
-                return s;
-            if ((s = d.hip(hipMemcpyAsync(c->d_W.p, c->d_R.p, vb * kr, hipMemcpyDeviceToDevice, c->stream), "restart W")))
-                return s;
-            std::fill(G.begin(), G.end(), cplx(0, 0));
-            for (int j = 0; j < kr; ++j) Gat(j, j) = w[j];
-            m = kr;
-        }
-        int added = 0;
-        for (int t = 0; t < nt; ++t) {
-            void* tv = d.vec(c->d_T, t);
-            double n0;
-            if ((s = d.norm(tv, n0))) return s;
-            if (n0 == 0.0) continue;
-            for (int pass = 0; pass < 2; ++pass) {
-                std::vector<cplx> coef;
-                if ((s = d.dots(c->d_V.p, m + added, tv, coef))) return s;
-                if ((s = d.subtract(c->d_V.p, m + added, coef, tv))) return s;
-            }
-            double nr;
-            if ((s = d.norm(tv, nr))) return s;
-            // a direction that lost all but 1e-8 of its norm lies in the span (linear dependence)
-            if (nr < 1e-8 * n0 || m + added >= mmax) continue;
-            if ((s = d.hip(launch_scale(d.cx, tv, 1.0 / nr, N, c->stream), "normalise"))) return s;
-            if ((s = d.hip(hipMemcpyAsync(d.vec(c->d_V, m + added), tv, vb, hipMemcpyDeviceToDevice, c->stream),
-                           "append")))
-                return s;
-            ++added;
-        }
-        if (added == 0) break;  // no new direction: stagnation
-        if ((s = sigma_impl(c, d.vec(c->d_V, m), d.vec(c->d_W, m), added, prec))) return s;
-        c->nsigma[pidx] += added;
-        for (int j = m; j < m + added; ++j) {
-            std::vector<cplx> col;
-            if ((s = d.dots(c->d_V.p, m + added, d.vec(c->d_W, j), col))) return s;
-            for (int i = 0; i < m + added; ++i) {
-                Gat(i, j) = col[i];
-                Gat(j, i) = std::conj(col[i]);
-            }
-        }
-        m += added;
-    }
-    for (int j = 0; j < k; ++j) {
-        energies[j] = theta[j];
-        resid[j] = rn[j];
-    }
-    if ((s = d.hip(hipStreamSynchronize(c->stream), "sync"))) return s;
-    *n_iter = std::min(it, max_iter);
-    *conv = converged;
+    D.G.assign((size_t)64 * 64, cplx(0, 0));
+    D.theta.assign(k, 0.0);
+    D.rn.assign(k, 0.0);
+    D.m = 0;
+    D.nv = k;  // pending: W[0..k) = H V[0..k)
+    D.it = 0;
+    D.converged = false;
+    D.done = false;
+    D.active = true;
     return STPCI_OK;
 }
 
-extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, double* energies, double* resid,
-                                       void* vecs_dev, int* n_iter) {
-    if (!c || !o || !energies || !resid) return STPCI_EINVAL;
+// After the pending sigma products: one Rayleigh-Ritz iteration.  Sets D.done
+// when converged, at max_iter, or when no new direction survives CGS2.
+static stpci_status dav_advance(stpci_ctx* c) {
+    DavState& D = c->dav;
+    stpci_status s;
+    const int64_t N = c->hs.sp.ndets;
+    const int k = D.opts.k;
+    const size_t vb = (size_t)N * scalar_bytes(c);
+    Dav d{c, N, scalar_bytes(c), c->cplx, c->stream};
+    auto Gat = [&](int i, int j) -> cplx& { return D.G[(size_t)i * 64 + j]; };
+    c->nsigma[D.pidx] += D.nv;
+    // new columns (and rows) of G = V^H W
+    for (int j = D.m; j < D.m + D.nv; ++j) {
+        std::vector<cplx> col;
+        if ((s = d.dots(c->d_V.p, D.m + D.nv, d.vec(c->d_W, j), col))) return s;
+        for (int i = 0; i < D.m + D.nv; ++i) {
+            Gat(i, j) = col[i];
+            Gat(j, i) = std::conj(col[i]);
+        }
+    }
+    D.m += D.nv;
+    D.nv = 0;
+    const int m = D.m;
+    D.it += 1;
+    std::vector<cplx> A((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) A[(size_t)i * m + j] = 0.5 * (Gat(i, j) + std::conj(Gat(j, i)));
+    std::vector<double> w;
+    std::vector<cplx> Y;
+    jacobi_heev(m, A, w, Y);
+    std::vector<cplx> Yk((size_t)m * k);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < k; ++j) Yk[(size_t)i * k + j] = Y[(size_t)i * m + j];
+    for (int j = 0; j < k; ++j) D.theta[j] = w[j];
+    if ((s = d.put_small(Yk, kYOff))) return s;
+    if ((s = d.hip(hipMemcpyAsync((char*)c->d_small.p + kThetaOff, D.theta.data(), k * 8, hipMemcpyHostToDevice,
+                                  c->stream),
+                   "theta")))
+        return s;
+    if ((s = d.hip(launch_combine(d.cx, c->d_V.p, c->d_W.p, N, m, c->d_small.p, k,
+                                  (const double*)((char*)c->d_small.p + kThetaOff), c->d_X.p, c->d_R.p, N, 1,
+                                  c->stream),
+                   "ritz")))
+        return s;
+    for (int j = 0; j < k; ++j)
+        if ((s = d.norm(d.vec(c->d_R, j), D.rn[j]))) return s;
+    c->history.push_back(DavRecord{D.theta, D.rn, D.pidx});
+    bool conv = true;
+    for (int j = 0; j < k; ++j) conv = conv && D.rn[j] <= D.tol;
+    D.converged = conv;
+    if (conv || D.it >= D.max_iter) {
+        D.done = true;
+        return STPCI_OK;
+    }
+    // corrections for unconverged roots (Eq. sparsePreconditioner, eps = 0)
+    int nt = 0;
+    for (int j = 0; j < k; ++j) {
+        if (D.rn[j] <= D.tol) continue;
+        if ((s = d.hip(launch_precond(c->dev, d.cx, (const double*)c->d_hd.p, (const double*)c->d_JK.p, c->e_core,
+                                      d.vec(c->d_R, j), d.vec(c->d_T, nt), D.theta[j], 1e-12, c->stream),
+                       "precond")))
+            return s;
+        ++nt;
+    }
+    int mm = m;
+    // thick restart when the space would overflow: keep the kr lowest Ritz
+    // vectors (V <- V Y_kr, W <- W Y_kr, G <- diag(theta_kr))
+    if (mm + nt > D.mmax) {
+        const int kr = std::max(k, std::min(D.kr_max, D.mmax - nt));
+        std::vector<cplx> Yr((size_t)mm * kr);
+        for (int i = 0; i < mm; ++i)
+            for (int j = 0; j < kr; ++j) Yr[(size_t)i * kr + j] = Y[(size_t)i * mm + j];
+        if ((s = d.put_small(Yr, kYOff))) return s;
+        if ((s = d.hip(launch_combine(d.cx, c->d_V.p, nullptr, N, mm, c->d_small.p, kr, nullptr, c->d_X.p, nullptr, N,
+                                      0, c->stream),
+                       "restart VY")))
+            return s;
+        if ((s = d.hip(launch_combine(d.cx, c->d_W.p, nullptr, N, mm, c->d_small.p, kr, nullptr, c->d_R.p, nullptr, N,
+                                      0, c->stream),
+                       "restart WY")))
+            return s;
+        if ((s = d.hip(hipMemcpyAsync(c->d_V.p, c->d_X.p, vb * kr, hipMemcpyDeviceToDevice, c->stream), "restart V")))
+            return s;
+        if ((s = d.hip(hipMemcpyAsync(c->d_W.p, c->d_R.p, vb * kr, hipMemcpyDeviceToDevice, c->stream), "restart W")))
+            return s;
+        std::fill(D.G.begin(), D.G.end(), cplx(0, 0));
+        for (int j = 0; j < kr; ++j) Gat(j, j) = w[j];
+        mm = kr;
+        D.m = kr;
+    }
+    int added = 0;
+    for (int t = 0; t < nt; ++t) {
+        void* tv = d.vec(c->d_T, t);
+        double n0;
+        if ((s = d.norm(tv, n0))) return s;
+        if (n0 == 0.0) continue;
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<cplx> coef;
+            if ((s = d.dots(c->d_V.p, mm + added, tv, coef))) return s;
+            if ((s = d.subtract(c->d_V.p, mm + added, coef, tv))) return s;
+        }
+        double nr;
+        if ((s = d.norm(tv, nr))) return s;
+        // a direction that lost all but 1e-8 of its norm lies in the span (linear dependence)
+        if (nr < 1e-8 * n0 || mm + added >= D.mmax) continue;
+        if ((s = d.hip(launch_scale(d.cx, tv, 1.0 / nr, N, c->stream), "normalise"))) return s;
+        if ((s = d.hip(hipMemcpyAsync(d.vec(c->d_V, mm + added), tv, vb, hipMemcpyDeviceToDevice, c->stream),
+                       "append")))
+            return s;
+        ++added;
+    }
+    if (added == 0) {  // no new direction: stagnation
+        D.done = true;
+        return STPCI_OK;
+    }
+    D.nv = added;
+    return STPCI_OK;
+}
+
+namespace stp {
+
+stpci_status dav_begin(stpci_ctx* c, const stpci_dav_opts* o) {
     stpci_status s = prepare(c);
     if (s) return s;
     if ((s = hip_check(c, hipSetDevice(c->device), "hipSetDevice"))) return s;
     const int64_t N = c->hs.sp.ndets;
-    const int k = o->k;
-    if (k < 1 || k > 16 || k > N) return set_err(c, STPCI_EINVAL, "k must be in [1, min(16, n_dets)]");
-    if (o->precision != STPCI_FP64 && o->precision != STPCI_FP32)
-        return set_err(c, STPCI_EINVAL, "unknown precision");
-    const double tol = o->tol_residual > 0 ? o->tol_residual : 1e-8;
+    if (o->k < 1 || o->k > 16 || o->k > N) return set_err(c, STPCI_EINVAL, "k must be in [1, min(16, n_dets)]");
+    if (o->precision != STPCI_FP64 && o->precision != STPCI_FP32) return set_err(c, STPCI_EINVAL, "unknown precision");
+    c->dav = DavState{};
+    c->dav.opts = *o;
+    c->dav.final_tol = o->tol_residual > 0 ? o->tol_residual : 1e-8;
     c->history.clear();
-    c->hist_k = k;
+    c->hist_k = o->k;
     c->nsigma[0] = c->nsigma[1] = 0;
-    int it_total = 0, it = 0;
-    bool conv = false;
-    const void* guess = o->guess_dev;
-    if (o->precision == STPCI_FP32) {
-        // phase A: FP32 contraction until the residual reaches a tolerance the
-        // FP32 products can resolve; phase B refines from those Ritz vectors
-        // with FP64 products to the requested tolerance.
-        const double tol_a = std::max(tol, 1e-4);
-        if ((s = dav_core(c, o, STPCI_FP32, guess, tol_a, energies, resid, &it, &conv))) return s;
-        it_total += it;
-        guess = c->d_X.p;
+    if (o->precision == STPCI_FP32)  // phase A: FP32 contraction to a residual FP32 products resolve
+        return dav_start(c, STPCI_FP32, o->guess_dev, std::max(c->dav.final_tol, 1e-4));
+    return dav_start(c, STPCI_FP64, o->guess_dev, c->dav.final_tol);
+}
+
+// The pending sigma work of the run: n vectors from V[m] into W[m].
+bool dav_pending(stpci_ctx* c, const void** in, void** out, int* n, stpci_precision* prec) {
+    DavState& D = c->dav;
+    if (!D.active || D.done || D.nv == 0) return false;
+    const size_t vb = (size_t)c->hs.sp.ndets * scalar_bytes(c);
+    *in = (const char*)c->d_V.p + (size_t)D.m * vb;
+    *out = (char*)c->d_W.p + (size_t)D.m * vb;
+    *n = D.nv;
+    *prec = D.prec;
+    return true;
+}
+
+// Advance after the pending products; moves from the FP32 phase to FP64
+// refinement (guess = the FP32 Ritz vectors) when the former ends.
+stpci_status dav_step_after_sigma(stpci_ctx* c, int* finished) {
+    DavState& D = c->dav;
+    stpci_status s = dav_advance(c);
+    if (s) return s;
+    if (D.done && D.prec == STPCI_FP32) {
+        D.it_prev += D.it;
+        const int keep = D.it_prev;
+        if ((s = dav_start(c, STPCI_FP64, c->d_X.p, D.final_tol))) return s;
+        D.it_prev = keep;
     }
-    if ((s = dav_core(c, o, STPCI_FP64, guess, tol, energies, resid, &it, &conv))) return s;
-    it_total += it;
+    *finished = D.done ? 1 : 0;
+    if (D.done) D.active = false;
+    return STPCI_OK;
+}
+
+stpci_status dav_collect(stpci_ctx* c, double* energies, double* resid, void* vecs_dev, int* n_iter) {
+    DavState& D = c->dav;
+    const int k = D.opts.k;
+    for (int j = 0; j < k; ++j) {
+        energies[j] = D.theta[j];
+        resid[j] = D.rn[j];
+    }
+    if (n_iter) *n_iter = D.it_prev + D.it;
     if (vecs_dev) {
-        const size_t vb = (size_t)N * scalar_bytes(c) * k;
-        if ((s = hip_check(c, hipMemcpyAsync(vecs_dev, c->d_X.p, vb, hipMemcpyDeviceToDevice, c->stream), "vecs out")))
-            return s;
-        if ((s = hip_check(c, hipStreamSynchronize(c->stream), "sync"))) return s;
+        const size_t vb = (size_t)c->hs.sp.ndets * scalar_bytes(c) * k;
+        stpci_status s = hip_check(c, hipMemcpyAsync(vecs_dev, c->d_X.p, vb, hipMemcpyDeviceToDevice, c->stream),
+                                   "vecs out");
+        if (s) return s;
     }
-    if (n_iter) *n_iter = it_total;
-    return conv ? STPCI_OK : set_err(c, STPCI_ENOCONV, "Davidson did not converge");
+    stpci_status s = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (s) return s;
+    return D.converged ? STPCI_OK : set_err(c, STPCI_ENOCONV, "Davidson did not converge");
+}
+
+}  // namespace stp
+
+extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, double* energies, double* resid,
+                                       void* vecs_dev, int* n_iter) {
+    if (!c || !o || !energies || !resid) return STPCI_EINVAL;
+    stpci_status s = dav_begin(c, o);
+    if (s) return s;
+    for (;;) {
+        const void* in;
+        void* out;
+        int n;
+        stpci_precision prec;
+        if (!dav_pending(c, &in, &out, &n, &prec)) break;
+        if ((s = sigma_impl(c, in, out, n, prec))) return s;
+        int fin = 0;
+        if ((s = dav_step_after_sigma(c, &fin))) return s;
+        if (fin) break;
+    }
+    return dav_collect(c, energies, resid, vecs_dev, n_iter);
 }
 
 extern "C" stpci_status stpci_dav_stats(const stpci_ctx* c, int* sigma_fp64, int* sigma_fp32) {

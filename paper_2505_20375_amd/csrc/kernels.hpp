@@ -24,6 +24,9 @@ hipError_t launch_sigma_symtile(const DevSpace& S, int deg_max, bool cplx, bool 
 // sigma = H c (one- and two-electron parts) in one pass over the intermediate determinants
 hipError_t launch_sigma_wave(const DevSpace& S, int deg_max, bool cplx, const void* gT, const void* hp,
                              const void* c, void* sigma, int n_vec, hipStream_t st);
+// grouped sigma over ndesc problems (descriptors and prefix offsets on the device)
+hipError_t launch_sigma_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
+                              int deg_max, bool cplx, bool f32, hipStream_t st);
 hipError_t launch_diag(const DevSpace& S, const double* hd, const double* JK, double e_core, double* out,
                        hipStream_t st);
 hipError_t launch_precond(const DevSpace& S, bool cplx, const double* hd, const double* JK, double e_core,

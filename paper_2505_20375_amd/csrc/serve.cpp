@@ -1,0 +1,358 @@
+// Continuous-batching request server for CI solves.
+//
+// Requests (integrals, space, Davidson options) queue on submission; their
+// host-side setup (string tables, transposed integrals) happens then.  Each
+// tick
+//   1. admits queued requests in FIFO order while the slot count and the
+//      device-memory budget allow (the footprint is computed exactly from
+//      the sizes the context will allocate),
+//   2. gathers the pending sigma products of every active request and runs
+//      them as grouped launches (one per scalar type and contraction
+//      precision) over the concatenated intermediate-determinant ranges,
+//   3. advances every active request by one Davidson iteration and retires
+//      the finished ones, releasing their memory for the next admissions.
+// Requests therefore join and leave between ticks while others are on the
+// device; their vectors stay resident from admission to completion.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/stpci.h"
+#include "../../include/stpci_serve.h"
+#include "ctx.hpp"
+#include "kernels.hpp"
+
+using namespace stp;
+
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+enum ReqState { QUEUED = 0, ACTIVE = 1, DONE = 2, FAILED = 3, CANCELLED = 4 };
+
+struct Req {
+    int id = 0;
+    stpci_ctx* ctx = nullptr;
+    stpci_dav_opts opts{};
+    int64_t footprint = 0;
+    int state = QUEUED;
+    stpci_status status = STPCI_OK;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    std::vector<double> energies, resid;
+    int n_iter = 0;
+    int64_t n_dets = 0;
+    double nnz = 0;
+    int sigma_vectors = 0;
+    std::string err;
+};
+
+}  // namespace
+
+struct stpci_server {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t budget = 0;
+    int max_active = 0;
+    int64_t used = 0, peak_used = 0;
+    int peak_active = 0;
+    int64_t ticks = 0, grouped_launches = 0;
+    std::vector<std::unique_ptr<Req>> reqs;
+    std::deque<int> queue;
+    std::vector<int> active;
+    DevBuf d_desc, d_jbegin;
+    std::string err;
+    ~stpci_server() {
+        for (auto& r : reqs) stpci_destroy(r->ctx);
+        (void)hipSetDevice(device);
+        d_desc.free_();
+        d_jbegin.free_();
+    }
+};
+
+// Device bytes a request holds while active: tables, integrals (with the
+// FP32 copies for the FP32 contraction), the schedule of the row-tiled
+// fallback kernel where the tile kernel does not apply, and the Davidson
+// vectors and workspace.
+static int64_t footprint(const stpci_ctx* c, const stpci_dav_opts& o) {
+    const HostSpace& H = c->hs;
+    int64_t b = 0;
+    b += (int64_t)(H.cats.size() * sizeof(Cat) + H.tabs.size() * sizeof(StrTab));
+    b += (int64_t)(H.bits.size() + H.ann.size() + H.cre.size() + H.work_cat.size()) * 4;
+    b += (int64_t)(H.work_begin.size() + H.space_begin.size()) * 8;
+    b += (int64_t)(c->gT.size() + c->hprime.size() + c->hd.size() + c->JK.size()) * 8;
+    if (o.precision == STPCI_FP32) b += (int64_t)(c->gT32.size() + c->hp32.size()) * 4;
+    if (!symtile_supported(H.max_deg, c->cplx)) b += H.sp.nwork_dets * 16 + (int64_t)H.sp.M * 4;
+    return b + dav_device_bytes(c, o);
+}
+
+static stpci_status srv_err(stpci_server* s, stpci_status st, const std::string& m) {
+    s->err = m;
+    return st;
+}
+
+extern "C" {
+
+stpci_status stpci_server_create(stpci_server** out, int hip_device, void* hip_stream, int64_t mem_budget_bytes,
+                                 int max_active) {
+    if (!out || hip_device < 0 || mem_budget_bytes <= 0 || max_active < 1) return STPCI_EINVAL;
+    *out = nullptr;
+    if (hipSetDevice(hip_device) != hipSuccess) return STPCI_EHIP;
+    stpci_server* s = new (std::nothrow) stpci_server();
+    if (!s) return STPCI_ENOMEM;
+    s->device = hip_device;
+    s->stream = (hipStream_t)hip_stream;
+    s->budget = mem_budget_bytes;
+    s->max_active = max_active;
+    *out = s;
+    return STPCI_OK;
+}
+
+void stpci_server_destroy(stpci_server* s) { delete s; }
+
+const char* stpci_server_last_error(const stpci_server* s) { return s ? s->err.c_str() : "null server"; }
+
+stpci_status stpci_server_submit(stpci_server* s, const stpci_request* r, int* id) {
+    if (!s || !r || !id || !r->opts) return STPCI_EINVAL;
+    std::unique_ptr<Req> q(new (std::nothrow) Req());
+    if (!q) return STPCI_ENOMEM;
+    stpci_status st = stpci_create(&q->ctx, s->device, (void*)s->stream);
+    if (st) return srv_err(s, st, "context creation failed");
+    if ((st = stpci_set_integrals(q->ctx, r->n_orb, r->scalar, r->spin_free, r->h, r->g, r->e_core)) ||
+        (st = stpci_set_space(q->ctx, r->n_elec, r->n_sub, r->sub_size, r->win_lo, r->win_hi))) {
+        std::string m = stpci_last_error(q->ctx);
+        stpci_destroy(q->ctx);
+        q->ctx = nullptr;
+        return srv_err(s, st, m);
+    }
+    if (q->ctx->hs.sp.M != q->ctx->M) {
+        stpci_destroy(q->ctx);
+        q->ctx = nullptr;
+        return srv_err(s, STPCI_EINVAL, "space and integrals cover different numbers of spin-orbitals");
+    }
+    q->opts = *r->opts;
+    q->opts.guess_dev = nullptr;
+    if (q->opts.k < 1 || q->opts.k > 16 || q->opts.k > q->ctx->hs.sp.ndets) {
+        stpci_destroy(q->ctx);
+        q->ctx = nullptr;
+        return srv_err(s, STPCI_EINVAL, "k must be in [1, min(16, n_dets)]");
+    }
+    q->footprint = footprint(q->ctx, q->opts);
+    if (q->footprint > s->budget) {
+        stpci_destroy(q->ctx);
+        q->ctx = nullptr;
+        return srv_err(s, STPCI_ENOMEM, "request footprint exceeds the server's memory budget");
+    }
+    q->n_dets = q->ctx->hs.sp.ndets;
+    q->nnz = q->ctx->hs.nnz;
+    q->id = (int)s->reqs.size();
+    q->t_submit = now_s();
+    *id = q->id;
+    s->queue.push_back(q->id);
+    s->reqs.push_back(std::move(q));
+    return STPCI_OK;
+}
+
+stpci_status stpci_server_cancel(stpci_server* s, int id) {
+    if (!s || id < 0 || id >= (int)s->reqs.size()) return STPCI_EINVAL;
+    Req& q = *s->reqs[id];
+    if (q.state == QUEUED) {
+        s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), id), s->queue.end());
+    } else if (q.state == ACTIVE) {
+        s->active.erase(std::remove(s->active.begin(), s->active.end(), id), s->active.end());
+        s->used -= q.footprint;
+    } else {
+        return STPCI_OK;
+    }
+    q.state = CANCELLED;
+    q.t_done = now_s();
+    stpci_destroy(q.ctx);
+    q.ctx = nullptr;
+    return STPCI_OK;
+}
+
+static stpci_status collect(Req& q) {
+    const int k = q.opts.k;
+    q.energies.assign(k, 0.0);
+    q.resid.assign(k, 0.0);
+    return dav_collect(q.ctx, q.energies.data(), q.resid.data(), nullptr, &q.n_iter);
+}
+
+static void retire(stpci_server* s, Req& q, stpci_status st) {
+    q.status = st;
+    q.state = (st == STPCI_OK || st == STPCI_ENOCONV) ? DONE : FAILED;
+    if (q.ctx) {
+        q.err = stpci_last_error(q.ctx);
+        q.sigma_vectors = q.ctx->nsigma[0] + q.ctx->nsigma[1];
+    }
+    q.t_done = now_s();
+    stpci_destroy(q.ctx);
+    q.ctx = nullptr;
+    s->used -= q.footprint;
+    s->active.erase(std::remove(s->active.begin(), s->active.end(), q.id), s->active.end());
+}
+
+stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) {
+    if (!s) return STPCI_EINVAL;
+    if (hipSetDevice(s->device) != hipSuccess) return srv_err(s, STPCI_EHIP, "hipSetDevice");
+    int finished = 0;
+    // 1. FIFO admission by slots and device-memory budget
+    while (!s->queue.empty() && (int)s->active.size() < s->max_active) {
+        Req& q = *s->reqs[s->queue.front()];
+        if (s->used + q.footprint > s->budget) break;
+        s->queue.pop_front();
+        q.state = ACTIVE;
+        q.t_admit = now_s();
+        s->active.push_back(q.id);
+        s->used += q.footprint;
+        stpci_status st = dav_begin(q.ctx, &q.opts);
+        if (!st && q.opts.precision == STPCI_FP32) st = ensure32(q.ctx);
+        if (st) {
+            retire(s, q, st);
+            ++finished;
+        }
+    }
+    s->peak_used = std::max(s->peak_used, s->used);
+    s->peak_active = std::max(s->peak_active, (int)s->active.size());
+    // 2. pending sigma products of all active requests, grouped by scalar type and precision
+    struct Item {
+        int id;
+        SigmaDesc d;
+        int deg;
+        int64_t nj;
+    };
+    std::vector<Item> groups[2][2];
+    std::vector<int> solo;
+    const std::vector<int> admitted(s->active);  // retire() edits the active list
+    for (int id : admitted) {
+        Req& q = *s->reqs[id];
+        const void* in;
+        void* out;
+        int n;
+        stpci_precision prec;
+        if (!dav_pending(q.ctx, &in, &out, &n, &prec)) continue;
+        stpci_ctx* c = q.ctx;
+        const bool f32 = prec == STPCI_FP32;
+        if (c->s2_kernel != 3) {
+            // spaces outside the tile kernel's limits take the context's own path
+            stpci_status st = sigma_impl(c, in, out, n, prec);
+            if (st) {
+                retire(s, q, st);
+                ++finished;
+            } else {
+                solo.push_back(id);
+            }
+            continue;
+        }
+        const size_t vb = (size_t)c->hs.sp.ndets * scalar_bytes(c);
+        for (int v0 = 0; v0 < n; v0 += 2) {
+            Item it;
+            it.id = id;
+            it.d.S = c->dev;
+            it.d.gT = f32 ? c->d_gT32.p : c->d_gT.p;
+            it.d.hp = f32 ? c->d_hp32.p : c->d_hp.p;
+            it.d.c = (const char*)in + v0 * vb;
+            it.d.sigma = (char*)out + v0 * vb;
+            it.d.n_vec = std::min(2, n - v0);
+            it.d.pad = 0;
+            it.deg = c->hs.max_deg;
+            it.nj = c->hs.sp.nwork_dets;
+            groups[c->cplx ? 1 : 0][f32 ? 1 : 0].push_back(it);
+        }
+    }
+    std::vector<int> stepped(solo);
+    for (int cx = 0; cx < 2; ++cx)
+        for (int f = 0; f < 2; ++f) {
+            auto& G = groups[cx][f];
+            if (G.empty()) continue;
+            std::vector<SigmaDesc> desc;
+            std::vector<int64_t> jb(1, 0);
+            int deg = 0;
+            for (auto& it : G) {
+                desc.push_back(it.d);
+                jb.push_back(jb.back() + it.nj);
+                deg = std::max(deg, it.deg);
+                if (stepped.empty() || stepped.back() != it.id) stepped.push_back(it.id);
+            }
+            stpci_status st = ensure(nullptr, s->d_desc, desc.size() * sizeof(SigmaDesc), "descriptors");
+            if (!st) st = ensure(nullptr, s->d_jbegin, jb.size() * 8, "descriptor offsets");
+            if (st) return srv_err(s, st, "descriptor allocation failed");
+            hipError_t e = hipMemcpyAsync(s->d_desc.p, desc.data(), desc.size() * sizeof(SigmaDesc),
+                                          hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(s->d_jbegin.p, jb.data(), jb.size() * 8, hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess)
+                e = launch_sigma_multi((const SigmaDesc*)s->d_desc.p, (int)desc.size(), (const int64_t*)s->d_jbegin.p,
+                                       jb.back(), deg, cx == 1, f == 1, s->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // descriptors are reused next launch
+            if (e != hipSuccess) return srv_err(s, STPCI_EHIP, hipGetErrorString(e));
+            ++s->grouped_launches;
+        }
+    // 3. one Davidson iteration for every request whose products were computed
+    std::sort(stepped.begin(), stepped.end());
+    stepped.erase(std::unique(stepped.begin(), stepped.end()), stepped.end());
+    for (int id : stepped) {
+        Req& q = *s->reqs[id];
+        if (q.state != ACTIVE) continue;
+        int fin = 0;
+        stpci_status st = dav_step_after_sigma(q.ctx, &fin);
+        if (st || fin) {
+            if (!st) st = collect(q);
+            retire(s, q, st);
+            ++finished;
+        }
+    }
+    ++s->ticks;
+    if (n_active) *n_active = (int)s->active.size() + (int)s->queue.size();  // pending after the step
+    if (n_finished) *n_finished = finished;
+    return STPCI_OK;
+}
+
+stpci_status stpci_server_result(const stpci_server* s, int id, int* state, double* energies, double* resid,
+                                 int* n_iter, double* t_submit, double* t_admit, double* t_done) {
+    if (!s || id < 0 || id >= (int)s->reqs.size()) return STPCI_EINVAL;
+    const Req& q = *s->reqs[id];
+    if (state) *state = q.state;
+    if (energies)
+        for (size_t j = 0; j < q.energies.size(); ++j) energies[j] = q.energies[j];
+    if (resid)
+        for (size_t j = 0; j < q.resid.size(); ++j) resid[j] = q.resid[j];
+    if (n_iter) *n_iter = q.n_iter;
+    if (t_submit) *t_submit = q.t_submit;
+    if (t_admit) *t_admit = q.t_admit;
+    if (t_done) *t_done = q.t_done;
+    return q.state == FAILED ? q.status : STPCI_OK;
+}
+
+stpci_status stpci_server_request_info(const stpci_server* s, int id, int64_t* n_dets, double* nnz_h,
+                                       int64_t* footprint_bytes, int* sigma_vectors) {
+    if (!s || id < 0 || id >= (int)s->reqs.size()) return STPCI_EINVAL;
+    const Req& q = *s->reqs[id];
+    if (n_dets) *n_dets = q.n_dets;
+    if (nnz_h) *nnz_h = q.nnz;
+    if (footprint_bytes) *footprint_bytes = q.footprint;
+    if (sigma_vectors) *sigma_vectors = q.sigma_vectors;
+    return STPCI_OK;
+}
+
+stpci_status stpci_server_stats(const stpci_server* s, int64_t* used_bytes, int64_t* peak_bytes, int* peak_active,
+                                int64_t* ticks, int64_t* grouped_launches) {
+    if (!s) return STPCI_EINVAL;
+    if (used_bytes) *used_bytes = s->used;
+    if (peak_bytes) *peak_bytes = s->peak_used;
+    if (peak_active) *peak_active = s->peak_active;
+    if (ticks) *ticks = s->ticks;
+    if (grouped_launches) *grouped_launches = s->grouped_launches;
+    return STPCI_OK;
+}
+
+}  // extern "C"

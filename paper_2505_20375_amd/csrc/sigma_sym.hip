@@ -46,23 +46,19 @@ __host__ __device__ constexpr int st_elems(int deg_cap) {
     return ((deg_cap + 3) >> 2) * (ST_TILE * NV + 16 / SB);
 }
 
+// Sigma contribution of one intermediate determinant J (index over the
+// work categories of S), computed by one wavefront with its LDS slice.
 template <bool CPLX, bool F32, int NV>
-__global__ __launch_bounds__(256) void k_sigma_symtile(DevSpace S, const typename PT<CPLX, F32>::T* __restrict__ gT,
-                                                      const typename PT<CPLX, F32>::T* __restrict__ hp,
-                                                      const typename VT<CPLX>::T* __restrict__ c,
-                                                      typename VT<CPLX>::T* __restrict__ sigma, int n_vec,
-                                                      int deg_cap) {
+__device__ __forceinline__ void symtile_det(const DevSpace& S, const typename PT<CPLX, F32>::T* __restrict__ gT,
+                                            const typename PT<CPLX, F32>::T* __restrict__ hp,
+                                            const typename VT<CPLX>::T* __restrict__ c,
+                                            typename VT<CPLX>::T* __restrict__ sigma, int n_vec, int deg_cap,
+                                            unsigned char* base, int lane, int64_t J) {
     using V = PT<CPLX, F32>;     // contraction arithmetic
     using V64 = VT<CPLX>;        // vector storage and sigma accumulation
     using T = typename V::T;
     constexpr int SB = sizeof(T);
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-    const int wpb = blockDim.x >> 6;
     const int ne = st_elems<NV, SB>(deg_cap);
-    const size_t slice = (size_t)2 * ne * SB + (size_t)deg_cap * 16;
-    unsigned char* base = smem + (size_t)wid * slice;
     T* dsh = reinterpret_cast<T*>(base);                         // padded [slot][NV]
     T* esh = dsh + ne;                                           // padded [slot][NV]
     int64_t* tgt = reinterpret_cast<int64_t*>(esh + ne);
@@ -71,141 +67,179 @@ __global__ __launch_bounds__(256) void k_sigma_symtile(DevSpace S, const typenam
     const int M = S.sp.M;
     const int MM = M * M;
     const int64_t nd = S.sp.ndets;
-    const int64_t total = S.sp.nwork_dets;
-    const int64_t nw = (int64_t)gridDim.x * wpb;
-    for (int64_t J = (int64_t)blockIdx.x * wpb + wid; J < total; J += nw) {
-        const int w = find_segment(S.work_begin, S.sp.nwork, J);
-        const Cat& C = S.cats[S.work_cat[w]];
-        const int64_t jloc = J - S.work_begin[w];
-        Det dt;
-        decode(S, C, jloc, dt);
-        const int deg = C.deg;
+    const int w = find_segment(S.work_begin, S.sp.nwork, J);
+    const Cat& C = S.cats[S.work_cat[w]];
+    const int64_t jloc = J - S.work_begin[w];
+    Det dt;
+    decode(S, C, jloc, dt);
+    const int deg = C.deg;
 
-        // ---- phase 1: moves, gathers, one-electron term
-        T one[NV];
+    // ---- phase 1: moves, gathers, one-electron term
+    T one[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) one[v] = V::zero();
-        for (int slot = lane; slot < ((deg + 3) & ~3); slot += 64) {
-            if (slot >= deg) {  // zero the padding slots of the last block
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    dsh[st_idx<NV, SB>(slot, v)] = V::zero();
-                    esh[st_idx<NV, SB>(slot, v)] = V::zero();
-                }
-                continue;
-            }
-            int cls, xs, ys, lx, ly, sg;
-            slot_move(S, C, dt, slot, cls, xs, ys, lx, ly);
-            const int64_t t = apply_move(S, C, cls, xs, ys, lx, ly, dt, sg);
-            const int x = S.sp.sub_off[xs] + lx, y = S.sp.sub_off[ys] + ly;
-            const int pair = y * M + x;
-            tgt[slot] = t;
-            coff[slot] = pair * MM;
-            rinf[slot] = (pair << 1) | (sg < 0 ? 1 : 0);
-            const T hv = hp[y * M + x];
+    for (int v = 0; v < NV; ++v) one[v] = V::zero();
+    for (int slot = lane; slot < ((deg + 3) & ~3); slot += 64) {
+        if (slot >= deg) {  // zero the padding slots of the last block
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                T val = (v < n_vec) ? V::from64(c[(int64_t)v * nd + t]) : V::zero();
-                if (sg < 0) val = V::scale(val, -1.0);
-                dsh[st_idx<NV, SB>(slot, v)] = val;
+                dsh[st_idx<NV, SB>(slot, v)] = V::zero();
                 esh[st_idx<NV, SB>(slot, v)] = V::zero();
-                one[v] = V::mad(hv, val, one[v]);
             }
+            continue;
         }
-        if (C.in_space) {
+        int cls, xs, ys, lx, ly, sg;
+        slot_move(S, C, dt, slot, cls, xs, ys, lx, ly);
+        const int64_t t = apply_move(S, C, cls, xs, ys, lx, ly, dt, sg);
+        const int x = S.sp.sub_off[xs] + lx, y = S.sp.sub_off[ys] + ly;
+        const int pair = y * M + x;
+        tgt[slot] = t;
+        coff[slot] = pair * MM;
+        rinf[slot] = (pair << 1) | (sg < 0 ? 1 : 0);
+        const T hv = hp[y * M + x];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const typename V64::T s = wave_sum<CPLX>(V::to64(one[v]));
-                if (lane == 0 && v < n_vec) V64::atomic_add(&sigma[(int64_t)v * nd + C.offset + jloc], s);
-            }
+        for (int v = 0; v < NV; ++v) {
+            T val = (v < n_vec) ? V::from64(c[(int64_t)v * nd + t]) : V::zero();
+            if (sg < 0) val = V::scale(val, -1.0);
+            dsh[st_idx<NV, SB>(slot, v)] = val;
+            esh[st_idx<NV, SB>(slot, v)] = V::zero();
+            one[v] = V::mad(hv, val, one[v]);
         }
-        wave_lds_sync();
+    }
+    if (C.in_space) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const typename V64::T s = wave_sum<CPLX>(V::to64(one[v]));
+            if (lane == 0 && v < n_vec) V64::atomic_add(&sigma[(int64_t)v * nd + C.offset + jloc], s);
+        }
+    }
+    wave_lds_sync();
 
-        // ---- phase 2: upper-triangle tiles of G_J
-        const int nb = (deg + ST_TILE - 1) / ST_TILE;
-        const int np = nb * (nb + 1) / 2;
-        const int p0 = (int)(((int64_t)lane * np) >> 6);
-        const int p1 = (int)(((int64_t)(lane + 1) * np) >> 6);
-        int b = 0, start = 0;
-        while (b < nb && start + (nb - b) <= p0) {
-            start += nb - b;
-            ++b;
-        }
-        int bp = b + (p0 - start);
-        int cur = -1;
-        int prow[ST_TILE];
-        T drow[ST_TILE][NV], erow[ST_TILE][NV];
-        for (int p = p0; p < p1; ++p) {
-            if (b != cur) {
-                if (cur >= 0) {
-#pragma unroll
-                    for (int r = 0; r < ST_TILE; ++r)
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) V::lds_add(&esh[st_idx<NV, SB>(cur * ST_TILE + r, v)], erow[r][v]);
-                }
-                cur = b;
-#pragma unroll
-                for (int r = 0; r < ST_TILE; ++r) {
-                    const int s = b * ST_TILE + r;
-                    // a padding row has d = 0 and adds zeros; its offset is kept in range
-                    prow[r] = (s < deg) ? (rinf[s] >> 1) : 0;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        drow[r][v] = dsh[st_idx<NV, SB>(s, v)];
-                        erow[r][v] = V::zero();
-                    }
-                }
-            }
-            const bool offdiag = (bp != b);
-#pragma unroll
-            for (int k = 0; k < ST_TILE; ++k) {
-                const int s = bp * ST_TILE + k;
-                if (s >= deg) break;
-                const int co = coff[s];
-                T dcol[NV], ecol[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    dcol[v] = dsh[st_idx<NV, SB>(s, v)];
-                    ecol[v] = V::zero();
-                }
-                T g[ST_TILE];
-#pragma unroll
-                for (int r = 0; r < ST_TILE; ++r) g[r] = gT[co + prow[r]];
+    // ---- phase 2: upper-triangle tiles of G_J
+    const int nb = (deg + ST_TILE - 1) / ST_TILE;
+    const int np = nb * (nb + 1) / 2;
+    const int p0 = (int)(((int64_t)lane * np) >> 6);
+    const int p1 = (int)(((int64_t)(lane + 1) * np) >> 6);
+    int b = 0, start = 0;
+    while (b < nb && start + (nb - b) <= p0) {
+        start += nb - b;
+        ++b;
+    }
+    int bp = b + (p0 - start);
+    int cur = -1;
+    int prow[ST_TILE];
+    T drow[ST_TILE][NV], erow[ST_TILE][NV];
+    for (int p = p0; p < p1; ++p) {
+        if (b != cur) {
+            if (cur >= 0) {
 #pragma unroll
                 for (int r = 0; r < ST_TILE; ++r)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        erow[r][v] = V::mad(g[r], dcol[v], erow[r][v]);
-                        ecol[v] = V::cmad(g[r], drow[r][v], ecol[v]);
-                    }
-                if (offdiag) {
+                    for (int v = 0; v < NV; ++v) V::lds_add(&esh[st_idx<NV, SB>(cur * ST_TILE + r, v)], erow[r][v]);
+            }
+            cur = b;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) V::lds_add(&esh[st_idx<NV, SB>(s, v)], ecol[v]);
+            for (int r = 0; r < ST_TILE; ++r) {
+                const int s = b * ST_TILE + r;
+                // a padding row has d = 0 and adds zeros; its offset is kept in range
+                prow[r] = (s < deg) ? (rinf[s] >> 1) : 0;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    drow[r][v] = dsh[st_idx<NV, SB>(s, v)];
+                    erow[r][v] = V::zero();
                 }
             }
-            if (++bp == nb) {
-                ++b;
-                bp = b;
-            }
         }
-        if (cur >= 0) {
+        const bool offdiag = (bp != b);
+#pragma unroll
+        for (int k = 0; k < ST_TILE; ++k) {
+            const int s = bp * ST_TILE + k;
+            if (s >= deg) break;
+            const int co = coff[s];
+            T dcol[NV], ecol[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                dcol[v] = dsh[st_idx<NV, SB>(s, v)];
+                ecol[v] = V::zero();
+            }
+            T g[ST_TILE];
+#pragma unroll
+            for (int r = 0; r < ST_TILE; ++r) g[r] = gT[co + prow[r]];
 #pragma unroll
             for (int r = 0; r < ST_TILE; ++r)
 #pragma unroll
-                for (int v = 0; v < NV; ++v) V::lds_add(&esh[st_idx<NV, SB>(cur * ST_TILE + r, v)], erow[r][v]);
-        }
-        wave_lds_sync();
-
-        // ---- phase 3: one atomic update of sigma per move and vector
-        for (int slot = lane; slot < deg; slot += 64) {
-            const double s = (rinf[slot] & 1) ? -0.5 : 0.5;
-            const int64_t t = tgt[slot];
+                for (int v = 0; v < NV; ++v) {
+                    erow[r][v] = V::mad(g[r], dcol[v], erow[r][v]);
+                    ecol[v] = V::cmad(g[r], drow[r][v], ecol[v]);
+                }
+            if (offdiag) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                if (v < n_vec)
-                    V64::atomic_add(&sigma[(int64_t)v * nd + t], V64::scale(V::to64(esh[st_idx<NV, SB>(slot, v)]), s));
+                for (int v = 0; v < NV; ++v) V::lds_add(&esh[st_idx<NV, SB>(s, v)], ecol[v]);
+            }
         }
-        wave_lds_sync();  // the next determinant reuses this wavefront's LDS slice
+        if (++bp == nb) {
+            ++b;
+            bp = b;
+        }
+    }
+    if (cur >= 0) {
+#pragma unroll
+        for (int r = 0; r < ST_TILE; ++r)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) V::lds_add(&esh[st_idx<NV, SB>(cur * ST_TILE + r, v)], erow[r][v]);
+    }
+    wave_lds_sync();
+
+    // ---- phase 3: one atomic update of sigma per move and vector
+    for (int slot = lane; slot < deg; slot += 64) {
+        const double s = (rinf[slot] & 1) ? -0.5 : 0.5;
+        const int64_t t = tgt[slot];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (v < n_vec)
+                V64::atomic_add(&sigma[(int64_t)v * nd + t], V64::scale(V::to64(esh[st_idx<NV, SB>(slot, v)]), s));
+    }
+    wave_lds_sync();  // the next determinant reuses this wavefront's LDS slice
+}
+
+template <bool CPLX, bool F32, int NV>
+__global__ __launch_bounds__(256) void k_sigma_symtile(DevSpace S, const typename PT<CPLX, F32>::T* __restrict__ gT,
+                                                      const typename PT<CPLX, F32>::T* __restrict__ hp,
+                                                      const typename VT<CPLX>::T* __restrict__ c,
+                                                      typename VT<CPLX>::T* __restrict__ sigma, int n_vec,
+                                                      int deg_cap) {
+    using T = typename PT<CPLX, F32>::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const size_t slice = (size_t)2 * st_elems<NV, (int)sizeof(T)>(deg_cap) * sizeof(T) + (size_t)deg_cap * 16;
+    unsigned char* base = smem + (size_t)wid * slice;
+    const int64_t total = S.sp.nwork_dets;
+    const int64_t nw = (int64_t)gridDim.x * wpb;
+    for (int64_t J = (int64_t)blockIdx.x * wpb + wid; J < total; J += nw)
+        symtile_det<CPLX, F32, NV>(S, gT, hp, c, sigma, n_vec, deg_cap, base, lane, J);
+}
+
+// Several sigma problems in one launch: descriptor d covers the global
+// determinant range [jbegin[d], jbegin[d+1]) of the combined grid.
+template <bool CPLX, bool F32>
+__global__ __launch_bounds__(256) void k_sigma_symtile_multi(const SigmaDesc* __restrict__ desc, int ndesc,
+                                                            const int64_t* __restrict__ jbegin, int deg_cap) {
+    using T = typename PT<CPLX, F32>::T;
+    using T64 = typename VT<CPLX>::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const size_t slice = (size_t)2 * st_elems<2, (int)sizeof(T)>(deg_cap) * sizeof(T) + (size_t)deg_cap * 16;
+    unsigned char* base = smem + (size_t)wid * slice;
+    const int64_t total = jbegin[ndesc];
+    const int64_t nw = (int64_t)gridDim.x * wpb;
+    for (int64_t J = (int64_t)blockIdx.x * wpb + wid; J < total; J += nw) {
+        const int q = find_segment(jbegin, ndesc, J);
+        const SigmaDesc& D = desc[q];
+        symtile_det<CPLX, F32, 2>(D.S, (const T*)D.gT, (const T*)D.hp, (const T64*)D.c, (T64*)D.sigma, D.n_vec,
+                                  deg_cap, base, lane, J - jbegin[q]);
     }
 }
 
@@ -266,6 +300,46 @@ hipError_t launch_sigma_symtile(const DevSpace& S, int deg_max, bool cplx, bool 
                    : launch_sym_all<true, false>(S, deg_max, gT, hp, c, sigma, n_vec, st);
     return f32 ? launch_sym_all<false, true>(S, deg_max, gT, hp, c, sigma, n_vec, st)
                : launch_sym_all<false, false>(S, deg_max, gT, hp, c, sigma, n_vec, st);
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_fill_zero_multi(const SigmaDesc* __restrict__ desc, int ndesc) {
+    using T64 = typename VT<CPLX>::T;
+    for (int q = 0; q < ndesc; ++q) {
+        T64* x = (T64*)desc[q].sigma;
+        const int64_t n = desc[q].S.sp.ndets * desc[q].n_vec;
+        for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+            x[e] = VT<CPLX>::zero();
+    }
+}
+
+hipError_t launch_sigma_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
+                              int deg_max, bool cplx, bool f32, hipStream_t st) {
+    const int sb = f32 ? (cplx ? 8 : 4) : (cplx ? 16 : 8);
+    const size_t per_wave = symtile_slice_bytes(deg_max, 2, sb);
+    int wpb = 4;
+    while (wpb > 1 && per_wave * wpb > 48 * 1024) wpb >>= 1;
+    const size_t lds = per_wave * wpb;
+    int64_t blocks = std::min<int64_t>((total + wpb - 1) / wpb, 256 * 64);
+    if (blocks < 1) blocks = 1;
+    if (cplx) {
+        hipLaunchKernelGGL(k_fill_zero_multi<true>, dim3(4096), dim3(256), 0, st, desc_dev, ndesc);
+        if (f32)
+            hipLaunchKernelGGL((k_sigma_symtile_multi<true, true>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st,
+                               desc_dev, ndesc, jbegin_dev, deg_max);
+        else
+            hipLaunchKernelGGL((k_sigma_symtile_multi<true, false>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st,
+                               desc_dev, ndesc, jbegin_dev, deg_max);
+    } else {
+        hipLaunchKernelGGL(k_fill_zero_multi<false>, dim3(4096), dim3(256), 0, st, desc_dev, ndesc);
+        if (f32)
+            hipLaunchKernelGGL((k_sigma_symtile_multi<false, true>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st,
+                               desc_dev, ndesc, jbegin_dev, deg_max);
+        else
+            hipLaunchKernelGGL((k_sigma_symtile_multi<false, false>), dim3((unsigned)blocks), dim3(64 * wpb), lds,
+                               st, desc_dev, ndesc, jbegin_dev, deg_max);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace stp

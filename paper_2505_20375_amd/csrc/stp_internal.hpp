@@ -99,4 +99,17 @@ struct Sigma2eSched {
     int32_t max_nj;    // largest count
 };
 
+// One problem of a grouped sigma launch (the request server): its space,
+// integrals (FP64, or FP32 copies for the FP32 contraction), input vectors
+// and output (n_vec <= 2 vectors, [n_vec][n_dets]).
+struct SigmaDesc {
+    DevSpace S;
+    const void* gT;
+    const void* hp;
+    const void* c;
+    void* sigma;
+    int32_t n_vec;
+    int32_t pad;
+};
+
 }  // namespace stp

@@ -102,25 +102,34 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_ev = ev0.elapsed_time(ev1)
-    n2, t2 = ctx.kernel_time("sigma2e")
-    n1, t1 = ctx.kernel_time("sigma1e")
+    n2, t2 = ctx.kernel_time("sigma")
     ctx.profile(False)
     ms_per_step = ms_ev / args.steps
     value = info.nnz_h * n_vec / (ms_per_step * 1e-3)
     log("sigma step: %.3f ms (events), %.3f ms (wall)" % (ms_per_step, wall * 1e3 / args.steps))
 
-    # roofline of the dominant kernel (the fused one- and two-electron sigma
-    # pass): algorithmic FP64 flops per launch = 8 (W1 + W2) n_vec
+    # roofline of the dominant kernel, the one-pass sigma kernel in use.  Pair
+    # kernel: 8 Wp n_vec flop per launch (Wp = sum over the (N-2)-electron
+    # intermediates of deg^2 complex multiply-adds, one- and two-electron
+    # parts together); the one-move form of Eq. sigmaL1e/2e needs
+    # 8 (W1 + W2) n_vec for the same sigma, reported beside it.
     W1, W2, n_inter, max_deg = ctx.work_counts()
-    flops = 8.0 * (W1 + W2) * n_vec
+    Wp, n_pair, max_pdeg = ctx.pair_counts()
+    kname = ctx.sigma_kernel()
+    flops_paper = 8.0 * (W1 + W2) * n_vec
+    flops = 8.0 * Wp * n_vec if kname == "pair" else flops_paper
     avg2 = t2 / max(n2, 1)
     achieved = flops / (avg2 * 1e-3) / 1e12
-    roof = {"kernel": "k_sigma_symtile (fused 1e + 2e sigma, FP64)", "bound": "alu",
-            "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": _traffic(n_vec),
+    achieved_paper = flops_paper / (avg2 * 1e-3) / 1e12
+    roof = {"kernel": "k_sigma_pair (one pass: pair-resolved 1e + 2e sigma, FP64)" if kname == "pair"
+            else "k_sigma_symtile (fused 1e + 2e sigma, FP64)",
+            "bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": _traffic(n_vec, kname),
             "avg_launch_ms": round(avg2, 4), "launches": n2, "flops_per_launch": flops,
             "algorithmic_bytes_per_launch": 2 * n_vec * n * 16,
-            "separate_sigma1e_avg_ms": round(t1 / max(n1, 1), 4)}
+            "paper_formulation_flops_per_launch": flops_paper,
+            "paper_formulation_equiv_tflops": round(achieved_paper, 3),
+            "frac_paper_formulation": round(achieved_paper / FP64_PEAK_TFLOPS, 4)}
 
     res = {
         "metric": "determinant-updates/s in H.c sigma",
@@ -175,32 +184,35 @@ def main():
     print(json.dumps(res))
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sigma_symtile_c2_traffic.txt")
-KERNEL_SOURCES = ["sigma_sym.hip", "stp_device.hpp", "stp_internal.hpp"]
+TRAFFIC_FILES = {"pair": os.path.join(ROOT, "profiles", "sigma_pair_c2_traffic.txt"),
+                 "tile": os.path.join(ROOT, "profiles", "sigma_symtile_c2_traffic.txt")}
+KERNEL_SOURCES = {"pair": ["sigma_pair.hip", "symtile.hpp", "stp_device.hpp", "stp_internal.hpp"],
+                  "tile": ["sigma_sym.hip", "stp_device.hpp", "stp_internal.hpp"]}
 
 
-def kernel_source_hash():
+def kernel_source_hash(kname="pair"):
     import hashlib
     hsh = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kname]:
         with open(os.path.join(ROOT, "paper_2505_20375_amd", "csrc", f), "rb") as fh:
             hsh.update(fh.read())
     return hsh.hexdigest()[:16]
 
 
-def _traffic(n_vec):
+def _traffic(n_vec, kname="pair"):
     """HBM bytes per launch of the sigma kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the factor the
     same counter reads on a plain copy of known size), or None when the kernel
     sources changed after the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES.get(kname)
+    if path is None or not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith(" "):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != kernel_source_hash() or int(kv.get("n_vec", 0)) != n_vec:
+    if kv.get("source_sha256") != kernel_source_hash(kname) or int(kv.get("n_vec", 0)) != n_vec:
         return None
     return float(kv["traffic_bytes_per_launch"])
 

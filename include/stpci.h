@@ -126,12 +126,32 @@ stpci_status stpci_category(const stpci_ctx* ctx, int cat, int* occ, int64_t* of
 /* Global occupation bitstring of the determinant at vector address addr. */
 stpci_status stpci_address_to_det(const stpci_ctx* ctx, int64_t addr, uint64_t* occ_bits);
 
-/* sigma_dev = H c_dev for n_vec vectors (Eq. sigmaL: one-electron part
- * Eq. sigmaL1e plus two-electron part Eq. sigmaL2e, the latter resolved over
- * every intermediate determinant one move away from the space, including
- * occupations outside the windows).  Device pointers, [n_vec][n_dets] in the
- * scalar type of the integrals; c_dev and sigma_dev must not overlap.
- * Asynchronous on the context stream. */
+/* Pair-resolved work of one sigma build for one vector (the default kernel):
+ * the two-electron operator, with the one-electron part folded in, resolved
+ * over (N-2)-electron intermediates K' (the resolution of Eq. sigmaL2e taken
+ * two electrons down): w_pair = sum_K' deg(K')^2 multiply-adds, deg = pair
+ * creations p < r from K' into the space; n_pair_intermediate = number of K';
+ * max_pair_deg = largest deg.  Zero for N < 2.  Any output may be NULL. */
+stpci_status stpci_pair_counts(const stpci_ctx* ctx, double* w_pair, int64_t* n_pair_intermediate,
+                               int* max_pair_deg);
+
+/* Select the sigma kernel used from the next device call on: "pair" (pair
+ * intermediates, the default where N >= 2 and the largest pair degree fits the
+ * per-wavefront LDS slice), "tile" (one-move intermediates of Eq. sigmaL2e,
+ * Hermitian tiles, one- and two-electron parts fused), "rowtile", "wave" and
+ * "simple" (earlier one-move forms), or "auto".  All compute the same sigma;
+ * a kernel that cannot handle the space makes the next device call fail with
+ * STPCI_EINVAL.  stpci_sigma_kernel reports the kernel in use after the first
+ * device call (static string). */
+stpci_status stpci_set_sigma_kernel(stpci_ctx* ctx, const char* name);
+stpci_status stpci_sigma_kernel(const stpci_ctx* ctx, const char** name);
+
+/* sigma_dev = H c_dev for n_vec vectors, H including e_core (Eq. sigmaL:
+ * one-electron part Eq. sigmaL1e plus two-electron part Eq. sigmaL2e, the
+ * latter resolved over every intermediate one or two electrons away from the
+ * space, including occupations outside the windows).  Device pointers,
+ * [n_vec][n_dets] in the scalar type of the integrals; c_dev and sigma_dev
+ * must not overlap.  Asynchronous on the context stream. */
 stpci_status stpci_sigma(stpci_ctx* ctx, const void* c_dev, void* sigma_dev, int n_vec, stpci_precision prec);
 
 /* diag_dev[i] = <i|H|i> (real, n_dets doubles).  The solver itself never

@@ -14,9 +14,9 @@
  *    than max_active are active and their footprints fit mem_budget_bytes
  *    (admission stops at the first request that does not fit, so later ones
  *    never overtake it); then runs the pending sigma products of all active
- *    requests as grouped launches, one per (scalar type, contraction
- *    precision) class, whose work items are the intermediate determinants of
- *    every request in the group; then advances each active request by one
+ *    requests as grouped launches, one per (kernel family, scalar type,
+ *    contraction precision) class, whose work items are the intermediate
+ *    determinants of every request in the group; then advances each active request by one
  *    Davidson iteration and retires the finished ones, releasing their
  *    device memory.  A request's vectors stay on the device from admission
  *    to retirement.

@@ -26,6 +26,15 @@ stpci_status stpci_test_heev(int n, const double* A, double* w, double* V);
 stpci_status stpci_test_moves(const stpci_ctx* ctx, int64_t max_dets_per_cat, int64_t* n_checked,
                               int64_t* n_bad);
 
+/* The same for the pair kernel: for up to max_dets_per_cat (N-2)-electron
+ * intermediates K' of every pair category, run the kernel's pair-slot
+ * arithmetic on the host and verify that every slot's target address holds
+ * K' + {p, r} (p < r both empty in K', the pair the slot reports) with the
+ * sign of a+_p a+_r |K'> from the global occupation bits.  n_checked: slots
+ * checked; n_bad: slots that fail. */
+stpci_status stpci_test_pairs(const stpci_ctx* ctx, int64_t max_dets_per_cat, int64_t* n_checked,
+                              int64_t* n_bad);
+
 #ifdef __cplusplus
 }
 #endif

@@ -74,6 +74,10 @@ _SIGS = {
     "stpci_kernel_time": ([_P, ctypes.c_char_p, _I64P, _DP], _I),
     "stpci_test_heev": ([_I, _P, _P, _P], _I),
     "stpci_test_moves": ([_P, _I64, _I64P, _I64P], _I),
+    "stpci_test_pairs": ([_P, _I64, _I64P, _I64P], _I),
+    "stpci_pair_counts": ([_P, _DP, _I64P, _IP], _I),
+    "stpci_set_sigma_kernel": ([_P, ctypes.c_char_p], _I),
+    "stpci_sigma_kernel": ([_P, ctypes.POINTER(ctypes.c_char_p)], _I),
     "stpci_server_create": ([ctypes.POINTER(_P), _I, _P, _I64, _I], _I),
     "stpci_server_destroy": ([_P], None),
     "stpci_server_last_error": ([_P], ctypes.c_char_p),
@@ -133,9 +137,9 @@ class Context:
         self.cplx = True
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.stpci_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()
@@ -220,6 +224,28 @@ class Context:
         self._check(_lib.stpci_test_moves(self._h, int(max_dets_per_cat), ctypes.byref(n), ctypes.byref(b)))
         return n.value, b.value
 
+    def test_pairs(self, max_dets_per_cat=1 << 40):
+        """Host check of the pair kernel's slot arithmetic: (slots checked, slots wrong)."""
+        n, b = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.stpci_test_pairs(self._h, int(max_dets_per_cat), ctypes.byref(n), ctypes.byref(b)))
+        return n.value, b.value
+
+    def pair_counts(self):
+        """(sum deg^2 over pair intermediates, number of pair intermediates, largest pair degree)."""
+        w, n, d = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int()
+        self._check(_lib.stpci_pair_counts(self._h, ctypes.byref(w), ctypes.byref(n), ctypes.byref(d)))
+        return w.value, n.value, d.value
+
+    def set_sigma_kernel(self, name):
+        """Select the sigma kernel ("pair", "tile", "rowtile", "wave", "simple" or "auto")."""
+        self._check(_lib.stpci_set_sigma_kernel(self._h, name.encode()))
+
+    def sigma_kernel(self):
+        """Name of the sigma kernel in use (after the first device call)."""
+        p = ctypes.c_char_p()
+        self._check(_lib.stpci_sigma_kernel(self._h, ctypes.byref(p)))
+        return p.value.decode()
+
     def dav_stats(self):
         """(FP64 sigma vectors, FP32 sigma vectors) spent by the last Davidson run."""
         a, b = ctypes.c_int(), ctypes.c_int()
@@ -266,9 +292,9 @@ class Server:
         self._k = {}
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.stpci_server_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()

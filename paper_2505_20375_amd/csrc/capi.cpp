@@ -20,7 +20,7 @@ stpci_ctx::~stpci_ctx() {
             (void)hipEventDestroy(e.a);
             (void)hipEventDestroy(e.b);
         }
-        for (DevBuf* b : {&d_gT32, &d_hp32, &d_s2blocks, &d_ygroup, &d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
+        for (DevBuf* b : {&d_pcats, &d_pwork, &d_pslot, &d_pA, &d_pA32, &d_gT32, &d_hp32, &d_s2blocks, &d_ygroup, &d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
                           &d_hp, &d_gT, &d_hd, &d_JK, &d_V, &d_W, &d_X, &d_R, &d_T, &d_partial, &d_small, &d_topv,
                           &d_topi})
             b->free_();
@@ -68,6 +68,63 @@ static stpci_status upload(stpci_ctx* c, DevBuf& b, const std::vector<T>& v, con
     return STPCI_OK;
 }
 
+// Pair-pair table of the pair kernel: A[(p,r),(q,s)] = g'_pqrs - g'_psrq for
+// p < r, q < s, g'_pqrs = (pq|rs) + (h_pq d_rs + d_pq h_rs) / (N - 1), stored
+// as pA[pair(q,s) * npairs + pair(p,r)], pair(p,r) = r (r - 1) / 2 + p.
+static void build_pair_table(stpci_ctx* c) {
+    const int M = c->M, N = c->hs.sp.N;
+    const int w = c->cplx ? 2 : 1;
+    const size_t NP = (size_t)M * (M - 1) / 2;
+    const double f = 1.0 / (double)(N - 1);
+    auto gp = [&](int p, int q, int r, int s, int k) {
+        double v = c->g[((((size_t)p * M + q) * M + r) * M + s) * w + k];
+        if (r == s) v += f * c->h[((size_t)p * M + q) * w + k];
+        if (p == q) v += f * c->h[((size_t)r * M + s) * w + k];
+        return v;
+    };
+    c->pA.assign(NP * NP * w, 0.0);
+    for (int r = 1; r < M; ++r)
+        for (int p = 0; p < r; ++p) {
+            const size_t P = (size_t)r * (r - 1) / 2 + p;
+            for (int s = 1; s < M; ++s)
+                for (int q = 0; q < s; ++q) {
+                    const size_t Q = (size_t)s * (s - 1) / 2 + q;
+                    for (int k = 0; k < w; ++k) c->pA[(Q * NP + P) * w + k] = gp(p, q, r, s, k) - gp(p, s, r, q, k);
+                }
+        }
+    c->pA32.assign(c->pA.begin(), c->pA.end());
+}
+
+// Sigma kernel prepare() selects for this context.
+int select_kernel(const stpci_ctx* c) {
+    const HostSpace& H = c->hs;
+    const bool ok[5] = {H.max_deg <= MAXDEG, true, sigma_wave_supported(H.max_deg), symtile_supported(H.max_deg, c->cplx),
+                        pair_supported(H.sp.N, H.pmax_deg, c->cplx)};
+    if (c->kernel_req >= 0) return ok[c->kernel_req] ? c->kernel_req : -1;
+    return ok[4] ? 4 : (ok[3] ? 3 : 1);
+}
+
+// Device bytes of the tables and integrals prepare() (and, for FP32, ensure32())
+// uploads; mirrors the uploads below.
+int64_t device_table_bytes(const stpci_ctx* c, bool f32) {
+    const HostSpace& H = c->hs;
+    const int k = select_kernel(c);
+    const int64_t sb = (int64_t)scalar_bytes(c);
+    int64_t b = (int64_t)(H.cats.size() * sizeof(Cat) + H.tabs.size() * sizeof(StrTab));
+    b += (int64_t)(H.bits.size() + H.ann.size() + H.cre.size() + H.work_cat.size()) * 4;
+    b += (int64_t)(H.work_begin.size() + H.space_begin.size()) * 8;
+    b += (int64_t)(c->hd.size() + c->JK.size()) * 8;
+    const int64_t M = c->M, NP = M * (M - 1) / 2;
+    if (k == 4) {
+        b += (int64_t)(H.pcats.size() * sizeof(PairCat) + H.pwork_begin.size() * 8 + H.pslot.size() * 4);
+        b += NP * NP * sb * (f32 ? 3 : 2) / 2;
+    } else {
+        b += (M * M + M * M * M * M) * sb * (f32 ? 3 : 2) / 2;
+        if (k == 1) b += H.sp.nwork_dets * 16 + M * 4;  // row-tile schedule (upper bound)
+    }
+    return b;
+}
+
 stpci_status prepare(stpci_ctx* c) {
     if (c->host_only) return set_err(c, STPCI_ESTATE, "host-only context has no device");
     if (!c->have_ints) return set_err(c, STPCI_ESTATE, "integrals not set");
@@ -89,19 +146,23 @@ stpci_status prepare(stpci_ctx* c) {
     if ((s = upload(c, c->d_work_cat, H.work_cat, "work categories"))) return s;
     if ((s = upload(c, c->d_work_begin, H.work_begin, "work offsets"))) return s;
     if ((s = upload(c, c->d_space_begin, H.space_begin, "space offsets"))) return s;
-    if ((s = upload(c, c->d_hp, c->hprime, "h'"))) return s;
-    if ((s = upload(c, c->d_gT, c->gT, "two-electron integrals"))) return s;
     if ((s = upload(c, c->d_hd, c->hd, "diagonal integrals"))) return s;
     if ((s = upload(c, c->d_JK, c->JK, "Coulomb-exchange integrals"))) return s;
-    // schedule of the tiled two-electron kernel
+    // sigma kernel: the requested one, else pair intermediates where they apply
     {
-        const char* kv = getenv("STPCI_SIGMA2E");
-        c->s2_kernel = 3;
-        if (kv && !strcmp(kv, "v0")) c->s2_kernel = 0;
-        if (kv && !strcmp(kv, "tiled")) c->s2_kernel = 1;
-        if (kv && !strcmp(kv, "wave")) c->s2_kernel = 2;
-        if (c->s2_kernel == 3 && !symtile_supported(H.max_deg, c->cplx)) c->s2_kernel = 1;
-        if (c->s2_kernel == 2 && !sigma_wave_supported(H.max_deg)) c->s2_kernel = 1;
+        const int k = select_kernel(c);
+        if (k < 0) return set_err(c, STPCI_EINVAL, "the requested sigma kernel does not support this space");
+        c->s2_kernel = k;
+    }
+    if (c->s2_kernel == 4) {
+        build_pair_table(c);
+        if ((s = upload(c, c->d_pcats, H.pcats, "pair categories"))) return s;
+        if ((s = upload(c, c->d_pwork, H.pwork_begin, "pair offsets"))) return s;
+        if ((s = upload(c, c->d_pslot, H.pslot, "pair slots"))) return s;
+        if ((s = upload(c, c->d_pA, c->pA, "pair-pair integrals"))) return s;
+    } else {
+        if ((s = upload(c, c->d_hp, c->hprime, "h'"))) return s;
+        if ((s = upload(c, c->d_gT, c->gT, "two-electron integrals"))) return s;
     }
     if (c->s2_kernel == 1) {
         int ngroups = 0;
@@ -150,6 +211,9 @@ stpci_status prepare(stpci_ctx* c) {
     D.work_cat = (const int32_t*)c->d_work_cat.p;
     D.work_begin = (const int64_t*)c->d_work_begin.p;
     D.space_begin = (const int64_t*)c->d_space_begin.p;
+    D.pcats = (const PairCat*)c->d_pcats.p;
+    D.pwork_begin = (const int64_t*)c->d_pwork.p;
+    D.pslot = (const uint32_t*)c->d_pslot.p;
     c->prepared = true;
     return STPCI_OK;
 }
@@ -170,50 +234,62 @@ static void record(stpci_ctx* c, int kind, bool start) {
 stpci_status ensure32(stpci_ctx* c) {
     if (c->have32) return STPCI_OK;
     stpci_status s;
-    if ((s = upload(c, c->d_gT32, c->gT32, "FP32 two-electron integrals"))) return s;
-    if ((s = upload(c, c->d_hp32, c->hp32, "FP32 h'"))) return s;
+    if (c->s2_kernel == 4) {
+        if ((s = upload(c, c->d_pA32, c->pA32, "FP32 pair-pair integrals"))) return s;
+    } else {
+        if ((s = upload(c, c->d_gT32, c->gT32, "FP32 two-electron integrals"))) return s;
+        if ((s = upload(c, c->d_hp32, c->hp32, "FP32 h'"))) return s;
+    }
     c->have32 = true;
     return STPCI_OK;
 }
 
 stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, stpci_precision prec) {
     if (prec != STPCI_FP64 && prec != STPCI_FP32) return set_err(c, STPCI_EINVAL, "unsupported sigma precision");
-    if (prec == STPCI_FP32) {
+    const bool f32 = prec == STPCI_FP32;
+    hipError_t e;
+    if (f32) {
         // category-block contraction in FP32 (FP32 accumulation); sigma accumulated in FP64
-        if (c->s2_kernel != 3) return set_err(c, STPCI_EINVAL, "FP32 contraction needs the tile kernel");
+        if (c->s2_kernel < 3) return set_err(c, STPCI_EINVAL, "the FP32 contraction needs a tile kernel");
         stpci_status s = ensure32(c);
         if (s) return s;
-        record(c, 2, true);
-        hipError_t e = launch_sigma_symtile(c->dev, c->hs.max_deg, c->cplx, true, c->d_gT32.p, c->d_hp32.p, cin,
-                                            sout, n_vec, c->stream);
-        record(c, 2, false);
-        return e == hipSuccess ? STPCI_OK : hip_check(c, e, "FP32 sigma launch");
     }
-    if (c->hs.max_deg > MAXDEG) return set_err(c, STPCI_EINVAL, "a determinant has more moves than MAXDEG");
-    hipError_t e;
-    if (c->s2_kernel >= 2) {
-        // one pass: zero sigma, then the fused one- and two-electron kernel
+    const int kind = f32 ? 2 : 1;
+    if (c->s2_kernel == 4) {
+        record(c, kind, true);
+        e = launch_sigma_pair(c->dev, c->hs.pmax_deg, c->cplx, f32, f32 ? c->d_pA32.p : c->d_pA.p, cin, sout, n_vec,
+                              c->e_core, c->stream);
+        record(c, kind, false);
+        return e == hipSuccess ? STPCI_OK : hip_check(c, e, "sigma launch");
+    }
+    if (c->s2_kernel == 3) {
+        record(c, kind, true);
+        e = launch_sigma_symtile(c->dev, c->hs.max_deg, c->cplx, f32, f32 ? c->d_gT32.p : c->d_gT.p,
+                                 f32 ? c->d_hp32.p : c->d_hp.p, cin, sout, n_vec, c->e_core, c->stream);
+        record(c, kind, false);
+        return e == hipSuccess ? STPCI_OK : hip_check(c, e, "sigma launch");
+    }
+    if (c->s2_kernel == 2) {
         record(c, 1, true);
-        if (c->s2_kernel == 3)
-            e = launch_sigma_symtile(c->dev, c->hs.max_deg, c->cplx, false, c->d_gT.p, c->d_hp.p, cin, sout, n_vec,
-                                     c->stream);
-        else
-            e = launch_sigma_wave(c->dev, c->hs.max_deg, c->cplx, c->d_gT.p, c->d_hp.p, cin, sout, n_vec, c->stream);
+        e = launch_sigma_wave(c->dev, c->hs.max_deg, c->cplx, c->d_gT.p, c->d_hp.p, cin, sout, n_vec, c->stream);
         record(c, 1, false);
-        if (e != hipSuccess) return hip_check(c, e, "sigma launch");
-        return STPCI_OK;
+    } else {
+        record(c, 0, true);
+        e = launch_sigma1e(c->dev, c->cplx, c->d_hp.p, cin, sout, n_vec, c->stream);
+        record(c, 0, false);
+        if (e != hipSuccess) return hip_check(c, e, "sigma1e launch");
+        record(c, 1, true);
+        if (c->s2_kernel == 0)
+            e = launch_sigma2e_v0(c->dev, c->cplx, c->d_gT.p, cin, sout, n_vec, c->stream);
+        else
+            e = launch_sigma2e_tiled(c->dev, c->s2, c->cplx, c->d_gT.p, cin, sout, n_vec, c->stream);
+        record(c, 1, false);
     }
-    record(c, 0, true);
-    e = launch_sigma1e(c->dev, c->cplx, c->d_hp.p, cin, sout, n_vec, c->stream);
-    record(c, 0, false);
-    if (e != hipSuccess) return hip_check(c, e, "sigma1e launch");
-    record(c, 1, true);
-    if (c->s2_kernel == 0)
-        e = launch_sigma2e_v0(c->dev, c->cplx, c->d_gT.p, cin, sout, n_vec, c->stream);
-    else
-        e = launch_sigma2e_tiled(c->dev, c->s2, c->cplx, c->d_gT.p, cin, sout, n_vec, c->stream);
-    record(c, 1, false);
-    if (e != hipSuccess) return hip_check(c, e, "sigma2e launch");
+    if (e != hipSuccess) return hip_check(c, e, "sigma launch");
+    if (c->e_core != 0.0) {
+        e = launch_axpy_core(c->cplx, sout, cin, c->e_core, c->hs.sp.ndets * n_vec, c->stream);
+        if (e != hipSuccess) return hip_check(c, e, "e_core term");
+    }
     return STPCI_OK;
 }
 
@@ -431,6 +507,25 @@ stpci_status stpci_test_moves(const stpci_ctx* c, int64_t max_dets_per_cat, int6
     return STPCI_OK;
 }
 
+stpci_status stpci_test_pairs(const stpci_ctx* c, int64_t max_dets_per_cat, int64_t* n_checked, int64_t* n_bad) {
+    if (!c || !n_checked || !n_bad) return STPCI_EINVAL;
+    if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
+    const HostSpace& H = c->hs;
+    DevSpace D{};
+    D.sp = H.sp;
+    D.cats = H.cats.data();
+    D.tabs = H.tabs.data();
+    D.bits = H.bits.data();
+    D.ann = H.ann.data();
+    D.cre = H.cre.data();
+    D.space_begin = H.space_begin.data();
+    D.pcats = H.pcats.data();
+    D.pwork_begin = H.pwork_begin.data();
+    D.pslot = H.pslot.data();
+    *n_bad = check_pairs_host(D, max_dets_per_cat, n_checked, host_to_bits, &H);
+    return STPCI_OK;
+}
+
 stpci_status stpci_category(const stpci_ctx* c, int cat, int* occ, int64_t* offset, int64_t* n_dets) {
     if (!c) return STPCI_EINVAL;
     if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
@@ -491,7 +586,7 @@ stpci_status stpci_kernel_time(stpci_ctx* c, const char* name, int64_t* launches
     if (!c || !name) return STPCI_EINVAL;
     int kind = -1;
     if (!std::strcmp(name, "sigma1e")) kind = 0;
-    if (!std::strcmp(name, "sigma2e")) kind = 1;
+    if (!std::strcmp(name, "sigma2e") || !std::strcmp(name, "sigma")) kind = 1;
     if (!std::strcmp(name, "sigma_fp32")) kind = 2;
     if (kind < 0) return set_err(c, STPCI_EINVAL, "unknown kernel name");
     if (c->host_only) return set_err(c, STPCI_ESTATE, "host-only context");
@@ -509,6 +604,41 @@ stpci_status stpci_kernel_time(stpci_ctx* c, const char* name, int64_t* launches
     }
     if (launches) *launches = n;
     if (total_ms) *total_ms = t;
+    return STPCI_OK;
+}
+
+stpci_status stpci_pair_counts(const stpci_ctx* c, double* w_pair, int64_t* n_pair_inter, int* max_pair_deg) {
+    if (!c) return STPCI_EINVAL;
+    if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
+    if (w_pair) *w_pair = c->hs.Wp;
+    if (n_pair_inter) *n_pair_inter = c->hs.sp.npwork_dets;
+    if (max_pair_deg) *max_pair_deg = c->hs.pmax_deg;
+    return STPCI_OK;
+}
+
+stpci_status stpci_set_sigma_kernel(stpci_ctx* c, const char* name) {
+    if (!c || !name) return STPCI_EINVAL;
+    static const char* names[5] = {"simple", "rowtile", "wave", "tile", "pair"};
+    int k = -1;
+    if (!std::strcmp(name, "auto")) k = -2;
+    for (int i = 0; i < 5; ++i)
+        if (!std::strcmp(name, names[i])) k = i;
+    if (k == -1) return set_err(c, STPCI_EINVAL, "unknown sigma kernel name");
+    c->kernel_req = (k == -2) ? -1 : k;
+    // device copies depend on the kernel: rebuild them on the next device call
+    for (DevBuf* b : {&c->d_pcats, &c->d_pwork, &c->d_pslot, &c->d_pA, &c->d_pA32, &c->d_gT32, &c->d_hp32,
+                      &c->d_s2blocks, &c->d_ygroup, &c->d_hp, &c->d_gT})
+        if (!c->host_only) b->free_();
+    c->have32 = false;
+    c->prepared = false;
+    return STPCI_OK;
+}
+
+stpci_status stpci_sigma_kernel(const stpci_ctx* c, const char** name) {
+    if (!c || !name) return STPCI_EINVAL;
+    static const char* names[5] = {"simple", "rowtile", "wave", "tile", "pair"};
+    if (!c->prepared) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "no device call made yet");
+    *name = names[c->s2_kernel];
     return STPCI_OK;
 }
 

@@ -63,6 +63,8 @@ struct stpci_ctx {
     std::vector<double> gT;        // gT[(y*M + x)*M*M + (y'*M + x')] = (x' y' | y x)
     std::vector<double> hd, JK;    // Re h_ii ; (ii|jj) - (ij|ji)
     std::vector<float> gT32, hp32; // FP32 copies for the FP32 contraction
+    std::vector<double> pA;        // pair-pair table of the pair kernel (built with the space)
+    std::vector<float> pA32;
 
     // space
     bool have_space = false;
@@ -74,12 +76,16 @@ struct stpci_ctx {
     stp::DevBuf d_hp, d_gT, d_hd, d_JK;
     stp::DevBuf d_gT32, d_hp32;
     bool have32 = false;
+    stp::DevBuf d_pcats, d_pwork, d_pslot, d_pA, d_pA32;
+    int kernel_req = -1;   // requested sigma kernel (stpci_set_sigma_kernel), -1: automatic
     stp::DevSpace dev{};
 
     // schedule of the tiled two-electron kernel
     stp::DevBuf d_s2blocks, d_ygroup;
     stp::Sigma2eSched s2{};
-    int s2_kernel = 2;   // 0: reference per-determinant kernel, 1: tiled, 2: fused wavefront-per-determinant
+    // sigma kernel: 0 simple per-determinant, 1 row-tiled, 2 wavefront, 3 Hermitian tiles over
+    // one-move intermediates, 4 Hermitian tiles over pair intermediates
+    int s2_kernel = 4;
 
     // Davidson workspace
     stp::DevBuf d_V, d_W, d_X, d_R, d_T, d_partial, d_small, d_topv, d_topi;
@@ -102,6 +108,8 @@ stpci_status prepare(stpci_ctx* c);
 stpci_status ensure(stpci_ctx* c, DevBuf& b, size_t bytes, const char* what);
 stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, stpci_precision prec);
 stpci_status ensure32(stpci_ctx* c);  // upload the FP32 integral copies once
+int select_kernel(const stpci_ctx* c);
+int64_t device_table_bytes(const stpci_ctx* c, bool f32);
 size_t scalar_bytes(const stpci_ctx* c);
 // step-wise Davidson (davidson.cpp)
 stpci_status dav_begin(stpci_ctx* c, const stpci_dav_opts* o);

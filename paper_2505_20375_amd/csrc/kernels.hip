@@ -427,6 +427,23 @@ hipError_t launch_combine(bool cplx, const void* A, const void* B, int64_t ld, i
     return hipGetLastError();
 }
 
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_axpy_core(typename VT<CPLX>::T* __restrict__ y,
+                                                  const typename VT<CPLX>::T* __restrict__ x, double a, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] = VT<CPLX>::add(y[e], VT<CPLX>::scale(x[e], a));
+}
+
+hipError_t launch_axpy_core(bool cplx, void* sigma, const void* c, double e_core, int64_t n, hipStream_t st) {
+    const int g = grid_for(n, 256, 8192);
+    if (cplx)
+        hipLaunchKernelGGL(k_axpy_core<true>, dim3(g), dim3(256), 0, st, (cd*)sigma, (const cd*)c, e_core, n);
+    else
+        hipLaunchKernelGGL(k_axpy_core<false>, dim3(g), dim3(256), 0, st, (double*)sigma, (const double*)c, e_core,
+                           n);
+    return hipGetLastError();
+}
+
 hipError_t launch_scale(bool cplx, void* x, double s, int64_t n, hipStream_t st) {
     int g = grid_for(n, 256, 8192);
     if (cplx)

@@ -1,4 +1,4 @@
-// Host-side launchers of the HIP kernels (kernels.hip).
+// Host-side launchers of the HIP kernels.
 #pragma once
 #include <hip/hip_runtime_api.h>
 
@@ -20,7 +20,21 @@ bool symtile_supported(int deg_max, bool cplx);
 // sigma = H c in one pass, Hermitian 4x4 tiles per intermediate determinant
 // f32: integrals gT/hp are FP32 (complex FP32 when cplx); c and sigma stay FP64.
 hipError_t launch_sigma_symtile(const DevSpace& S, int deg_max, bool cplx, bool f32, const void* gT, const void* hp,
-                                const void* c, void* sigma, int n_vec, hipStream_t st);
+                                const void* c, void* sigma, int n_vec, double e_core, hipStream_t st);
+// sigma = H c in one pass over the (N-2)-electron pair intermediates; A is the
+// pair-pair table A[(q,s)-pair * npairs + (p,r)-pair] (FP32 when f32)
+bool pair_supported(int n_elec, int deg_max, bool cplx);
+size_t pair_slice_bytes(int deg_max, int nv, int sb);
+hipError_t launch_sigma_pair(const DevSpace& S, int deg_max, bool cplx, bool f32, const void* A, const void* c,
+                             void* sigma, int n_vec, double e_core, hipStream_t st);
+hipError_t launch_sigma_pair_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
+                                   int deg_max, bool cplx, bool f32, hipStream_t st);
+// sigma <- e_core * c (zero when e_core == 0)
+hipError_t launch_fill_init(bool cplx, void* sigma, const void* c, double e_core, int64_t n, hipStream_t st);
+hipError_t launch_fill_init_multi(bool cplx, const SigmaDesc* desc_dev, int ndesc, hipStream_t st);
+// sigma += e_core * c
+hipError_t launch_axpy_core(bool cplx, void* sigma, const void* c, double e_core, int64_t n, hipStream_t st);
+int waves_per_group(size_t per_wave);
 // sigma = H c (one- and two-electron parts) in one pass over the intermediate determinants
 hipError_t launch_sigma_wave(const DevSpace& S, int deg_max, bool cplx, const void* gT, const void* hp,
                              const void* c, void* sigma, int n_vec, hipStream_t st);
@@ -43,5 +57,7 @@ hipError_t launch_scale(bool cplx, void* x, double s, int64_t n, hipStream_t st)
 int64_t check_moves_host(const DevSpace& S, int64_t max_dets_per_cat, int64_t* n_checked,
                          bool (*to_bits)(const void*, int64_t, uint64_t*), const void* user);
 hipError_t launch_unit(bool cplx, void* x, int64_t n, int64_t at, hipStream_t st);
+int64_t check_pairs_host(const DevSpace& S, int64_t max_dets_per_cat, int64_t* n_checked,
+                         bool (*to_bits)(const void*, int64_t, uint64_t*), const void* user);
 
 }  // namespace stp

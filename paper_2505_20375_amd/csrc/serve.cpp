@@ -84,15 +84,7 @@ struct stpci_server {
 // fallback kernel where the tile kernel does not apply, and the Davidson
 // vectors and workspace.
 static int64_t footprint(const stpci_ctx* c, const stpci_dav_opts& o) {
-    const HostSpace& H = c->hs;
-    int64_t b = 0;
-    b += (int64_t)(H.cats.size() * sizeof(Cat) + H.tabs.size() * sizeof(StrTab));
-    b += (int64_t)(H.bits.size() + H.ann.size() + H.cre.size() + H.work_cat.size()) * 4;
-    b += (int64_t)(H.work_begin.size() + H.space_begin.size()) * 8;
-    b += (int64_t)(c->gT.size() + c->hprime.size() + c->hd.size() + c->JK.size()) * 8;
-    if (o.precision == STPCI_FP32) b += (int64_t)(c->gT32.size() + c->hp32.size()) * 4;
-    if (!symtile_supported(H.max_deg, c->cplx)) b += H.sp.nwork_dets * 16 + (int64_t)H.sp.M * 4;
-    return b + dav_device_bytes(c, o);
+    return device_table_bytes(c, o.precision == STPCI_FP32) + dav_device_bytes(c, o);
 }
 
 static stpci_status srv_err(stpci_server* s, stpci_status st, const std::string& m) {
@@ -227,10 +219,9 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
     struct Item {
         int id;
         SigmaDesc d;
-        int deg;
         int64_t nj;
     };
-    std::vector<Item> groups[2][2];
+    std::vector<Item> groups[2][2][2];   // [pair kernel][complex][FP32]
     std::vector<int> solo;
     const std::vector<int> admitted(s->active);  // retire() edits the active list
     for (int id : admitted) {
@@ -242,7 +233,7 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
         if (!dav_pending(q.ctx, &in, &out, &n, &prec)) continue;
         stpci_ctx* c = q.ctx;
         const bool f32 = prec == STPCI_FP32;
-        if (c->s2_kernel != 3) {
+        if (c->s2_kernel < 3) {
             // spaces outside the tile kernel's limits take the context's own path
             stpci_status st = sigma_impl(c, in, out, n, prec);
             if (st) {
@@ -253,26 +244,35 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
             }
             continue;
         }
+        const bool pair = c->s2_kernel == 4;
         const size_t vb = (size_t)c->hs.sp.ndets * scalar_bytes(c);
         for (int v0 = 0; v0 < n; v0 += 2) {
             Item it;
             it.id = id;
             it.d.S = c->dev;
-            it.d.gT = f32 ? c->d_gT32.p : c->d_gT.p;
-            it.d.hp = f32 ? c->d_hp32.p : c->d_hp.p;
+            if (pair) {
+                it.d.gT = f32 ? c->d_pA32.p : c->d_pA.p;
+                it.d.hp = nullptr;
+                it.d.deg = c->hs.pmax_deg;
+                it.nj = c->hs.sp.npwork_dets;
+            } else {
+                it.d.gT = f32 ? c->d_gT32.p : c->d_gT.p;
+                it.d.hp = f32 ? c->d_hp32.p : c->d_hp.p;
+                it.d.deg = c->hs.max_deg;
+                it.nj = c->hs.sp.nwork_dets;
+            }
             it.d.c = (const char*)in + v0 * vb;
             it.d.sigma = (char*)out + v0 * vb;
+            it.d.e_core = c->e_core;
             it.d.n_vec = std::min(2, n - v0);
-            it.d.pad = 0;
-            it.deg = c->hs.max_deg;
-            it.nj = c->hs.sp.nwork_dets;
-            groups[c->cplx ? 1 : 0][f32 ? 1 : 0].push_back(it);
+            groups[pair ? 1 : 0][c->cplx ? 1 : 0][f32 ? 1 : 0].push_back(it);
         }
     }
     std::vector<int> stepped(solo);
+    for (int pk = 0; pk < 2; ++pk)
     for (int cx = 0; cx < 2; ++cx)
         for (int f = 0; f < 2; ++f) {
-            auto& G = groups[cx][f];
+            auto& G = groups[pk][cx][f];
             if (G.empty()) continue;
             std::vector<SigmaDesc> desc;
             std::vector<int64_t> jb(1, 0);
@@ -280,7 +280,7 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
             for (auto& it : G) {
                 desc.push_back(it.d);
                 jb.push_back(jb.back() + it.nj);
-                deg = std::max(deg, it.deg);
+                deg = std::max(deg, it.d.deg);
                 if (stepped.empty() || stepped.back() != it.id) stepped.push_back(it.id);
             }
             stpci_status st = ensure(nullptr, s->d_desc, desc.size() * sizeof(SigmaDesc), "descriptors");
@@ -291,8 +291,11 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
             if (e == hipSuccess)
                 e = hipMemcpyAsync(s->d_jbegin.p, jb.data(), jb.size() * 8, hipMemcpyHostToDevice, s->stream);
             if (e == hipSuccess)
-                e = launch_sigma_multi((const SigmaDesc*)s->d_desc.p, (int)desc.size(), (const int64_t*)s->d_jbegin.p,
-                                       jb.back(), deg, cx == 1, f == 1, s->stream);
+                e = pk ? launch_sigma_pair_multi((const SigmaDesc*)s->d_desc.p, (int)desc.size(),
+                                                 (const int64_t*)s->d_jbegin.p, jb.back(), deg, cx == 1, f == 1,
+                                                 s->stream)
+                       : launch_sigma_multi((const SigmaDesc*)s->d_desc.p, (int)desc.size(),
+                                            (const int64_t*)s->d_jbegin.p, jb.back(), deg, cx == 1, f == 1, s->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // descriptors are reused next launch
             if (e != hipSuccess) return srv_err(s, STPCI_EHIP, hipGetErrorString(e));
             ++s->grouped_launches;

@@ -1,0 +1,351 @@
+// Pair-resolved sigma build (the library's default for N >= 2).
+//
+// The Hamiltonian restricted to N electrons is written as one two-body
+// operator, H - e_core = sum_{p<r, q<s} A[(p,r),(q,s)] a+_p a+_r a_s a_q with
+//   A[(p,r),(q,s)] = g'_pqrs - g'_psrq,
+//   g'_pqrs = (pq|rs) + (h_pq d_rs + d_pq h_rs) / (N - 1),
+// (the one-electron part folded into the two-electron integrals, which is
+// exact on the N-electron sector).  A is Hermitian in the pair indices.
+// Inserting the identity over (N-2)-electron determinants K' between the
+// creation and annihilation pairs (the resolution of Eq. sigmaL2e taken two
+// electrons down):
+//   d[Q]  = sgn(a+_q a+_s |K'>) c[K' + {q, s}]         (gather)
+//   e     = A_K' d,   A_K'[P, Q] = A[pair P, pair Q]    (Hermitian tiles)
+//   sigma[K' + {p, r}] += sgn(a+_p a+_r |K'>) e[P]      (scatter)
+// over the pairs P, Q that lead from K' into the space.  The K' are grouped
+// into occupation categories of the same subspaces (STP-DAS); targets are
+// addressed through the per-subspace string tables, as in the one-move form.
+// One wavefront handles one K' with its LDS slice.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "kernels.hpp"
+#include "stp_device.hpp"
+#include "symtile.hpp"
+
+namespace stp {
+
+// Per-wave header after the slot arrays (bytes, 16-aligned).
+struct PairHdr {
+    int64_t rank[KMAX];      // local string ranks of K'
+    int64_t cbase[NPCLS];    // class: target offset + untouched subspaces' rank * stride
+    int64_t cstra[NPCLS];    // class: target stride of subspace a
+    int64_t cstrb[NPCLS];    // class: target stride of subspace b
+    uint32_t str[KMAX];      // local strings of K'
+    int32_t voff[KMAX];      // first empty-orbital position of subspace k
+    int32_t vcre[MMAX];      // creation of the empty orbital at position v on K' (sign * (rank + 1))
+    uint8_t vglob[MMAX];     // global index of the empty orbital at position v
+};
+static_assert(sizeof(PairHdr) % 16 == 0, "pair header alignment");
+
+// ---- the pair arithmetic, shared by the kernel (one lane per item) and the
+// host check (loops over items)
+
+// Subspace k of K' (local index jloc in its category): rank, string, first
+// empty-orbital position.
+__host__ __device__ inline void pair_hdr_sub(const DevSpace& S, const PairCat& P, int64_t jloc, int k, PairHdr* hd) {
+    const int64_t r = (jloc / P.stride[k]) % P.count[k];
+    hd->rank[k] = r;
+    hd->str[k] = S.bits[S.tabs[P.tab[k]].bits_off + r];
+    int vo = 0;
+    for (int q = 0; q < k; ++q) vo += S.sp.sub_m[q] - P.occ[q];
+    hd->voff[k] = vo;
+}
+
+// Global orbital g: when empty in K', its position among the empties, and the
+// creation a+_g on its subspace string.  Needs pair_hdr_sub of every subspace.
+__host__ __device__ inline void pair_hdr_orb(const DevSpace& S, const PairCat& P, int g, PairHdr* hd) {
+    const int K = S.sp.K;
+    int k = 0;
+    while (k + 1 < K && g >= S.sp.sub_off[k + 1]) ++k;
+    const int l = g - S.sp.sub_off[k];
+    const uint32_t s = hd->str[k];
+    if ((s >> l) & 1u) return;
+    const int v = hd->voff[k] + popc32(~s & lowmask(l));
+    const StrTab& t = S.tabs[P.tab[k]];
+    hd->vglob[v] = (uint8_t)g;
+    hd->vcre[v] = (t.cre_off >= 0) ? S.cre[t.cre_off + hd->rank[k] * t.m + l] : 0;
+}
+
+// Pair class c: target offset plus the untouched subspaces' rank * stride,
+// and the target strides of the two created subspaces.
+__host__ __device__ inline void pair_hdr_cls(const DevSpace& S, const PairCat& P, int c, PairHdr* hd) {
+    const int a = P.cls_a[c], b = P.cls_b[c];
+    const Cat& T2 = S.cats[P.cls_target[c]];
+    int64_t bs = T2.offset;
+    for (int k = 0; k < S.sp.K; ++k)
+        if (k != a && k != b) bs += hd->rank[k] * T2.stride[k];
+    hd->cbase[c] = bs;
+    hd->cstra[c] = T2.stride[a];
+    hd->cstrb[c] = T2.stride[b];
+}
+
+// Slot `slot` < deg of K': target address, pair index r (r - 1) / 2 + p of the
+// created pair p < r, and the sign of a+_p a+_r |K'> (true: negative).
+__host__ __device__ inline bool pair_slot(const DevSpace& S, const PairCat& P, const PairHdr* hd, int slot,
+                                          int64_t& addr, int& pi) {
+    const uint32_t info = S.pslot[P.slot_off + slot];
+    const int cl = (int)(info & 255u), i = (int)((info >> 8) & 255u), j = (int)(info >> 16);
+    const int a = P.cls_a[cl], b = P.cls_b[cl];
+    const int va = hd->voff[a] + i, vb = hd->voff[b] + j;
+    const int gp = hd->vglob[va], gr = hd->vglob[vb];
+    bool neg;
+    if (a != b) {
+        const int ca = hd->vcre[va], cb = hd->vcre[vb];
+        const int64_t ra = (ca < 0 ? -ca : ca) - 1, rb = (cb < 0 ? -cb : cb) - 1;
+        neg = ((ca < 0) != (cb < 0)) != (P.cls_phase[cl] != 0);
+        addr = hd->cbase[cl] + ra * hd->cstra[cl] + rb * hd->cstrb[cl];
+    } else {
+        // a+_r first on the K' string, then a+_p (p < r) on the result
+        const int c1 = hd->vcre[vb];
+        const int64_t r1 = (c1 < 0 ? -c1 : c1) - 1;
+        const StrTab& t1 = S.tabs[S.tabs[P.tab[a]].tab_up];
+        const int c2 = S.cre[t1.cre_off + r1 * t1.m + (gp - S.sp.sub_off[a])];
+        const int64_t r2 = (c2 < 0 ? -c2 : c2) - 1;
+        neg = (c1 < 0) != (c2 < 0);
+        addr = hd->cbase[cl] + r2 * hd->cstra[cl];
+    }
+    pi = gr * (gr - 1) / 2 + gp;
+    return neg;
+}
+
+// LDS bytes of one wavefront's slice: d and e (padded blocks), targets,
+// column offsets, row pair indices, header.
+__host__ __device__ inline size_t pair_slice(int deg_max, int nv, int sb) {
+    const size_t ne = (size_t)((deg_max + 3) >> 2) * (ST_TILE * nv + 16 / sb);
+    return 2 * ne * sb + (size_t)((deg_max + 3) & ~3) * 16 + sizeof(PairHdr);
+}
+
+size_t pair_slice_bytes(int deg_max, int nv, int sb) { return pair_slice(deg_max, nv, sb); }
+
+bool pair_supported(int n_elec, int deg_max, bool cplx) {
+    return n_elec >= 2 && deg_max > 0 && pair_slice_bytes(deg_max, 2, cplx ? 16 : 8) <= 64 * 1024;
+}
+
+template <bool CPLX, bool F32, int NV>
+__device__ __forceinline__ void pair_det(const DevSpace& S, const typename PT<CPLX, F32>::T* __restrict__ A,
+                                         const typename VT<CPLX>::T* __restrict__ c,
+                                         typename VT<CPLX>::T* __restrict__ sigma, int n_vec, int deg_cap,
+                                         unsigned char* base, int lane, int64_t J) {
+    using V = PT<CPLX, F32>;
+    using V64 = VT<CPLX>;
+    using T = typename V::T;
+    constexpr int SB = sizeof(T);
+    const int cap4 = (deg_cap + 3) & ~3;
+    const int ne = st_elems<NV, SB>(deg_cap);
+    T* dsh = reinterpret_cast<T*>(base);
+    T* esh = dsh + ne;
+    int64_t* tgt = reinterpret_cast<int64_t*>(esh + ne);
+    int32_t* coff = reinterpret_cast<int32_t*>(tgt + cap4);   // pair(Q) * npairs
+    int32_t* rinf = coff + cap4;                              // pair(P) << 1 | negative sign
+    PairHdr* hd = reinterpret_cast<PairHdr*>(rinf + cap4);
+    const int K = S.sp.K;
+    const int64_t nd = S.sp.ndets;
+    const int w = find_segment(S.pwork_begin, S.sp.npcat, J);
+    const PairCat& P = S.pcats[w];
+    const int64_t jloc = J - S.pwork_begin[w];
+    const int deg = P.deg;
+
+    // ---- phase 1: strings of K', its empty orbitals and class bases, then
+    // per pair slot the target, sign and gathered coefficients
+    if (lane < K) pair_hdr_sub(S, P, jloc, lane, hd);
+    wave_lds_sync();
+    if (lane < S.sp.M) pair_hdr_orb(S, P, lane, hd);
+    if (lane < P.ncls) pair_hdr_cls(S, P, lane, hd);
+    wave_lds_sync();
+    const int NP = S.sp.npairs;
+    for (int slot = lane; slot < ((deg + 3) & ~3); slot += 64) {
+        if (slot >= deg) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                dsh[st_idx<NV, SB>(slot, v)] = V::zero();
+                esh[st_idx<NV, SB>(slot, v)] = V::zero();
+            }
+            coff[slot] = 0;
+            rinf[slot] = 0;
+            continue;
+        }
+        int64_t addr;
+        int pi;
+        const bool neg = pair_slot(S, P, hd, slot, addr, pi);
+        tgt[slot] = addr;
+        coff[slot] = pi * NP;
+        rinf[slot] = (pi << 1) | (neg ? 1 : 0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            T val = (v < n_vec) ? V::from64(c[(int64_t)v * nd + addr]) : V::zero();
+            if (neg) val = V::scale(val, -1.0);
+            dsh[st_idx<NV, SB>(slot, v)] = val;
+            esh[st_idx<NV, SB>(slot, v)] = V::zero();
+        }
+    }
+    wave_lds_sync();
+
+    // ---- phase 2: e = A_K' d
+    tile_contract<CPLX, F32, NV>(A, dsh, esh, rinf, coff, deg, lane);
+    wave_lds_sync();
+
+    // ---- phase 3: sigma[K' + P] += sgn(P) e[P]
+    for (int slot = lane; slot < deg; slot += 64) {
+        const double sg = (rinf[slot] & 1) ? -1.0 : 1.0;
+        const int64_t t = tgt[slot];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (v < n_vec)
+                V64::atomic_add(&sigma[(int64_t)v * nd + t], V64::scale(V::to64(esh[st_idx<NV, SB>(slot, v)]), sg));
+    }
+    wave_lds_sync();  // the next K' reuses this wavefront's LDS slice
+}
+
+template <bool CPLX, bool F32, int NV>
+__global__ __launch_bounds__(256) void k_sigma_pair(DevSpace S, const typename PT<CPLX, F32>::T* __restrict__ A,
+                                                   const typename VT<CPLX>::T* __restrict__ c,
+                                                   typename VT<CPLX>::T* __restrict__ sigma, int n_vec, int deg_cap) {
+    using T = typename PT<CPLX, F32>::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    unsigned char* base = smem + (size_t)wid * pair_slice(deg_cap, NV, (int)sizeof(T));
+    const int64_t total = S.sp.npwork_dets;
+    const int64_t nw = (int64_t)gridDim.x * wpb;
+    for (int64_t J = (int64_t)blockIdx.x * wpb + wid; J < total; J += nw)
+        pair_det<CPLX, F32, NV>(S, A, c, sigma, n_vec, deg_cap, base, lane, J);
+}
+
+// Several problems in one launch: descriptor q covers [jbegin[q], jbegin[q+1])
+// of the combined range of pair intermediates.
+template <bool CPLX, bool F32>
+__global__ __launch_bounds__(256) void k_sigma_pair_multi(const SigmaDesc* __restrict__ desc, int ndesc,
+                                                         const int64_t* __restrict__ jbegin, int deg_cap) {
+    using T = typename PT<CPLX, F32>::T;
+    using T64 = typename VT<CPLX>::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    unsigned char* base = smem + (size_t)wid * pair_slice(deg_cap, 2, (int)sizeof(T));
+    const int64_t total = jbegin[ndesc];
+    const int64_t nw = (int64_t)gridDim.x * wpb;
+    for (int64_t J = (int64_t)blockIdx.x * wpb + wid; J < total; J += nw) {
+        const int q = find_segment(jbegin, ndesc, J);
+        const SigmaDesc& D = desc[q];
+        pair_det<CPLX, F32, 2>(D.S, (const T*)D.gT, (const T64*)D.c, (T64*)D.sigma, D.n_vec, deg_cap, base, lane,
+                               J - jbegin[q]);
+    }
+}
+
+template <bool CPLX, bool F32, int NV>
+static hipError_t launch_pair_nv(const DevSpace& S, int deg_max, const void* A, const void* c, void* sigma, int nv,
+                                 hipStream_t st) {
+    using T = typename PT<CPLX, F32>::T;
+    using T64 = typename VT<CPLX>::T;
+    const size_t per_wave = pair_slice_bytes(deg_max, NV, (int)sizeof(T));
+    const int wpb = waves_per_group(per_wave);
+    const size_t lds = per_wave * wpb;
+    int64_t blocks = (S.sp.npwork_dets + wpb - 1) / wpb;
+    blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, 256 * 64));
+    hipLaunchKernelGGL((k_sigma_pair<CPLX, F32, NV>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, S,
+                       (const T*)A, (const T64*)c, (T64*)sigma, nv, deg_max);
+    return hipGetLastError();
+}
+
+template <bool CPLX, bool F32>
+static hipError_t launch_pair_all(const DevSpace& S, int deg_max, const void* A, const void* c, void* sigma,
+                                  int n_vec, double e_core, hipStream_t st) {
+    using T64 = typename VT<CPLX>::T;
+    hipError_t e = launch_fill_init(CPLX, sigma, c, e_core, S.sp.ndets * n_vec, st);
+    if (e != hipSuccess) return e;
+    for (int v0 = 0; v0 < n_vec; v0 += 2) {
+        const int nv = (n_vec - v0 >= 2) ? 2 : 1;
+        const int64_t off = (int64_t)v0 * S.sp.ndets;
+        const T64* cc = (const T64*)c + off;
+        T64* ss = (T64*)sigma + off;
+        e = (nv == 2) ? launch_pair_nv<CPLX, F32, 2>(S, deg_max, A, cc, ss, 2, st)
+                      : launch_pair_nv<CPLX, F32, 1>(S, deg_max, A, cc, ss, 1, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_sigma_pair(const DevSpace& S, int deg_max, bool cplx, bool f32, const void* A, const void* c,
+                             void* sigma, int n_vec, double e_core, hipStream_t st) {
+    if (cplx)
+        return f32 ? launch_pair_all<true, true>(S, deg_max, A, c, sigma, n_vec, e_core, st)
+                   : launch_pair_all<true, false>(S, deg_max, A, c, sigma, n_vec, e_core, st);
+    return f32 ? launch_pair_all<false, true>(S, deg_max, A, c, sigma, n_vec, e_core, st)
+               : launch_pair_all<false, false>(S, deg_max, A, c, sigma, n_vec, e_core, st);
+}
+
+hipError_t launch_sigma_pair_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
+                                   int deg_max, bool cplx, bool f32, hipStream_t st) {
+    const int sb = f32 ? (cplx ? 8 : 4) : (cplx ? 16 : 8);
+    const size_t per_wave = pair_slice_bytes(deg_max, 2, sb);
+    const int wpb = waves_per_group(per_wave);
+    const size_t lds = per_wave * wpb;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + wpb - 1) / wpb, 256 * 64));
+    hipError_t e = launch_fill_init_multi(cplx, desc_dev, ndesc, st);
+    if (e != hipSuccess) return e;
+    const dim3 g((unsigned)blocks), t(64 * wpb);
+    if (cplx) {
+        if (f32)
+            hipLaunchKernelGGL((k_sigma_pair_multi<true, true>), g, t, lds, st, desc_dev, ndesc, jbegin_dev, deg_max);
+        else
+            hipLaunchKernelGGL((k_sigma_pair_multi<true, false>), g, t, lds, st, desc_dev, ndesc, jbegin_dev,
+                               deg_max);
+    } else {
+        if (f32)
+            hipLaunchKernelGGL((k_sigma_pair_multi<false, true>), g, t, lds, st, desc_dev, ndesc, jbegin_dev,
+                               deg_max);
+        else
+            hipLaunchKernelGGL((k_sigma_pair_multi<false, false>), g, t, lds, st, desc_dev, ndesc, jbegin_dev,
+                               deg_max);
+    }
+    return hipGetLastError();
+}
+
+// Host check of the pair arithmetic above (the same functions, run on the
+// host tables): for up to max_dets_per_cat K' of every pair category, every
+// slot's target must be K' + {p, r} in the space, with the sign of
+// a+_p a+_r |K'> from the global occupation bits and the pair index of p < r.
+int64_t check_pairs_host(const DevSpace& S, int64_t max_dets_per_cat, int64_t* n_checked,
+                         bool (*to_bits)(const void*, int64_t, uint64_t*), const void* user) {
+    int64_t bad = 0, checked = 0;
+    const int K = S.sp.K;
+    for (int w = 0; w < S.sp.npcat; ++w) {
+        const PairCat& P = S.pcats[w];
+        const int64_t step = P.size <= max_dets_per_cat ? 1 : P.size / max_dets_per_cat;
+        for (int64_t j = 0; j < P.size; j += step) {
+            PairHdr hd;
+            for (int k = 0; k < K; ++k) pair_hdr_sub(S, P, j, k, &hd);
+            for (int g = 0; g < S.sp.M; ++g) pair_hdr_orb(S, P, g, &hd);
+            for (int c = 0; c < P.ncls; ++c) pair_hdr_cls(S, P, c, &hd);
+            uint64_t Kb = 0;
+            for (int k = 0; k < K; ++k) Kb |= (uint64_t)hd.str[k] << S.sp.sub_off[k];
+            for (int slot = 0; slot < P.deg; ++slot) {
+                int64_t t;
+                int pi;
+                const bool neg = pair_slot(S, P, &hd, slot, t, pi);
+                ++checked;
+                // recover p < r from the pair index
+                int r = 1;
+                while ((r + 1) * r / 2 <= pi) ++r;
+                const int p = pi - r * (r - 1) / 2;
+                const bool free_pr = p < r && !((Kb >> p) & 1ULL) && !((Kb >> r) & 1ULL);
+                const uint64_t want = Kb | (1ULL << p) | (1ULL << r);
+                const int par = __builtin_popcountll(Kb & ((1ULL << r) - 1ULL)) +
+                                __builtin_popcountll(Kb & ((1ULL << p) - 1ULL));
+                uint64_t got = 0;
+                if (!free_pr || t < 0 || t >= S.sp.ndets || !to_bits(user, t, &got) || got != want ||
+                    neg != ((par & 1) != 0))
+                    ++bad;
+            }
+        }
+    }
+    if (n_checked) *n_checked = checked;
+    return bad;
+}
+
+}  // namespace stp

@@ -26,25 +26,9 @@
 
 #include "kernels.hpp"
 #include "stp_device.hpp"
+#include "symtile.hpp"
 
 namespace stp {
-
-constexpr int ST_TILE = 4;
-
-// LDS index of (slot, vector): blocks of 4 slots are padded by 16 bytes so
-// that the lanes of a wavefront, which read blocks at a stride of one block,
-// start on different banks (a b128 read then touches each bank once per 16
-// lanes).
-template <int NV, int SB>
-__device__ __forceinline__ int st_idx(int slot, int v) {
-    constexpr int blk = ST_TILE * NV + 16 / SB;  // elements per padded block
-    return (slot >> 2) * blk + (slot & 3) * NV + v;
-}
-
-template <int NV, int SB>
-__host__ __device__ constexpr int st_elems(int deg_cap) {
-    return ((deg_cap + 3) >> 2) * (ST_TILE * NV + 16 / SB);
-}
 
 // Sigma contribution of one intermediate determinant J (index over the
 // work categories of S), computed by one wavefront with its LDS slice.
@@ -79,12 +63,14 @@ __device__ __forceinline__ void symtile_det(const DevSpace& S, const typename PT
 #pragma unroll
     for (int v = 0; v < NV; ++v) one[v] = V::zero();
     for (int slot = lane; slot < ((deg + 3) & ~3); slot += 64) {
-        if (slot >= deg) {  // zero the padding slots of the last block
+        if (slot >= deg) {  // padding slots of the last block: d = e = 0, in-range indices
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 dsh[st_idx<NV, SB>(slot, v)] = V::zero();
                 esh[st_idx<NV, SB>(slot, v)] = V::zero();
             }
+            coff[slot] = 0;
+            rinf[slot] = 0;
             continue;
         }
         int cls, xs, ys, lx, ly, sg;
@@ -114,79 +100,8 @@ __device__ __forceinline__ void symtile_det(const DevSpace& S, const typename PT
     }
     wave_lds_sync();
 
-    // ---- phase 2: upper-triangle tiles of G_J
-    const int nb = (deg + ST_TILE - 1) / ST_TILE;
-    const int np = nb * (nb + 1) / 2;
-    const int p0 = (int)(((int64_t)lane * np) >> 6);
-    const int p1 = (int)(((int64_t)(lane + 1) * np) >> 6);
-    int b = 0, start = 0;
-    while (b < nb && start + (nb - b) <= p0) {
-        start += nb - b;
-        ++b;
-    }
-    int bp = b + (p0 - start);
-    int cur = -1;
-    int prow[ST_TILE];
-    T drow[ST_TILE][NV], erow[ST_TILE][NV];
-    for (int p = p0; p < p1; ++p) {
-        if (b != cur) {
-            if (cur >= 0) {
-#pragma unroll
-                for (int r = 0; r < ST_TILE; ++r)
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) V::lds_add(&esh[st_idx<NV, SB>(cur * ST_TILE + r, v)], erow[r][v]);
-            }
-            cur = b;
-#pragma unroll
-            for (int r = 0; r < ST_TILE; ++r) {
-                const int s = b * ST_TILE + r;
-                // a padding row has d = 0 and adds zeros; its offset is kept in range
-                prow[r] = (s < deg) ? (rinf[s] >> 1) : 0;
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    drow[r][v] = dsh[st_idx<NV, SB>(s, v)];
-                    erow[r][v] = V::zero();
-                }
-            }
-        }
-        const bool offdiag = (bp != b);
-#pragma unroll
-        for (int k = 0; k < ST_TILE; ++k) {
-            const int s = bp * ST_TILE + k;
-            if (s >= deg) break;
-            const int co = coff[s];
-            T dcol[NV], ecol[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                dcol[v] = dsh[st_idx<NV, SB>(s, v)];
-                ecol[v] = V::zero();
-            }
-            T g[ST_TILE];
-#pragma unroll
-            for (int r = 0; r < ST_TILE; ++r) g[r] = gT[co + prow[r]];
-#pragma unroll
-            for (int r = 0; r < ST_TILE; ++r)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    erow[r][v] = V::mad(g[r], dcol[v], erow[r][v]);
-                    ecol[v] = V::cmad(g[r], drow[r][v], ecol[v]);
-                }
-            if (offdiag) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) V::lds_add(&esh[st_idx<NV, SB>(s, v)], ecol[v]);
-            }
-        }
-        if (++bp == nb) {
-            ++b;
-            bp = b;
-        }
-    }
-    if (cur >= 0) {
-#pragma unroll
-        for (int r = 0; r < ST_TILE; ++r)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) V::lds_add(&esh[st_idx<NV, SB>(cur * ST_TILE + r, v)], erow[r][v]);
-    }
+    // ---- phase 2: e = G_J d over the upper-triangle tiles
+    tile_contract<CPLX, F32, NV>(gT, dsh, esh, rinf, coff, deg, lane);
     wave_lds_sync();
 
     // ---- phase 3: one atomic update of sigma per move and vector
@@ -244,9 +159,38 @@ __global__ __launch_bounds__(256) void k_sigma_symtile_multi(const SigmaDesc* __
 }
 
 template <bool CPLX>
-__global__ __launch_bounds__(256) void k_fill_zero(typename VT<CPLX>::T* __restrict__ x, int64_t n) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        x[e] = VT<CPLX>::zero();
+__global__ __launch_bounds__(256) void k_fill_init(typename VT<CPLX>::T* __restrict__ sigma,
+                                                  const typename VT<CPLX>::T* __restrict__ c, double e_core,
+                                                  int64_t n) {
+    fill_init<CPLX>(sigma, c, e_core, n, blockIdx.x * (int64_t)blockDim.x + threadIdx.x,
+                    (int64_t)gridDim.x * blockDim.x);
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_fill_init_multi(const SigmaDesc* __restrict__ desc, int ndesc) {
+    using T64 = typename VT<CPLX>::T;
+    for (int q = 0; q < ndesc; ++q)
+        fill_init<CPLX>((T64*)desc[q].sigma, (const T64*)desc[q].c, desc[q].e_core,
+                        desc[q].S.sp.ndets * desc[q].n_vec, blockIdx.x * (int64_t)blockDim.x + threadIdx.x,
+                        (int64_t)gridDim.x * blockDim.x);
+}
+
+hipError_t launch_fill_init(bool cplx, void* sigma, const void* c, double e_core, int64_t n, hipStream_t st) {
+    const int zg = (int)std::max<int64_t>(1, std::min<int64_t>(8192, (n + 255) / 256));
+    if (cplx)
+        hipLaunchKernelGGL(k_fill_init<true>, dim3(zg), dim3(256), 0, st, (cd*)sigma, (const cd*)c, e_core, n);
+    else
+        hipLaunchKernelGGL(k_fill_init<false>, dim3(zg), dim3(256), 0, st, (double*)sigma, (const double*)c, e_core,
+                           n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_init_multi(bool cplx, const SigmaDesc* desc_dev, int ndesc, hipStream_t st) {
+    if (cplx)
+        hipLaunchKernelGGL(k_fill_init_multi<true>, dim3(4096), dim3(256), 0, st, desc_dev, ndesc);
+    else
+        hipLaunchKernelGGL(k_fill_init_multi<false>, dim3(4096), dim3(256), 0, st, desc_dev, ndesc);
+    return hipGetLastError();
 }
 
 size_t symtile_slice_bytes(int deg_max, int nv, int sb) {
@@ -256,17 +200,23 @@ size_t symtile_slice_bytes(int deg_max, int nv, int sb) {
 
 bool symtile_supported(int deg_max, bool cplx) { return symtile_slice_bytes(deg_max, 2, cplx ? 16 : 8) <= 64 * 1024; }
 
+// Waves per workgroup for a per-wave LDS slice: at most 4 and 48 KB per group.
+int waves_per_group(size_t per_wave) {
+    int wpb = 4;
+    while (wpb > 1 && per_wave * wpb > 48 * 1024) wpb >>= 1;
+    return wpb;
+}
+
 template <bool CPLX, bool F32, int NV>
 static hipError_t launch_sym_nv(const DevSpace& S, int deg_max, const void* gT, const void* hp, const void* c,
                                 void* sigma, int nv, hipStream_t st) {
     using T = typename PT<CPLX, F32>::T;
     using T64 = typename VT<CPLX>::T;
     const size_t per_wave = symtile_slice_bytes(deg_max, NV, (int)sizeof(T));
-    int wpb = 4;
-    while (wpb > 1 && per_wave * wpb > 48 * 1024) wpb >>= 1;
+    const int wpb = waves_per_group(per_wave);
     const size_t lds = per_wave * wpb;
     int64_t blocks = (S.sp.nwork_dets + wpb - 1) / wpb;
-    blocks = std::min<int64_t>(blocks, 256 * 64);
+    blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, 256 * 64));
     hipLaunchKernelGGL((k_sigma_symtile<CPLX, F32, NV>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, S,
                        (const T*)gT, (const T*)hp, (const T64*)c, (T64*)sigma, nv, deg_max);
     return hipGetLastError();
@@ -274,12 +224,9 @@ static hipError_t launch_sym_nv(const DevSpace& S, int deg_max, const void* gT, 
 
 template <bool CPLX, bool F32>
 static hipError_t launch_sym_all(const DevSpace& S, int deg_max, const void* gT, const void* hp, const void* c,
-                                 void* sigma, int n_vec, hipStream_t st) {
+                                 void* sigma, int n_vec, double e_core, hipStream_t st) {
     using T64 = typename VT<CPLX>::T;
-    const int64_t n = S.sp.ndets * n_vec;
-    const int zg = (int)std::min<int64_t>(8192, (n + 255) / 256);
-    hipLaunchKernelGGL(k_fill_zero<CPLX>, dim3(zg), dim3(256), 0, st, (T64*)sigma, n);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_fill_init(CPLX, sigma, c, e_core, S.sp.ndets * n_vec, st);
     if (e != hipSuccess) return e;
     for (int v0 = 0; v0 < n_vec; v0 += 2) {
         const int nv = (n_vec - v0 >= 2) ? 2 : 1;
@@ -294,36 +241,24 @@ static hipError_t launch_sym_all(const DevSpace& S, int deg_max, const void* gT,
 }
 
 hipError_t launch_sigma_symtile(const DevSpace& S, int deg_max, bool cplx, bool f32, const void* gT, const void* hp,
-                                const void* c, void* sigma, int n_vec, hipStream_t st) {
+                                const void* c, void* sigma, int n_vec, double e_core, hipStream_t st) {
     if (cplx)
-        return f32 ? launch_sym_all<true, true>(S, deg_max, gT, hp, c, sigma, n_vec, st)
-                   : launch_sym_all<true, false>(S, deg_max, gT, hp, c, sigma, n_vec, st);
-    return f32 ? launch_sym_all<false, true>(S, deg_max, gT, hp, c, sigma, n_vec, st)
-               : launch_sym_all<false, false>(S, deg_max, gT, hp, c, sigma, n_vec, st);
-}
-
-template <bool CPLX>
-__global__ __launch_bounds__(256) void k_fill_zero_multi(const SigmaDesc* __restrict__ desc, int ndesc) {
-    using T64 = typename VT<CPLX>::T;
-    for (int q = 0; q < ndesc; ++q) {
-        T64* x = (T64*)desc[q].sigma;
-        const int64_t n = desc[q].S.sp.ndets * desc[q].n_vec;
-        for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-            x[e] = VT<CPLX>::zero();
-    }
+        return f32 ? launch_sym_all<true, true>(S, deg_max, gT, hp, c, sigma, n_vec, e_core, st)
+                   : launch_sym_all<true, false>(S, deg_max, gT, hp, c, sigma, n_vec, e_core, st);
+    return f32 ? launch_sym_all<false, true>(S, deg_max, gT, hp, c, sigma, n_vec, e_core, st)
+               : launch_sym_all<false, false>(S, deg_max, gT, hp, c, sigma, n_vec, e_core, st);
 }
 
 hipError_t launch_sigma_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
                               int deg_max, bool cplx, bool f32, hipStream_t st) {
     const int sb = f32 ? (cplx ? 8 : 4) : (cplx ? 16 : 8);
     const size_t per_wave = symtile_slice_bytes(deg_max, 2, sb);
-    int wpb = 4;
-    while (wpb > 1 && per_wave * wpb > 48 * 1024) wpb >>= 1;
+    const int wpb = waves_per_group(per_wave);
     const size_t lds = per_wave * wpb;
-    int64_t blocks = std::min<int64_t>((total + wpb - 1) / wpb, 256 * 64);
-    if (blocks < 1) blocks = 1;
+    int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + wpb - 1) / wpb, 256 * 64));
+    hipError_t e = launch_fill_init_multi(cplx, desc_dev, ndesc, st);
+    if (e != hipSuccess) return e;
     if (cplx) {
-        hipLaunchKernelGGL(k_fill_zero_multi<true>, dim3(4096), dim3(256), 0, st, desc_dev, ndesc);
         if (f32)
             hipLaunchKernelGGL((k_sigma_symtile_multi<true, true>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st,
                                desc_dev, ndesc, jbegin_dev, deg_max);
@@ -331,7 +266,6 @@ hipError_t launch_sigma_multi(const SigmaDesc* desc_dev, int ndesc, const int64_
             hipLaunchKernelGGL((k_sigma_symtile_multi<true, false>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st,
                                desc_dev, ndesc, jbegin_dev, deg_max);
     } else {
-        hipLaunchKernelGGL(k_fill_zero_multi<false>, dim3(4096), dim3(256), 0, st, desc_dev, ndesc);
         if (f32)
             hipLaunchKernelGGL((k_sigma_symtile_multi<false, true>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st,
                                desc_dev, ndesc, jbegin_dev, deg_max);

@@ -186,8 +186,93 @@ bool HostSpace::build(int n_elec, int n_sub, const int* sub_size, const int* win
     sp.nwork = (int)work_cat.size();
     sp.nwork_dets = w;
 
+    // pair intermediates: every (N-2)-electron tuple from which a pair
+    // creation p < r (both in subspace a = b, or p in a < r in b) reaches the
+    // space; windows do not apply to the intermediates themselves
+    pcats.clear();
+    pwork_begin.assign(1, 0);
+    pslot.clear();
+    Wp = sum_pdeg = 0;
+    pmax_deg = 0;
+    if (n_elec >= 2) {
+        std::vector<std::vector<int>> pt;
+        enum_tuples(K, sub_size, zlo.data(), zhi.data(), n_elec - 2, pt);
+        int64_t pw = 0;
+        for (auto& t : pt) {
+            PairCat P{};
+            for (int k = 0; k < KMAX; ++k) { P.occ[k] = 0; P.tab[k] = -1; P.count[k] = 1; P.stride[k] = 0; }
+            int64_t sz = 1;
+            for (int k = K - 1; k >= 0; --k) {
+                P.occ[k] = t[k];
+                P.count[k] = binom(sub_size[k], t[k]);
+                P.stride[k] = sz;
+                sz *= P.count[k];
+            }
+            P.size = sz;
+            int begin = 0;
+            P.ncls = 0;
+            for (int a = 0; a < K; ++a)
+                for (int b = a; b < K; ++b) {
+                    const int va = sub_size[a] - t[a], vb = sub_size[b] - t[b];
+                    const int cnt = (a == b) ? va * (va - 1) / 2 : va * vb;
+                    if (cnt <= 0) continue;
+                    std::vector<int> u = t;
+                    u[a] += 1;
+                    u[b] += 1;
+                    if (!in_space(u)) continue;
+                    auto it = idx.find(u);
+                    if (it == idx.end()) continue;
+                    const int c = P.ncls++;
+                    P.cls_a[c] = a;
+                    P.cls_b[c] = b;
+                    P.cls_begin[c] = begin;
+                    P.cls_target[c] = it->second;
+                    int par = 0;
+                    for (int k = a; k < b; ++k) par += t[k];
+                    P.cls_phase[c] = par & 1;
+                    begin += cnt;
+                }
+            P.cls_begin[P.ncls] = begin;
+            P.deg = begin;
+            if (begin == 0) continue;
+            P.slot_off = (int32_t)pslot.size();
+            for (int c = 0; c < P.ncls; ++c) {
+                const int a = P.cls_a[c], b = P.cls_b[c];
+                const int va = sub_size[a] - t[a], vb = sub_size[b] - t[b];
+                if (a == b) {
+                    for (int j = 1; j < va; ++j)
+                        for (int i = 0; i < j; ++i) pslot.push_back((uint32_t)c | (uint32_t)i << 8 | (uint32_t)j << 16);
+                } else {
+                    for (int j = 0; j < vb; ++j)
+                        for (int i = 0; i < va; ++i) pslot.push_back((uint32_t)c | (uint32_t)i << 8 | (uint32_t)j << 16);
+                }
+            }
+            pcats.push_back(P);
+            pw += sz;
+            pwork_begin.push_back(pw);
+            Wp += (double)sz * begin * begin;
+            sum_pdeg += (double)sz * begin;
+            pmax_deg = std::max(pmax_deg, begin);
+        }
+        sp.npwork_dets = pw;
+    }
+    sp.npcat = (int)pcats.size();
+    sp.npairs = M * (M - 1) / 2;
+
     // string tables: which (m, n) need bits, ann, cre
     std::map<std::pair<int, int>, int> need;  // bit0 bits, bit1 ann, bit2 cre
+    for (const PairCat& P : pcats) {
+        for (int k = 0; k < K; ++k) {
+            need[{sub_size[k], P.occ[k]}] |= 1 | 4;
+            if (P.occ[k] < sub_size[k]) need[{sub_size[k], P.occ[k] + 1}] |= 1;
+        }
+        for (int c = 0; c < P.ncls; ++c) {
+            const int a = P.cls_a[c];
+            need[{sub_size[a], P.occ[a] + 1}] |= 1 | ((a == P.cls_b[c]) ? 4 : 0);
+            if (a == P.cls_b[c]) need[{sub_size[a], P.occ[a] + 2}] |= 1;
+            need[{sub_size[P.cls_b[c]], P.occ[P.cls_b[c]] + 1}] |= 1;
+        }
+    }
     for (int c = 0; c < sp.ncat; ++c) {
         const Cat& C = cats[c];
         for (int k = 0; k < K; ++k) need[{sub_size[k], C.occ[k]}] |= 1;
@@ -262,6 +347,8 @@ bool HostSpace::build(int n_elec, int n_sub, const int* sub_size, const int* win
     }
     for (auto& C : cats)
         for (int k = 0; k < K; ++k) C.tab[k] = tab_of[sub_size[k]][C.occ[k]];
+    for (auto& P : pcats)
+        for (int k = 0; k < K; ++k) P.tab[k] = tab_of[sub_size[k]][P.occ[k]];
 
     // work counts
     W1 = W2 = nnz = sum_deg = 0;

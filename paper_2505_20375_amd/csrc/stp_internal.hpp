@@ -10,7 +10,8 @@ constexpr int MMAX = 64;         // spin-orbitals in total
 constexpr int MSUB = 32;         // spin-orbitals per subspace (local strings are uint32 masks)
 constexpr int NCLS = KMAX * KMAX;
 constexpr int MAXDEG = 1024;
-constexpr int DET_BYTES = 96;   // sizeof of the device-side decoded determinant (ranks + masks)    // moves per determinant handled by the per-determinant 2e kernel
+constexpr int DET_BYTES = 96;   // sizeof of the device-side decoded determinant (ranks + masks)
+constexpr int NPCLS = KMAX * (KMAX + 1) / 2;   // pair classes (a <= b)
 
 // A local string table: all strings of n electrons in an m-orbital subspace,
 // ranked in colexicographic order (= ascending value of the bit mask).
@@ -57,6 +58,29 @@ struct Cat {
     int32_t cls_phase[NCLS];    // 0/1: parity of electrons passed between subspaces
 };
 
+// One pair-intermediate category: an (N-2)-electron occupation tuple
+// (n'_1..n'_K), any 0 <= n'_k <= m_k, from which creating a pair of electrons
+// p < r reaches the space.  Pair class c creates p in subspace cls_a[c] and r
+// in subspace cls_b[c] >= cls_a[c]; its slots are listed in pslot[slot_off ..
+// slot_off + deg) as cls | i << 8 | j << 16 with p = i-th and r = j-th empty
+// orbital of their subspaces (i < j inside one subspace), p fastest.
+struct PairCat {
+    int32_t occ[KMAX];
+    int32_t tab[KMAX];          // string table of (subspace k, occ[k])
+    int64_t count[KMAX];
+    int64_t stride[KMAX];
+    int64_t size;
+    int32_t deg;                // pair creations into the space
+    int32_t ncls;
+    int32_t slot_off;           // into pslot[]
+    int32_t pad_;
+    int32_t cls_a[NPCLS];
+    int32_t cls_b[NPCLS];
+    int32_t cls_begin[NPCLS + 1];
+    int32_t cls_target[NPCLS];  // space category reached
+    int32_t cls_phase[NPCLS];   // 0/1: parity of the electrons of subspaces a..b-1 (a < b)
+};
+
 struct Space {
     int32_t K, M, N;
     int32_t sub_off[KMAX];
@@ -66,6 +90,9 @@ struct Space {
     int32_t nwork;              // categories with deg > 0 (intermediates of the 2e sum)
     int64_t ndets;              // determinants in the space
     int64_t nwork_dets;         // determinants over all work categories
+    int32_t npcat;              // pair-intermediate categories (N >= 2)
+    int32_t npairs;             // M (M - 1) / 2 ordered orbital pairs p < r
+    int64_t npwork_dets;        // determinants over all pair-intermediate categories
 };
 
 // Device view passed by value to kernels.
@@ -79,6 +106,9 @@ struct DevSpace {
     const int32_t* work_cat;     // [nwork] category index
     const int64_t* work_begin;   // [nwork + 1] prefix over sizes
     const int64_t* space_begin;  // [nspace + 1] vector offsets
+    const PairCat* pcats;        // [npcat]
+    const int64_t* pwork_begin;  // [npcat + 1] prefix over sizes
+    const uint32_t* pslot;       // slot tables of the pair categories
 };
 
 // Schedule of the tiled two-electron kernel: blocks of consecutive
@@ -104,12 +134,13 @@ struct Sigma2eSched {
 // and output (n_vec <= 2 vectors, [n_vec][n_dets]).
 struct SigmaDesc {
     DevSpace S;
-    const void* gT;
-    const void* hp;
+    const void* gT;     // pair-pair integrals (pair kernel) or transposed (pq|rs) (tile kernel)
+    const void* hp;     // h' (tile kernel only)
     const void* c;
     void* sigma;
+    double e_core;
     int32_t n_vec;
-    int32_t pad;
+    int32_t deg;        // largest degree of this problem's intermediates
 };
 
 }  // namespace stp

@@ -15,9 +15,11 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
 
-def _run_sigma(pb, c_or, n_vec=1):
+def _run_sigma(pb, c_or, n_vec=1, kernel=None):
     import torch
     ctx = pb.context()
+    if kernel:
+        ctx.set_sigma_kernel(kernel)
     x = pb.to_device(c_or) if n_vec == 1 else torch.cat([pb.to_device(v) for v in c_or])
     out = torch.empty_like(x)
     ctx.sigma(x, out, n_vec=n_vec)
@@ -107,3 +109,37 @@ def test_sigma_config2_full_size_sampled_rows():
     rows = np.unique(np.concatenate([[0, len(pb.dets) - 1], rng.choice(len(pb.dets), 3000, replace=False)]))
     s_ref = pb.oracle_sigma(c, rows=rows)
     assert rel_err(s_gpu[rows], s_ref) <= TOL
+
+
+@pytest.mark.parametrize("kernel", ["pair", "tile", "rowtile", "wave", "simple"])
+@pytest.mark.parametrize("name", ["T4", "c1"])
+def test_every_kernel_matches_oracle(kernel, name):
+    """Each sigma kernel (pair intermediates, one-move Hermitian tiles and the
+    earlier one-move forms) reproduces the oracle."""
+    print("case", kernel, name, flush=True)
+    pb = Problem.named(name)
+    c = pb.vector()
+    assert rel_err(_run_sigma(pb, c, kernel=kernel), pb.oracle_sigma(c)) <= TOL
+
+
+def test_default_kernel_is_pair():
+    import torch
+    pb = Problem.named("T4")
+    ctx = pb.context()
+    x = pb.to_device(pb.vector())
+    ctx.sigma(x, torch.empty_like(x))
+    torch.cuda.synchronize()
+    assert ctx.sigma_kernel() == "pair"
+
+
+@pytest.mark.parametrize("kernel", ["pair", "tile", "rowtile"])
+def test_core_energy_term(kernel):
+    """sigma includes e_core * c."""
+    import torch
+    from oracle import csc
+    ints = synth.complex_integrals(10, 31)
+    ints.e_core = -3.25
+    pb = Problem(ints, synth.SpaceSpec(4, [4, 6], [1, 1], [3, 3]), seed=5)
+    c = pb.vector()
+    ref = csc.sigma(pb.dets, pb.h, pb.g, c, e_core=ints.e_core)
+    assert rel_err(_run_sigma(pb, c, kernel=kernel), ref) <= TOL

@@ -167,3 +167,47 @@ def test_kernel_move_arithmetic_on_host(name, cap):
     c = host_ctx(sp.n_elec, sp.sub, sp.lo, sp.hi)
     n, bad = c.test_moves(cap)
     assert n > 0 and bad == 0
+
+
+@pytest.mark.parametrize("name,cap", [("T2", 1 << 40), ("T3", 1 << 40), ("T4", 1 << 40), ("T8", 1 << 40),
+                                      ("c1", 1 << 40), ("c2", 3000), ("c3p", 200)])
+def test_pair_kernel_arithmetic_on_host(name, cap):
+    """The pair-slot enumeration, signs and target addresses of the pair
+    kernel (same code, compiled for the host) agree with the global fermion
+    sign of a+_p a+_r on the occupation bits and stay inside the space."""
+    sp = (synth.CONFIGS.get(name) or synth.TSPACES[name])["space"]
+    c = host_ctx(sp.n_elec, sp.sub, sp.lo, sp.hi)
+    n, bad = c.test_pairs(cap)
+    assert n > 0 and bad == 0
+
+
+def brute_pair_counts(n, sub, lo, hi):
+    """sum over (N-2)-electron bit strings K' of deg(K')^2, deg = pairs p < r
+    empty in K' with K' + {p, r} in the space."""
+    M = sum(sub)
+    inset = set(int(b) for b in ospace.enumerate_dets(n, sub, lo, hi))
+    W = 0
+    nk = 0
+    maxd = 0
+    for K in ospace.enumerate_dets(n - 2, [M]):
+        K = int(K)
+        d = sum(1 for r in range(M) for p in range(r)
+                if not (K >> p) & 1 and not (K >> r) & 1 and (K | 1 << p | 1 << r) in inset)
+        if d:
+            W += d * d
+            nk += 1
+            maxd = max(maxd, d)
+    return W, nk, maxd
+
+
+@pytest.mark.parametrize("n,sub,lo,hi", [
+    (3, [7], None, None),
+    (4, [4, 6], [1, 1], [3, 3]),
+    (5, [3, 3, 3], [1, 0, 1], [2, 2, 2]),
+    (2, [3, 4], [0, 1], [1, 2]),
+])
+def test_pair_counts_match_brute_force(n, sub, lo, hi):
+    c = host_ctx(n, sub, lo, hi)
+    W, nk, maxd = brute_pair_counts(n, sub, lo, hi)
+    w, npi, md = c.pair_counts()
+    assert (w, npi, md) == (W, nk, maxd)

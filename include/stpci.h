@@ -137,7 +137,12 @@ stpci_status stpci_pair_counts(const stpci_ctx* ctx, double* w_pair, int64_t* n_
 
 /* Select the sigma kernel used from the next device call on: "pair" (pair
  * intermediates, the default where N >= 2 and the largest pair degree fits the
- * per-wavefront LDS slice), "tile" (one-move intermediates of Eq. sigmaL2e,
+ * per-wavefront LDS slice; each pair contribution is stored once and summed
+ * per target in a fixed order, so sigma is deterministic, when that workspace
+ * -- n_dets * N (N - 1) / 2 * 2 scalars -- fits a quarter of the free device
+ * memory or 1 GB, else contributions are added with device atomics),
+ * "pair_atomic" (the pair kernel with device atomics), "tile" (one-move
+ * intermediates of Eq. sigmaL2e,
  * Hermitian tiles, one- and two-electron parts fused), "rowtile", "wave" and
  * "simple" (earlier one-move forms), or "auto".  All compute the same sigma;
  * a kernel that cannot handle the space makes the next device call fail with

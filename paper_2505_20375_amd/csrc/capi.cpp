@@ -20,7 +20,7 @@ stpci_ctx::~stpci_ctx() {
             (void)hipEventDestroy(e.a);
             (void)hipEventDestroy(e.b);
         }
-        for (DevBuf* b : {&d_pcats, &d_pwork, &d_pslot, &d_pA, &d_pA32, &d_gT32, &d_hp32, &d_s2blocks, &d_ygroup, &d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
+        for (DevBuf* b : {&d_E, &d_pcats, &d_pwork, &d_pslot, &d_pA, &d_pA32, &d_gT32, &d_hp32, &d_s2blocks, &d_ygroup, &d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
                           &d_hp, &d_gT, &d_hd, &d_JK, &d_V, &d_W, &d_X, &d_R, &d_T, &d_partial, &d_small, &d_topv,
                           &d_topi})
             b->free_();
@@ -100,7 +100,10 @@ int select_kernel(const stpci_ctx* c) {
     const HostSpace& H = c->hs;
     const bool ok[5] = {H.max_deg <= MAXDEG, true, sigma_wave_supported(H.max_deg), symtile_supported(H.max_deg, c->cplx),
                         pair_supported(H.sp.N, H.pmax_deg, c->cplx)};
-    if (c->kernel_req >= 0) return ok[c->kernel_req] ? c->kernel_req : -1;
+    if (c->kernel_req >= 0) {
+        const int k = c->kernel_req == 5 ? 4 : c->kernel_req;  // 5: pair kernel with device atomics
+        return ok[k] ? k : -1;
+    }
     return ok[4] ? 4 : (ok[3] ? 3 : 1);
 }
 
@@ -155,6 +158,14 @@ stpci_status prepare(stpci_ctx* c) {
         c->s2_kernel = k;
     }
     if (c->s2_kernel == 4) {
+        // scatter: store-and-reduce when its workspace fits a quarter of the
+        // free device memory (or 1 GB), device atomics otherwise
+        size_t fr = 0, tot = 0;
+        (void)hipMemGetInfo(&fr, &tot);
+        DevSpace tmp{};
+        tmp.sp = H.sp;
+        const size_t eb = pair_store_bytes(tmp, c->cplx);
+        c->pair_store = c->kernel_req != 5 && (eb <= ((size_t)1 << 30) || eb <= fr / 4);
         build_pair_table(c);
         if ((s = upload(c, c->d_pcats, H.pcats, "pair categories"))) return s;
         if ((s = upload(c, c->d_pwork, H.pwork_begin, "pair offsets"))) return s;
@@ -257,8 +268,14 @@ stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, st
     const int kind = f32 ? 2 : 1;
     if (c->s2_kernel == 4) {
         record(c, kind, true);
-        e = launch_sigma_pair(c->dev, c->hs.pmax_deg, c->cplx, f32, f32 ? c->d_pA32.p : c->d_pA.p, cin, sout, n_vec,
-                              c->e_core, c->stream);
+        void* E = nullptr;
+        if (c->pair_store) {
+            stpci_status s = ensure(c, c->d_E, pair_store_bytes(c->dev, c->cplx), "pair contribution workspace");
+            if (s) return s;
+            E = c->d_E.p;
+        }
+        e = launch_sigma_pair(c->dev, c->hs.pmax_deg, c->cplx, f32, f32 ? c->d_pA32.p : c->d_pA.p, cin, sout, E,
+                              n_vec, c->e_core, c->stream);
         record(c, kind, false);
         return e == hipSuccess ? STPCI_OK : hip_check(c, e, "sigma launch");
     }
@@ -618,15 +635,15 @@ stpci_status stpci_pair_counts(const stpci_ctx* c, double* w_pair, int64_t* n_pa
 
 stpci_status stpci_set_sigma_kernel(stpci_ctx* c, const char* name) {
     if (!c || !name) return STPCI_EINVAL;
-    static const char* names[5] = {"simple", "rowtile", "wave", "tile", "pair"};
+    static const char* names[6] = {"simple", "rowtile", "wave", "tile", "pair", "pair_atomic"};
     int k = -1;
     if (!std::strcmp(name, "auto")) k = -2;
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 6; ++i)
         if (!std::strcmp(name, names[i])) k = i;
     if (k == -1) return set_err(c, STPCI_EINVAL, "unknown sigma kernel name");
     c->kernel_req = (k == -2) ? -1 : k;
     // device copies depend on the kernel: rebuild them on the next device call
-    for (DevBuf* b : {&c->d_pcats, &c->d_pwork, &c->d_pslot, &c->d_pA, &c->d_pA32, &c->d_gT32, &c->d_hp32,
+    for (DevBuf* b : {&c->d_E, &c->d_pcats, &c->d_pwork, &c->d_pslot, &c->d_pA, &c->d_pA32, &c->d_gT32, &c->d_hp32,
                       &c->d_s2blocks, &c->d_ygroup, &c->d_hp, &c->d_gT})
         if (!c->host_only) b->free_();
     c->have32 = false;
@@ -638,7 +655,7 @@ stpci_status stpci_sigma_kernel(const stpci_ctx* c, const char** name) {
     if (!c || !name) return STPCI_EINVAL;
     static const char* names[5] = {"simple", "rowtile", "wave", "tile", "pair"};
     if (!c->prepared) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "no device call made yet");
-    *name = names[c->s2_kernel];
+    *name = (c->s2_kernel == 4 && !c->pair_store) ? "pair_atomic" : names[c->s2_kernel];
     return STPCI_OK;
 }
 

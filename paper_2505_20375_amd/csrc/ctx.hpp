@@ -77,6 +77,8 @@ struct stpci_ctx {
     stp::DevBuf d_gT32, d_hp32;
     bool have32 = false;
     stp::DevBuf d_pcats, d_pwork, d_pslot, d_pA, d_pA32;
+    stp::DevBuf d_E;         // pair contributions of the store-and-reduce scatter
+    bool pair_store = false; // pair kernel: store-and-reduce (true) or device atomics
     int kernel_req = -1;   // requested sigma kernel (stpci_set_sigma_kernel), -1: automatic
     stp::DevSpace dev{};
 

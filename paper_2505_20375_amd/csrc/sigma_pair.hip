@@ -37,6 +37,8 @@ struct PairHdr {
     int32_t voff[KMAX];      // first empty-orbital position of subspace k
     int32_t vcre[MMAX];      // creation of the empty orbital at position v on K' (sign * (rank + 1))
     uint8_t vglob[MMAX];     // global index of the empty orbital at position v
+    uint64_t kbits;          // global occupation bits of K'
+    uint64_t pad_;
 };
 static_assert(sizeof(PairHdr) % 16 == 0, "pair header alignment");
 
@@ -82,10 +84,19 @@ __host__ __device__ inline void pair_hdr_cls(const DevSpace& S, const PairCat& P
     hd->cstrb[c] = T2.stride[b];
 }
 
+// Global occupation bits of K' (after pair_hdr_sub of every subspace).
+__host__ __device__ inline void pair_hdr_bits(const DevSpace& S, PairHdr* hd) {
+    uint64_t b = 0;
+    for (int k = 0; k < S.sp.K; ++k) b |= (uint64_t)hd->str[k] << S.sp.sub_off[k];
+    hd->kbits = b;
+}
+
 // Slot `slot` < deg of K': target address, pair index r (r - 1) / 2 + p of the
-// created pair p < r, and the sign of a+_p a+_r |K'> (true: negative).
+// created pair p < r, the position q of {p, r} among the occupied pairs of the
+// target (q = i_r (i_r - 1) / 2 + i_p, i_x = occupied orbitals of the target
+// below x), and the sign of a+_p a+_r |K'> (true: negative).
 __host__ __device__ inline bool pair_slot(const DevSpace& S, const PairCat& P, const PairHdr* hd, int slot,
-                                          int64_t& addr, int& pi) {
+                                          int64_t& addr, int& pi, int& q) {
     const uint32_t info = S.pslot[P.slot_off + slot];
     const int cl = (int)(info & 255u), i = (int)((info >> 8) & 255u), j = (int)(info >> 16);
     const int a = P.cls_a[cl], b = P.cls_b[cl];
@@ -108,39 +119,46 @@ __host__ __device__ inline bool pair_slot(const DevSpace& S, const PairCat& P, c
         addr = hd->cbase[cl] + r2 * hd->cstra[cl];
     }
     pi = gr * (gr - 1) / 2 + gp;
+    const int ip = popc64(hd->kbits & ((1ULL << gp) - 1ULL));
+    const int ir = popc64(hd->kbits & ((1ULL << gr) - 1ULL)) + 1;
+    q = ir * (ir - 1) / 2 + ip;
     return neg;
 }
 
-// LDS bytes of one wavefront's slice: d and e (padded blocks), targets,
-// column offsets, row pair indices, header.
-__host__ __device__ inline size_t pair_slice(int deg_max, int nv, int sb) {
-    const size_t ne = (size_t)((deg_max + 3) >> 2) * (ST_TILE * nv + 16 / sb);
-    return 2 * ne * sb + (size_t)((deg_max + 3) & ~3) * 16 + sizeof(PairHdr);
+// LDS layout of one wavefront's slice: d (contraction type) and e (FP64),
+// targets, row pair indices, header.
+__host__ __device__ inline SliceLayout pair_layout(int deg_max, int nv, bool cplx, bool f32) {
+    const int se = cplx ? 16 : 8;
+    const int sb = f32 ? se / 2 : se;
+    return SliceLayout(deg_max, nv, sb, se, sizeof(PairHdr));
 }
 
-size_t pair_slice_bytes(int deg_max, int nv, int sb) { return pair_slice(deg_max, nv, sb); }
+size_t pair_slice_bytes(int deg_max, int nv, bool cplx, bool f32) { return pair_layout(deg_max, nv, cplx, f32).bytes; }
 
 bool pair_supported(int n_elec, int deg_max, bool cplx) {
-    return n_elec >= 2 && deg_max > 0 && pair_slice_bytes(deg_max, 2, cplx ? 16 : 8) <= 64 * 1024;
+    return n_elec >= 2 && deg_max > 0 && pair_slice_bytes(deg_max, 2, cplx, false) <= 64 * 1024;
 }
 
-template <bool CPLX, bool F32, int NV>
+// STORE: e[P] goes to E[(target * nq + q) * NV + v] (each entry written by
+// exactly one K'; k_pair_reduce sums them), else it is added to sigma with
+// device atomics.
+template <bool CPLX, bool F32, int NV, bool STORE>
 __device__ __forceinline__ void pair_det(const DevSpace& S, const typename PT<CPLX, F32>::T* __restrict__ A,
                                          const typename VT<CPLX>::T* __restrict__ c,
-                                         typename VT<CPLX>::T* __restrict__ sigma, int n_vec, int deg_cap,
-                                         unsigned char* base, int lane, int64_t J) {
+                                         typename VT<CPLX>::T* __restrict__ sigma, typename VT<CPLX>::T* __restrict__ E,
+                                         int nq, int n_vec, int deg_cap, unsigned char* base, int lane, int64_t J) {
     using V = PT<CPLX, F32>;
     using V64 = VT<CPLX>;
     using T = typename V::T;
+    using TE = typename V64::T;
     constexpr int SB = sizeof(T);
-    const int cap4 = (deg_cap + 3) & ~3;
-    const int ne = st_elems<NV, SB>(deg_cap);
-    T* dsh = reinterpret_cast<T*>(base);
-    T* esh = dsh + ne;
-    int64_t* tgt = reinterpret_cast<int64_t*>(esh + ne);
-    int32_t* coff = reinterpret_cast<int32_t*>(tgt + cap4);   // pair(Q) * npairs
-    int32_t* rinf = coff + cap4;                              // pair(P) << 1 | negative sign
-    PairHdr* hd = reinterpret_cast<PairHdr*>(rinf + cap4);
+    constexpr int SE = sizeof(TE);
+    const SliceLayout L(deg_cap, NV, SB, SE, sizeof(PairHdr));
+    T* dsh = reinterpret_cast<T*>(base + L.d_off);                 // padded [slot][NV]
+    TE* esh = reinterpret_cast<TE*>(base + L.e_off);               // padded [slot][NV], FP64
+    int64_t* tgt = reinterpret_cast<int64_t*>(base + L.tgt_off);   // target address
+    int32_t* rinf = reinterpret_cast<int32_t*>(base + L.i0_off);   // pair(P) << 1 | negative sign
+    PairHdr* hd = reinterpret_cast<PairHdr*>(base + L.x_off);
     const int K = S.sp.K;
     const int64_t nd = S.sp.ndets;
     const int w = find_segment(S.pwork_begin, S.sp.npcat, J);
@@ -154,6 +172,7 @@ __device__ __forceinline__ void pair_det(const DevSpace& S, const typename PT<CP
     wave_lds_sync();
     if (lane < S.sp.M) pair_hdr_orb(S, P, lane, hd);
     if (lane < P.ncls) pair_hdr_cls(S, P, lane, hd);
+    if (lane == 63) pair_hdr_bits(S, hd);
     wave_lds_sync();
     const int NP = S.sp.npairs;
     for (int slot = lane; slot < ((deg + 3) & ~3); slot += 64) {
@@ -161,58 +180,86 @@ __device__ __forceinline__ void pair_det(const DevSpace& S, const typename PT<CP
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 dsh[st_idx<NV, SB>(slot, v)] = V::zero();
-                esh[st_idx<NV, SB>(slot, v)] = V::zero();
+                esh[st_idx<NV, SE>(slot, v)] = V64::zero();
             }
-            coff[slot] = 0;
             rinf[slot] = 0;
             continue;
         }
         int64_t addr;
-        int pi;
-        const bool neg = pair_slot(S, P, hd, slot, addr, pi);
-        tgt[slot] = addr;
-        coff[slot] = pi * NP;
+        int pi, q;
+        const bool neg = pair_slot(S, P, hd, slot, addr, pi, q);
+        tgt[slot] = STORE ? addr * nq + q : addr;
         rinf[slot] = (pi << 1) | (neg ? 1 : 0);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             T val = (v < n_vec) ? V::from64(c[(int64_t)v * nd + addr]) : V::zero();
             if (neg) val = V::scale(val, -1.0);
             dsh[st_idx<NV, SB>(slot, v)] = val;
-            esh[st_idx<NV, SB>(slot, v)] = V::zero();
+            esh[st_idx<NV, SE>(slot, v)] = V64::zero();
         }
     }
     wave_lds_sync();
 
     // ---- phase 2: e = A_K' d
-    tile_contract<CPLX, F32, NV>(A, dsh, esh, rinf, coff, deg, lane);
+    tile_contract<CPLX, F32, NV>(A, NP, dsh, esh, rinf, deg, lane);
     wave_lds_sync();
 
     // ---- phase 3: sigma[K' + P] += sgn(P) e[P]
     for (int slot = lane; slot < deg; slot += 64) {
         const double sg = (rinf[slot] & 1) ? -1.0 : 1.0;
         const int64_t t = tgt[slot];
+        if (STORE) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-            if (v < n_vec)
-                V64::atomic_add(&sigma[(int64_t)v * nd + t], V64::scale(V::to64(esh[st_idx<NV, SB>(slot, v)]), sg));
+            for (int v = 0; v < NV; ++v) E[t * NV + v] = V64::scale(esh[st_idx<NV, SE>(slot, v)], sg);
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < n_vec)
+                    V64::atomic_add(&sigma[(int64_t)v * nd + t], V64::scale(esh[st_idx<NV, SE>(slot, v)], sg));
+        }
     }
     wave_lds_sync();  // the next K' reuses this wavefront's LDS slice
 }
 
-template <bool CPLX, bool F32, int NV>
+template <bool CPLX, bool F32, int NV, bool STORE>
 __global__ __launch_bounds__(256) void k_sigma_pair(DevSpace S, const typename PT<CPLX, F32>::T* __restrict__ A,
                                                    const typename VT<CPLX>::T* __restrict__ c,
-                                                   typename VT<CPLX>::T* __restrict__ sigma, int n_vec, int deg_cap) {
+                                                   typename VT<CPLX>::T* __restrict__ sigma,
+                                                   typename VT<CPLX>::T* __restrict__ E, int nq, int n_vec,
+                                                   int deg_cap) {
     using T = typename PT<CPLX, F32>::T;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
-    unsigned char* base = smem + (size_t)wid * pair_slice(deg_cap, NV, (int)sizeof(T));
+    unsigned char* base = smem + (size_t)wid * pair_layout(deg_cap, NV, CPLX, F32).bytes;
     const int64_t total = S.sp.npwork_dets;
     const int64_t nw = (int64_t)gridDim.x * wpb;
     for (int64_t J = (int64_t)blockIdx.x * wpb + wid; J < total; J += nw)
-        pair_det<CPLX, F32, NV>(S, A, c, sigma, n_vec, deg_cap, base, lane, J);
+        pair_det<CPLX, F32, NV, STORE>(S, A, c, sigma, E, nq, n_vec, deg_cap, base, lane, J);
+}
+
+// sigma[v][L] = e_core c[v][L] + sum_q E[(L * nq + q) * NV + v]: the pair
+// contributions of every target, summed in a fixed order.
+template <bool CPLX, int NV>
+__global__ __launch_bounds__(256) void k_pair_reduce(typename VT<CPLX>::T* __restrict__ sigma,
+                                                    const typename VT<CPLX>::T* __restrict__ c,
+                                                    const typename VT<CPLX>::T* __restrict__ E, double e_core,
+                                                    int64_t nd, int nq, int n_vec) {
+    using V64 = VT<CPLX>;
+    using TE = typename V64::T;
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < nd; L += (int64_t)gridDim.x * blockDim.x) {
+        TE acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = V64::zero();
+        const TE* e = E + L * nq * NV;
+        for (int q = 0; q < nq; ++q)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] = V64::add(acc[v], e[q * NV + v]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (v < n_vec) sigma[(int64_t)v * nd + L] = V64::add(V64::scale(c[(int64_t)v * nd + L], e_core), acc[v]);
+    }
 }
 
 // Several problems in one launch: descriptor q covers [jbegin[q], jbegin[q+1])
@@ -226,63 +273,80 @@ __global__ __launch_bounds__(256) void k_sigma_pair_multi(const SigmaDesc* __res
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
-    unsigned char* base = smem + (size_t)wid * pair_slice(deg_cap, 2, (int)sizeof(T));
+    unsigned char* base = smem + (size_t)wid * pair_layout(deg_cap, 2, CPLX, F32).bytes;
     const int64_t total = jbegin[ndesc];
     const int64_t nw = (int64_t)gridDim.x * wpb;
     for (int64_t J = (int64_t)blockIdx.x * wpb + wid; J < total; J += nw) {
         const int q = find_segment(jbegin, ndesc, J);
         const SigmaDesc& D = desc[q];
-        pair_det<CPLX, F32, 2>(D.S, (const T*)D.gT, (const T64*)D.c, (T64*)D.sigma, D.n_vec, deg_cap, base, lane,
-                               J - jbegin[q]);
+        pair_det<CPLX, F32, 2, false>(D.S, (const T*)D.gT, (const T64*)D.c, (T64*)D.sigma, nullptr, 0, D.n_vec,
+                                      deg_cap, base, lane, J - jbegin[q]);
     }
 }
 
-template <bool CPLX, bool F32, int NV>
-static hipError_t launch_pair_nv(const DevSpace& S, int deg_max, const void* A, const void* c, void* sigma, int nv,
-                                 hipStream_t st) {
+template <bool CPLX, bool F32, int NV, bool STORE>
+static hipError_t launch_pair_nv(const DevSpace& S, int deg_max, const void* A, const void* c, void* sigma, void* E,
+                                 int nq, int nv, double e_core, hipStream_t st) {
     using T = typename PT<CPLX, F32>::T;
     using T64 = typename VT<CPLX>::T;
-    const size_t per_wave = pair_slice_bytes(deg_max, NV, (int)sizeof(T));
+    const size_t per_wave = pair_slice_bytes(deg_max, NV, CPLX, F32);
     const int wpb = waves_per_group(per_wave);
     const size_t lds = per_wave * wpb;
     int64_t blocks = (S.sp.npwork_dets + wpb - 1) / wpb;
     blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, 256 * 64));
-    hipLaunchKernelGGL((k_sigma_pair<CPLX, F32, NV>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, S,
-                       (const T*)A, (const T64*)c, (T64*)sigma, nv, deg_max);
+    hipLaunchKernelGGL((k_sigma_pair<CPLX, F32, NV, STORE>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, S,
+                       (const T*)A, (const T64*)c, (T64*)sigma, (T64*)E, nq, nv, deg_max);
+    if (STORE) {
+        const int64_t nd = S.sp.ndets;
+        const int g = (int)std::max<int64_t>(1, std::min<int64_t>(16384, (nd + 255) / 256));
+        hipLaunchKernelGGL((k_pair_reduce<CPLX, NV>), dim3(g), dim3(256), 0, st, (T64*)sigma, (const T64*)c,
+                           (const T64*)E, e_core, nd, nq, nv);
+    }
     return hipGetLastError();
 }
 
 template <bool CPLX, bool F32>
 static hipError_t launch_pair_all(const DevSpace& S, int deg_max, const void* A, const void* c, void* sigma,
-                                  int n_vec, double e_core, hipStream_t st) {
+                                  void* E, int n_vec, double e_core, hipStream_t st) {
     using T64 = typename VT<CPLX>::T;
-    hipError_t e = launch_fill_init(CPLX, sigma, c, e_core, S.sp.ndets * n_vec, st);
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    const int nq = S.sp.N * (S.sp.N - 1) / 2;
+    if (!E) {
+        e = launch_fill_init(CPLX, sigma, c, e_core, S.sp.ndets * n_vec, st);
+        if (e != hipSuccess) return e;
+    }
     for (int v0 = 0; v0 < n_vec; v0 += 2) {
         const int nv = (n_vec - v0 >= 2) ? 2 : 1;
         const int64_t off = (int64_t)v0 * S.sp.ndets;
         const T64* cc = (const T64*)c + off;
         T64* ss = (T64*)sigma + off;
-        e = (nv == 2) ? launch_pair_nv<CPLX, F32, 2>(S, deg_max, A, cc, ss, 2, st)
-                      : launch_pair_nv<CPLX, F32, 1>(S, deg_max, A, cc, ss, 1, st);
+        if (E)
+            e = (nv == 2) ? launch_pair_nv<CPLX, F32, 2, true>(S, deg_max, A, cc, ss, E, nq, 2, e_core, st)
+                          : launch_pair_nv<CPLX, F32, 1, true>(S, deg_max, A, cc, ss, E, nq, 1, e_core, st);
+        else
+            e = (nv == 2) ? launch_pair_nv<CPLX, F32, 2, false>(S, deg_max, A, cc, ss, nullptr, 0, 2, 0.0, st)
+                          : launch_pair_nv<CPLX, F32, 1, false>(S, deg_max, A, cc, ss, nullptr, 0, 1, 0.0, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
+size_t pair_store_bytes(const DevSpace& S, bool cplx) {
+    return (size_t)S.sp.ndets * (size_t)(S.sp.N * (S.sp.N - 1) / 2) * 2 * (cplx ? 16 : 8);
+}
+
 hipError_t launch_sigma_pair(const DevSpace& S, int deg_max, bool cplx, bool f32, const void* A, const void* c,
-                             void* sigma, int n_vec, double e_core, hipStream_t st) {
+                             void* sigma, void* E, int n_vec, double e_core, hipStream_t st) {
     if (cplx)
-        return f32 ? launch_pair_all<true, true>(S, deg_max, A, c, sigma, n_vec, e_core, st)
-                   : launch_pair_all<true, false>(S, deg_max, A, c, sigma, n_vec, e_core, st);
-    return f32 ? launch_pair_all<false, true>(S, deg_max, A, c, sigma, n_vec, e_core, st)
-               : launch_pair_all<false, false>(S, deg_max, A, c, sigma, n_vec, e_core, st);
+        return f32 ? launch_pair_all<true, true>(S, deg_max, A, c, sigma, E, n_vec, e_core, st)
+                   : launch_pair_all<true, false>(S, deg_max, A, c, sigma, E, n_vec, e_core, st);
+    return f32 ? launch_pair_all<false, true>(S, deg_max, A, c, sigma, E, n_vec, e_core, st)
+               : launch_pair_all<false, false>(S, deg_max, A, c, sigma, E, n_vec, e_core, st);
 }
 
 hipError_t launch_sigma_pair_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
                                    int deg_max, bool cplx, bool f32, hipStream_t st) {
-    const int sb = f32 ? (cplx ? 8 : 4) : (cplx ? 16 : 8);
-    const size_t per_wave = pair_slice_bytes(deg_max, 2, sb);
+    const size_t per_wave = pair_slice_bytes(deg_max, 2, cplx, f32);
     const int wpb = waves_per_group(per_wave);
     const size_t lds = per_wave * wpb;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + wpb - 1) / wpb, 256 * 64));
@@ -322,12 +386,13 @@ int64_t check_pairs_host(const DevSpace& S, int64_t max_dets_per_cat, int64_t* n
             for (int k = 0; k < K; ++k) pair_hdr_sub(S, P, j, k, &hd);
             for (int g = 0; g < S.sp.M; ++g) pair_hdr_orb(S, P, g, &hd);
             for (int c = 0; c < P.ncls; ++c) pair_hdr_cls(S, P, c, &hd);
+            pair_hdr_bits(S, &hd);
             uint64_t Kb = 0;
             for (int k = 0; k < K; ++k) Kb |= (uint64_t)hd.str[k] << S.sp.sub_off[k];
             for (int slot = 0; slot < P.deg; ++slot) {
                 int64_t t;
-                int pi;
-                const bool neg = pair_slot(S, P, &hd, slot, t, pi);
+                int pi, q;
+                const bool neg = pair_slot(S, P, &hd, slot, t, pi, q);
                 ++checked;
                 // recover p < r from the pair index
                 int r = 1;
@@ -337,9 +402,16 @@ int64_t check_pairs_host(const DevSpace& S, int64_t max_dets_per_cat, int64_t* n
                 const uint64_t want = Kb | (1ULL << p) | (1ULL << r);
                 const int par = __builtin_popcountll(Kb & ((1ULL << r) - 1ULL)) +
                                 __builtin_popcountll(Kb & ((1ULL << p) - 1ULL));
+                // q: index of {p, r} in the list of the target's occupied pairs (i < j)
+                int occ[64], no = 0, qw = -1;
+                for (int x = 0; x < S.sp.M; ++x)
+                    if ((want >> x) & 1ULL) occ[no++] = x;
+                for (int jj = 1, n = 0; jj < no && qw < 0; ++jj)
+                    for (int ii = 0; ii < jj; ++ii, ++n)
+                        if (occ[ii] == p && occ[jj] == r) qw = n;
                 uint64_t got = 0;
                 if (!free_pr || t < 0 || t >= S.sp.ndets || !to_bits(user, t, &got) || got != want ||
-                    neg != ((par & 1) != 0))
+                    neg != ((par & 1) != 0) || q != qw)
                     ++bad;
             }
         }

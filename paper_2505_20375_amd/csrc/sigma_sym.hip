@@ -30,6 +30,13 @@
 
 namespace stp {
 
+// LDS layout of one wavefront's slice: d (contraction type), e (FP64),
+// targets, row move indices.
+__host__ __device__ inline SliceLayout symtile_layout(int deg_max, int nv, bool cplx, bool f32) {
+    const int se = cplx ? 16 : 8;
+    return SliceLayout(deg_max, nv, f32 ? se / 2 : se, se, 0);
+}
+
 // Sigma contribution of one intermediate determinant J (index over the
 // work categories of S), computed by one wavefront with its LDS slice.
 template <bool CPLX, bool F32, int NV>
@@ -41,13 +48,14 @@ __device__ __forceinline__ void symtile_det(const DevSpace& S, const typename PT
     using V = PT<CPLX, F32>;     // contraction arithmetic
     using V64 = VT<CPLX>;        // vector storage and sigma accumulation
     using T = typename V::T;
+    using TE = typename V64::T;
     constexpr int SB = sizeof(T);
-    const int ne = st_elems<NV, SB>(deg_cap);
-    T* dsh = reinterpret_cast<T*>(base);                         // padded [slot][NV]
-    T* esh = dsh + ne;                                           // padded [slot][NV]
-    int64_t* tgt = reinterpret_cast<int64_t*>(esh + ne);
-    int32_t* coff = reinterpret_cast<int32_t*>(tgt + deg_cap);   // pair(m) * M^2
-    int32_t* rinf = coff + deg_cap;                              // pair(m) << 1 | negative sign
+    constexpr int SE = sizeof(TE);
+    const SliceLayout L(deg_cap, NV, SB, SE, 0);
+    T* dsh = reinterpret_cast<T*>(base + L.d_off);                 // padded [slot][NV]
+    TE* esh = reinterpret_cast<TE*>(base + L.e_off);               // padded [slot][NV], FP64
+    int64_t* tgt = reinterpret_cast<int64_t*>(base + L.tgt_off);   // target address
+    int32_t* rinf = reinterpret_cast<int32_t*>(base + L.i0_off);   // pair(m) << 1 | negative sign
     const int M = S.sp.M;
     const int MM = M * M;
     const int64_t nd = S.sp.ndets;
@@ -67,9 +75,8 @@ __device__ __forceinline__ void symtile_det(const DevSpace& S, const typename PT
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 dsh[st_idx<NV, SB>(slot, v)] = V::zero();
-                esh[st_idx<NV, SB>(slot, v)] = V::zero();
+                esh[st_idx<NV, SE>(slot, v)] = V64::zero();
             }
-            coff[slot] = 0;
             rinf[slot] = 0;
             continue;
         }
@@ -79,7 +86,6 @@ __device__ __forceinline__ void symtile_det(const DevSpace& S, const typename PT
         const int x = S.sp.sub_off[xs] + lx, y = S.sp.sub_off[ys] + ly;
         const int pair = y * M + x;
         tgt[slot] = t;
-        coff[slot] = pair * MM;
         rinf[slot] = (pair << 1) | (sg < 0 ? 1 : 0);
         const T hv = hp[y * M + x];
 #pragma unroll
@@ -87,7 +93,7 @@ __device__ __forceinline__ void symtile_det(const DevSpace& S, const typename PT
             T val = (v < n_vec) ? V::from64(c[(int64_t)v * nd + t]) : V::zero();
             if (sg < 0) val = V::scale(val, -1.0);
             dsh[st_idx<NV, SB>(slot, v)] = val;
-            esh[st_idx<NV, SB>(slot, v)] = V::zero();
+            esh[st_idx<NV, SE>(slot, v)] = V64::zero();
             one[v] = V::mad(hv, val, one[v]);
         }
     }
@@ -101,7 +107,7 @@ __device__ __forceinline__ void symtile_det(const DevSpace& S, const typename PT
     wave_lds_sync();
 
     // ---- phase 2: e = G_J d over the upper-triangle tiles
-    tile_contract<CPLX, F32, NV>(gT, dsh, esh, rinf, coff, deg, lane);
+    tile_contract<CPLX, F32, NV>(gT, MM, dsh, esh, rinf, deg, lane);
     wave_lds_sync();
 
     // ---- phase 3: one atomic update of sigma per move and vector
@@ -111,7 +117,7 @@ __device__ __forceinline__ void symtile_det(const DevSpace& S, const typename PT
 #pragma unroll
         for (int v = 0; v < NV; ++v)
             if (v < n_vec)
-                V64::atomic_add(&sigma[(int64_t)v * nd + t], V64::scale(V::to64(esh[st_idx<NV, SB>(slot, v)]), s));
+                V64::atomic_add(&sigma[(int64_t)v * nd + t], V64::scale(esh[st_idx<NV, SE>(slot, v)], s));
     }
     wave_lds_sync();  // the next determinant reuses this wavefront's LDS slice
 }
@@ -127,8 +133,7 @@ __global__ __launch_bounds__(256) void k_sigma_symtile(DevSpace S, const typenam
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
-    const size_t slice = (size_t)2 * st_elems<NV, (int)sizeof(T)>(deg_cap) * sizeof(T) + (size_t)deg_cap * 16;
-    unsigned char* base = smem + (size_t)wid * slice;
+    unsigned char* base = smem + (size_t)wid * symtile_layout(deg_cap, NV, CPLX, F32).bytes;
     const int64_t total = S.sp.nwork_dets;
     const int64_t nw = (int64_t)gridDim.x * wpb;
     for (int64_t J = (int64_t)blockIdx.x * wpb + wid; J < total; J += nw)
@@ -146,8 +151,7 @@ __global__ __launch_bounds__(256) void k_sigma_symtile_multi(const SigmaDesc* __
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
-    const size_t slice = (size_t)2 * st_elems<2, (int)sizeof(T)>(deg_cap) * sizeof(T) + (size_t)deg_cap * 16;
-    unsigned char* base = smem + (size_t)wid * slice;
+    unsigned char* base = smem + (size_t)wid * symtile_layout(deg_cap, 2, CPLX, F32).bytes;
     const int64_t total = jbegin[ndesc];
     const int64_t nw = (int64_t)gridDim.x * wpb;
     for (int64_t J = (int64_t)blockIdx.x * wpb + wid; J < total; J += nw) {
@@ -193,12 +197,11 @@ hipError_t launch_fill_init_multi(bool cplx, const SigmaDesc* desc_dev, int ndes
     return hipGetLastError();
 }
 
-size_t symtile_slice_bytes(int deg_max, int nv, int sb) {
-    const size_t ne = (size_t)((deg_max + 3) >> 2) * (ST_TILE * nv + 16 / sb);
-    return 2 * ne * sb + (size_t)deg_max * 16;
+size_t symtile_slice_bytes(int deg_max, int nv, bool cplx, bool f32) {
+    return symtile_layout(deg_max, nv, cplx, f32).bytes;
 }
 
-bool symtile_supported(int deg_max, bool cplx) { return symtile_slice_bytes(deg_max, 2, cplx ? 16 : 8) <= 64 * 1024; }
+bool symtile_supported(int deg_max, bool cplx) { return symtile_slice_bytes(deg_max, 2, cplx, false) <= 64 * 1024; }
 
 // Waves per workgroup for a per-wave LDS slice: at most 4 and 48 KB per group.
 int waves_per_group(size_t per_wave) {
@@ -212,7 +215,7 @@ static hipError_t launch_sym_nv(const DevSpace& S, int deg_max, const void* gT, 
                                 void* sigma, int nv, hipStream_t st) {
     using T = typename PT<CPLX, F32>::T;
     using T64 = typename VT<CPLX>::T;
-    const size_t per_wave = symtile_slice_bytes(deg_max, NV, (int)sizeof(T));
+    const size_t per_wave = symtile_slice_bytes(deg_max, NV, CPLX, F32);
     const int wpb = waves_per_group(per_wave);
     const size_t lds = per_wave * wpb;
     int64_t blocks = (S.sp.nwork_dets + wpb - 1) / wpb;
@@ -251,8 +254,7 @@ hipError_t launch_sigma_symtile(const DevSpace& S, int deg_max, bool cplx, bool 
 
 hipError_t launch_sigma_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
                               int deg_max, bool cplx, bool f32, hipStream_t st) {
-    const int sb = f32 ? (cplx ? 8 : 4) : (cplx ? 16 : 8);
-    const size_t per_wave = symtile_slice_bytes(deg_max, 2, sb);
+    const size_t per_wave = symtile_slice_bytes(deg_max, 2, cplx, f32);
     const int wpb = waves_per_group(per_wave);
     const size_t lds = per_wave * wpb;
     int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + wpb - 1) / wpb, 256 * 64));

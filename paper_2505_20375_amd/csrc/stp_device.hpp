@@ -151,6 +151,7 @@ __host__ __device__ __forceinline__ int nth_set(uint32_t v, int i) {
 
 __host__ __device__ __forceinline__ uint32_t lowmask(int m) { return (m >= 32) ? 0xffffffffu : ((1u << m) - 1u); }
 __host__ __device__ __forceinline__ int popc32(uint32_t v) { return __builtin_popcount(v); }
+__host__ __device__ __forceinline__ int popc64(uint64_t v) { return __builtin_popcountll(v); }
 
 // Apply the move of class `cls` (local orbitals lx in xs, ly in ys) to d.
 // Returns the vector address of the target and its sign.

@@ -111,7 +111,7 @@ def test_sigma_config2_full_size_sampled_rows():
     assert rel_err(s_gpu[rows], s_ref) <= TOL
 
 
-@pytest.mark.parametrize("kernel", ["pair", "tile", "rowtile", "wave", "simple"])
+@pytest.mark.parametrize("kernel", ["pair", "pair_atomic", "tile", "rowtile", "wave", "simple"])
 @pytest.mark.parametrize("name", ["T4", "c1"])
 def test_every_kernel_matches_oracle(kernel, name):
     """Each sigma kernel (pair intermediates, one-move Hermitian tiles and the
@@ -132,7 +132,7 @@ def test_default_kernel_is_pair():
     assert ctx.sigma_kernel() == "pair"
 
 
-@pytest.mark.parametrize("kernel", ["pair", "tile", "rowtile"])
+@pytest.mark.parametrize("kernel", ["pair", "pair_atomic", "tile", "rowtile"])
 def test_core_energy_term(kernel):
     """sigma includes e_core * c."""
     import torch
@@ -143,3 +143,18 @@ def test_core_energy_term(kernel):
     c = pb.vector()
     ref = csc.sigma(pb.dets, pb.h, pb.g, c, e_core=ints.e_core)
     assert rel_err(_run_sigma(pb, c, kernel=kernel), ref) <= TOL
+
+
+def test_pair_store_mode_is_deterministic():
+    """The store-and-reduce scatter sums every target's contributions in a
+    fixed order: repeated sigma builds are bitwise equal."""
+    import torch
+    pb = Problem.named("T4")
+    ctx = pb.context()
+    x = pb.to_device(pb.vector())
+    a, b = torch.empty_like(x), torch.empty_like(x)
+    ctx.sigma(x, a)
+    ctx.sigma(x, b)
+    torch.cuda.synchronize()
+    assert ctx.sigma_kernel() == "pair"
+    assert torch.equal(a, b)

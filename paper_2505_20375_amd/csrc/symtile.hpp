@@ -102,23 +102,26 @@ __device__ __forceinline__ void tile_contract(const typename PT<CPLX, F32>::T* _
 
     // table offsets: rows of block b (reread when b changes), columns of one
     // half tile (2 columns) of block bp
+    // (byte offsets from the table base, 32-bit: the table is below 4 GB)
     constexpr int H = ST_TILE / 2;
-    int ro[ST_TILE], co[H];
+    const char* tb = reinterpret_cast<const char*>(tab);
+    uint32_t ro[ST_TILE], co[H];
     int lrb = -1;
     auto offsets = [&](const TileWalk& w, int half) {
         if (w.b != lrb) {
             lrb = w.b;
 #pragma unroll
-            for (int r = 0; r < ST_TILE; ++r) ro[r] = rinf[w.b * ST_TILE + r] >> 1;
+            for (int r = 0; r < ST_TILE; ++r) ro[r] = (uint32_t)(rinf[w.b * ST_TILE + r] >> 1) * (uint32_t)sizeof(T);
         }
 #pragma unroll
-        for (int k = 0; k < H; ++k) co[k] = (rinf[w.bp * ST_TILE + half * H + k] >> 1) * stride;
+        for (int k = 0; k < H; ++k)
+            co[k] = (uint32_t)(rinf[w.bp * ST_TILE + half * H + k] >> 1) * (uint32_t)(stride * (int)sizeof(T));
     };
     auto load = [&](T (&g)[H][ST_TILE]) {
 #pragma unroll
         for (int k = 0; k < H; ++k)
 #pragma unroll
-            for (int r = 0; r < ST_TILE; ++r) g[k][r] = tab[co[k] + ro[r]];
+            for (int r = 0; r < ST_TILE; ++r) g[k][r] = *reinterpret_cast<const T*>(tb + (co[k] + ro[r]));
     };
 
     TileWalk cw{nb, 0, 0};   // tile being contracted
@@ -149,7 +152,8 @@ __device__ __forceinline__ void tile_contract(const typename PT<CPLX, F32>::T* _
                     erow[r][v] = V::zero();
                 }
         }
-        const bool offdiag = cw.bp != cw.b;
+        // diagonal tiles add their full 4 x 4 block through the rows only
+        const double cscale = (cw.bp != cw.b) ? 1.0 : 0.0;
 #pragma unroll
         for (int k = 0; k < H; ++k) {
             const int s = cw.bp * ST_TILE + half * H + k;
@@ -166,10 +170,8 @@ __device__ __forceinline__ void tile_contract(const typename PT<CPLX, F32>::T* _
                     erow[r][v] = V::mad(g[k][r], dcol[v], erow[r][v]);
                     ecol[v] = V::cmad(g[k][r], drow[r][v], ecol[v]);
                 }
-            if (offdiag && s < deg) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) IO::add_e(esh, s, v, ecol[v]);
-            }
+            for (int v = 0; v < NV; ++v) IO::add_e(esh, s, v, V::scale(ecol[v], cscale));
         }
     };
 

@@ -40,6 +40,9 @@ def _load():
         lib.oracle_h_row.argtypes = [ctypes.c_int, I64, P, P, P, ctypes.c_double, I64, P, I64]
         lib.oracle_h_row.restype = I64
         lib.oracle_diag.argtypes = [ctypes.c_int, I64, P, P, P, ctypes.c_double, P, ctypes.c_int]
+        lib.oracle_h_row_window.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, ctypes.c_double,
+                                            ctypes.c_uint64, P, P, I64]
+        lib.oracle_h_row_window.restype = I64
         _lib = lib
     return _lib
 
@@ -94,6 +97,29 @@ def h_row(dets, h, g, row, e_core=0.0):
         cap = int(n)
     buf = buf[:3 * n].reshape(n, 3)
     return buf[:, 0].astype(np.int64), buf[:, 1] + 1j * buf[:, 2]
+
+
+def h_row_window(sub, lo, hi, h, g, bits, e_core=0.0):
+    """Row of P H P for determinant `bits` of the windowed space (subspace
+    sizes sub, windows [lo, hi]) without a determinant list: (column bit
+    strings, values), the diagonal first."""
+    lib = _load()
+    h, g = _c128(h), _c128(g)
+    K = len(sub)
+    lo = list(lo) if lo is not None else [0] * K
+    hi = list(hi) if hi is not None else list(sub)
+    arr = lambda x: np.ascontiguousarray(x, dtype=np.int32)
+    sub_a, lo_a, hi_a = arr(sub), arr(lo), arr(hi)
+    cap = 1 << 16
+    while True:
+        ob = np.zeros(cap, dtype=np.uint64)
+        ov = np.zeros(2 * cap)
+        n = lib.oracle_h_row_window(h.shape[0], K, _ptr(sub_a), _ptr(lo_a), _ptr(hi_a), _ptr(h), _ptr(g),
+                                    float(e_core), ctypes.c_uint64(int(bits)), _ptr(ob), _ptr(ov), cap)
+        if n <= cap:
+            break
+        cap = int(n)
+    return ob[:n], ov[0:2 * n:2] + 1j * ov[1:2 * n:2]
 
 
 def diag(dets, h, g, e_core=0.0, nthreads=0):

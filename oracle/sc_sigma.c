@@ -229,6 +229,63 @@ int64_t oracle_h_row(int M, int64_t n, const uint64_t* dets, const double* h, co
     return w;
 }
 
+/* Row L of P H P for a windowed space given by its subspaces (contiguous,
+ * sizes sub[k], electron windows [lo[k], hi[k]]), without a determinant list:
+ * every determinant reached from L by at most two electron moves is kept when
+ * its subspace occupations lie in the windows.  Writes (bits, re, im) triples
+ * (bits stored through a uint64 view) and returns the count (at most cap are
+ * written).  Used on spaces too large to enumerate. */
+static int in_windows(uint64_t b, int K, const int* sub, const int* lo, const int* hi) {
+    int off = 0;
+    for (int k = 0; k < K; ++k) {
+        uint64_t m = (sub[k] >= 64) ? ~0ULL : (((1ULL << sub[k]) - 1ULL) << off);
+        int n = popc(b & m);
+        if (n < lo[k] || n > hi[k]) return 0;
+        off += sub[k];
+    }
+    return 1;
+}
+
+int64_t oracle_h_row_window(int M, int K, const int* sub, const int* lo, const int* hi, const double* h,
+                            const double* g, double e_core, uint64_t L, uint64_t* bits, double* vals, int64_t cap) {
+    ham_t H = {M, (const cplx*)h, (const cplx*)g, e_core};
+    int occ[64], vir[64];
+    int no = occ_list(L, occ), nv = 0;
+    for (int i = 0; i < M; ++i) if (!(L & (1ULL << i))) vir[nv++] = i;
+    int64_t w = 0;
+#define EMITB(b, val) do { if (w < cap) { bits[w] = (b); vals[2 * w] = creal(val); vals[2 * w + 1] = cimag(val); } \
+        ++w; } while (0)
+    EMITB(L, diag_elem(&H, L));
+    for (int a = 0; a < no; ++a)
+        for (int b = 0; b < nv; ++b) {
+            int p = occ[a], q = vir[b];
+            uint64_t Kd = (L & ~(1ULL << p)) | (1ULL << q);
+            if (!in_windows(Kd, K, sub, lo, hi)) continue;
+            int s2 = 1;
+            uint64_t u1 = 0, u2 = 0;
+            annih(Kd, q, &u1, &s2);
+            creat(u1, p, &u2, &s2);
+            EMITB(Kd, (double)s2 * single_elem(&H, Kd, p, q));
+        }
+    for (int a = 0; a < no; ++a)
+        for (int a2 = a + 1; a2 < no; ++a2)
+            for (int b = 0; b < nv; ++b)
+                for (int b2 = b + 1; b2 < nv; ++b2) {
+                    int p = occ[a], r = occ[a2], q = vir[b], s = vir[b2];
+                    uint64_t Kd = (L & ~((1ULL << p) | (1ULL << r))) | (1ULL << q) | (1ULL << s);
+                    if (!in_windows(Kd, K, sub, lo, hi)) continue;
+                    int sg = 1;
+                    uint64_t t1 = 0, t2 = 0, t3 = 0, t4 = 0;
+                    annih(Kd, q, &t1, &sg);
+                    annih(t1, s, &t2, &sg);
+                    creat(t2, r, &t3, &sg);
+                    creat(t3, p, &t4, &sg);
+                    EMITB(Kd, (double)sg * double_elem(&H, p, q, r, s));
+                }
+#undef EMITB
+    return w;
+}
+
 /* Diagonal elements <b|H|b> for a list of determinants (real part). */
 void oracle_diag(int M, int64_t n, const uint64_t* dets, const double* h, const double* g,
                  double e_core, double* out, int nthreads) {

@@ -7,6 +7,7 @@ Used by the tests to move seeded vectors between the oracle's order
 (ascending bitstring) and the library's layout.
 """
 import itertools
+import math
 
 import numpy as np
 
@@ -52,3 +53,46 @@ class Perm:
         out = np.empty_like(x_lib)
         out[self.idx] = x_lib
         return out
+
+
+def local_rank(mask):
+    """Position of `mask` among the masks of equal popcount sorted ascending:
+    the number of smaller masks with as many bits, counted by choosing, for
+    each set bit i (at bit position b), the masks that agree above b and have
+    0 at b: C(b, i + 1) of them."""
+    r, i = 0, 0
+    b = 0
+    while mask:
+        if mask & 1:
+            r += math.comb(b, i + 1)
+            i += 1
+        mask >>= 1
+        b += 1
+    return r
+
+
+def address(bits, n_elec, sub, lo=None, hi=None):
+    """Vector address of determinant `bits` under the documented layout, or -1."""
+    lo = list(lo) if lo is not None else [0] * len(sub)
+    hi = list(hi) if hi is not None else list(sub)
+    bits = int(bits)
+    loc, occ, off = [], [], 0
+    for m in sub:
+        s = (bits >> off) & ((1 << m) - 1)
+        loc.append(s)
+        occ.append(bin(s).count("1"))
+        off += m
+    cats = categories(n_elec, sub, lo, hi)
+    t = tuple(occ)
+    if t not in cats:
+        return -1
+    base = 0
+    for c in cats:
+        if c == t:
+            break
+        base += math.prod(math.comb(m, n) for m, n in zip(sub, c))
+    a, stride = 0, 1
+    for k in reversed(range(len(sub))):
+        a += local_rank(loc[k]) * stride
+        stride *= math.comb(sub[k], t[k])
+    return base + a

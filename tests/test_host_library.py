@@ -211,3 +211,16 @@ def test_pair_counts_match_brute_force(n, sub, lo, hi):
     W, nk, maxd = brute_pair_counts(n, sub, lo, hi)
     w, npi, md = c.pair_counts()
     assert (w, npi, md) == (W, nk, maxd)
+
+
+@pytest.mark.parametrize("n,sub,lo,hi", [
+    (5, [4, 4, 4], [1, 1, 1], [2, 3, 2]),
+    (4, [4, 6], [1, 1], [3, 3]),
+    (3, [9], None, None),
+])
+def test_layout_address_formula(n, sub, lo, hi):
+    """The closed-form address of the test layout module agrees with its
+    explicit enumeration (and therefore with the library, test above)."""
+    ref = layout.layout_dets(n, sub, lo, hi)
+    for a, b in enumerate(ref):
+        assert layout.address(int(b), n, sub, lo, hi) == a

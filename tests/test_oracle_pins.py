@@ -208,3 +208,23 @@ def test_gap_bound_holds_on_exact_spectrum():
     g_lo = bounds.gap_lower_bound(th[0], th[1], rn[1])
     if g_lo > 0:
         assert abs(th[0] - w[0]) <= bounds.gap_bound(rn[0], g_lo) + 1e-14
+
+
+@pytest.mark.parametrize("n,sub,lo,hi", [
+    (4, [4, 6], [1, 1], [3, 3]),
+    (5, [4, 4, 4], [1, 1, 1], [2, 3, 2]),
+    (4, [10], None, None),
+])
+def test_windowed_row_equals_listed_row(n, sub, lo, hi):
+    """The list-free row of P H P (used on spaces too large to enumerate)
+    equals the row taken over the explicit determinant list."""
+    M = sum(sub)
+    ints = synth.complex_integrals(M, 55)
+    dets = space.enumerate_dets(n, sub, lo, hi)
+    for row in (0, len(dets) // 3, len(dets) - 1):
+        idx, v1 = csc.h_row(dets, ints.h, ints.g, row, e_core=0.7)
+        bits, v2 = csc.h_row_window(sub, lo, hi, ints.h, ints.g, int(dets[row]), e_core=0.7)
+        a = dict(zip(dets[idx].tolist(), v1))
+        b = dict(zip(bits.tolist(), v2))
+        assert a.keys() == b.keys()
+        assert max(abs(a[k] - b[k]) for k in a) < 1e-14

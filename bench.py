@@ -5,11 +5,13 @@ integrals seeded as (pq|rs) = sum_P L^P_pq L^P_rs with a rank-32 Hermitian
 factor (entries N(0, 0.03)); 2 roots, so one step is the sigma build of the
 2 new Davidson directions (n_vec = 2), inputs resident in HBM.
 Metric: det-updates/s = nnz(H) * n_vec / t_step (nonzero couplings applied
-per second).  Also reported: the dominant kernel against its roofline, the
-Davidson solve latency (p50/p99) at the 1e-8 Eh certificate, and the CPU
-oracle on a bounded sample of rows.
+per second).  Also reported: the dominant kernel against its roofline (HIP
+events recorded by the library around that kernel), the FP32-contraction
+form, the Davidson solve latency (p50/p99) with its gap-theorem energy bound,
+a continuous-batching serving run, and the CPU oracle on a bounded sample of
+rows.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-solve]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-solve] [--serve N]
 """
 from __future__ import annotations
 
@@ -103,6 +105,7 @@ def main():
     wall = time.perf_counter() - t0
     ms_ev = ev0.elapsed_time(ev1)
     n2, t2 = ctx.kernel_time("sigma")
+    n3, t3 = ctx.kernel_time("sigma_reduce")
     ctx.profile(False)
     ms_per_step = ms_ev / args.steps
     value = info.nnz_h * n_vec / (ms_per_step * 1e-3)
@@ -127,6 +130,7 @@ def main():
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": _traffic(n_vec, kname),
             "avg_launch_ms": round(avg2, 4), "launches": n2, "flops_per_launch": flops,
             "algorithmic_bytes_per_launch": 2 * n_vec * n * 16,
+            "reduce_avg_ms": round(t3 / n3, 4) if n3 else None,
             "paper_formulation_flops_per_launch": flops_paper,
             "paper_formulation_equiv_tflops": round(achieved_paper, 3),
             "frac_paper_formulation": round(achieved_paper / FP64_PEAK_TFLOPS, 4)}

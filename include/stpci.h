@@ -204,9 +204,13 @@ stpci_status stpci_dav_stats(const stpci_ctx* ctx, int* sigma_fp64, int* sigma_f
 
 /* Kernel timing with HIP events on the context stream.  enable != 0 starts
  * recording every kernel launch of the sigma build; stpci_kernel_time
- * returns, for kernel `name` ("sigma1e", "sigma2e" -- the whole fused pass
- * when the one-electron term is folded in -- or "sigma_fp32"), the number of recorded
- * launches and their summed duration in milliseconds (synchronises). */
+ * returns, for kernel `name`, the number of recorded launches and their
+ * summed duration in milliseconds (synchronises).  Names: "sigma" (alias
+ * "sigma2e": the FP64 one-pass sigma kernel -- the pair kernel, or the fused
+ * one-move kernel), "sigma_fp32" (the same with the FP32 contraction),
+ * "sigma_reduce" (the per-target sum of the pair kernel's store-and-reduce
+ * scatter), "sigma1e" (the separate one-electron kernel of the earlier
+ * one-move forms). */
 stpci_status stpci_profile(stpci_ctx* ctx, int enable);
 stpci_status stpci_kernel_time(stpci_ctx* ctx, const char* name, int64_t* launches, double* total_ms);
 

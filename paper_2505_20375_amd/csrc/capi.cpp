@@ -267,7 +267,16 @@ stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, st
     }
     const int kind = f32 ? 2 : 1;
     if (c->s2_kernel == 4) {
-        record(c, kind, true);
+        // events bracket the pair kernel (kind 1 or 2) and the reduce (kind 3) separately
+        struct Mark {
+            stpci_ctx* c;
+            int kind;
+            static void fn(void* u, int what, bool start) {
+                Mark* m = static_cast<Mark*>(u);
+                record(m->c, what == 0 ? m->kind : 3, start);
+            }
+        } mark{c, kind};
+        const LaunchMarks mk{&Mark::fn, &mark};
         void* E = nullptr;
         if (c->pair_store) {
             stpci_status s = ensure(c, c->d_E, pair_store_bytes(c->dev, c->cplx), "pair contribution workspace");
@@ -275,8 +284,7 @@ stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, st
             E = c->d_E.p;
         }
         e = launch_sigma_pair(c->dev, c->hs.pmax_deg, c->cplx, f32, f32 ? c->d_pA32.p : c->d_pA.p, cin, sout, E,
-                              n_vec, c->e_core, c->stream);
-        record(c, kind, false);
+                              n_vec, c->e_core, c->profile ? &mk : nullptr, c->stream);
         return e == hipSuccess ? STPCI_OK : hip_check(c, e, "sigma launch");
     }
     if (c->s2_kernel == 3) {
@@ -605,6 +613,7 @@ stpci_status stpci_kernel_time(stpci_ctx* c, const char* name, int64_t* launches
     if (!std::strcmp(name, "sigma1e")) kind = 0;
     if (!std::strcmp(name, "sigma2e") || !std::strcmp(name, "sigma")) kind = 1;
     if (!std::strcmp(name, "sigma_fp32")) kind = 2;
+    if (!std::strcmp(name, "sigma_reduce")) kind = 3;
     if (kind < 0) return set_err(c, STPCI_EINVAL, "unknown kernel name");
     if (c->host_only) return set_err(c, STPCI_ESTATE, "host-only context");
     stpci_status s = hip_check(c, hipStreamSynchronize(c->stream), "stream sync");

@@ -28,8 +28,13 @@ size_t pair_slice_bytes(int deg_max, int nv, bool cplx, bool f32);
 // E: NULL (accumulate with device atomics) or pair_store_bytes of workspace
 // (each pair contribution stored once, then summed per target: deterministic)
 size_t pair_store_bytes(const DevSpace& S, bool cplx);
+// optional callback around each launch (what: 0 the pair kernel, 1 the reduce)
+struct LaunchMarks {
+    void (*fn)(void* user, int what, bool start);
+    void* user;
+};
 hipError_t launch_sigma_pair(const DevSpace& S, int deg_max, bool cplx, bool f32, const void* A, const void* c,
-                             void* sigma, void* E, int n_vec, double e_core, hipStream_t st);
+                             void* sigma, void* E, int n_vec, double e_core, const LaunchMarks* mk, hipStream_t st);
 hipError_t launch_sigma_pair_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
                                    int deg_max, bool cplx, bool f32, hipStream_t st);
 // sigma <- e_core * c (zero when e_core == 0)

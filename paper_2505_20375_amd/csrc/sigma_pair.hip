@@ -286,7 +286,7 @@ __global__ __launch_bounds__(256) void k_sigma_pair_multi(const SigmaDesc* __res
 
 template <bool CPLX, bool F32, int NV, bool STORE>
 static hipError_t launch_pair_nv(const DevSpace& S, int deg_max, const void* A, const void* c, void* sigma, void* E,
-                                 int nq, int nv, double e_core, hipStream_t st) {
+                                 int nq, int nv, double e_core, const LaunchMarks* mk, hipStream_t st) {
     using T = typename PT<CPLX, F32>::T;
     using T64 = typename VT<CPLX>::T;
     const size_t per_wave = pair_slice_bytes(deg_max, NV, CPLX, F32);
@@ -294,20 +294,24 @@ static hipError_t launch_pair_nv(const DevSpace& S, int deg_max, const void* A, 
     const size_t lds = per_wave * wpb;
     int64_t blocks = (S.sp.npwork_dets + wpb - 1) / wpb;
     blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, 256 * 64));
+    if (mk) mk->fn(mk->user, 0, true);
     hipLaunchKernelGGL((k_sigma_pair<CPLX, F32, NV, STORE>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, S,
                        (const T*)A, (const T64*)c, (T64*)sigma, (T64*)E, nq, nv, deg_max);
+    if (mk) mk->fn(mk->user, 0, false);
     if (STORE) {
         const int64_t nd = S.sp.ndets;
         const int g = (int)std::max<int64_t>(1, std::min<int64_t>(16384, (nd + 255) / 256));
+        if (mk) mk->fn(mk->user, 1, true);
         hipLaunchKernelGGL((k_pair_reduce<CPLX, NV>), dim3(g), dim3(256), 0, st, (T64*)sigma, (const T64*)c,
                            (const T64*)E, e_core, nd, nq, nv);
+        if (mk) mk->fn(mk->user, 1, false);
     }
     return hipGetLastError();
 }
 
 template <bool CPLX, bool F32>
 static hipError_t launch_pair_all(const DevSpace& S, int deg_max, const void* A, const void* c, void* sigma,
-                                  void* E, int n_vec, double e_core, hipStream_t st) {
+                                  void* E, int n_vec, double e_core, const LaunchMarks* mk, hipStream_t st) {
     using T64 = typename VT<CPLX>::T;
     hipError_t e;
     const int nq = S.sp.N * (S.sp.N - 1) / 2;
@@ -321,11 +325,11 @@ static hipError_t launch_pair_all(const DevSpace& S, int deg_max, const void* A,
         const T64* cc = (const T64*)c + off;
         T64* ss = (T64*)sigma + off;
         if (E)
-            e = (nv == 2) ? launch_pair_nv<CPLX, F32, 2, true>(S, deg_max, A, cc, ss, E, nq, 2, e_core, st)
-                          : launch_pair_nv<CPLX, F32, 1, true>(S, deg_max, A, cc, ss, E, nq, 1, e_core, st);
+            e = (nv == 2) ? launch_pair_nv<CPLX, F32, 2, true>(S, deg_max, A, cc, ss, E, nq, 2, e_core, mk, st)
+                          : launch_pair_nv<CPLX, F32, 1, true>(S, deg_max, A, cc, ss, E, nq, 1, e_core, mk, st);
         else
-            e = (nv == 2) ? launch_pair_nv<CPLX, F32, 2, false>(S, deg_max, A, cc, ss, nullptr, 0, 2, 0.0, st)
-                          : launch_pair_nv<CPLX, F32, 1, false>(S, deg_max, A, cc, ss, nullptr, 0, 1, 0.0, st);
+            e = (nv == 2) ? launch_pair_nv<CPLX, F32, 2, false>(S, deg_max, A, cc, ss, nullptr, 0, 2, 0.0, mk, st)
+                          : launch_pair_nv<CPLX, F32, 1, false>(S, deg_max, A, cc, ss, nullptr, 0, 1, 0.0, mk, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -336,12 +340,12 @@ size_t pair_store_bytes(const DevSpace& S, bool cplx) {
 }
 
 hipError_t launch_sigma_pair(const DevSpace& S, int deg_max, bool cplx, bool f32, const void* A, const void* c,
-                             void* sigma, void* E, int n_vec, double e_core, hipStream_t st) {
+                             void* sigma, void* E, int n_vec, double e_core, const LaunchMarks* mk, hipStream_t st) {
     if (cplx)
-        return f32 ? launch_pair_all<true, true>(S, deg_max, A, c, sigma, E, n_vec, e_core, st)
-                   : launch_pair_all<true, false>(S, deg_max, A, c, sigma, E, n_vec, e_core, st);
-    return f32 ? launch_pair_all<false, true>(S, deg_max, A, c, sigma, E, n_vec, e_core, st)
-               : launch_pair_all<false, false>(S, deg_max, A, c, sigma, E, n_vec, e_core, st);
+        return f32 ? launch_pair_all<true, true>(S, deg_max, A, c, sigma, E, n_vec, e_core, mk, st)
+                   : launch_pair_all<true, false>(S, deg_max, A, c, sigma, E, n_vec, e_core, mk, st);
+    return f32 ? launch_pair_all<false, true>(S, deg_max, A, c, sigma, E, n_vec, e_core, mk, st)
+               : launch_pair_all<false, false>(S, deg_max, A, c, sigma, E, n_vec, e_core, mk, st);
 }
 
 hipError_t launch_sigma_pair_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,

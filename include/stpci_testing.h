@@ -10,7 +10,7 @@
 extern "C" {
 #endif
 
-/* Eigen-decomposition of a Hermitian n x n matrix with the host Jacobi
+/* Eigen-decomposition of a Hermitian n x n matrix with the host eigensolver
  * solver that the Davidson driver uses for its projected problem.
  * A: host [n][n] complex (interleaved), read only; w: n eigenvalues
  * ascending; V: [n][n] complex, eigenvectors as columns.  Host memory only;

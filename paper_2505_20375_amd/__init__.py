@@ -357,7 +357,7 @@ class Server:
 
 
 def heev(A):
-    """Host Jacobi eigensolver used by the Davidson driver (exposed for tests)."""
+    """Host Hermitian eigensolver used by the Davidson driver (exposed for tests)."""
     A = np.ascontiguousarray(A, dtype=np.complex128)
     n = A.shape[0]
     w = np.zeros(n)

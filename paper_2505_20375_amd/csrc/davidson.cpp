@@ -2,13 +2,14 @@
 // r = HC - EC appended after preconditioning, convergence on ||r||;
 // preconditioner of Eq. sparsePreconditioner with the 1e-12 guard).
 // Vectors stay on the device; only the small projected problem (at most 64 x
-// 64) is solved on the host with a cyclic complex Jacobi method.
+// 64) is solved on the host (Householder tridiagonalisation and implicit QL).
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <limits>
 #include <numeric>
 #include <sstream>
 
@@ -22,62 +23,128 @@ namespace stp {
 
 // Eigen-decomposition of a Hermitian n x n matrix A (row-major), eigenvalues
 // ascending in w, eigenvectors as columns of V (row-major n x n).
-void jacobi_heev(int n, std::vector<cplx> A, std::vector<double>& w, std::vector<cplx>& V) {
-    V.assign((size_t)n * n, cplx(0, 0));
-    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+// Householder reduction to tridiagonal form, A = Q T Q^H, a diagonal phase
+// change D that makes the off-diagonal of T real and non-negative, then the
+// implicit QL iteration with Wilkinson shifts on the real symmetric
+// tridiagonal matrix, T = D Z L Z^T D^H, so that V = Q D Z.
+void herm_eig(int n, std::vector<cplx> A, std::vector<double>& w, std::vector<cplx>& V) {
     auto a = [&](int i, int j) -> cplx& { return A[(size_t)i * n + j]; };
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0, tot = 0;
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) {
-                double x = std::norm(a(i, j));
-                tot += x;
-                if (i != j) off += x;
-            }
-        if (off <= 1e-30 * std::max(tot, 1e-300)) break;
-        for (int p = 0; p < n - 1; ++p)
-            for (int q = p + 1; q < n; ++q) {
-                cplx apq = a(p, q);
-                double r = std::abs(apq);
-                if (r < 1e-300) continue;
-                cplx ph = apq / r;  // e^{i phi}
-                double app = a(p, p).real(), aqq = a(q, q).real();
-                double tau = (aqq - app) / (2.0 * r);
-                double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
-                double cs = 1.0 / std::sqrt(1.0 + t * t), sn = t * cs;
-                // J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] on (p, q)
-                cplx Jpp = cs, Jpq = sn, Jqp = -sn * std::conj(ph), Jqq = cs * std::conj(ph);
-                for (int k = 0; k < n; ++k) {  // columns: A <- A J
-                    cplx akp = a(k, p), akq = a(k, q);
-                    a(k, p) = akp * Jpp + akq * Jqp;
-                    a(k, q) = akp * Jpq + akq * Jqq;
-                }
-                for (int k = 0; k < n; ++k) {  // rows: A <- J^H A
-                    cplx apk = a(p, k), aqk = a(q, k);
-                    a(p, k) = std::conj(Jpp) * apk + std::conj(Jqp) * aqk;
-                    a(q, k) = std::conj(Jpq) * apk + std::conj(Jqq) * aqk;
-                }
-                a(p, q) = 0;
-                a(q, p) = 0;
-                a(p, p) = a(p, p).real();
-                a(q, q) = a(q, q).real();
-                for (int k = 0; k < n; ++k) {
-                    cplx vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
-                    V[(size_t)k * n + p] = vkp * Jpp + vkq * Jqp;
-                    V[(size_t)k * n + q] = vkp * Jpq + vkq * Jqq;
-                }
-            }
+    std::vector<cplx> Q((size_t)n * n, cplx(0, 0));
+    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+    std::vector<cplx> v(n), p(n);
+    // ---- Householder: zero column k below its subdiagonal entry
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m0 = k + 1;
+        double xn2 = 0;
+        for (int i = m0; i < n; ++i) xn2 += std::norm(a(i, k));
+        const double xn = std::sqrt(xn2);
+        if (xn == 0.0) continue;
+        const cplx x0 = a(m0, k);
+        const cplx ph = (std::abs(x0) > 0) ? x0 / std::abs(x0) : cplx(1, 0);
+        const cplx alpha = -ph * xn;
+        double vn2 = 0;
+        for (int i = m0; i < n; ++i) {
+            v[i] = a(i, k);
+            if (i == m0) v[i] -= alpha;
+            vn2 += std::norm(v[i]);
+        }
+        if (vn2 == 0.0) continue;
+        const double tau = 2.0 / vn2;
+        // p = tau * A_sub v over the trailing block, q = p - (tau/2)(v^H p) v
+        for (int i = m0; i < n; ++i) {
+            cplx t = 0;
+            for (int j = m0; j < n; ++j) t += a(i, j) * v[j];
+            p[i] = tau * t;
+        }
+        cplx vp = 0;
+        for (int i = m0; i < n; ++i) vp += std::conj(v[i]) * p[i];
+        for (int i = m0; i < n; ++i) p[i] -= 0.5 * tau * vp * v[i];
+        for (int i = m0; i < n; ++i)
+            for (int j = m0; j < n; ++j) a(i, j) -= v[i] * std::conj(p[j]) + p[i] * std::conj(v[j]);
+        a(m0, k) = alpha;
+        a(k, m0) = std::conj(alpha);
+        for (int i = m0 + 1; i < n; ++i) a(i, k) = a(k, i) = 0;
+        // Q <- Q H, H = I - tau v v^H
+        for (int r = 0; r < n; ++r) {
+            cplx t = 0;
+            for (int j = m0; j < n; ++j) t += Q[(size_t)r * n + j] * v[j];
+            t *= tau;
+            for (int j = m0; j < n; ++j) Q[(size_t)r * n + j] -= t * std::conj(v[j]);
+        }
     }
+    // ---- real tridiagonal: d (diagonal), e[i] = |T[i+1][i]|, phases D
+    std::vector<double> d(n), e(n, 0.0);
+    std::vector<cplx> D(n, cplx(1, 0));
+    for (int i = 0; i < n; ++i) d[i] = a(i, i).real();
+    for (int i = 0; i + 1 < n; ++i) {
+        const cplx t = a(i + 1, i);
+        e[i] = std::abs(t);
+        D[i + 1] = (e[i] > 0) ? D[i] * (t / e[i]) : D[i];
+    }
+    // ---- implicit QL with Wilkinson shifts, rotations accumulated in Z
+    std::vector<double> Z((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+    const double eps = std::numeric_limits<double>::epsilon();
+    for (int l = 0; l < n; ++l) {
+        for (int iter = 0; iter < 100; ++iter) {
+            int m = l;
+            for (; m + 1 < n; ++m) {
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= eps * dd) break;
+            }
+            if (m == l) break;
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+            double sn = 1.0, cs = 1.0, pp = 0.0;
+            int i = m - 1;
+            bool early = false;
+            for (; i >= l; --i) {
+                const double f = sn * e[i], b = cs * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {  // split: deflate and restart
+                    d[i + 1] -= pp;
+                    e[m] = 0.0;
+                    early = true;
+                    break;
+                }
+                sn = f / r;
+                cs = g / r;
+                g = d[i + 1] - pp;
+                r = (d[i] - g) * sn + 2.0 * cs * b;
+                pp = sn * r;
+                d[i + 1] = g + pp;
+                g = cs * r - b;
+                for (int k = 0; k < n; ++k) {
+                    double& z0 = Z[(size_t)k * n + i];
+                    double& z1 = Z[(size_t)k * n + i + 1];
+                    const double fz = z1;
+                    z1 = sn * z0 + cs * fz;
+                    z0 = cs * z0 - sn * fz;
+                }
+            }
+            if (early) continue;
+            d[l] -= pp;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+    }
+    // ---- V = Q D Z, eigenvalues ascending
     std::vector<int> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int i, int j) { return a(i, i).real() < a(j, j).real(); });
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] < d[y]; });
     w.resize(n);
-    std::vector<cplx> Vs((size_t)n * n);
+    V.assign((size_t)n * n, cplx(0, 0));
     for (int jj = 0; jj < n; ++jj) {
-        w[jj] = a(ord[jj], ord[jj]).real();
-        for (int i = 0; i < n; ++i) Vs[(size_t)i * n + jj] = V[(size_t)i * n + ord[jj]];
+        const int j = ord[jj];
+        w[jj] = d[j];
+        for (int r = 0; r < n; ++r) {
+            cplx t = 0;
+            for (int k = 0; k < n; ++k) t += Q[(size_t)r * n + k] * D[k] * Z[(size_t)k * n + j];
+            V[(size_t)r * n + jj] = t;
+        }
     }
-    V.swap(Vs);
 }
 
 }  // namespace stp
@@ -153,7 +220,7 @@ extern "C" stpci_status stpci_test_heev(int n, const double* A, double* w, doubl
     for (size_t i = 0; i < M.size(); ++i) M[i] = cplx(A[2 * i], A[2 * i + 1]);
     std::vector<double> ww;
     std::vector<cplx> VV;
-    jacobi_heev(n, M, ww, VV);
+    herm_eig(n, M, ww, VV);
     for (int i = 0; i < n; ++i) w[i] = ww[i];
     for (size_t i = 0; i < VV.size(); ++i) { V[2 * i] = VV[i].real(); V[2 * i + 1] = VV[i].imag(); }
     return STPCI_OK;
@@ -303,7 +370,7 @@ static stpci_status dav_advance(stpci_ctx* c) {
         for (int j = 0; j < m; ++j) A[(size_t)i * m + j] = 0.5 * (Gat(i, j) + std::conj(Gat(j, i)));
     std::vector<double> w;
     std::vector<cplx> Y;
-    jacobi_heev(m, A, w, Y);
+    herm_eig(m, A, w, Y);
     std::vector<cplx> Yk((size_t)m * k);
     for (int i = 0; i < m; ++i)
         for (int j = 0; j < k; ++j) Yk[(size_t)i * k + j] = Y[(size_t)i * m + j];

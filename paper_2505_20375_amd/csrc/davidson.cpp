@@ -155,7 +155,8 @@ namespace {
 constexpr size_t kYOff = 0;                 // Ritz coefficients, up to 64 x 32 complex
 constexpr size_t kThetaOff = 64 * 32 * 16;  // Ritz values, 64 doubles
 constexpr size_t kDotsOff = kThetaOff + 64 * 8;
-constexpr size_t kCoefOff = kDotsOff + 64 * 16;
+constexpr int kDotsMax = 64 * 16;           // dot products fetched in one round trip
+constexpr size_t kCoefOff = kDotsOff + (size_t)kDotsMax * 16;
 constexpr size_t kSmallBytes = kCoefOff + 64 * 16;
 
 struct Dav {
@@ -193,6 +194,25 @@ struct Dav {
         return hip(hipMemcpyAsync((char*)c->d_small.p + byte_off, buf.data(), buf.size() * 8,
                                   hipMemcpyHostToDevice, st),
                    "small upload");
+    }
+
+    // queue out[off + i] = <A_i | w>, i < m, in the dot-product area (no sync)
+    stpci_status issue_dots(const void* A, int m, const void* w, int off) {
+        char* small = (char*)c->d_small.p + kDotsOff + (size_t)off * (cx ? 16 : 8);
+        return hip(launch_dots(cx, A, N, m, w, N, c->d_partial.p, small, st), "dots");
+    }
+
+    // fetch the first `count` queued dot products (one round trip)
+    stpci_status fetch(int count, std::vector<cplx>& out) {
+        std::vector<double> raw((size_t)count * (cx ? 2 : 1));
+        stpci_status s = hip(hipMemcpyAsync(raw.data(), (char*)c->d_small.p + kDotsOff, raw.size() * 8,
+                                            hipMemcpyDeviceToHost, st),
+                             "dots copy");
+        if (s) return s;
+        if ((s = hip(hipStreamSynchronize(st), "sync"))) return s;
+        out.resize(count);
+        for (int i = 0; i < count; ++i) out[i] = cx ? cplx(raw[2 * i], raw[2 * i + 1]) : cplx(raw[i], 0.0);
+        return STPCI_OK;
     }
 
     stpci_status norm(const void* x, double& n) {
@@ -352,14 +372,18 @@ static stpci_status dav_advance(stpci_ctx* c) {
     Dav d{c, N, scalar_bytes(c), c->cplx, c->stream};
     auto Gat = [&](int i, int j) -> cplx& { return D.G[(size_t)i * 64 + j]; };
     c->nsigma[D.pidx] += D.nv;
-    // new columns (and rows) of G = V^H W
-    for (int j = D.m; j < D.m + D.nv; ++j) {
-        std::vector<cplx> col;
-        if ((s = d.dots(c->d_V.p, D.m + D.nv, d.vec(c->d_W, j), col))) return s;
-        for (int i = 0; i < D.m + D.nv; ++i) {
-            Gat(i, j) = col[i];
-            Gat(j, i) = std::conj(col[i]);
-        }
+    // new columns (and rows) of G = V^H W, one round trip
+    {
+        const int mt = D.m + D.nv;
+        for (int j = D.m; j < mt; ++j)
+            if ((s = d.issue_dots(c->d_V.p, mt, d.vec(c->d_W, j), (j - D.m) * mt))) return s;
+        std::vector<cplx> cols;
+        if ((s = d.fetch(D.nv * mt, cols))) return s;
+        for (int j = D.m; j < mt; ++j)
+            for (int i = 0; i < mt; ++i) {
+                Gat(i, j) = cols[(size_t)(j - D.m) * mt + i];
+                Gat(j, i) = std::conj(cols[(size_t)(j - D.m) * mt + i]);
+            }
     }
     D.m += D.nv;
     D.nv = 0;
@@ -385,8 +409,13 @@ static stpci_status dav_advance(stpci_ctx* c) {
                                   c->stream),
                    "ritz")))
         return s;
-    for (int j = 0; j < k; ++j)
-        if ((s = d.norm(d.vec(c->d_R, j), D.rn[j]))) return s;
+    {
+        for (int j = 0; j < k; ++j)
+            if ((s = d.issue_dots(d.vec(c->d_R, j), 1, d.vec(c->d_R, j), j))) return s;
+        std::vector<cplx> r2;
+        if ((s = d.fetch(k, r2))) return s;
+        for (int j = 0; j < k; ++j) D.rn[j] = std::sqrt(std::max(0.0, r2[j].real()));
+    }
     c->history.push_back(DavRecord{D.theta, D.rn, D.pidx});
     bool conv = true;
     for (int j = 0; j < k; ++j) conv = conv && D.rn[j] <= D.tol;
@@ -431,26 +460,93 @@ static stpci_status dav_advance(stpci_ctx* c) {
         mm = kr;
         D.m = kr;
     }
+    // block orthonormalisation of the corrections: two classical Gram-Schmidt
+    // passes against V, then two Cholesky QR passes among themselves; a
+    // direction that keeps less than 1e-8 of its norm lies in the span
+    // (linear dependence) and is dropped
     int added = 0;
-    for (int t = 0; t < nt; ++t) {
-        void* tv = d.vec(c->d_T, t);
-        double n0;
-        if ((s = d.norm(tv, n0))) return s;
-        if (n0 == 0.0) continue;
+    if (nt > 0) {
+        std::vector<cplx> n0v;
+        for (int t = 0; t < nt; ++t)
+            if ((s = d.issue_dots(d.vec(c->d_T, t), 1, d.vec(c->d_T, t), t))) return s;
+        if ((s = d.fetch(nt, n0v))) return s;
         for (int pass = 0; pass < 2; ++pass) {
+            for (int t = 0; t < nt; ++t)
+                if ((s = d.issue_dots(c->d_V.p, mm, d.vec(c->d_T, t), t * mm))) return s;
             std::vector<cplx> coef;
-            if ((s = d.dots(c->d_V.p, mm + added, tv, coef))) return s;
-            if ((s = d.subtract(c->d_V.p, mm + added, coef, tv))) return s;
+            if ((s = d.fetch(nt * mm, coef))) return s;
+            for (int t = 0; t < nt; ++t) {
+                std::vector<cplx> ct(coef.begin() + (size_t)t * mm, coef.begin() + (size_t)(t + 1) * mm);
+                if ((s = d.subtract(c->d_V.p, mm, ct, d.vec(c->d_T, t)))) return s;
+            }
         }
-        double nr;
-        if ((s = d.norm(tv, nr))) return s;
-        // a direction that lost all but 1e-8 of its norm lies in the span (linear dependence)
-        if (nr < 1e-8 * n0 || mm + added >= D.mmax) continue;
-        if ((s = d.hip(launch_scale(d.cx, tv, 1.0 / nr, N, c->stream), "normalise"))) return s;
-        if ((s = d.hip(hipMemcpyAsync(d.vec(c->d_V, mm + added), tv, vb, hipMemcpyDeviceToDevice, c->stream),
-                       "append")))
-            return s;
-        ++added;
+        // Cholesky QR: T_keep = Q R, Q = T R^-1 written to V[mm..] (first pass)
+        // and re-orthonormalised in place through T (second pass)
+        const int room = D.mmax - mm;
+        std::vector<int> keep;
+        for (int qr = 0; qr < 2; ++qr) {
+            void* src = (qr == 0) ? c->d_T.p : d.vec(c->d_V, mm);
+            const int ns = (qr == 0) ? nt : (int)keep.size();
+            if (ns == 0) break;
+            for (int t = 0; t < ns; ++t)
+                if ((s = d.issue_dots(src, ns, (char*)src + (size_t)t * vb, t * ns))) return s;
+            std::vector<cplx> Gm;  // Gm[t * ns + i] = <src_i | src_t>
+            if ((s = d.fetch(ns * ns, Gm))) return s;
+            std::vector<cplx> R((size_t)ns * ns, cplx(0, 0));
+            std::vector<int> kept;
+            for (int t = 0; t < ns; ++t) {
+                double r2 = Gm[(size_t)t * ns + t].real();
+                for (int i : kept) {
+                    cplx v = Gm[(size_t)t * ns + i];
+                    for (int j : kept) {
+                        if (j >= i) break;
+                        v -= std::conj(R[(size_t)j * ns + i]) * R[(size_t)j * ns + t];
+                    }
+                    R[(size_t)i * ns + t] = v / R[(size_t)i * ns + i];
+                    r2 -= std::norm(R[(size_t)i * ns + t]);
+                }
+                const double ref = (qr == 0) ? n0v[t].real() : 1.0;
+                if (r2 <= 1e-16 * ref || (int)kept.size() >= room) continue;
+                R[(size_t)t * ns + t] = std::sqrt(r2);
+                kept.push_back(t);
+            }
+            // Y = R^-1 on the kept columns (upper triangular), ns x kept
+            const int nk = (int)kept.size();
+            std::vector<cplx> Y((size_t)ns * std::max(nk, 1), cplx(0, 0));
+            for (int jj = 0; jj < nk; ++jj) {
+                // solve R[kept, kept] y = e_jj by back substitution over kept indices
+                std::vector<cplx> y(nk, cplx(0, 0));
+                for (int ii = jj; ii >= 0; --ii) {
+                    cplx v = (ii == jj) ? cplx(1, 0) : cplx(0, 0);
+                    for (int ll = ii + 1; ll <= jj; ++ll) v -= R[(size_t)kept[ii] * ns + kept[ll]] * y[ll];
+                    y[ii] = v / R[(size_t)kept[ii] * ns + kept[ii]];
+                }
+                for (int ii = 0; ii <= jj; ++ii) Y[(size_t)kept[ii] * nk + jj] = y[ii];
+            }
+            if (qr == 0) {
+                keep = kept;
+                if (nk == 0) break;
+                if ((s = d.put_small(Y, kYOff))) return s;
+                if ((s = d.hip(launch_combine(d.cx, c->d_T.p, nullptr, N, ns, c->d_small.p, nk, nullptr,
+                                              d.vec(c->d_V, mm), nullptr, N, 0, c->stream),
+                               "cholqr")))
+                    return s;
+            } else {
+                if (nk < ns) {  // the second pass dropped a direction: keep the first pass' result
+                    break;
+                }
+                if ((s = d.put_small(Y, kYOff))) return s;
+                if ((s = d.hip(launch_combine(d.cx, d.vec(c->d_V, mm), nullptr, N, ns, c->d_small.p, nk, nullptr,
+                                              c->d_T.p, nullptr, N, 0, c->stream),
+                               "cholqr2")))
+                    return s;
+                if ((s = d.hip(hipMemcpyAsync(d.vec(c->d_V, mm), c->d_T.p, vb * nk, hipMemcpyDeviceToDevice,
+                                              c->stream),
+                               "append")))
+                    return s;
+            }
+        }
+        added = (int)keep.size();
     }
     if (added == 0) {  // no new direction: stagnation
         D.done = true;

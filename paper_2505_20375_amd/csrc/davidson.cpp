@@ -173,7 +173,7 @@ struct Dav {
     // out[i] = <A_i | w> for i < m  (host result)
     stpci_status dots(const void* A, int m, const void* w, std::vector<cplx>& out) {
         char* small = (char*)c->d_small.p + kDotsOff;
-        stpci_status s = hip(launch_dots(cx, A, N, m, w, N, c->d_partial.p, small, st), "dots");
+        stpci_status s = hip(launch_dots(cx, A, N, m, w, 1, N, c->d_partial.p, small, st), "dots");
         if (s) return s;
         std::vector<double> buf((size_t)m * (cx ? 2 : 1));
         if ((s = hip(hipMemcpyAsync(buf.data(), small, buf.size() * 8, hipMemcpyDeviceToHost, st), "dots copy")))
@@ -196,10 +196,11 @@ struct Dav {
                    "small upload");
     }
 
-    // queue out[off + i] = <A_i | w>, i < m, in the dot-product area (no sync)
-    stpci_status issue_dots(const void* A, int m, const void* w, int off) {
+    // queue out[off + t m + i] = <A_i | W_t>, i < m, t < nw, in the dot-product
+    // area (no sync); A and W are consecutive vectors of N scalars
+    stpci_status issue_dots(const void* A, int m, const void* W, int nw, int off) {
         char* small = (char*)c->d_small.p + kDotsOff + (size_t)off * (cx ? 16 : 8);
-        return hip(launch_dots(cx, A, N, m, w, N, c->d_partial.p, small, st), "dots");
+        return hip(launch_dots(cx, A, N, m, W, nw, N, c->d_partial.p, small, st), "dots");
     }
 
     // fetch the first `count` queued dot products (one round trip)
@@ -228,6 +229,18 @@ struct Dav {
         if (s) return s;
         return hip(launch_combine(cx, A, nullptr, N, m, (char*)c->d_small.p + kCoefOff, 1, nullptr, x, nullptr, N,
                                   2, st),
+                   "cgs");
+    }
+
+    // X_t <- X_t - sum_i A_i coef[t m + i] for t < nx (X_t consecutive vectors)
+    stpci_status subtract_block(const void* A, int m, const std::vector<cplx>& coef, int nx, void* X) {
+        std::vector<cplx> Y((size_t)m * nx);  // row-major m x nx
+        for (int t = 0; t < nx; ++t)
+            for (int i = 0; i < m; ++i) Y[(size_t)i * nx + t] = coef[(size_t)t * m + i];
+        stpci_status s = put_small(Y, kYOff);
+        if (s) return s;
+        return hip(launch_combine(cx, A, nullptr, N, m, (char*)c->d_small.p + kYOff, nx, nullptr, X, nullptr, N, 2,
+                                  st),
                    "cgs");
     }
 };
@@ -277,7 +290,7 @@ int64_t dav_device_bytes(const stpci_ctx* c, const stpci_dav_opts& o) {
     const int k = o.k, kr = std::min(2 * k, 32);
     const int mmax = subspace_cap(subspace_request(o), k, N);
     int64_t b = vb * (2LL * mmax + 2LL * kr + k);
-    b += (int64_t)dots_blocks(N) * 64 * 16 + (int64_t)kSmallBytes;
+    b += (int64_t)dots_blocks(N) * kDotsMax * 16 + (int64_t)kSmallBytes;
     if (!o.guess_dev) b += 1024LL * k * 16;  // top-k partials: at most 1024 blocks
     return b;
 }
@@ -311,7 +324,7 @@ static stpci_status dav_start(stpci_ctx* c, stpci_precision prec, const void* gu
     if ((s = ensure(c, c->d_X, vb * D.kr_max, "Ritz vectors"))) return s;
     if ((s = ensure(c, c->d_R, vb * D.kr_max, "residuals"))) return s;
     if ((s = ensure(c, c->d_T, vb * k, "corrections"))) return s;
-    if ((s = ensure(c, c->d_partial, (size_t)dots_blocks(N) * 64 * 16, "dot partials"))) return s;
+    if ((s = ensure(c, c->d_partial, (size_t)dots_blocks(N) * kDotsMax * 16, "dot partials"))) return s;
     if ((s = ensure(c, c->d_small, kSmallBytes, "small workspace"))) return s;
     Dav d{c, N, scalar_bytes(c), c->cplx, c->stream};
     if (guess_dev) {
@@ -375,8 +388,7 @@ static stpci_status dav_advance(stpci_ctx* c) {
     // new columns (and rows) of G = V^H W, one round trip
     {
         const int mt = D.m + D.nv;
-        for (int j = D.m; j < mt; ++j)
-            if ((s = d.issue_dots(c->d_V.p, mt, d.vec(c->d_W, j), (j - D.m) * mt))) return s;
+        if ((s = d.issue_dots(c->d_V.p, mt, d.vec(c->d_W, D.m), D.nv, 0))) return s;
         std::vector<cplx> cols;
         if ((s = d.fetch(D.nv * mt, cols))) return s;
         for (int j = D.m; j < mt; ++j)
@@ -411,7 +423,7 @@ static stpci_status dav_advance(stpci_ctx* c) {
         return s;
     {
         for (int j = 0; j < k; ++j)
-            if ((s = d.issue_dots(d.vec(c->d_R, j), 1, d.vec(c->d_R, j), j))) return s;
+            if ((s = d.issue_dots(d.vec(c->d_R, j), 1, d.vec(c->d_R, j), 1, j))) return s;
         std::vector<cplx> r2;
         if ((s = d.fetch(k, r2))) return s;
         for (int j = 0; j < k; ++j) D.rn[j] = std::sqrt(std::max(0.0, r2[j].real()));
@@ -468,17 +480,13 @@ static stpci_status dav_advance(stpci_ctx* c) {
     if (nt > 0) {
         std::vector<cplx> n0v;
         for (int t = 0; t < nt; ++t)
-            if ((s = d.issue_dots(d.vec(c->d_T, t), 1, d.vec(c->d_T, t), t))) return s;
+            if ((s = d.issue_dots(d.vec(c->d_T, t), 1, d.vec(c->d_T, t), 1, t))) return s;
         if ((s = d.fetch(nt, n0v))) return s;
         for (int pass = 0; pass < 2; ++pass) {
-            for (int t = 0; t < nt; ++t)
-                if ((s = d.issue_dots(c->d_V.p, mm, d.vec(c->d_T, t), t * mm))) return s;
+            if ((s = d.issue_dots(c->d_V.p, mm, c->d_T.p, nt, 0))) return s;
             std::vector<cplx> coef;
             if ((s = d.fetch(nt * mm, coef))) return s;
-            for (int t = 0; t < nt; ++t) {
-                std::vector<cplx> ct(coef.begin() + (size_t)t * mm, coef.begin() + (size_t)(t + 1) * mm);
-                if ((s = d.subtract(c->d_V.p, mm, ct, d.vec(c->d_T, t)))) return s;
-            }
+            if ((s = d.subtract_block(c->d_V.p, mm, coef, nt, c->d_T.p))) return s;
         }
         // Cholesky QR: T_keep = Q R, Q = T R^-1 written to V[mm..] (first pass)
         // and re-orthonormalised in place through T (second pass)
@@ -488,8 +496,7 @@ static stpci_status dav_advance(stpci_ctx* c) {
             void* src = (qr == 0) ? c->d_T.p : d.vec(c->d_V, mm);
             const int ns = (qr == 0) ? nt : (int)keep.size();
             if (ns == 0) break;
-            for (int t = 0; t < ns; ++t)
-                if ((s = d.issue_dots(src, ns, (char*)src + (size_t)t * vb, t * ns))) return s;
+            if ((s = d.issue_dots(src, ns, src, ns, 0))) return s;
             std::vector<cplx> Gm;  // Gm[t * ns + i] = <src_i | src_t>
             if ((s = d.fetch(ns * ns, Gm))) return s;
             std::vector<cplx> R((size_t)ns * ns, cplx(0, 0));

@@ -209,48 +209,79 @@ __global__ __launch_bounds__(256) void k_diag_topk(DevSpace S, const double* hd,
 // ---------------------------------------------------------------------------
 // Vector algebra (memory-bound; wavefront + block reductions, fixed order)
 // ---------------------------------------------------------------------------
-constexpr int DOTV = 8;   // vectors per launch row
+constexpr int DOTV = 8;   // vectors V_i per workgroup
+constexpr int DOTW = 2;   // vectors W_t per workgroup
 
-// partial[block][i] = sum over the block's range of conj(V_i) * w
+// partial[block][t * m + i] = sum over the block's element range of
+// conj(V_i) W_t, for i < m, t < nw (V_i = Vb + i ld, W_t = W + t ld).
+// blockIdx.x: group of DOTV vectors V, blockIdx.y: element range,
+// blockIdx.z: group of DOTW vectors W.  Each V element is read once per W
+// group, each W element once per V group.
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_dots(const typename VT<CPLX>::T* __restrict__ Vb, int64_t ld, int m,
-                                              const typename VT<CPLX>::T* __restrict__ w, int64_t n,
+                                              const typename VT<CPLX>::T* __restrict__ W, int nw, int64_t n,
                                               typename VT<CPLX>::T* __restrict__ partial) {
     using V = VT<CPLX>;
     using T = typename V::T;
-    const int i0 = blockIdx.y * DOTV;
-    T acc[DOTV];
+    const int i0 = blockIdx.x * DOTV;
+    const int t0 = blockIdx.z * DOTW;
+    T acc[DOTW][DOTV];
 #pragma unroll
-    for (int i = 0; i < DOTV; ++i) acc[i] = V::zero();
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        T wv = w[e];
+    for (int t = 0; t < DOTW; ++t)
+#pragma unroll
+        for (int i = 0; i < DOTV; ++i) acc[t][i] = V::zero();
+    for (int64_t e = blockIdx.y * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.y * blockDim.x) {
+        T wv[DOTW];
+#pragma unroll
+        for (int t = 0; t < DOTW; ++t) wv[t] = (t0 + t < nw) ? W[(int64_t)(t0 + t) * ld + e] : V::zero();
 #pragma unroll
         for (int i = 0; i < DOTV; ++i)
-            if (i0 + i < m) acc[i] = V::add(acc[i], V::conjmul(Vb[(int64_t)(i0 + i) * ld + e], wv));
+            if (i0 + i < m) {
+                const T a = Vb[(int64_t)(i0 + i) * ld + e];
+#pragma unroll
+                for (int t = 0; t < DOTW; ++t) acc[t][i] = V::cmad(a, wv[t], acc[t][i]);
+            }
     }
-    __shared__ T red[256];
-    for (int i = 0; i < DOTV; ++i) {
-        if (i0 + i >= m) break;
-        red[threadIdx.x] = acc[i];
-        __syncthreads();
-        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) red[threadIdx.x] = V::add(red[threadIdx.x], red[threadIdx.x + s]);
-            __syncthreads();
+    // wavefront sums (fixed butterfly), then the 4 wavefronts in order
+    __shared__ T red[4][DOTW * DOTV];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < DOTW; ++t)
+#pragma unroll
+        for (int i = 0; i < DOTV; ++i) {
+            T x = acc[t][i];
+            for (int off = 32; off > 0; off >>= 1) x = V::add(x, V::shfl_xor(x, off));
+            if (lane == 0) red[wv][t * DOTV + i] = x;
         }
-        if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * m + i0 + i] = red[0];
-        __syncthreads();
+    __syncthreads();
+    const int j = threadIdx.x;
+    if (j < DOTW * DOTV) {
+        const int t = j / DOTV, i = j % DOTV;
+        if (t0 + t < nw && i0 + i < m) {
+            const T x = V::add(V::add(red[0][j], red[1][j]), V::add(red[2][j], red[3][j]));
+            partial[(int64_t)blockIdx.y * m * nw + (int64_t)(t0 + t) * m + i0 + i] = x;
+        }
     }
 }
 
+// out[i] = sum over blocks of partial[b][i]: one workgroup per output, the
+// block partials split over its threads, then a fixed-order tree (the result
+// does not depend on timing).
 template <bool CPLX>
-__global__ void k_reduce_partials(const typename VT<CPLX>::T* __restrict__ partial, int nblk, int m,
-                                  typename VT<CPLX>::T* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_reduce_partials(const typename VT<CPLX>::T* __restrict__ partial, int nblk,
+                                                         int m, typename VT<CPLX>::T* __restrict__ out) {
     using V = VT<CPLX>;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
+    const int i = blockIdx.x;
     typename V::T s = V::zero();
-    for (int b = 0; b < nblk; ++b) s = V::add(s, partial[(int64_t)b * m + i]);
-    out[i] = s;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s = V::add(s, partial[(int64_t)b * m + i]);
+    __shared__ typename V::T red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = V::add(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = red[0];
 }
 
 // out_j = sum_i A_i * Y[i][j]  (+ beta_j * out_j when accumulate)   for j < k
@@ -396,21 +427,23 @@ hipError_t launch_diag_topk(const DevSpace& S, const double* hd, const double* J
     return hipGetLastError();
 }
 
-int dots_blocks(int64_t n) { return grid_for(n, 256, 1024); }
+int dots_blocks(int64_t n) { return grid_for(n, 256, 256); }
 
-hipError_t launch_dots(bool cplx, const void* Vb, int64_t ld, int m, const void* w, int64_t n, void* partial,
-                       void* out, hipStream_t st) {
-    int nb = dots_blocks(n);
-    dim3 grid(nb, (m + DOTV - 1) / DOTV);
+hipError_t launch_dots(bool cplx, const void* Vb, int64_t ld, int m, const void* W, int nw, int64_t n,
+                       void* partial, void* out, hipStream_t st) {
+    if (m <= 0 || nw <= 0) return hipSuccess;
+    const int nb = dots_blocks(n);
+    const dim3 grid((m + DOTV - 1) / DOTV, nb, (nw + DOTW - 1) / DOTW);
     if (cplx) {
-        hipLaunchKernelGGL(k_dots<true>, grid, dim3(256), 0, st, (const cd*)Vb, ld, m, (const cd*)w, n,
+        hipLaunchKernelGGL(k_dots<true>, grid, dim3(256), 0, st, (const cd*)Vb, ld, m, (const cd*)W, nw, n,
                            (cd*)partial);
-        hipLaunchKernelGGL(k_reduce_partials<true>, dim3(1), dim3(64), 0, st, (const cd*)partial, nb, m, (cd*)out);
+        hipLaunchKernelGGL(k_reduce_partials<true>, dim3(m * nw), dim3(256), 0, st, (const cd*)partial, nb, m * nw,
+                           (cd*)out);
     } else {
-        hipLaunchKernelGGL(k_dots<false>, grid, dim3(256), 0, st, (const double*)Vb, ld, m, (const double*)w, n,
+        hipLaunchKernelGGL(k_dots<false>, grid, dim3(256), 0, st, (const double*)Vb, ld, m, (const double*)W, nw, n,
                            (double*)partial);
-        hipLaunchKernelGGL(k_reduce_partials<false>, dim3(1), dim3(64), 0, st, (const double*)partial, nb, m,
-                           (double*)out);
+        hipLaunchKernelGGL(k_reduce_partials<false>, dim3(m * nw), dim3(256), 0, st, (const double*)partial, nb,
+                           m * nw, (double*)out);
     }
     return hipGetLastError();
 }

@@ -57,8 +57,10 @@ int topk_blocks(const DevSpace& S);
 hipError_t launch_diag_topk(const DevSpace& S, const double* hd, const double* JK, double e_core, int k,
                             double* vals, int64_t* idx, hipStream_t st);
 int dots_blocks(int64_t n);
-hipError_t launch_dots(bool cplx, const void* Vb, int64_t ld, int m, const void* w, int64_t n, void* partial,
-                       void* out, hipStream_t st);
+// out[t * m + i] = <V_i | W_t> for i < m, t < nw (V_i = Vb + i ld, W_t = W + t ld);
+// partial holds dots_blocks(n) * m * nw scalars
+hipError_t launch_dots(bool cplx, const void* Vb, int64_t ld, int m, const void* W, int nw, int64_t n,
+                       void* partial, void* out, hipStream_t st);
 hipError_t launch_combine(bool cplx, const void* A, const void* B, int64_t ld, int m, const void* Y, int k,
                           const double* theta, void* X, void* R, int64_t n, int mode, hipStream_t st);
 hipError_t launch_scale(bool cplx, void* x, double s, int64_t n, hipStream_t st);

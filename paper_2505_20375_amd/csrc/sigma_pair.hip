@@ -240,25 +240,31 @@ __global__ __launch_bounds__(256) void k_sigma_pair(DevSpace S, const typename P
 }
 
 // sigma[v][L] = e_core c[v][L] + sum_q E[(L * nq + q) * NV + v]: the pair
-// contributions of every target, summed in a fixed order.
+// contributions of every target, summed in a fixed order.  Four lanes share a
+// target: lane g adds entries g, g + 4, ... of its nq * NV contiguous
+// entries (so every read instruction covers 64 contiguous bytes per target),
+// then the lanes holding the same vector (g mod NV) are combined by a fixed
+// butterfly.
+constexpr int PR_LANES = 4;
 template <bool CPLX, int NV>
 __global__ __launch_bounds__(256) void k_pair_reduce(typename VT<CPLX>::T* __restrict__ sigma,
                                                     const typename VT<CPLX>::T* __restrict__ c,
                                                     const typename VT<CPLX>::T* __restrict__ E, double e_core,
                                                     int64_t nd, int nq, int n_vec) {
+    static_assert(PR_LANES % NV == 0, "each lane must hold one vector");
     using V64 = VT<CPLX>;
     using TE = typename V64::T;
-    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < nd; L += (int64_t)gridDim.x * blockDim.x) {
-        TE acc[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = V64::zero();
-        const TE* e = E + L * nq * NV;
-        for (int q = 0; q < nq; ++q)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] = V64::add(acc[v], e[q * NV + v]);
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-            if (v < n_vec) sigma[(int64_t)v * nd + L] = V64::add(V64::scale(c[(int64_t)v * nd + L], e_core), acc[v]);
+    const int g = threadIdx.x & (PR_LANES - 1);
+    const int per = nq * NV;
+    const int64_t step = (int64_t)gridDim.x * (blockDim.x / PR_LANES);
+    // L is equal on the four lanes of a group, so groups enter and leave the
+    // loop together and the shuffles stay inside active groups
+    for (int64_t L = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / PR_LANES; L < nd; L += step) {
+        TE acc = V64::zero();
+        const TE* e = E + L * per;
+        for (int f = g; f < per; f += PR_LANES) acc = V64::add(acc, e[f]);
+        for (int m = NV; m < PR_LANES; m <<= 1) acc = V64::add(acc, V64::shfl_xor(acc, m));
+        if (g < NV && g < n_vec) sigma[(int64_t)g * nd + L] = V64::add(V64::scale(c[(int64_t)g * nd + L], e_core), acc);
     }
 }
 
@@ -300,7 +306,7 @@ static hipError_t launch_pair_nv(const DevSpace& S, int deg_max, const void* A, 
     if (mk) mk->fn(mk->user, 0, false);
     if (STORE) {
         const int64_t nd = S.sp.ndets;
-        const int g = (int)std::max<int64_t>(1, std::min<int64_t>(16384, (nd + 255) / 256));
+        const int g = (int)std::max<int64_t>(1, std::min<int64_t>(16384, (nd * PR_LANES + 255) / 256));
         if (mk) mk->fn(mk->user, 1, true);
         hipLaunchKernelGGL((k_pair_reduce<CPLX, NV>), dim3(g), dim3(256), 0, st, (T64*)sigma, (const T64*)c,
                            (const T64*)E, e_core, nd, nq, nv);

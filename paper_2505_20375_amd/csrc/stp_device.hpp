@@ -30,6 +30,7 @@ struct VT<false> {
     static __device__ __forceinline__ void lds_add(T* p, T v) { atomicAdd(p, v); }
     static __device__ __forceinline__ double re(T a) { return a; }
     static __device__ __forceinline__ double abs2(T a) { return a * a; }
+    static __device__ __forceinline__ T shfl_xor(T a, int m) { return __shfl_xor(a, m, 64); }
 };
 template <>
 struct VT<true> {
@@ -66,6 +67,7 @@ struct VT<true> {
     }
     static __device__ __forceinline__ double re(T a) { return a.x; }
     static __device__ __forceinline__ double abs2(T a) { return a.x * a.x + a.y * a.y; }
+    static __device__ __forceinline__ T shfl_xor(T a, int m) { return cd{__shfl_xor(a.x, m, 64), __shfl_xor(a.y, m, 64)}; }
 };
 
 struct alignas(8) cf {

@@ -30,8 +30,12 @@
  * Memory: the server copies everything a request needs at submission; the
  * caller keeps ownership of its arrays.  Device memory of a request is
  * allocated by the server on admission and freed on retirement or
- * cancellation.  The server is used by one host thread at a time; all its
- * device work runs in order on the stream given at creation.
+ * cancellation.  The server is used by one host thread at a time.  Grouped
+ * sigma launches run on the stream given at creation; each active request's
+ * own work (Davidson vector algebra, products outside the grouped kernels)
+ * runs on a stream the server owns (default priority, reused across
+ * requests), advanced by up to 8 host worker threads inside
+ * stpci_server_tick.
  * Errors: every call returns a status; stpci_server_last_error() describes
  * the last server-level failure.  A request that fails on the device is
  * retired with its status (STPCI_ENOCONV counts as finished, with the
@@ -95,7 +99,8 @@ stpci_status stpci_server_cancel(stpci_server* srv, int id);
 /* One scheduling step (admission, grouped sigma, one Davidson iteration per
  * active request, retirement).  n_pending: requests queued or active after
  * the step; n_finished: requests retired during it.  Synchronises the
- * server stream. */
+ * server stream; request streams may still hold the tail of their
+ * iteration's work, which the next tick orders before its grouped launches. */
 stpci_status stpci_server_tick(stpci_server* srv, int* n_pending, int* n_finished);
 
 /* State, results and timings of request id.  energies, resid: host arrays of

@@ -11,17 +11,22 @@
 //      precision) over the concatenated intermediate-determinant ranges,
 //   3. advances every active request by one Davidson iteration and retires
 //      the finished ones, releasing their memory for the next admissions.
+//      Each active request owns a HIP stream; the iterations of different
+//      requests run on host worker threads, so that one request's host work
+//      and synchronisation round trips overlap the others' device work.
 // Requests therefore join and leave between ticks while others are on the
 // device; their vectors stay resident from admission to completion.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <deque>
 #include <memory>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/stpci.h"
@@ -43,6 +48,7 @@ enum ReqState { QUEUED = 0, ACTIVE = 1, DONE = 2, FAILED = 3, CANCELLED = 4 };
 struct Req {
     int id = 0;
     stpci_ctx* ctx = nullptr;
+    hipStream_t stream = nullptr;  // owned by the server's pool while active
     stpci_dav_opts opts{};
     int64_t footprint = 0;
     int state = QUEUED;
@@ -70,14 +76,27 @@ struct stpci_server {
     std::deque<int> queue;
     std::vector<int> active;
     DevBuf d_desc, d_jbegin;
+    std::vector<hipStream_t> free_streams;  // request streams not in use
     std::string err;
     ~stpci_server() {
-        for (auto& r : reqs) stpci_destroy(r->ctx);
         (void)hipSetDevice(device);
+        for (auto& r : reqs) {
+            stpci_destroy(r->ctx);
+            if (r->stream) (void)hipStreamDestroy(r->stream);
+        }
+        for (hipStream_t st : free_streams) (void)hipStreamDestroy(st);
         d_desc.free_();
         d_jbegin.free_();
     }
 };
+
+// Hand a request's stream back to the pool once its work has drained.
+static void release_stream(stpci_server* s, Req& q) {
+    if (!q.stream) return;
+    (void)hipStreamSynchronize(q.stream);
+    s->free_streams.push_back(q.stream);
+    q.stream = nullptr;
+}
 
 // Device bytes a request holds while active: tables, integrals (with the
 // FP32 copies for the FP32 contraction), the schedule of the row-tiled
@@ -86,6 +105,9 @@ struct stpci_server {
 static int64_t footprint(const stpci_ctx* c, const stpci_dav_opts& o) {
     return device_table_bytes(c, o.precision == STPCI_FP32) + dav_device_bytes(c, o);
 }
+
+// host threads that advance the active requests' Davidson iterations
+constexpr int kWorkers = 8;
 
 static stpci_status srv_err(stpci_server* s, stpci_status st, const std::string& m) {
     s->err = m;
@@ -169,6 +191,7 @@ stpci_status stpci_server_cancel(stpci_server* s, int id) {
     q.t_done = now_s();
     stpci_destroy(q.ctx);
     q.ctx = nullptr;
+    release_stream(s, q);
     return STPCI_OK;
 }
 
@@ -189,6 +212,7 @@ static void retire(stpci_server* s, Req& q, stpci_status st) {
     q.t_done = now_s();
     stpci_destroy(q.ctx);
     q.ctx = nullptr;
+    release_stream(s, q);
     s->used -= q.footprint;
     s->active.erase(std::remove(s->active.begin(), s->active.end(), q.id), s->active.end());
 }
@@ -206,7 +230,18 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
         q.t_admit = now_s();
         s->active.push_back(q.id);
         s->used += q.footprint;
-        stpci_status st = dav_begin(q.ctx, &q.opts);
+        stpci_status st = STPCI_OK;
+        if (s->free_streams.empty()) {
+            hipStream_t ns = nullptr;
+            if (hipStreamCreateWithFlags(&ns, hipStreamNonBlocking) != hipSuccess) st = STPCI_EHIP;
+            else s->free_streams.push_back(ns);
+        }
+        if (!st) {
+            q.stream = s->free_streams.back();
+            s->free_streams.pop_back();
+            q.ctx->stream = q.stream;
+            st = dav_begin(q.ctx, &q.opts);
+        }
         if (!st && q.opts.precision == STPCI_FP32) st = ensure32(q.ctx);
         if (st) {
             retire(s, q, st);
@@ -269,6 +304,13 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
         }
     }
     std::vector<int> stepped(solo);
+    // the grouped launches read vectors the requests' own streams wrote
+    for (int pk = 0; pk < 2; ++pk)
+        for (int cx = 0; cx < 2; ++cx)
+            for (int f = 0; f < 2; ++f)
+                for (auto& it : groups[pk][cx][f])
+                    if (hipStreamSynchronize(s->reqs[it.id]->stream) != hipSuccess)
+                        return srv_err(s, STPCI_EHIP, "request stream synchronisation failed");
     for (int pk = 0; pk < 2; ++pk)
     for (int cx = 0; cx < 2; ++cx)
         for (int f = 0; f < 2; ++f) {
@@ -300,17 +342,37 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
             if (e != hipSuccess) return srv_err(s, STPCI_EHIP, hipGetErrorString(e));
             ++s->grouped_launches;
         }
-    // 3. one Davidson iteration for every request whose products were computed
+    // 3. one Davidson iteration for every request whose products were
+    // computed, on worker threads (each request on its own stream; a
+    // request's state is touched by one thread only)
     std::sort(stepped.begin(), stepped.end());
     stepped.erase(std::unique(stepped.begin(), stepped.end()), stepped.end());
-    for (int id : stepped) {
-        Req& q = *s->reqs[id];
-        if (q.state != ACTIVE) continue;
-        int fin = 0;
-        stpci_status st = dav_step_after_sigma(q.ctx, &fin);
-        if (st || fin) {
-            if (!st) st = collect(q);
-            retire(s, q, st);
+    stepped.erase(std::remove_if(stepped.begin(), stepped.end(),
+                                 [&](int id) { return s->reqs[id]->state != ACTIVE; }),
+                  stepped.end());
+    const int ns = (int)stepped.size();
+    std::vector<stpci_status> sts(ns, STPCI_OK);
+    std::vector<int> fins(ns, 0);
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        if (hipSetDevice(s->device) != hipSuccess) {
+            for (int i; (i = next.fetch_add(1)) < ns;) sts[i] = STPCI_EHIP;
+            return;
+        }
+        for (int i; (i = next.fetch_add(1)) < ns;) {
+            Req& q = *s->reqs[stepped[i]];
+            sts[i] = dav_step_after_sigma(q.ctx, &fins[i]);
+            if (!sts[i] && fins[i]) sts[i] = collect(q);
+        }
+    };
+    const int nthreads = std::min(ns, kWorkers);
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthreads; ++t) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
+    for (int i = 0; i < ns; ++i) {
+        if (sts[i] || fins[i]) {
+            retire(s, *s->reqs[stepped[i]], sts[i]);
             ++finished;
         }
     }

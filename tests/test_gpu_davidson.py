@@ -23,6 +23,18 @@ def test_davidson_matches_dense_eigh(name, k):
     assert np.max(np.abs(e - w[:k])) <= 1e-9
 
 
+@pytest.mark.parametrize("n,k", [(7, 3), (8, 1), (1, 8)])
+def test_davidson_tiny_spaces(n, k):
+    """Spaces of 8, 1 and 8 determinants; k up to the whole space."""
+    print("case", n, k, flush=True)
+    ints = synth.complex_integrals(8, 60 + n, rank=8, sigma_f=0.05)
+    pb = Problem(ints, synth.SpaceSpec(n, [8]), seed=2)
+    H = dense.hamiltonian(pb.dets, pb.h, pb.g)
+    w = np.linalg.eigvalsh(H)
+    e, r, it, st = pb.context().davidson(k=k, tol=1e-9, max_iter=100)
+    assert np.max(np.abs(e - w[:k])) <= 1e-9
+
+
 def test_davidson_medium_two_roots():
     ints = synth.complex_integrals(16, 21, rank=32, sigma_f=0.03)
     pb = Problem(ints, synth.SpaceSpec(5, [8, 8]), seed=1)

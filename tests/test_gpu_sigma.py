@@ -54,6 +54,34 @@ def test_sigma_medium_spaces(sub, lo, hi, n):
     assert rel_err(_run_sigma(pb, c), pb.oracle_sigma(c)) <= TOL
 
 
+@pytest.mark.parametrize("n,sub,lo,hi", [
+    (1, [8], None, None),                    # one electron: no pair intermediates
+    (2, [8], None, None),                    # one pair intermediate per pair class (the empty determinant)
+    (7, [8], None, None),                    # one hole
+    (8, [8], None, None),                    # a single determinant (N = M)
+    (1, [4, 4], [0, 0], [1, 1]),             # one electron in two subspaces
+    (2, [4, 4], [1, 0], [2, 1]),             # windows leave one category pattern per subspace
+    (7, [4, 4], [3, 3], [4, 4]),
+])
+def test_sigma_edge_electron_counts(n, sub, lo, hi):
+    """Degenerate spaces at the ends of the electron count, with the default
+    kernel choice (the pair form where it applies, N >= 2)."""
+    print("case", n, sub, lo, hi, flush=True)
+    ints = synth.complex_integrals(sum(sub), 41 + n, rank=8, sigma_f=0.05)
+    pb = Problem(ints, synth.SpaceSpec(n, sub, lo or [], hi or []), seed=3)
+    c = pb.vector()
+    assert rel_err(_run_sigma(pb, c), pb.oracle_sigma(c)) <= TOL
+
+
+def test_sigma_three_vectors():
+    """An odd vector count above the kernel's two-vector width."""
+    pb = Problem.named("T4")
+    cs = [pb.vector(s) for s in (1, 2, 3)]
+    out = _run_sigma(pb, cs, n_vec=3)
+    for c, s in zip(cs, out):
+        assert rel_err(s, pb.oracle_sigma(c)) <= TOL
+
+
 def test_sigma_partition_invariance():
     """FCI as 1, 2 or 3 open-window subspaces gives the same sigma."""
     ints = synth.complex_integrals(12, 5)

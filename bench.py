@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak
+BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bfloat16 matrix-core peak
 HBM_PEAK_GBS = 8000.0
 
 
@@ -155,31 +156,57 @@ def main():
         "roofline": roof,
     }
 
-    # precision form: FP32 contraction of the same step
-    for _ in range(max(1, args.warmup)):
-        ctx.sigma(c, out, n_vec=n_vec, precision=stpci.FP32)
+    # precision forms of the same step: FP32 contraction (VALU) and BF16
+    # contraction (matrix cores, FP32 accumulation; executed matrix-core flops
+    # include the padding of each batch's dense product over all pairs)
     out64 = torch.empty_like(out)
     ctx.sigma(c, out64, n_vec=n_vec)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        ctx.sigma(c, out, n_vec=n_vec, precision=stpci.FP32)
-    e1.record()
-    torch.cuda.synchronize()
-    ms32 = e0.elapsed_time(e1) / args.steps
-    rel = float(torch.linalg.vector_norm(out - out64) / torch.linalg.vector_norm(out64))
-    res["precision"] = {"sigma_fp32_ms": ms32, "sigma_fp64_ms": ms_per_step, "sigma_speedup": ms_per_step / ms32,
-                        "sigma_fp32_rel_err": rel,
-                        "contraction": "FP32 integrals, coefficients and accumulation; FP64 sigma, residual, "
-                                       "orthogonalisation and subspace solve"}
+    prec = {"sigma_fp64_ms": ms_per_step,
+            "contraction": "FP32: integrals, coefficients and accumulation in FP32 on the vector ALUs; "
+                           "BF16: bfloat16 integrals and coefficients on the matrix cores "
+                           "(v_mfma_f32_16x16x32_bf16), FP32 accumulation; both: FP64 sigma sums, residual, "
+                           "orthogonalisation and subspace solve"}
+    for pname, pcode in (("fp32", stpci.FP32), ("bf16", stpci.BF16)):
+        for _ in range(max(1, args.warmup)):
+            ctx.sigma(c, out, n_vec=n_vec, precision=pcode)
+        torch.cuda.synchronize()
+        ctx.profile(pname == "bf16")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            ctx.sigma(c, out, n_vec=n_vec, precision=pcode)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_p = e0.elapsed_time(e1) / args.steps
+        prec["sigma_%s_ms" % pname] = ms_p
+        prec["sigma_%s_speedup" % pname] = ms_per_step / ms_p
+        prec["sigma_%s_rel_err" % pname] = float(torch.linalg.vector_norm(out - out64) /
+                                                 torch.linalg.vector_norm(out64))
+        if pname == "bf16":
+            nb, tb = ctx.kernel_time("sigma_bf16")
+            ctx.profile(False)
+            npp = (sp.n_spin_orb * (sp.n_spin_orb - 1) // 2 + 31) // 32 * 32
+            nbatch = -(-n_pair // (16 // n_vec))
+            mf_flops = nbatch * npp * npp * 16 * 2 * 4   # four real products per complex batch
+            kms = tb / max(nb, 1)
+            prec["bf16_matrix_core"] = {
+                "kernel": "k_sigma_pair_mfma", "avg_launch_ms": round(kms, 4),
+                "executed_tflops": round(mf_flops / (kms * 1e-3) / 1e12, 3),
+                "useful_tflops": round(flops / (kms * 1e-3) / 1e12, 3),
+                "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac_executed": round(mf_flops / (kms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4),
+                "executed_flops_per_launch": mf_flops, "useful_flops_per_launch": flops}
+    prec["sigma_speedup"] = prec["sigma_fp32_speedup"]   # FP32 over FP64
+    res["precision"] = prec
     if not args.no_solve:
         res["solve"] = _solve(ctx, roots, args.solves, stpci.FP64)
-        mixed = _solve(ctx, roots, args.solves, stpci.FP32)
-        res["precision"]["solve_mixed"] = mixed
-        res["precision"]["solve_speedup"] = res["solve"]["p50_ms"] / mixed["p50_ms"]
-        res["precision"]["energy_diff_eh"] = max(abs(a - b) for a, b in zip(mixed["energies"],
-                                                                            res["solve"]["energies"]))
+        for pname, pcode in (("mixed", stpci.FP32), ("mixed_bf16", stpci.BF16)):
+            sol = _solve(ctx, roots, args.solves, pcode)
+            prec["solve_" + pname] = sol
+            prec["solve_speedup" + ("" if pname == "mixed" else "_bf16")] = res["solve"]["p50_ms"] / sol["p50_ms"]
+            prec["energy_diff_eh" + ("" if pname == "mixed" else "_bf16")] = max(
+                abs(a - b) for a, b in zip(sol["energies"], res["solve"]["energies"]))
     if args.serve > 0:
         del ctx
         res["serving"] = _serve(args.serve, args.serve_max_dets, args.serve_rate)
@@ -227,6 +254,8 @@ def _solve(ctx, roots, nsolve, precision):
     bound from the second root), reported as energy_bound_eh (<= 1e-8 Eh)."""
     import numpy as np
     import torch
+    import paper_2505_20375_amd as stpci
+    label = {stpci.FP64: "fp64", stpci.FP32: "fp32+fp64", stpci.BF16: "bf16+fp64"}[precision]
     times, its = [], []
     e = r = None
     for i in range(nsolve):
@@ -236,14 +265,15 @@ def _solve(ctx, roots, nsolve, precision):
         torch.cuda.synchronize()
         times.append((time.perf_counter() - t0) * 1e3)
         its.append(it)
-        log("solve %d (%s): %.1f ms, %d iterations" % (i, "fp32+fp64" if precision else "fp64", times[-1], it))
+        log("solve %d (%s): %.1f ms, %d iterations" % (i, label, times[-1], it))
     gamma = (e[1] - r[1]) - e[0] if len(e) > 1 else None
     cert = (r[0] ** 2 / gamma) if gamma and gamma > 0 else None
     n64, n32 = ctx.dav_stats()
+    nbf = ctx.dav_sigma_count(stpci.BF16)
     return {"p50_ms": float(np.percentile(times, 50)), "p99_ms": float(np.percentile(times, 99)),
             "n": nsolve, "iterations": its[-1], "energies": [float(x) for x in e],
             "resid": [float(x) for x in r], "energy_bound_eh": cert, "tol_residual": 1e-5,
-            "sigma_vectors_fp64": n64, "sigma_vectors_fp32": n32}
+            "sigma_vectors_fp64": n64, "sigma_vectors_fp32": n32 - nbf, "sigma_vectors_bf16": nbf}
 
 
 def _serve(nreq, max_dets, rate):

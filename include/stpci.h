@@ -67,8 +67,18 @@ typedef enum {
 typedef enum { STPCI_REAL64 = 0, STPCI_COMPLEX128 = 1 } stpci_scalar;
 
 /* Arithmetic of the category-block contractions (sigma build).  The Davidson
- * residual, orthogonalisation and subspace problem are always FP64. */
-typedef enum { STPCI_FP64 = 0, STPCI_FP32 = 1 } stpci_precision;
+ * residual, orthogonalisation and subspace problem are always FP64.
+ *  STPCI_FP64: FP64 throughout.
+ *  STPCI_FP32: integrals, coefficients and products in FP32, sums over the
+ *    contraction in FP32 and FP64, sigma FP64 (tile and pair kernels).
+ *  STPCI_BF16: pair kernel only; each batch of 16 / n pair intermediates
+ *    (n = vectors per pass, 1 or 2) is contracted as one dense product over
+ *    all pairs on the matrix cores (bfloat16 integrals and coefficients, FP32
+ *    accumulation), the per-target sums in FP64.  Relative sigma error of
+ *    the order of the bfloat16 rounding (2^-9); requires the workgroup's LDS
+ *    slice (pair table width rounded to 32, 16 / n intermediates) to fit
+ *    160 KB, else STPCI_EINVAL.  Not in the paper (which is FP64 throughout). */
+typedef enum { STPCI_FP64 = 0, STPCI_FP32 = 1, STPCI_BF16 = 2 } stpci_precision;
 
 /* Create a context on HIP device `hip_device` issuing work on `hip_stream`
  * (a hipStream_t, NULL for the default stream).  hip_device = -1 creates a
@@ -156,7 +166,8 @@ stpci_status stpci_sigma_kernel(const stpci_ctx* ctx, const char** name);
  * latter resolved over every intermediate one or two electrons away from the
  * space, including occupations outside the windows).  Device pointers,
  * [n_vec][n_dets] in the scalar type of the integrals; c_dev and sigma_dev
- * must not overlap.  Asynchronous on the context stream. */
+ * must not overlap.  prec: contraction arithmetic (stpci_precision).
+ * Asynchronous on the context stream. */
 stpci_status stpci_sigma(stpci_ctx* ctx, const void* c_dev, void* sigma_dev, int n_vec, stpci_precision prec);
 
 /* diag_dev[i] = <i|H|i> (real, n_dets doubles).  The solver itself never
@@ -196,11 +207,14 @@ stpci_status stpci_davidson(stpci_ctx* ctx, const stpci_dav_opts* opts, double* 
 stpci_status stpci_dav_history(const stpci_ctx* ctx, int* n_iter, int cap, double* energies, double* resid);
 
 /* Sigma products spent by the last Davidson run, counted in vectors: with
- * precision STPCI_FP32 the run first iterates with FP32 contractions to a
- * residual of max(tol_residual, 1e-4), then refines from those Ritz vectors
- * with FP64 contractions to tol_residual (the reported energies and residuals
- * are always those of the FP64 phase). */
+ * precision STPCI_FP32 (STPCI_BF16) the run first iterates with FP32 (BF16)
+ * contractions to a residual of max(tol_residual, 1e-4) (BF16:
+ * max(tol_residual, 2e-2)), then refines from those Ritz vectors with FP64
+ * contractions to tol_residual (the reported energies and residuals are
+ * always those of the FP64 phase).  sigma_fp32 counts the reduced-precision
+ * products of either kind; stpci_dav_sigma_count splits them by precision. */
 stpci_status stpci_dav_stats(const stpci_ctx* ctx, int* sigma_fp64, int* sigma_fp32);
+stpci_status stpci_dav_sigma_count(const stpci_ctx* ctx, stpci_precision prec, int* n_vectors);
 
 /* Kernel timing with HIP events on the context stream.  enable != 0 starts
  * recording every kernel launch of the sigma build; stpci_kernel_time
@@ -208,6 +222,7 @@ stpci_status stpci_dav_stats(const stpci_ctx* ctx, int* sigma_fp64, int* sigma_f
  * summed duration in milliseconds (synchronises).  Names: "sigma" (alias
  * "sigma2e": the FP64 one-pass sigma kernel -- the pair kernel, or the fused
  * one-move kernel), "sigma_fp32" (the same with the FP32 contraction),
+ * "sigma_bf16" (the matrix-core pair kernel of the BF16 contraction),
  * "sigma_reduce" (the per-target sum of the pair kernel's store-and-reduce
  * scatter), "sigma1e" (the separate one-electron kernel of the earlier
  * one-move forms). */

@@ -30,7 +30,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
 REAL64, COMPLEX128 = 0, 1
-FP64, FP32 = 0, 1
+FP64, FP32, BF16 = 0, 1, 2
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", ENOCONV: "ENOCONV", ESTATE: "ESTATE"}
 
 
@@ -70,6 +70,7 @@ _SIGS = {
     "stpci_davidson": ([_P, ctypes.POINTER(DavOpts), _DP, _DP, _P, _IP], _I),
     "stpci_dav_history": ([_P, _IP, _I, _DP, _DP], _I),
     "stpci_dav_stats": ([_P, _IP, _IP], _I),
+    "stpci_dav_sigma_count": ([_P, _I, _IP], _I),
     "stpci_profile": ([_P, _I], _I),
     "stpci_kernel_time": ([_P, ctypes.c_char_p, _I64P, _DP], _I),
     "stpci_test_heev": ([_I, _P, _P, _P], _I),
@@ -247,10 +248,17 @@ class Context:
         return p.value.decode()
 
     def dav_stats(self):
-        """(FP64 sigma vectors, FP32 sigma vectors) spent by the last Davidson run."""
+        """(FP64 sigma vectors, reduced-precision sigma vectors) spent by the
+        last Davidson run."""
         a, b = ctypes.c_int(), ctypes.c_int()
         self._check(_lib.stpci_dav_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def dav_sigma_count(self, precision):
+        """Sigma vectors of one contraction precision spent by the last run."""
+        n = ctypes.c_int()
+        self._check(_lib.stpci_dav_sigma_count(self._h, int(precision), ctypes.byref(n)))
+        return n.value
 
     def profile(self, enable=True):
         self._check(_lib.stpci_profile(self._h, int(bool(enable))))

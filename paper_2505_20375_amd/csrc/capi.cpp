@@ -20,7 +20,7 @@ stpci_ctx::~stpci_ctx() {
             (void)hipEventDestroy(e.a);
             (void)hipEventDestroy(e.b);
         }
-        for (DevBuf* b : {&d_E, &d_pcats, &d_pwork, &d_pslot, &d_pA, &d_pA32, &d_gT32, &d_hp32, &d_s2blocks, &d_ygroup, &d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
+        for (DevBuf* b : {&d_E, &d_pcats, &d_pwork, &d_pslot, &d_pA, &d_pA32, &d_pAbf, &d_gT32, &d_hp32, &d_s2blocks, &d_ygroup, &d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
                           &d_hp, &d_gT, &d_hd, &d_JK, &d_V, &d_W, &d_X, &d_R, &d_T, &d_partial, &d_small, &d_topv,
                           &d_topi})
             b->free_();
@@ -93,6 +93,28 @@ static void build_pair_table(stpci_ctx* c) {
                 }
         }
     c->pA32.assign(c->pA.begin(), c->pA.end());
+    // bfloat16 copy for the matrix-core form: row-major [P][Q] = A[P, Q]
+    // (= pA[Q * NP + P]) padded to npp columns and rows; complex tables hold
+    // the real part, the imaginary part and its negation
+    const size_t npp = (size_t)pair_mfma_npp((int)NP);
+    const int nm = c->cplx ? 3 : 1;
+    c->pAbf.assign(nm * npp * npp, 0);
+    auto bf = [](double x) {
+        const float f = (float)x;
+        uint32_t u;
+        std::memcpy(&u, &f, 4);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    };
+    for (size_t P = 0; P < NP; ++P)
+        for (size_t Q = 0; Q < NP; ++Q) {
+            const double* a = &c->pA[(Q * NP + P) * w];
+            c->pAbf[P * npp + Q] = bf(a[0]);
+            if (c->cplx) {
+                c->pAbf[npp * npp + P * npp + Q] = bf(a[1]);
+                c->pAbf[2 * npp * npp + P * npp + Q] = bf(-a[1]);
+            }
+        }
 }
 
 // Sigma kernel prepare() selects for this context.
@@ -225,6 +247,8 @@ stpci_status prepare(stpci_ctx* c) {
     D.pcats = (const PairCat*)c->d_pcats.p;
     D.pwork_begin = (const int64_t*)c->d_pwork.p;
     D.pslot = (const uint32_t*)c->d_pslot.p;
+    c->have32 = false;   // the reduced-precision copies follow the tables rebuilt above
+    c->have_bf = false;
     c->prepared = true;
     return STPCI_OK;
 }
@@ -242,6 +266,14 @@ static void record(stpci_ctx* c, int kind, bool start) {
     }
 }
 
+stpci_status ensure_bf16(stpci_ctx* c) {
+    if (c->have_bf) return STPCI_OK;
+    stpci_status s = upload(c, c->d_pAbf, c->pAbf, "bfloat16 pair-pair integrals");
+    if (s) return s;
+    c->have_bf = true;
+    return STPCI_OK;
+}
+
 stpci_status ensure32(stpci_ctx* c) {
     if (c->have32) return STPCI_OK;
     stpci_status s;
@@ -256,9 +288,33 @@ stpci_status ensure32(stpci_ctx* c) {
 }
 
 stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, stpci_precision prec) {
-    if (prec != STPCI_FP64 && prec != STPCI_FP32) return set_err(c, STPCI_EINVAL, "unsupported sigma precision");
+    if (prec != STPCI_FP64 && prec != STPCI_FP32 && prec != STPCI_BF16)
+        return set_err(c, STPCI_EINVAL, "unsupported sigma precision");
     const bool f32 = prec == STPCI_FP32;
     hipError_t e;
+    if (prec == STPCI_BF16) {
+        // pair products on the matrix cores (bfloat16 operands, FP32 accumulation)
+        if (c->s2_kernel != 4 || !pair_mfma_supported(c->dev, c->hs.pmax_deg, c->cplx))
+            return set_err(c, STPCI_EINVAL, "the BF16 contraction needs the pair kernel within its LDS limits");
+        stpci_status s = ensure_bf16(c);
+        if (s) return s;
+        struct Mark {
+            stpci_ctx* c;
+            static void fn(void* u, int what, bool start) {
+                Mark* m = static_cast<Mark*>(u);
+                record(m->c, what == 0 ? 4 : 3, start);
+            }
+        } mark{c};
+        const LaunchMarks mk{&Mark::fn, &mark};
+        void* E = nullptr;
+        if (c->pair_store) {
+            if ((s = ensure(c, c->d_E, pair_store_bytes(c->dev, c->cplx), "pair contribution workspace"))) return s;
+            E = c->d_E.p;
+        }
+        e = launch_sigma_pair_mfma(c->dev, c->hs.pmax_deg, c->cplx, c->d_pAbf.p, cin, sout, E, n_vec, c->e_core,
+                                   c->profile ? &mk : nullptr, c->stream);
+        return e == hipSuccess ? STPCI_OK : hip_check(c, e, "sigma launch");
+    }
     if (f32) {
         // category-block contraction in FP32 (FP32 accumulation); sigma accumulated in FP64
         if (c->s2_kernel < 3) return set_err(c, STPCI_EINVAL, "the FP32 contraction needs a tile kernel");
@@ -465,6 +521,7 @@ stpci_status stpci_set_integrals(stpci_ctx* c, int n_orb, stpci_scalar scalar, i
     c->gT32.assign(c->gT.begin(), c->gT.end());
     c->hp32.assign(c->hprime.begin(), c->hprime.end());
     c->have32 = false;
+    c->have_bf = false;
     c->have_ints = true;
     c->prepared = false;
     return STPCI_OK;
@@ -614,6 +671,7 @@ stpci_status stpci_kernel_time(stpci_ctx* c, const char* name, int64_t* launches
     if (!std::strcmp(name, "sigma2e") || !std::strcmp(name, "sigma")) kind = 1;
     if (!std::strcmp(name, "sigma_fp32")) kind = 2;
     if (!std::strcmp(name, "sigma_reduce")) kind = 3;
+    if (!std::strcmp(name, "sigma_bf16")) kind = 4;
     if (kind < 0) return set_err(c, STPCI_EINVAL, "unknown kernel name");
     if (c->host_only) return set_err(c, STPCI_ESTATE, "host-only context");
     stpci_status s = hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
@@ -652,10 +710,11 @@ stpci_status stpci_set_sigma_kernel(stpci_ctx* c, const char* name) {
     if (k == -1) return set_err(c, STPCI_EINVAL, "unknown sigma kernel name");
     c->kernel_req = (k == -2) ? -1 : k;
     // device copies depend on the kernel: rebuild them on the next device call
-    for (DevBuf* b : {&c->d_E, &c->d_pcats, &c->d_pwork, &c->d_pslot, &c->d_pA, &c->d_pA32, &c->d_gT32, &c->d_hp32,
+    for (DevBuf* b : {&c->d_E, &c->d_pcats, &c->d_pwork, &c->d_pslot, &c->d_pA, &c->d_pA32, &c->d_pAbf, &c->d_gT32, &c->d_hp32,
                       &c->d_s2blocks, &c->d_ygroup, &c->d_hp, &c->d_gT})
         if (!c->host_only) b->free_();
     c->have32 = false;
+    c->have_bf = false;
     c->prepared = false;
     return STPCI_OK;
 }

@@ -40,6 +40,8 @@ struct DavState {
     int m = 0;    // vectors in V with their W known
     int nv = 0;   // pending: W[m..m+nv) = H V[m..m+nv)
     int it = 0, it_prev = 0;
+    double best_rn = -1.0;   // reduced-precision phase: smallest largest-residual so far
+    int stall = 0;           // iterations since it last dropped by 10 %
     bool converged = false, done = false, active = false;
     std::vector<std::complex<double>> G;
     std::vector<double> theta, rn;
@@ -65,6 +67,7 @@ struct stpci_ctx {
     std::vector<float> gT32, hp32; // FP32 copies for the FP32 contraction
     std::vector<double> pA;        // pair-pair table of the pair kernel (built with the space)
     std::vector<float> pA32;
+    std::vector<uint16_t> pAbf;   // bfloat16 pair-pair table of the matrix-core form
 
     // space
     bool have_space = false;
@@ -76,7 +79,8 @@ struct stpci_ctx {
     stp::DevBuf d_hp, d_gT, d_hd, d_JK;
     stp::DevBuf d_gT32, d_hp32;
     bool have32 = false;
-    stp::DevBuf d_pcats, d_pwork, d_pslot, d_pA, d_pA32;
+    bool have_bf = false;
+    stp::DevBuf d_pcats, d_pwork, d_pslot, d_pA, d_pA32, d_pAbf;
     stp::DevBuf d_E;         // pair contributions of the store-and-reduce scatter
     bool pair_store = false; // pair kernel: store-and-reduce (true) or device atomics
     int kernel_req = -1;   // requested sigma kernel (stpci_set_sigma_kernel), -1: automatic
@@ -93,7 +97,7 @@ struct stpci_ctx {
     stp::DevBuf d_V, d_W, d_X, d_R, d_T, d_partial, d_small, d_topv, d_topi;
     std::vector<stp::DavRecord> history;
     int hist_k = 0;
-    int nsigma[2] = {0, 0};   // sigma builds of the last Davidson run: FP64, FP32 (vectors)
+    int nsigma[3] = {0, 0, 0};   // sigma builds of the last Davidson run: FP64, FP32, BF16 (vectors)
     stp::DavState dav;
 
     // profiling
@@ -110,6 +114,7 @@ stpci_status prepare(stpci_ctx* c);
 stpci_status ensure(stpci_ctx* c, DevBuf& b, size_t bytes, const char* what);
 stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, stpci_precision prec);
 stpci_status ensure32(stpci_ctx* c);  // upload the FP32 integral copies once
+stpci_status ensure_bf16(stpci_ctx* c);  // upload the bfloat16 pair table once
 int select_kernel(const stpci_ctx* c);
 int64_t device_table_bytes(const stpci_ctx* c, bool f32);
 size_t scalar_bytes(const stpci_ctx* c);

@@ -304,7 +304,9 @@ static stpci_status dav_start(stpci_ctx* c, stpci_precision prec, const void* gu
     const int k = o.k;
     D.prec = prec;
     D.tol = tol;
-    D.pidx = (prec == STPCI_FP32) ? 1 : 0;
+    D.pidx = (prec == STPCI_FP32) ? 1 : (prec == STPCI_BF16) ? 2 : 0;
+    D.best_rn = -1.0;
+    D.stall = 0;
     const size_t vb = (size_t)N * scalar_bytes(c);
     D.kr_max = std::min(2 * k, 32);
     int mmax = subspace_request(o);
@@ -432,6 +434,18 @@ static stpci_status dav_advance(stpci_ctx* c) {
     bool conv = true;
     for (int j = 0; j < k; ++j) conv = conv && D.rn[j] <= D.tol;
     D.converged = conv;
+    if (D.prec != STPCI_FP64 && !conv) {
+        // a reduced-precision phase also ends when its largest residual has
+        // not dropped by 10 % over 5 iterations (its rounding floor)
+        const double r = *std::max_element(D.rn.begin(), D.rn.end());
+        if (D.best_rn < 0 || r < 0.9 * D.best_rn) {
+            D.best_rn = r;
+            D.stall = 0;
+        } else if (++D.stall >= 5) {
+            D.done = true;
+            return STPCI_OK;
+        }
+    }
     if (conv || D.it >= D.max_iter) {
         D.done = true;
         return STPCI_OK;
@@ -571,15 +585,20 @@ stpci_status dav_begin(stpci_ctx* c, const stpci_dav_opts* o) {
     if ((s = hip_check(c, hipSetDevice(c->device), "hipSetDevice"))) return s;
     const int64_t N = c->hs.sp.ndets;
     if (o->k < 1 || o->k > 16 || o->k > N) return set_err(c, STPCI_EINVAL, "k must be in [1, min(16, n_dets)]");
-    if (o->precision != STPCI_FP64 && o->precision != STPCI_FP32) return set_err(c, STPCI_EINVAL, "unknown precision");
+    if (o->precision != STPCI_FP64 && o->precision != STPCI_FP32 && o->precision != STPCI_BF16)
+        return set_err(c, STPCI_EINVAL, "unknown precision");
     c->dav = DavState{};
     c->dav.opts = *o;
     c->dav.final_tol = o->tol_residual > 0 ? o->tol_residual : 1e-8;
     c->history.clear();
     c->hist_k = o->k;
-    c->nsigma[0] = c->nsigma[1] = 0;
-    if (o->precision == STPCI_FP32)  // phase A: FP32 contraction to a residual FP32 products resolve
+    c->nsigma[0] = c->nsigma[1] = c->nsigma[2] = 0;
+    // phase A: reduced-precision contractions to a residual their products
+    // resolve (FP32 about 1e-7 relative, BF16 about 2^-9)
+    if (o->precision == STPCI_FP32)
         return dav_start(c, STPCI_FP32, o->guess_dev, std::max(c->dav.final_tol, 1e-4));
+    if (o->precision == STPCI_BF16)
+        return dav_start(c, STPCI_BF16, o->guess_dev, std::max(c->dav.final_tol, 2e-2));
     return dav_start(c, STPCI_FP64, o->guess_dev, c->dav.final_tol);
 }
 
@@ -595,13 +614,13 @@ bool dav_pending(stpci_ctx* c, const void** in, void** out, int* n, stpci_precis
     return true;
 }
 
-// Advance after the pending products; moves from the FP32 phase to FP64
-// refinement (guess = the FP32 Ritz vectors) when the former ends.
+// Advance after the pending products; moves from a reduced-precision phase to
+// FP64 refinement (guess = its Ritz vectors) when the former ends.
 stpci_status dav_step_after_sigma(stpci_ctx* c, int* finished) {
     DavState& D = c->dav;
     stpci_status s = dav_advance(c);
     if (s) return s;
-    if (D.done && D.prec == STPCI_FP32) {
+    if (D.done && D.prec != STPCI_FP64) {
         D.it_prev += D.it;
         const int keep = D.it_prev;
         if ((s = dav_start(c, STPCI_FP64, c->d_X.p, D.final_tol))) return s;
@@ -655,7 +674,13 @@ extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, do
 extern "C" stpci_status stpci_dav_stats(const stpci_ctx* c, int* sigma_fp64, int* sigma_fp32) {
     if (!c) return STPCI_EINVAL;
     if (sigma_fp64) *sigma_fp64 = c->nsigma[0];
-    if (sigma_fp32) *sigma_fp32 = c->nsigma[1];
+    if (sigma_fp32) *sigma_fp32 = c->nsigma[1] + c->nsigma[2];
+    return STPCI_OK;
+}
+
+extern "C" stpci_status stpci_dav_sigma_count(const stpci_ctx* c, stpci_precision prec, int* n_vectors) {
+    if (!c || !n_vectors || prec < STPCI_FP64 || prec > STPCI_BF16) return STPCI_EINVAL;
+    *n_vectors = c->nsigma[(int)prec];
     return STPCI_OK;
 }
 

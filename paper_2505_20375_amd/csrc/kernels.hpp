@@ -33,6 +33,19 @@ struct LaunchMarks {
     void (*fn)(void* user, int what, bool start);
     void* user;
 };
+// sigma = e_core c + the stored pair contributions E (nv = 1 or 2 vectors of
+// the store layout), summed in a fixed order.
+hipError_t launch_pair_reduce(const DevSpace& S, bool cplx, int nv, void* sigma, const void* c, const void* E,
+                              int n_vec, double e_core, hipStream_t st);
+// BF16 matrix-core form of the pair sigma build: Ab holds the pair-pair table
+// in bfloat16, row-major [P][Q] with npp (a multiple of 32) columns; complex:
+// three matrices (real part, imaginary part, negated imaginary part).
+// E non-null: store-and-reduce scatter, else device atomics.
+bool pair_mfma_supported(const DevSpace& S, int deg_max, bool cplx);
+int pair_mfma_npp(int npairs);
+hipError_t launch_sigma_pair_mfma(const DevSpace& S, int deg_max, bool cplx, const void* Ab, const void* c,
+                                  void* sigma, void* E, int n_vec, double e_core, const LaunchMarks* mk,
+                                  hipStream_t st);
 hipError_t launch_sigma_pair(const DevSpace& S, int deg_max, bool cplx, bool f32, const void* A, const void* c,
                              void* sigma, void* E, int n_vec, double e_core, const LaunchMarks* mk, hipStream_t st);
 hipError_t launch_sigma_pair_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,

@@ -99,11 +99,16 @@ static void release_stream(stpci_server* s, Req& q) {
 }
 
 // Device bytes a request holds while active: tables, integrals (with the
-// FP32 copies for the FP32 contraction), the schedule of the row-tiled
+// FP32 or bfloat16 copies of the reduced-precision forms), the schedule of the row-tiled
 // fallback kernel where the tile kernel does not apply, and the Davidson
 // vectors and workspace.
 static int64_t footprint(const stpci_ctx* c, const stpci_dav_opts& o) {
-    return device_table_bytes(c, o.precision == STPCI_FP32) + dav_device_bytes(c, o);
+    int64_t b = device_table_bytes(c, o.precision == STPCI_FP32) + dav_device_bytes(c, o);
+    if (o.precision == STPCI_BF16 && select_kernel(c) == 4) {  // the bfloat16 pair table
+        const int64_t npp = pair_mfma_npp(c->M * (c->M - 1) / 2);
+        b += npp * npp * (c->cplx ? 3 : 1) * 2;
+    }
+    return b;
 }
 
 // host threads that advance the active requests' Davidson iterations
@@ -268,8 +273,9 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
         if (!dav_pending(q.ctx, &in, &out, &n, &prec)) continue;
         stpci_ctx* c = q.ctx;
         const bool f32 = prec == STPCI_FP32;
-        if (c->s2_kernel < 3) {
-            // spaces outside the tile kernel's limits take the context's own path
+        if (c->s2_kernel < 3 || prec == STPCI_BF16) {
+            // spaces outside the tile kernel's limits, and the BF16 contraction,
+            // take the context's own path
             stpci_status st = sigma_impl(c, in, out, n, prec);
             if (st) {
                 retire(s, q, st);

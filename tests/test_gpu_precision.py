@@ -1,8 +1,11 @@
-"""Precision form: category-block contractions in FP32 with FP32 accumulation,
-Davidson residual, orthogonalisation and subspace problem in FP64, and FP64
-refinement of the FP32 iterate.  Energies after refinement must agree with
-the all-FP64 result and with exact diagonalisation within 1e-8 Eh; the FP32
-sigma error against FP64 is bounded by single-precision rounding."""
+"""Precision form: category-block contractions in FP32 (VALU) or BF16 (matrix
+cores, FP32 accumulation), Davidson residual, orthogonalisation and subspace
+problem in FP64, and FP64 refinement of the reduced-precision iterate.
+Energies after refinement must agree with the all-FP64 result and with exact
+diagonalisation within 1e-8 Eh; the sigma error against FP64 is bounded by
+the rounding of the contraction type (FP32: 2^-24 relative per operand, the
+bound 2e-6 allows the accumulation over up to a few hundred terms; BF16:
+2^-9 per operand, bound 2e-2)."""
 import numpy as np
 import pytest
 
@@ -64,3 +67,54 @@ def test_mixed_precision_davidson_config2():
     assert np.max(np.abs(e32 - e64)) <= 1e-8
     assert np.all(r32 <= 1e-6)
     assert n32 > n64
+
+
+@pytest.mark.parametrize("name", ["T4", "c1", "T8", "c2"])
+def test_bf16_sigma_error_is_bfloat16_rounding(name):
+    """The matrix-core form against the FP64 sigma: relative error of the
+    order of bfloat16 rounding of integrals and coefficients (not zero: the
+    reduced arithmetic really ran)."""
+    import paper_2505_20375_amd as stpci
+    pb = Problem.named(name)
+    c = pb.vector()
+    s64 = _sigma(pb, c, stpci.FP64)
+    sbf = _sigma(pb, c, stpci.BF16)
+    err = rel_err(sbf, s64)
+    print("bf16 sigma relative error", name, err)
+    assert 1e-6 < err <= 2e-2
+
+
+def test_bf16_sigma_two_vectors_and_atomic_scatter():
+    """Two vectors per pass (8 intermediates per product) and the device-atomic
+    scatter give the same products as one vector with the stored scatter."""
+    import torch
+    import paper_2505_20375_amd as stpci
+    pb = Problem.named("T4")
+    c1, c2 = pb.vector(1), pb.vector(2)
+    ref = []
+    for kernel in ("pair", "pair_atomic"):
+        ctx = pb.context()
+        ctx.set_sigma_kernel(kernel)
+        x = torch.cat([pb.to_device(c1), pb.to_device(c2)])
+        out = torch.empty_like(x)
+        ctx.sigma(x, out, n_vec=2, precision=stpci.BF16)
+        one = torch.empty_like(x[:len(pb.dets)])
+        ctx.sigma(x[:len(pb.dets)], one, n_vec=1, precision=stpci.BF16)
+        torch.cuda.synchronize()
+        n = len(pb.dets)
+        ref.append((pb.from_device(out[:n]), pb.from_device(out[n:]), pb.from_device(one)))
+    for a, b, o in ref:
+        assert rel_err(a, o) <= 1e-6   # same bfloat16 products, FP32 sums in another order
+        assert rel_err(b, pb.oracle_sigma(c2)) <= 2e-2
+    assert rel_err(ref[0][0], ref[1][0]) <= 1e-6
+
+
+@pytest.mark.parametrize("name,k", [("T4", 2), ("c1", 1)])
+def test_bf16_davidson_matches_exact(name, k):
+    import paper_2505_20375_amd as stpci
+    pb = Problem.named(name)
+    w = np.linalg.eigvalsh(dense.hamiltonian(pb.dets, pb.h, pb.g, real=not pb.cplx))
+    ctx = pb.context()
+    e, r, it, st = ctx.davidson(k=k, tol=1e-8, precision=stpci.BF16)
+    assert ctx.dav_sigma_count(stpci.BF16) > 0
+    assert np.max(np.abs(e - w[:k])) <= 1e-8

@@ -79,7 +79,7 @@ __device__ __forceinline__ typename VT<CPLX>::T make_scalar(double re, double im
 }
 
 template <bool CPLX, int NV, bool STORE>
-__global__ __launch_bounds__(256) void k_sigma_pair_mfma(DevSpace S, const uint16_t* __restrict__ Ab, int npp,
+__global__ __launch_bounds__(512) void k_sigma_pair_mfma(DevSpace S, const uint16_t* __restrict__ Ab, int npp,
                                                         const typename VT<CPLX>::T* __restrict__ c,
                                                         typename VT<CPLX>::T* __restrict__ sigma,
                                                         typename VT<CPLX>::T* __restrict__ E, int nq, int n_vec,
@@ -208,10 +208,16 @@ static size_t mfma_lds_bytes(int nv, int deg_max, int npp, bool cplx) {
     return MfmaLayout(MF_COLS / nv, deg_max, npp, cplx).bytes;
 }
 
+constexpr size_t MF_LDS_MAX = 160 * 1024;
+
+// Single vectors use the 16-intermediate batch where its slice fits, else
+// the 8-intermediate batch of the two-vector kernel with the second column
+// of each intermediate left zero.
+static bool single_fits(int deg_max, int npp, bool cplx) { return mfma_lds_bytes(1, deg_max, npp, cplx) <= MF_LDS_MAX; }
+
 bool pair_mfma_supported(const DevSpace& S, int deg_max, bool cplx) {
     const int npp = pair_mfma_npp(S.sp.npairs);
-    return S.sp.N >= 2 && deg_max > 0 && deg_max < 32768 && mfma_lds_bytes(1, deg_max, npp, cplx) <= 160 * 1024 &&
-           mfma_lds_bytes(2, deg_max, npp, cplx) <= 160 * 1024;
+    return S.sp.N >= 2 && deg_max > 0 && deg_max < 32768 && mfma_lds_bytes(2, deg_max, npp, cplx) <= MF_LDS_MAX;
 }
 
 template <bool CPLX, int NV, bool STORE>
@@ -223,7 +229,7 @@ static hipError_t launch_mfma_nv(const DevSpace& S, int deg_max, const void* Ab,
     const int nq = S.sp.N * (S.sp.N - 1) / 2;
     const int64_t nbatch = (S.sp.npwork_dets + MF_COLS / NV - 1) / (MF_COLS / NV);
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(nbatch, 256 * 8));
-    hipLaunchKernelGGL((k_sigma_pair_mfma<CPLX, NV, STORE>), dim3((unsigned)blocks), dim3(256), lds, st, S,
+    hipLaunchKernelGGL((k_sigma_pair_mfma<CPLX, NV, STORE>), dim3((unsigned)blocks), dim3(512), lds, st, S,
                        (const uint16_t*)Ab, npp, (const T64*)c, (T64*)sigma, (T64*)E, nq, n_vec, deg_max);
     return hipGetLastError();
 }
@@ -237,23 +243,25 @@ static hipError_t launch_mfma_all(const DevSpace& S, int deg_max, const void* Ab
         e = launch_fill_init(CPLX, sigma, c, e_core, S.sp.ndets * n_vec, st);
         if (e != hipSuccess) return e;
     }
+    const bool one = single_fits(deg_max, pair_mfma_npp(S.sp.npairs), CPLX);
     for (int v0 = 0; v0 < n_vec; v0 += 2) {
         const int nv = (n_vec - v0 >= 2) ? 2 : 1;
+        const int kv = (nv == 1 && one) ? 1 : 2;   // vector width of the kernel (and of E)
         const int64_t off = (int64_t)v0 * S.sp.ndets;
         const T64* cc = (const T64*)c + off;
         T64* ss = (T64*)sigma + off;
         if (mk) mk->fn(mk->user, 0, true);
         if (E)
-            e = (nv == 2) ? launch_mfma_nv<CPLX, 2, true>(S, deg_max, Ab, cc, ss, E, 2, st)
+            e = (kv == 2) ? launch_mfma_nv<CPLX, 2, true>(S, deg_max, Ab, cc, ss, E, nv, st)
                           : launch_mfma_nv<CPLX, 1, true>(S, deg_max, Ab, cc, ss, E, 1, st);
         else
-            e = (nv == 2) ? launch_mfma_nv<CPLX, 2, false>(S, deg_max, Ab, cc, ss, nullptr, 2, st)
+            e = (kv == 2) ? launch_mfma_nv<CPLX, 2, false>(S, deg_max, Ab, cc, ss, nullptr, nv, st)
                           : launch_mfma_nv<CPLX, 1, false>(S, deg_max, Ab, cc, ss, nullptr, 1, st);
         if (mk) mk->fn(mk->user, 0, false);
         if (e != hipSuccess) return e;
         if (E) {
             if (mk) mk->fn(mk->user, 1, true);
-            e = launch_pair_reduce(S, CPLX, nv, ss, cc, E, nv, e_core, st);
+            e = launch_pair_reduce(S, CPLX, kv, ss, cc, E, nv, e_core, st);
             if (mk) mk->fn(mk->user, 1, false);
             if (e != hipSuccess) return e;
         }

@@ -217,7 +217,7 @@ def main():
 
 TRAFFIC_FILES = {"pair": os.path.join(ROOT, "profiles", "sigma_pair_c2_traffic.txt"),
                  "tile": os.path.join(ROOT, "profiles", "sigma_symtile_c2_traffic.txt")}
-KERNEL_SOURCES = {"pair": ["sigma_pair.hip", "symtile.hpp", "stp_device.hpp", "stp_internal.hpp"],
+KERNEL_SOURCES = {"pair": ["sigma_pair.hip", "pair_arith.hpp", "symtile.hpp", "stp_device.hpp", "stp_internal.hpp"],
                   "tile": ["sigma_sym.hip", "stp_device.hpp", "stp_internal.hpp"]}
 
 

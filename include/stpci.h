@@ -209,7 +209,8 @@ stpci_status stpci_dav_history(const stpci_ctx* ctx, int* n_iter, int cap, doubl
 /* Sigma products spent by the last Davidson run, counted in vectors: with
  * precision STPCI_FP32 (STPCI_BF16) the run first iterates with FP32 (BF16)
  * contractions to a residual of max(tol_residual, 1e-4) (BF16:
- * max(tol_residual, 2e-2)), then refines from those Ritz vectors with FP64
+ * max(tol_residual, 2e-2), or until its largest residual has not dropped by
+ * 10 % over 8 iterations), then refines from those Ritz vectors with FP64
  * contractions to tol_residual (the reported energies and residuals are
  * always those of the FP64 phase).  sigma_fp32 counts the reduced-precision
  * products of either kind; stpci_dav_sigma_count splits them by precision. */

@@ -40,7 +40,7 @@ struct DavState {
     int m = 0;    // vectors in V with their W known
     int nv = 0;   // pending: W[m..m+nv) = H V[m..m+nv)
     int it = 0, it_prev = 0;
-    double best_rn = -1.0;   // reduced-precision phase: smallest largest-residual so far
+    double best_rn = -1.0;   // BF16 phase: smallest largest-residual so far
     int stall = 0;           // iterations since it last dropped by 10 %
     bool converged = false, done = false, active = false;
     std::vector<std::complex<double>> G;

@@ -434,14 +434,14 @@ static stpci_status dav_advance(stpci_ctx* c) {
     bool conv = true;
     for (int j = 0; j < k; ++j) conv = conv && D.rn[j] <= D.tol;
     D.converged = conv;
-    if (D.prec != STPCI_FP64 && !conv) {
-        // a reduced-precision phase also ends when its largest residual has
-        // not dropped by 10 % over 5 iterations (its rounding floor)
+    if (D.prec == STPCI_BF16 && !conv) {
+        // the BF16 phase also ends when its largest residual has not dropped
+        // by 10 % over 8 iterations (the bfloat16 rounding floor of sigma)
         const double r = *std::max_element(D.rn.begin(), D.rn.end());
         if (D.best_rn < 0 || r < 0.9 * D.best_rn) {
             D.best_rn = r;
             D.stall = 0;
-        } else if (++D.stall >= 5) {
+        } else if (++D.stall >= 8) {
             D.done = true;
             return STPCI_OK;
         }

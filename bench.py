@@ -198,6 +198,23 @@ def main():
                 "frac_executed": round(mf_flops / (kms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4),
                 "executed_flops_per_launch": mf_flops, "useful_flops_per_launch": flops}
     prec["sigma_speedup"] = prec["sigma_fp32_speedup"]   # FP32 over FP64
+    # intermediates whose gathered coefficients are all zero are skipped:
+    # FP64 sigma of vectors with a random 1 % and 0.1 % of their entries nonzero
+    sparse = {}
+    gs = torch.Generator(device="cuda").manual_seed(2103)
+    for dens in (1e-2, 1e-3):
+        cs = c * (torch.rand(c.shape, generator=gs, device="cuda") < dens)
+        for _ in range(max(1, args.warmup)):
+            ctx.sigma(cs, out, n_vec=n_vec)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            ctx.sigma(cs, out, n_vec=n_vec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_s = e0.elapsed_time(e1) / args.steps
+        sparse["density_%g" % dens] = {"sigma_fp64_ms": ms_s, "speedup_vs_dense": ms_per_step / ms_s}
+    res["sparse_vectors"] = sparse
     res["precision"] = prec
     if not args.no_solve:
         res["solve"] = _solve(ctx, roots, args.solves, stpci.FP64)

@@ -118,6 +118,7 @@ __global__ __launch_bounds__(512) void k_sigma_pair_mfma(DevSpace S, const uint1
         __syncthreads();
 
         // ---- phase 1: one wavefront per K' of the batch
+        int nz = 0;   // a nonzero coefficient among this lane's gathers
         for (int b = wid; b < BK; b += nwv) {
             const int64_t J = j0 + b;
             if (J >= total) break;
@@ -142,6 +143,7 @@ __global__ __launch_bounds__(512) void k_sigma_pair_mfma(DevSpace S, const uint1
                 for (int v = 0; v < NV; ++v) {
                     if (v >= n_vec) break;
                     const TE x = c[(int64_t)v * nd + addr];
+                    nz |= V64::abs2(x) != 0.0;
                     const float sg = neg ? -1.0f : 1.0f;
                     const int col = b * NV + v;
                     Dr[col * ldd + pi] = bf16_bits(sg * (float)V64::re(x));
@@ -149,7 +151,23 @@ __global__ __launch_bounds__(512) void k_sigma_pair_mfma(DevSpace S, const uint1
                 }
             }
         }
-        __syncthreads();
+        // a batch whose gathered coefficients are all zero contributes nothing
+        // (zero blocks skipped, here per batch of intermediates): no product,
+        // and in store mode zeros for its entries
+        if (!__syncthreads_or(nz)) {
+            if (STORE)
+                for (int b = wid; b < BK; b += nwv) {
+                    const int64_t J = j0 + b;
+                    if (J >= total) break;
+                    const int deg = S.pcats[find_segment(S.pwork_begin, S.sp.npcat, J)].deg;
+                    for (int slot = lane; slot < deg; slot += 64)
+#pragma unroll
+                        for (int v = 0; v < NV; ++v)
+                            if (v < n_vec) E[tgt[b * deg_cap + slot] * NV + v] = V64::zero();
+                }
+            __syncthreads();   // the next batch rewrites the slice
+            continue;
+        }
 
         // ---- phases 2 and 3: 16-row tiles of E over the wavefronts
         const int bcol = cl / NV, vcol = cl % NV;   // this lane's output column

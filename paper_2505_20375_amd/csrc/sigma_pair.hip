@@ -78,6 +78,7 @@ __device__ __forceinline__ void pair_det(const DevSpace& S, const typename PT<CP
     if (lane == 63) pair_hdr_bits(S, hd);
     wave_lds_sync();
     const int NP = S.sp.npairs;
+    bool nz = false;   // a nonzero coefficient among this lane's slots
     for (int slot = lane; slot < ((deg + 3) & ~3); slot += 64) {
         if (slot >= deg) {
 #pragma unroll
@@ -95,20 +96,26 @@ __device__ __forceinline__ void pair_det(const DevSpace& S, const typename PT<CP
         rinf[slot] = (pi << 1) | (neg ? 1 : 0);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            T val = (v < n_vec) ? V::from64(c[(int64_t)v * nd + addr]) : V::zero();
+            const TE x = (v < n_vec) ? c[(int64_t)v * nd + addr] : V64::zero();
+            nz = nz || V64::abs2(x) != 0.0;
+            T val = V::from64(x);
             if (neg) val = V::scale(val, -1.0);
             dsh[st_idx<NV, SB>(slot, v)] = val;
             esh[st_idx<NV, SE>(slot, v)] = V64::zero();
         }
     }
     wave_lds_sync();
+    // an intermediate whose gathered coefficients are all zero contributes
+    // nothing (the categorical skipping of zero blocks, here per
+    // intermediate): no contraction, and in store mode zeros for its entries
+    const bool live = __ballot(nz) != 0;
 
     // ---- phase 2: e = A_K' d
-    tile_contract<CPLX, F32, NV>(A, NP, dsh, esh, rinf, deg, lane);
+    if (live) tile_contract<CPLX, F32, NV>(A, NP, dsh, esh, rinf, deg, lane);
     wave_lds_sync();
 
     // ---- phase 3: sigma[K' + P] += sgn(P) e[P]
-    for (int slot = lane; slot < deg; slot += 64) {
+    for (int slot = lane; slot < ((STORE || live) ? deg : 0); slot += 64) {
         const double sg = (rinf[slot] & 1) ? -1.0 : 1.0;
         const int64_t t = tgt[slot];
         if (STORE) {

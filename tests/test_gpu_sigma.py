@@ -188,6 +188,33 @@ def test_pair_store_mode_is_deterministic():
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("kernel,prec", [("pair", "fp64"), ("pair_atomic", "fp64"), ("pair", "fp32"),
+                                         ("pair", "bf16"), ("pair_atomic", "bf16")])
+def test_sparse_vector_after_dense(kernel, prec):
+    """Intermediates (BF16: batches of them) whose gathered coefficients are
+    all zero skip the contraction; in store mode they must still overwrite
+    their entries of the contribution workspace.  A dense sigma first fills
+    the workspace, then a vector confined to one category (so that most
+    intermediates see only zeros) must give the oracle's sigma."""
+    import torch
+    import paper_2505_20375_amd as stpci
+    code = {"fp64": stpci.FP64, "fp32": stpci.FP32, "bf16": stpci.BF16}[prec]
+    tol = {"fp64": TOL, "fp32": 2e-6, "bf16": 2e-2}[prec]
+    ints = synth.complex_integrals(12, 9)
+    sp = synth.SpaceSpec(6, [4, 4, 4])
+    pb = Problem(ints, sp, seed=5)
+    occ = np.array([[bin(int(b) >> (4 * k) & 0xF).count("1") for k in range(3)] for b in pb.dets])
+    sparse = pb.vector(8) * np.all(occ == (4, 2, 0), axis=1)
+    ctx = pb.context()
+    ctx.set_sigma_kernel(kernel)
+    xd, xs = pb.to_device(pb.vector(7)), pb.to_device(sparse)
+    out = torch.empty_like(xd)
+    ctx.sigma(xd, out, precision=code)
+    ctx.sigma(xs, out, precision=code)
+    torch.cuda.synchronize()
+    assert rel_err(pb.from_device(out), pb.oracle_sigma(sparse)) <= tol
+
+
 def test_sigma_config3p_sampled_rows():
     """Full-size STP-DAS space (40 spinors, 12|16|12, windows [2..6]|[4..10]|[2..6],
     11 electrons: 1,365,867,360 determinants in 10 categories, 21.9 GB per

@@ -206,6 +206,15 @@ stpci_status stpci_davidson(stpci_ctx* ctx, const stpci_dav_opts* opts, double* 
  * resid[i*k + j].  Either array may be NULL. */
 stpci_status stpci_dav_history(const stpci_ctx* ctx, int* n_iter, int cap, double* energies, double* resid);
 
+/* Largest coefficient change of each Ritz vector per iteration of the last
+ * Davidson run (Results: reported per iteration beside the energies and
+ * residual norms): dc[i*k + j] = max_a |x_j[a] - ph x_j'[a]| for iteration
+ * i < cap, x_j' the Ritz vector of the previous iteration and ph the unit
+ * phase of <x_j'|x_j> (Ritz vectors are defined up to a phase); NaN on the
+ * first iteration of a run and of the FP64 phase after a reduced-precision
+ * one.  dc: host array of cap * k doubles. */
+stpci_status stpci_dav_history_dc(const stpci_ctx* ctx, int cap, double* dc);
+
 /* Sigma products spent by the last Davidson run, counted in vectors: with
  * precision STPCI_FP32 (STPCI_BF16) the run first iterates with FP32 (BF16)
  * contractions to a residual of max(tol_residual, 1e-4) (BF16:

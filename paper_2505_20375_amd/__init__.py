@@ -71,6 +71,7 @@ _SIGS = {
     "stpci_dav_history": ([_P, _IP, _I, _DP, _DP], _I),
     "stpci_dav_stats": ([_P, _IP, _IP], _I),
     "stpci_dav_sigma_count": ([_P, _I, _IP], _I),
+    "stpci_dav_history_dc": ([_P, _I, _DP], _I),
     "stpci_profile": ([_P, _I], _I),
     "stpci_kernel_time": ([_P, ctypes.c_char_p, _I64P, _DP], _I),
     "stpci_test_heev": ([_I, _P, _P, _P], _I),
@@ -208,16 +209,29 @@ class Context:
         e = (ctypes.c_double * k)()
         r = (ctypes.c_double * k)()
         it = ctypes.c_int()
+        self._last_k = int(k)
         st = _lib.stpci_davidson(self._h, ctypes.byref(o), e, r, _ptr(vecs) if vecs is not None else None,
                                  ctypes.byref(it))
         if st != OK and not (allow_noconv and st == ENOCONV):
             self._check(st)
         return np.array(e[:]), np.array(r[:]), it.value, st
 
-    def history(self):
+    def history(self, full=False):
+        """Iterations of the last Davidson run; with full=True, a dict of
+        [iterations][k] arrays: energies, residual norms and the largest
+        coefficient change of each Ritz vector ("dc", NaN on the first
+        iteration of each phase)."""
         n = ctypes.c_int()
         self._check(_lib.stpci_dav_history(self._h, ctypes.byref(n), 0, None, None))
-        return n.value
+        if not full:
+            return n.value
+        k = self._last_k
+        e = np.zeros(n.value * k)
+        r = np.zeros(n.value * k)
+        dc = np.zeros(n.value * k)
+        self._check(_lib.stpci_dav_history(self._h, ctypes.byref(n), n.value, e.ctypes.data_as(_DP), r.ctypes.data_as(_DP)))
+        self._check(_lib.stpci_dav_history_dc(self._h, n.value, dc.ctypes.data_as(_DP)))
+        return {"energies": e.reshape(-1, k), "resid": r.reshape(-1, k), "dc": dc.reshape(-1, k)}
 
     def test_moves(self, max_dets_per_cat=1 << 40):
         """Host check of the kernels' move arithmetic: (moves checked, moves wrong)."""

@@ -28,6 +28,7 @@ struct KernelEvent {
 
 struct DavRecord {
     std::vector<double> e, r;
+    std::vector<double> dc;   // max |x_j - phase x_j(previous iteration)|, NaN on a run's first iteration
     int precision = 0;
 };
 
@@ -40,6 +41,7 @@ struct DavState {
     int m = 0;    // vectors in V with their W known
     int nv = 0;   // pending: W[m..m+nv) = H V[m..m+nv)
     int it = 0, it_prev = 0;
+    bool have_xp = false;    // d_Xp holds the previous iteration's Ritz vectors
     double best_rn = -1.0;   // BF16 phase: smallest largest-residual so far
     int stall = 0;           // iterations since it last dropped by 10 %
     bool converged = false, done = false, active = false;
@@ -94,7 +96,7 @@ struct stpci_ctx {
     int s2_kernel = 4;
 
     // Davidson workspace
-    stp::DevBuf d_V, d_W, d_X, d_R, d_T, d_partial, d_small, d_topv, d_topi;
+    stp::DevBuf d_V, d_W, d_X, d_Xp, d_R, d_T, d_partial, d_small, d_topv, d_topi;
     std::vector<stp::DavRecord> history;
     int hist_k = 0;
     int nsigma[3] = {0, 0, 0};   // sigma builds of the last Davidson run: FP64, FP32, BF16 (vectors)

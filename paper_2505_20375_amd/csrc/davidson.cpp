@@ -289,7 +289,7 @@ int64_t dav_device_bytes(const stpci_ctx* c, const stpci_dav_opts& o) {
     const int64_t vb = N * (int64_t)scalar_bytes(c);
     const int k = o.k, kr = std::min(2 * k, 32);
     const int mmax = subspace_cap(subspace_request(o), k, N);
-    int64_t b = vb * (2LL * mmax + 2LL * kr + k);
+    int64_t b = vb * (2LL * mmax + 2LL * kr + 2LL * k);
     b += (int64_t)dots_blocks(N) * kDotsMax * 16 + (int64_t)kSmallBytes;
     if (!o.guess_dev) b += 1024LL * k * 16;  // top-k partials: at most 1024 blocks
     return b;
@@ -306,6 +306,7 @@ static stpci_status dav_start(stpci_ctx* c, stpci_precision prec, const void* gu
     D.tol = tol;
     D.pidx = (prec == STPCI_FP32) ? 1 : (prec == STPCI_BF16) ? 2 : 0;
     D.best_rn = -1.0;
+    D.have_xp = false;
     D.stall = 0;
     const size_t vb = (size_t)N * scalar_bytes(c);
     D.kr_max = std::min(2 * k, 32);
@@ -326,6 +327,7 @@ static stpci_status dav_start(stpci_ctx* c, stpci_precision prec, const void* gu
     if ((s = ensure(c, c->d_X, vb * D.kr_max, "Ritz vectors"))) return s;
     if ((s = ensure(c, c->d_R, vb * D.kr_max, "residuals"))) return s;
     if ((s = ensure(c, c->d_T, vb * k, "corrections"))) return s;
+    if ((s = ensure(c, c->d_Xp, vb * k, "previous Ritz vectors"))) return s;
     if ((s = ensure(c, c->d_partial, (size_t)dots_blocks(N) * kDotsMax * 16, "dot partials"))) return s;
     if ((s = ensure(c, c->d_small, kSmallBytes, "small workspace"))) return s;
     Dav d{c, N, scalar_bytes(c), c->cplx, c->stream};
@@ -423,14 +425,41 @@ static stpci_status dav_advance(stpci_ctx* c) {
                                   c->stream),
                    "ritz")))
         return s;
+    std::vector<double> dc(k, std::nan(""));
     {
+        // residual norms and, from the second iteration, the overlaps
+        // <x_j(previous) | x_j> that phase-align the change of each Ritz vector
         for (int j = 0; j < k; ++j)
             if ((s = d.issue_dots(d.vec(c->d_R, j), 1, d.vec(c->d_R, j), 1, j))) return s;
+        if (D.have_xp)
+            for (int j = 0; j < k; ++j)
+                if ((s = d.issue_dots(d.vec(c->d_Xp, j), 1, d.vec(c->d_X, j), 1, k + j))) return s;
         std::vector<cplx> r2;
-        if ((s = d.fetch(k, r2))) return s;
+        if ((s = d.fetch(D.have_xp ? 2 * k : k, r2))) return s;
         for (int j = 0; j < k; ++j) D.rn[j] = std::sqrt(std::max(0.0, r2[j].real()));
+        if (D.have_xp) {
+            // max |x_j - ph_j x_j(previous)|, ph_j = <x_prev|x>/|<x_prev|x>| (Results: the
+            // largest coefficient change reported per iteration beside E and ||r||)
+            for (int j = 0; j < k; ++j) {
+                const cplx o = r2[k + j];
+                const double a = std::abs(o);
+                const cplx ph = a > 0 ? o / a : cplx(1.0, 0.0);
+                double* out = (double*)((char*)c->d_small.p + kDotsOff) + (size_t)j * (d.cx ? 2 : 1);
+                if ((s = d.hip(launch_maxdiff(d.cx, d.vec(c->d_X, j), d.vec(c->d_Xp, j), ph.real(), ph.imag(), N,
+                                              c->d_partial.p, out, c->stream),
+                               "coefficient change")))
+                    return s;
+            }
+            std::vector<cplx> m;
+            if ((s = d.fetch(k, m))) return s;
+            for (int j = 0; j < k; ++j) dc[j] = m[j].real();
+        }
+        if ((s = d.hip(hipMemcpyAsync(c->d_Xp.p, c->d_X.p, (size_t)k * N * d.sb, hipMemcpyDeviceToDevice, c->stream),
+                       "previous Ritz vectors")))
+            return s;
+        D.have_xp = true;
     }
-    c->history.push_back(DavRecord{D.theta, D.rn, D.pidx});
+    c->history.push_back(DavRecord{D.theta, D.rn, dc, D.pidx});
     bool conv = true;
     for (int j = 0; j < k; ++j) conv = conv && D.rn[j] <= D.tol;
     D.converged = conv;
@@ -681,6 +710,14 @@ extern "C" stpci_status stpci_dav_stats(const stpci_ctx* c, int* sigma_fp64, int
 extern "C" stpci_status stpci_dav_sigma_count(const stpci_ctx* c, stpci_precision prec, int* n_vectors) {
     if (!c || !n_vectors || prec < STPCI_FP64 || prec > STPCI_BF16) return STPCI_EINVAL;
     *n_vectors = c->nsigma[(int)prec];
+    return STPCI_OK;
+}
+
+extern "C" stpci_status stpci_dav_history_dc(const stpci_ctx* c, int cap, double* dc) {
+    if (!c || !dc || cap < 0) return STPCI_EINVAL;
+    const int n = (int)c->history.size(), k = c->hist_k;
+    for (int i = 0; i < std::min(n, cap); ++i)
+        for (int j = 0; j < k; ++j) dc[i * k + j] = c->history[i].dc[j];
     return STPCI_OK;
 }
 

@@ -284,6 +284,60 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const typename VT<CPLX>
     if (threadIdx.x == 0) out[i] = red[0];
 }
 
+// partial[block] = max over the block's range of |x - ph y| (ph = phr + i phi;
+// real vectors use phr only)
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_maxdiff(const typename VT<CPLX>::T* __restrict__ x,
+                                                const typename VT<CPLX>::T* __restrict__ y, double phr, double phi,
+                                                int64_t n, double* __restrict__ partial) {
+    double m = 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double d2;
+        if constexpr (CPLX) {
+            const cd a = x[e], b = y[e];
+            const double re = a.x - (phr * b.x - phi * b.y), im = a.y - (phr * b.y + phi * b.x);
+            d2 = re * re + im * im;
+        } else {
+            const double re = x[e] - phr * y[e];
+            d2 = re * re;
+        }
+        m = fmax(m, d2);
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = sqrt(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+}
+
+// out[0] = max of nblk partials; out[1] = 0 when out holds a complex slot
+__global__ __launch_bounds__(256) void k_reduce_max(const double* __restrict__ partial, int nblk, int cplx_slot,
+                                                    double* __restrict__ out) {
+    double m = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) m = fmax(m, partial[b]);
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        if (cplx_slot) out[1] = 0.0;
+    }
+}
+
+hipError_t launch_maxdiff(bool cplx, const void* x, const void* y, double phr, double phi, int64_t n, void* partial,
+                          double* out, hipStream_t st) {
+    const int nb = dots_blocks(n);
+    if (cplx)
+        hipLaunchKernelGGL(k_maxdiff<true>, dim3(nb), dim3(256), 0, st, (const cd*)x, (const cd*)y, phr, phi, n,
+                           (double*)partial);
+    else
+        hipLaunchKernelGGL(k_maxdiff<false>, dim3(nb), dim3(256), 0, st, (const double*)x, (const double*)y, phr, phi,
+                           n, (double*)partial);
+    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, st, (const double*)partial, nb, cplx ? 1 : 0, out);
+    return hipGetLastError();
+}
+
 // out_j = sum_i A_i * Y[i][j]  (+ beta_j * out_j when accumulate)   for j < k
 // optionally R_j = sum_i B_i * Y[i][j] - theta_j * out_j
 template <bool CPLX>

@@ -74,6 +74,10 @@ int dots_blocks(int64_t n);
 // partial holds dots_blocks(n) * m * nw scalars
 hipError_t launch_dots(bool cplx, const void* Vb, int64_t ld, int m, const void* W, int nw, int64_t n,
                        void* partial, void* out, hipStream_t st);
+// out[0] = max_e |x_e - ph y_e| (ph = phr + i phi), out[1] = 0 for complex
+// vectors; partial holds dots_blocks(n) doubles
+hipError_t launch_maxdiff(bool cplx, const void* x, const void* y, double phr, double phi, int64_t n, void* partial,
+                          double* out, hipStream_t st);
 hipError_t launch_combine(bool cplx, const void* A, const void* B, int64_t ld, int m, const void* Y, int k,
                           const double* theta, void* X, void* R, int64_t n, int mode, hipStream_t st);
 hipError_t launch_scale(bool cplx, void* x, double s, int64_t n, hipStream_t st);

@@ -84,3 +84,29 @@ def test_davidson_config2_certified():
     assert rel_err(s_gpu[rows], s_rows) <= 1e-12
     res = s_gpu - e[0] * x
     assert abs(np.linalg.norm(res) - r[0]) <= 1e-9
+
+
+def test_history_reports_coefficient_change():
+    """Per-iteration record (Results: energy, residual and the largest
+    coefficient change of each Ritz vector): NaN on the first iteration, then
+    finite and non-negative, small at convergence, and consistent with the
+    residual (a converged run restarted from its own vectors barely moves)."""
+    import torch
+    pb = Problem.named("T4")
+    ctx = pb.context()
+    n = len(pb.dets)
+    vecs = torch.zeros(2 * n, dtype=torch.complex128, device="cuda")
+    e, r, it, st = ctx.davidson(k=2, tol=1e-10, vecs=vecs)
+    h = ctx.history(full=True)
+    assert h["dc"].shape == (it, 2) and h["energies"].shape == (it, 2)
+    assert np.all(np.isnan(h["dc"][0]))
+    assert np.all(np.isfinite(h["dc"][1:])) and np.all(h["dc"][1:] >= 0)
+    assert np.max(h["dc"][-1]) < 1e-6
+    assert np.allclose(h["energies"][-1], e) and np.allclose(h["resid"][-1], r)
+    # restarted from converged vectors: one or two iterations, tiny changes
+    e2, r2, it2, _ = ctx.davidson(k=2, tol=1e-10, guess=vecs)
+    h2 = ctx.history(full=True)
+    assert it2 <= 2
+    if it2 > 1:
+        assert np.max(h2["dc"][1:]) < 1e-8
+    assert np.max(np.abs(e2 - e)) < 1e-10

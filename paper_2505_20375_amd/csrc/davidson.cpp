@@ -154,7 +154,8 @@ namespace {
 // layout of the small device workspace
 constexpr size_t kYOff = 0;                 // Ritz coefficients, up to 64 x 32 complex
 constexpr size_t kThetaOff = 64 * 32 * 16;  // Ritz values, 64 doubles
-constexpr size_t kDotsOff = kThetaOff + 64 * 8;
+constexpr size_t kDcOff = kThetaOff + 64 * 8;  // Ritz coefficient changes, 16 complex slots
+constexpr size_t kDotsOff = kDcOff + 16 * 16;  // (directly before the dots: fetched with them)
 constexpr int kDotsMax = 64 * 16;           // dot products fetched in one round trip
 constexpr size_t kCoefOff = kDotsOff + (size_t)kDotsMax * 16;
 constexpr size_t kSmallBytes = kCoefOff + 64 * 16;
@@ -203,16 +204,22 @@ struct Dav {
         return hip(launch_dots(cx, A, N, m, W, nw, N, c->d_partial.p, small, st), "dots");
     }
 
-    // fetch the first `count` queued dot products (one round trip)
-    stpci_status fetch(int count, std::vector<cplx>& out) {
-        std::vector<double> raw((size_t)count * (cx ? 2 : 1));
-        stpci_status s = hip(hipMemcpyAsync(raw.data(), (char*)c->d_small.p + kDotsOff, raw.size() * 8,
+    // fetch the first `count` queued dot products (one round trip); with dc,
+    // also the first dc->size() Ritz coefficient changes in the same copy
+    stpci_status fetch(int count, std::vector<cplx>& out, std::vector<double>* dc = nullptr) {
+        const size_t w = cx ? 2 : 1;
+        const size_t pre = dc ? (kDotsOff - kDcOff) / 8 : 0;   // doubles before the dots
+        std::vector<double> raw(pre + (size_t)count * w);
+        stpci_status s = hip(hipMemcpyAsync(raw.data(), (char*)c->d_small.p + kDotsOff - pre * 8, raw.size() * 8,
                                             hipMemcpyDeviceToHost, st),
                              "dots copy");
         if (s) return s;
         if ((s = hip(hipStreamSynchronize(st), "sync"))) return s;
         out.resize(count);
-        for (int i = 0; i < count; ++i) out[i] = cx ? cplx(raw[2 * i], raw[2 * i + 1]) : cplx(raw[i], 0.0);
+        for (int i = 0; i < count; ++i)
+            out[i] = cx ? cplx(raw[pre + 2 * i], raw[pre + 2 * i + 1]) : cplx(raw[pre + i], 0.0);
+        if (dc)
+            for (size_t j = 0; j < dc->size(); ++j) (*dc)[j] = raw[j * w];
         return STPCI_OK;
     }
 
@@ -426,6 +433,7 @@ static stpci_status dav_advance(stpci_ctx* c) {
                    "ritz")))
         return s;
     std::vector<double> dc(k, std::nan(""));
+    bool dc_pending = false;
     {
         // residual norms and, from the second iteration, the overlaps
         // <x_j(previous) | x_j> that phase-align the change of each Ritz vector
@@ -440,19 +448,18 @@ static stpci_status dav_advance(stpci_ctx* c) {
         if (D.have_xp) {
             // max |x_j - ph_j x_j(previous)|, ph_j = <x_prev|x>/|<x_prev|x>| (Results: the
             // largest coefficient change reported per iteration beside E and ||r||)
+            // (fetched with the next round trip's dot products)
             for (int j = 0; j < k; ++j) {
                 const cplx o = r2[k + j];
                 const double a = std::abs(o);
                 const cplx ph = a > 0 ? o / a : cplx(1.0, 0.0);
-                double* out = (double*)((char*)c->d_small.p + kDotsOff) + (size_t)j * (d.cx ? 2 : 1);
+                double* out = (double*)((char*)c->d_small.p + kDcOff) + (size_t)j * (d.cx ? 2 : 1);
                 if ((s = d.hip(launch_maxdiff(d.cx, d.vec(c->d_X, j), d.vec(c->d_Xp, j), ph.real(), ph.imag(), N,
                                               c->d_partial.p, out, c->stream),
                                "coefficient change")))
                     return s;
             }
-            std::vector<cplx> m;
-            if ((s = d.fetch(k, m))) return s;
-            for (int j = 0; j < k; ++j) dc[j] = m[j].real();
+            dc_pending = true;
         }
         if ((s = d.hip(hipMemcpyAsync(c->d_Xp.p, c->d_X.p, (size_t)k * N * d.sb, hipMemcpyDeviceToDevice, c->stream),
                        "previous Ritz vectors")))
@@ -460,6 +467,16 @@ static stpci_status dav_advance(stpci_ctx* c) {
         D.have_xp = true;
     }
     c->history.push_back(DavRecord{D.theta, D.rn, dc, D.pidx});
+    // the coefficient changes of this iteration, where no later round trip
+    // of the iteration brings them
+    auto fetch_dc = [&]() -> stpci_status {
+        if (!dc_pending) return STPCI_OK;
+        std::vector<cplx> none;
+        stpci_status st2 = d.fetch(0, none, &dc);
+        c->history.back().dc = dc;
+        dc_pending = false;
+        return st2;
+    };
     bool conv = true;
     for (int j = 0; j < k; ++j) conv = conv && D.rn[j] <= D.tol;
     D.converged = conv;
@@ -472,12 +489,12 @@ static stpci_status dav_advance(stpci_ctx* c) {
             D.stall = 0;
         } else if (++D.stall >= 8) {
             D.done = true;
-            return STPCI_OK;
+            return fetch_dc();
         }
     }
     if (conv || D.it >= D.max_iter) {
         D.done = true;
-        return STPCI_OK;
+        return fetch_dc();
     }
     // corrections for unconverged roots (Eq. sparsePreconditioner, eps = 0)
     int nt = 0;
@@ -521,14 +538,22 @@ static stpci_status dav_advance(stpci_ctx* c) {
     // (linear dependence) and is dropped
     int added = 0;
     if (nt > 0) {
+        // norms before orthogonalisation and the first pass's projections in
+        // one round trip (with the pending coefficient changes)
         std::vector<cplx> n0v;
         for (int t = 0; t < nt; ++t)
             if ((s = d.issue_dots(d.vec(c->d_T, t), 1, d.vec(c->d_T, t), 1, t))) return s;
-        if ((s = d.fetch(nt, n0v))) return s;
         for (int pass = 0; pass < 2; ++pass) {
-            if ((s = d.issue_dots(c->d_V.p, mm, c->d_T.p, nt, 0))) return s;
-            std::vector<cplx> coef;
-            if ((s = d.fetch(nt * mm, coef))) return s;
+            const int off = pass == 0 ? nt : 0;
+            if ((s = d.issue_dots(c->d_V.p, mm, c->d_T.p, nt, off))) return s;
+            std::vector<cplx> got;
+            if ((s = d.fetch(off + nt * mm, got, dc_pending ? &dc : nullptr))) return s;
+            if (dc_pending) {
+                c->history.back().dc = dc;
+                dc_pending = false;
+            }
+            if (pass == 0) n0v.assign(got.begin(), got.begin() + nt);
+            const std::vector<cplx> coef(got.begin() + off, got.end());
             if ((s = d.subtract_block(c->d_V.p, mm, coef, nt, c->d_T.p))) return s;
         }
         // Cholesky QR: T_keep = Q R, Q = T R^-1 written to V[mm..] (first pass)

@@ -45,6 +45,8 @@ def test_sigma_small_spaces(name):
     ([8, 8], None, None, 5),                   # the same space as two open-window subspaces
     ([6, 5, 5], [1, 1, 1], [3, 3, 2], 5),      # windows: outside-window intermediates
     ([4, 4, 4, 4], [0, 1, 0, 1], [2, 2, 2, 2], 5),
+    ([2] * 8, None, None, 6),                  # eight subspaces (the library's maximum), open windows
+    ([2] * 8, [0, 1, 0, 1, 0, 1, 0, 1], [1, 2, 1, 2, 1, 2, 1, 2], 6),   # eight subspaces, windows
 ])
 def test_sigma_medium_spaces(sub, lo, hi, n):
     print("case", sub, lo, hi, n, flush=True)

@@ -146,6 +146,29 @@ def test_invalid_inputs_are_rejected():
     assert e.value.status in (stpci.EINVAL, stpci.ESTATE)
 
 
+def test_report_and_precision_arguments_are_checked():
+    """Argument checks of the reporting calls and of the precision codes
+    (host-only context: nothing touches a device)."""
+    import ctypes
+    c = stpci.Context(device=-1)
+    n = ctypes.c_int()
+    assert stpci._lib.stpci_dav_sigma_count(c._h, 3, ctypes.byref(n)) == stpci.EINVAL
+    assert stpci._lib.stpci_dav_sigma_count(c._h, -1, ctypes.byref(n)) == stpci.EINVAL
+    assert stpci._lib.stpci_dav_sigma_count(None, 0, ctypes.byref(n)) == stpci.EINVAL
+    for p in (stpci.FP64, stpci.FP32, stpci.BF16):
+        assert stpci._lib.stpci_dav_sigma_count(c._h, p, ctypes.byref(n)) == stpci.OK
+        assert n.value == 0
+    buf = (ctypes.c_double * 4)()
+    assert stpci._lib.stpci_dav_history_dc(c._h, -1, buf) == stpci.EINVAL
+    assert stpci._lib.stpci_dav_history_dc(c._h, 4, None) == stpci.EINVAL
+    assert stpci._lib.stpci_dav_history_dc(c._h, 4, buf) == stpci.OK
+    c.set_space(2, [4])
+    assert c.history() == 0
+    # an unknown precision code is rejected before any device work
+    with pytest.raises(stpci.StpciError):
+        c.sigma(0, 0, precision=7)
+
+
 def test_host_eigensolver_matches_lapack():
     rng = np.random.default_rng(0)
     for n in (1, 2, 5, 17, 40):

@@ -44,6 +44,7 @@ def main():
     ap.add_argument("--solves", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--serve", type=int, default=48, help="requests in the serving run (0: skip)")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the sparse-vector sigma timings")
     ap.add_argument("--serve-max-dets", type=int, default=300000)
     ap.add_argument("--serve-rate", type=float, default=40.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--copy-calib-mb", type=float, default=0.0,
@@ -202,7 +203,7 @@ def main():
     # FP64 sigma of vectors with a random 1 % and 0.1 % of their entries nonzero
     sparse = {}
     gs = torch.Generator(device="cuda").manual_seed(2103)
-    for dens in (1e-2, 1e-3):
+    for dens in (() if args.no_sparse else (1e-2, 1e-3)):
         cs = c * (torch.rand(c.shape, generator=gs, device="cuda") < dens)
         for _ in range(max(1, args.warmup)):
             ctx.sigma(cs, out, n_vec=n_vec)
@@ -214,7 +215,8 @@ def main():
         torch.cuda.synchronize()
         ms_s = e0.elapsed_time(e1) / args.steps
         sparse["density_%g" % dens] = {"sigma_fp64_ms": ms_s, "speedup_vs_dense": ms_per_step / ms_s}
-    res["sparse_vectors"] = sparse
+    if sparse:
+        res["sparse_vectors"] = sparse
     res["precision"] = prec
     if not args.no_solve:
         res["solve"] = _solve(ctx, roots, args.solves, stpci.FP64)

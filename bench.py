@@ -122,13 +122,17 @@ def main():
     Wp, n_pair, max_pdeg = ctx.pair_counts()
     kname = ctx.sigma_kernel()
     flops_paper = 8.0 * (W1 + W2) * n_vec
-    flops = 8.0 * Wp * n_vec if kname == "pair" else flops_paper
+    pair = kname.startswith("pair")
+    flops = 8.0 * Wp * n_vec if pair else flops_paper
     avg2 = t2 / max(n2, 1)
     achieved = flops / (avg2 * 1e-3) / 1e12
     achieved_paper = flops_paper / (avg2 * 1e-3) / 1e12
-    roof = {"kernel": "k_sigma_pair (one pass: pair-resolved 1e + 2e sigma, FP64)" if kname == "pair"
-            else "k_sigma_symtile (fused 1e + 2e sigma, FP64)",
-            "bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+    kdesc = {"pair_mf64": "k_sigma_pair_mf64 (one pass: pair-resolved 1e + 2e sigma, FP64 matrix cores, "
+                          "v_mfma_f64_4x4x4f64)",
+             "pair_valu": "k_sigma_pair (one pass: pair-resolved 1e + 2e sigma, FP64 vector ALUs)"}
+    roof = {"kernel": kdesc.get(kname.replace("_atomic", ""), "k_sigma_symtile (fused 1e + 2e sigma, FP64)"),
+            "bound": "mfma" if kname.startswith("pair_mf64") else "alu",
+            "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": _traffic(n_vec, kname),
             "avg_launch_ms": round(avg2, 4), "launches": n2, "flops_per_launch": flops,
             "algorithmic_bytes_per_launch": 2 * n_vec * n * 16,
@@ -136,7 +140,10 @@ def main():
             "paper_formulation_flops_per_launch": flops_paper,
             "paper_formulation_equiv_tflops": round(achieved_paper, 3),
             "frac_paper_formulation": round(achieved_paper / FP64_PEAK_TFLOPS, 4)}
-
+    if kname.startswith("pair_mf64"):
+        # executed matrix-core flops: 16-row tiles x 4-column steps over the
+        # pair degree rounded up to 32, two real products of 4 columns each
+        roof["executed_flops_per_launch"] = ctx_pair_mf64_flops(ctx, n_vec)
     res = {
         "metric": "determinant-updates/s in H.c sigma",
         "value": value,
@@ -234,13 +241,27 @@ def main():
     print(json.dumps(res))
 
 
-TRAFFIC_FILES = {"pair": os.path.join(ROOT, "profiles", "sigma_pair_c2_traffic.txt"),
+def ctx_pair_mf64_flops(ctx, n_vec):
+    """Matrix-core flops of one launch of the FP64 matrix-core pair kernel:
+    per intermediate, cap = degree rounded up to 32 rows and steps, two real
+    4-column products (512 flop per v_mfma_f64_4x4x4f64, one per 16 rows x
+    4 steps): 16 cap^2 flop per intermediate and pass of at most two vectors.
+    Exact when every intermediate has the largest degree (the FCI workload),
+    an upper bound otherwise."""
+    _, n_pair, max_pdeg = ctx.pair_counts()
+    cap = (max_pdeg + 31) // 32 * 32
+    return float(n_pair * 16 * cap * cap * ((n_vec + 1) // 2))
+
+
+TRAFFIC_FILES = {"pair_valu": os.path.join(ROOT, "profiles", "sigma_pair_c2_traffic.txt"),
+                 "pair_mf64": os.path.join(ROOT, "profiles", "sigma_pair_mf64_c2_traffic.txt"),
                  "tile": os.path.join(ROOT, "profiles", "sigma_symtile_c2_traffic.txt")}
-KERNEL_SOURCES = {"pair": ["sigma_pair.hip", "pair_arith.hpp", "symtile.hpp", "stp_device.hpp", "stp_internal.hpp"],
+KERNEL_SOURCES = {"pair_valu": ["sigma_pair.hip", "pair_arith.hpp", "symtile.hpp", "stp_device.hpp", "stp_internal.hpp"],
+                  "pair_mf64": ["sigma_mf64.hip", "pair_arith.hpp", "stp_device.hpp", "stp_internal.hpp"],
                   "tile": ["sigma_sym.hip", "stp_device.hpp", "stp_internal.hpp"]}
 
 
-def kernel_source_hash(kname="pair"):
+def kernel_source_hash(kname="pair_mf64"):
     import hashlib
     hsh = hashlib.sha256()
     for f in KERNEL_SOURCES[kname]:
@@ -249,11 +270,13 @@ def kernel_source_hash(kname="pair"):
     return hsh.hexdigest()[:16]
 
 
-def _traffic(n_vec, kname="pair"):
+def _traffic(n_vec, kname="pair_mf64"):
     """HBM bytes per launch of the sigma kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the factor the
     same counter reads on a plain copy of known size), or None when the kernel
     sources changed after the counters were taken."""
+    if kname not in KERNEL_SOURCES:   # atomic scatter or another kernel: no counter summary
+        return None
     path = TRAFFIC_FILES.get(kname)
     if path is None or not os.path.exists(path):
         return None

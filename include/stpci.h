@@ -150,14 +150,19 @@ stpci_status stpci_pair_counts(const stpci_ctx* ctx, double* w_pair, int64_t* n_
  * per-wavefront LDS slice; each pair contribution is stored once and summed
  * per target in a fixed order, so sigma is deterministic, when that workspace
  * -- n_dets * N (N - 1) / 2 * 2 scalars -- fits a quarter of the free device
- * memory or 1 GB, else contributions are added with device atomics),
- * "pair_atomic" (the pair kernel with device atomics), "tile" (one-move
- * intermediates of Eq. sigmaL2e,
- * Hermitian tiles, one- and two-electron parts fused), "rowtile", "wave" and
- * "simple" (earlier one-move forms), or "auto".  All compute the same sigma;
- * a kernel that cannot handle the space makes the next device call fail with
- * STPCI_EINVAL.  stpci_sigma_kernel reports the kernel in use after the first
- * device call (static string). */
+ * memory or 1 GB, else contributions are added with device atomics; FP64
+ * products run on the matrix cores when the pair table (16 or 8 bytes per
+ * pair-pair entry) fits 4 MB, the L2 of one XCD, else on the vector ALUs with
+ * Hermitian tiles), "pair_atomic" (the same with device atomics),
+ * "pair_mf64" and "pair_valu" (the pair form with the FP64 products forced
+ * onto the matrix cores or the vector ALUs), "tile" (one-move intermediates
+ * of Eq. sigmaL2e, Hermitian tiles, one- and two-electron parts fused),
+ * "rowtile", "wave" and "simple" (earlier one-move forms), or "auto".  All
+ * compute the same sigma; a kernel that cannot handle the space makes the
+ * next device call fail with STPCI_EINVAL.  stpci_sigma_kernel reports the
+ * kernel in use after the first device call (static string): "pair_mf64",
+ * "pair_valu" (store-and-reduce scatter), "pair_mf64_atomic",
+ * "pair_valu_atomic", "tile", "rowtile", "wave" or "simple". */
 stpci_status stpci_set_sigma_kernel(stpci_ctx* ctx, const char* name);
 stpci_status stpci_sigma_kernel(const stpci_ctx* ctx, const char** name);
 

@@ -123,7 +123,10 @@ int select_kernel(const stpci_ctx* c) {
     const bool ok[5] = {H.max_deg <= MAXDEG, true, sigma_wave_supported(H.max_deg), symtile_supported(H.max_deg, c->cplx),
                         pair_supported(H.sp.N, H.pmax_deg, c->cplx)};
     if (c->kernel_req >= 0) {
-        const int k = c->kernel_req == 5 ? 4 : c->kernel_req;  // 5: pair kernel with device atomics
+        // 4..7: the pair form (automatic unit; with device atomics; on the FP64
+        // matrix cores; on the vector ALUs)
+        const int k = (c->kernel_req >= 4) ? 4 : c->kernel_req;
+        if (c->kernel_req == 6 && !pair_mf64_supported(H.sp.N, H.pmax_deg)) return -1;
         return ok[k] ? k : -1;
     }
     return ok[4] ? 4 : (ok[3] ? 3 : 1);
@@ -188,6 +191,13 @@ stpci_status prepare(stpci_ctx* c) {
         tmp.sp = H.sp;
         const size_t eb = pair_store_bytes(tmp, c->cplx);
         c->pair_store = c->kernel_req != 5 && (eb <= ((size_t)1 << 30) || eb <= fr / 4);
+        // FP64 products on the matrix cores where the pair table stays in one
+        // XCD's L2 (they read both triangles of each tile); the vector-ALU
+        // kernel reads one triangle and wins when the table spills to the MALL
+        const size_t table = (size_t)H.sp.npairs * H.sp.npairs * scalar_bytes(c);
+        const bool auto_unit = c->kernel_req < 0 || c->kernel_req == 4 || c->kernel_req == 5;
+        c->pair_mf64 = pair_mf64_supported(H.sp.N, H.pmax_deg) &&
+                       (c->kernel_req == 6 || (auto_unit && table <= ((size_t)4 << 20)));
         build_pair_table(c);
         if ((s = upload(c, c->d_pcats, H.pcats, "pair categories"))) return s;
         if ((s = upload(c, c->d_pwork, H.pwork_begin, "pair offsets"))) return s;
@@ -339,8 +349,12 @@ stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, st
             if (s) return s;
             E = c->d_E.p;
         }
-        e = launch_sigma_pair(c->dev, c->hs.pmax_deg, c->cplx, f32, f32 ? c->d_pA32.p : c->d_pA.p, cin, sout, E,
-                              n_vec, c->e_core, c->profile ? &mk : nullptr, c->stream);
+        if (c->pair_mf64 && !f32)
+            e = launch_sigma_pair_mf64(c->dev, c->hs.pmax_deg, c->cplx, c->d_pA.p, cin, sout, E, n_vec, c->e_core,
+                                       c->profile ? &mk : nullptr, c->stream);
+        else
+            e = launch_sigma_pair(c->dev, c->hs.pmax_deg, c->cplx, f32, f32 ? c->d_pA32.p : c->d_pA.p, cin, sout,
+                                  E, n_vec, c->e_core, c->profile ? &mk : nullptr, c->stream);
         return e == hipSuccess ? STPCI_OK : hip_check(c, e, "sigma launch");
     }
     if (c->s2_kernel == 3) {
@@ -702,10 +716,10 @@ stpci_status stpci_pair_counts(const stpci_ctx* c, double* w_pair, int64_t* n_pa
 
 stpci_status stpci_set_sigma_kernel(stpci_ctx* c, const char* name) {
     if (!c || !name) return STPCI_EINVAL;
-    static const char* names[6] = {"simple", "rowtile", "wave", "tile", "pair", "pair_atomic"};
+    static const char* names[8] = {"simple", "rowtile", "wave", "tile", "pair", "pair_atomic", "pair_mf64", "pair_valu"};
     int k = -1;
     if (!std::strcmp(name, "auto")) k = -2;
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 8; ++i)
         if (!std::strcmp(name, names[i])) k = i;
     if (k == -1) return set_err(c, STPCI_EINVAL, "unknown sigma kernel name");
     c->kernel_req = (k == -2) ? -1 : k;
@@ -723,7 +737,11 @@ stpci_status stpci_sigma_kernel(const stpci_ctx* c, const char** name) {
     if (!c || !name) return STPCI_EINVAL;
     static const char* names[5] = {"simple", "rowtile", "wave", "tile", "pair"};
     if (!c->prepared) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "no device call made yet");
-    *name = (c->s2_kernel == 4 && !c->pair_store) ? "pair_atomic" : names[c->s2_kernel];
+    if (c->s2_kernel == 4)
+        *name = c->pair_mf64 ? (c->pair_store ? "pair_mf64" : "pair_mf64_atomic")
+                             : (c->pair_store ? "pair_valu" : "pair_valu_atomic");
+    else
+        *name = names[c->s2_kernel];
     return STPCI_OK;
 }
 

@@ -85,6 +85,7 @@ struct stpci_ctx {
     stp::DevBuf d_pcats, d_pwork, d_pslot, d_pA, d_pA32, d_pAbf;
     stp::DevBuf d_E;         // pair contributions of the store-and-reduce scatter
     bool pair_store = false; // pair kernel: store-and-reduce (true) or device atomics
+    bool pair_mf64 = false;   // FP64 pair products on the matrix cores (else the vector-ALU tiles)
     int kernel_req = -1;   // requested sigma kernel (stpci_set_sigma_kernel), -1: automatic
     stp::DevSpace dev{};
 

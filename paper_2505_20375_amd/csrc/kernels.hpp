@@ -41,6 +41,13 @@ hipError_t launch_pair_reduce(const DevSpace& S, bool cplx, int nv, void* sigma,
 // in bfloat16, row-major [P][Q] with npp (a multiple of 32) columns; complex:
 // three matrices (real part, imaginary part, negated imaginary part).
 // E non-null: store-and-reduce scatter, else device atomics.
+// FP64 matrix-core form of the pair sigma build (v_mfma_f64_4x4x4f64), same
+// arguments and scatter modes as launch_sigma_pair with the FP64 table.
+bool pair_mf64_supported(int n_elec, int deg_max);
+size_t pair_mf64_slice_bytes(int deg_max);
+hipError_t launch_sigma_pair_mf64(const DevSpace& S, int deg_max, bool cplx, const void* A, const void* c,
+                                  void* sigma, void* E, int n_vec, double e_core, const LaunchMarks* mk,
+                                  hipStream_t st);
 bool pair_mfma_supported(const DevSpace& S, int deg_max, bool cplx);
 int pair_mfma_npp(int npairs);
 hipError_t launch_sigma_pair_mfma(const DevSpace& S, int deg_max, bool cplx, const void* Ab, const void* c,

@@ -141,7 +141,8 @@ def test_sigma_config2_full_size_sampled_rows():
     assert rel_err(s_gpu[rows], s_ref) <= TOL
 
 
-@pytest.mark.parametrize("kernel", ["pair", "pair_atomic", "tile", "rowtile", "wave", "simple"])
+@pytest.mark.parametrize("kernel", ["pair", "pair_atomic", "pair_mf64", "pair_valu", "tile", "rowtile", "wave",
+                                    "simple"])
 @pytest.mark.parametrize("name", ["T4", "c1"])
 def test_every_kernel_matches_oracle(kernel, name):
     """Each sigma kernel (pair intermediates, one-move Hermitian tiles and the
@@ -153,16 +154,28 @@ def test_every_kernel_matches_oracle(kernel, name):
 
 
 def test_default_kernel_is_pair():
+    """The pair form is the default; with a pair table of at most 4 MB its FP64
+    products run on the matrix cores, with a larger one on the vector ALUs."""
     import torch
     pb = Problem.named("T4")
     ctx = pb.context()
     x = pb.to_device(pb.vector())
     ctx.sigma(x, torch.empty_like(x))
     torch.cuda.synchronize()
-    assert ctx.sigma_kernel() == "pair"
+    assert ctx.sigma_kernel() == "pair_mf64"
+    import paper_2505_20375_amd as stpci
+    big = stpci.Context(0)            # 40 spinors: 780 pairs, a 9.7 MB complex table
+    ints = synth.complex_integrals(40, 3, rank=4, sigma_f=0.05)
+    big.set_integrals(ints.h, ints.g)
+    big.set_space(4, [20, 20])
+    n = big.space_info().n_dets
+    y = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    big.sigma(y, torch.empty_like(y))
+    torch.cuda.synchronize()
+    assert big.sigma_kernel() == "pair_valu"
 
 
-@pytest.mark.parametrize("kernel", ["pair", "pair_atomic", "tile", "rowtile"])
+@pytest.mark.parametrize("kernel", ["pair", "pair_atomic", "pair_mf64", "pair_valu", "tile", "rowtile"])
 def test_core_energy_term(kernel):
     """sigma includes e_core * c."""
     import torch
@@ -186,11 +199,17 @@ def test_pair_store_mode_is_deterministic():
     ctx.sigma(x, a)
     ctx.sigma(x, b)
     torch.cuda.synchronize()
-    assert ctx.sigma_kernel() == "pair"
+    assert ctx.sigma_kernel() in ("pair_mf64", "pair_valu")
+    assert torch.equal(a, b)
+    ctx.set_sigma_kernel("pair_valu")
+    ctx.sigma(x, a)
+    ctx.sigma(x, b)
+    torch.cuda.synchronize()
+    assert ctx.sigma_kernel() == "pair_valu"
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("kernel,prec", [("pair", "fp64"), ("pair_atomic", "fp64"), ("pair", "fp32"),
+@pytest.mark.parametrize("kernel,prec", [("pair", "fp64"), ("pair_atomic", "fp64"), ("pair_valu", "fp64"), ("pair", "fp32"),
                                          ("pair", "bf16"), ("pair_atomic", "bf16")])
 def test_sparse_vector_after_dense(kernel, prec):
     """Intermediates (BF16: batches of them) whose gathered coefficients are

@@ -55,6 +55,9 @@ hipError_t launch_sigma_pair_mfma(const DevSpace& S, int deg_max, bool cplx, con
                                   hipStream_t st);
 hipError_t launch_sigma_pair(const DevSpace& S, int deg_max, bool cplx, bool f32, const void* A, const void* c,
                              void* sigma, void* E, int n_vec, double e_core, const LaunchMarks* mk, hipStream_t st);
+// Grouped FP64 matrix-core pair products of several problems (device atomics).
+hipError_t launch_sigma_pair_mf64_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
+                                        int deg_max, bool cplx, hipStream_t st);
 hipError_t launch_sigma_pair_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
                                    int deg_max, bool cplx, bool f32, hipStream_t st);
 // sigma <- e_core * c (zero when e_core == 0)

@@ -261,7 +261,7 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
         SigmaDesc d;
         int64_t nj;
     };
-    std::vector<Item> groups[2][2][2];   // [pair kernel][complex][FP32]
+    std::vector<Item> groups[3][2][2];   // [tile, pair vector ALUs, pair FP64 matrix cores][complex][FP32]
     std::vector<int> solo;
     const std::vector<int> admitted(s->active);  // retire() edits the active list
     for (int id : admitted) {
@@ -306,18 +306,19 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
             it.d.sigma = (char*)out + v0 * vb;
             it.d.e_core = c->e_core;
             it.d.n_vec = std::min(2, n - v0);
-            groups[pair ? 1 : 0][c->cplx ? 1 : 0][f32 ? 1 : 0].push_back(it);
+            const int kind = !pair ? 0 : (c->pair_mf64 && !f32) ? 2 : 1;
+            groups[kind][c->cplx ? 1 : 0][f32 ? 1 : 0].push_back(it);
         }
     }
     std::vector<int> stepped(solo);
     // the grouped launches read vectors the requests' own streams wrote
-    for (int pk = 0; pk < 2; ++pk)
+    for (int pk = 0; pk < 3; ++pk)
         for (int cx = 0; cx < 2; ++cx)
             for (int f = 0; f < 2; ++f)
                 for (auto& it : groups[pk][cx][f])
                     if (hipStreamSynchronize(s->reqs[it.id]->stream) != hipSuccess)
                         return srv_err(s, STPCI_EHIP, "request stream synchronisation failed");
-    for (int pk = 0; pk < 2; ++pk)
+    for (int pk = 0; pk < 3; ++pk)
     for (int cx = 0; cx < 2; ++cx)
         for (int f = 0; f < 2; ++f) {
             auto& G = groups[pk][cx][f];
@@ -339,7 +340,10 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
             if (e == hipSuccess)
                 e = hipMemcpyAsync(s->d_jbegin.p, jb.data(), jb.size() * 8, hipMemcpyHostToDevice, s->stream);
             if (e == hipSuccess)
-                e = pk ? launch_sigma_pair_multi((const SigmaDesc*)s->d_desc.p, (int)desc.size(),
+                e = pk == 2 ? launch_sigma_pair_mf64_multi((const SigmaDesc*)s->d_desc.p, (int)desc.size(),
+                                                           (const int64_t*)s->d_jbegin.p, jb.back(), deg, cx == 1,
+                                                           s->stream)
+                    : pk ? launch_sigma_pair_multi((const SigmaDesc*)s->d_desc.p, (int)desc.size(),
                                                  (const int64_t*)s->d_jbegin.p, jb.back(), deg, cx == 1, f == 1,
                                                  s->stream)
                        : launch_sigma_multi((const SigmaDesc*)s->d_desc.p, (int)desc.size(),

@@ -77,6 +77,7 @@ _SIGS = {
     "stpci_test_heev": ([_I, _P, _P, _P], _I),
     "stpci_test_moves": ([_P, _I64, _I64P, _I64P], _I),
     "stpci_test_pairs": ([_P, _I64, _I64P, _I64P], _I),
+    "stpci_test_pair_groups": ([_P, _I64P, _I64P], _I),
     "stpci_pair_counts": ([_P, _DP, _I64P, _IP], _I),
     "stpci_set_sigma_kernel": ([_P, ctypes.c_char_p], _I),
     "stpci_sigma_kernel": ([_P, ctypes.POINTER(ctypes.c_char_p)], _I),
@@ -243,6 +244,12 @@ class Context:
         """Host check of the pair kernel's slot arithmetic: (slots checked, slots wrong)."""
         n, b = ctypes.c_int64(), ctypes.c_int64()
         self._check(_lib.stpci_test_pairs(self._h, int(max_dets_per_cat), ctypes.byref(n), ctypes.byref(b)))
+        return n.value, b.value
+
+    def test_pair_groups(self):
+        """Host check of the grouped pair kernel's items: (items, violations)."""
+        n, b = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.stpci_test_pair_groups(self._h, ctypes.byref(n), ctypes.byref(b)))
         return n.value, b.value
 
     def pair_counts(self):

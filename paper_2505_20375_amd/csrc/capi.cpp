@@ -123,10 +123,12 @@ int select_kernel(const stpci_ctx* c) {
     const bool ok[5] = {H.max_deg <= MAXDEG, true, sigma_wave_supported(H.max_deg), symtile_supported(H.max_deg, c->cplx),
                         pair_supported(H.sp.N, H.pmax_deg, c->cplx)};
     if (c->kernel_req >= 0) {
-        // 4..7: the pair form (automatic unit; with device atomics; on the FP64
-        // matrix cores; on the vector ALUs)
+        // 4..8: the pair form (automatic unit; with device atomics; on the FP64
+        // matrix cores; on the vector ALUs; grouped intermediates on the FP64
+        // matrix cores)
         const int k = (c->kernel_req >= 4) ? 4 : c->kernel_req;
         if (c->kernel_req == 6 && !pair_mf64_supported(H.sp.N, H.pmax_deg)) return -1;
+        if (c->kernel_req == 8 && !(ok[4] && pair_grp_supported(H.sp))) return -1;
         return ok[k] ? k : -1;
     }
     return ok[4] ? 4 : (ok[3] ? 3 : 1);
@@ -198,6 +200,15 @@ stpci_status prepare(stpci_ctx* c) {
         const bool auto_unit = c->kernel_req < 0 || c->kernel_req == 4 || c->kernel_req == 5;
         c->pair_mf64 = pair_mf64_supported(H.sp.N, H.pmax_deg) &&
                        (c->kernel_req == 6 || (auto_unit && table <= ((size_t)4 << 20)));
+        // spaces of one subspace: four intermediates per table read
+        c->pair_grp = false;
+        c->grp_items.clear();
+        if (c->kernel_req == 8 || (auto_unit && pair_grp_supported(H.sp))) {
+            c->pair_grp = build_pair_groups(H, c->grp_items);
+            if (!c->pair_grp && c->kernel_req == 8)
+                return set_err(c, STPCI_EINVAL, "the grouped pair kernel does not support this space");
+            if (c->pair_grp && (s = upload(c, c->d_grp, c->grp_items, "pair groups"))) return s;
+        }
         build_pair_table(c);
         if ((s = upload(c, c->d_pcats, H.pcats, "pair categories"))) return s;
         if ((s = upload(c, c->d_pwork, H.pwork_begin, "pair offsets"))) return s;
@@ -349,7 +360,11 @@ stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, st
             if (s) return s;
             E = c->d_E.p;
         }
-        if (c->pair_mf64 && !f32)
+        if (c->pair_grp && !f32)
+            e = launch_sigma_pair_grp(c->dev, (const GrpItem*)c->d_grp.p, (int)c->grp_items.size(), c->cplx,
+                                      c->d_pA.p, cin, sout, E, n_vec, c->e_core, c->profile ? &mk : nullptr,
+                                      c->stream);
+        else if (c->pair_mf64 && !f32)
             e = launch_sigma_pair_mf64(c->dev, c->hs.pmax_deg, c->cplx, c->d_pA.p, cin, sout, E, n_vec, c->e_core,
                                        c->profile ? &mk : nullptr, c->stream);
         else
@@ -622,6 +637,44 @@ stpci_status stpci_test_pairs(const stpci_ctx* c, int64_t max_dets_per_cat, int6
     return STPCI_OK;
 }
 
+stpci_status stpci_test_pair_groups(const stpci_ctx* c, int64_t* n_items, int64_t* n_bad) {
+    if (!c || !n_items || !n_bad) return STPCI_EINVAL;
+    if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
+    const HostSpace& H = c->hs;
+    std::vector<GrpItem> items;
+    if (!build_pair_groups(H, items))
+        return set_err(const_cast<stpci_ctx*>(c), STPCI_EINVAL, "the grouped pair kernel does not support this space");
+    const PairCat& P = H.pcats[0];
+    const StrTab& T = H.tabs[P.tab[0]];
+    const int64_t cnt = P.count[0];
+    std::vector<int> seen((size_t)cnt, 0);
+    int64_t bad = 0;
+    for (const GrpItem& it : items) {
+        if (it.n < 1 || it.n > GRP_U) {
+            ++bad;
+            continue;
+        }
+        for (int u = 0; u < GRP_U; ++u) {
+            const int64_t j = it.j[u];
+            if (u >= it.n) {
+                bad += (j != -1);
+                continue;
+            }
+            if (j < 0 || j >= cnt) {
+                ++bad;
+                continue;
+            }
+            ++seen[(size_t)j];
+            const uint32_t s = H.bits[T.bits_off + j];
+            if ((s & it.core) != it.core || __builtin_popcount(s ^ it.core) != 1) ++bad;
+        }
+    }
+    for (int x : seen) bad += (x != 1);
+    *n_items = (int64_t)items.size();
+    *n_bad = bad;
+    return STPCI_OK;
+}
+
 stpci_status stpci_category(const stpci_ctx* c, int cat, int* occ, int64_t* offset, int64_t* n_dets) {
     if (!c) return STPCI_EINVAL;
     if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
@@ -716,15 +769,16 @@ stpci_status stpci_pair_counts(const stpci_ctx* c, double* w_pair, int64_t* n_pa
 
 stpci_status stpci_set_sigma_kernel(stpci_ctx* c, const char* name) {
     if (!c || !name) return STPCI_EINVAL;
-    static const char* names[8] = {"simple", "rowtile", "wave", "tile", "pair", "pair_atomic", "pair_mf64", "pair_valu"};
+    static const char* names[9] = {"simple",    "rowtile",   "wave",      "tile",    "pair",
+                                   "pair_atomic", "pair_mf64", "pair_valu", "pair_grp"};
     int k = -1;
     if (!std::strcmp(name, "auto")) k = -2;
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 9; ++i)
         if (!std::strcmp(name, names[i])) k = i;
     if (k == -1) return set_err(c, STPCI_EINVAL, "unknown sigma kernel name");
     c->kernel_req = (k == -2) ? -1 : k;
     // device copies depend on the kernel: rebuild them on the next device call
-    for (DevBuf* b : {&c->d_E, &c->d_pcats, &c->d_pwork, &c->d_pslot, &c->d_pA, &c->d_pA32, &c->d_pAbf, &c->d_gT32, &c->d_hp32,
+    for (DevBuf* b : {&c->d_E, &c->d_grp, &c->d_pcats, &c->d_pwork, &c->d_pslot, &c->d_pA, &c->d_pA32, &c->d_pAbf, &c->d_gT32, &c->d_hp32,
                       &c->d_s2blocks, &c->d_ygroup, &c->d_hp, &c->d_gT})
         if (!c->host_only) b->free_();
     c->have32 = false;
@@ -737,7 +791,9 @@ stpci_status stpci_sigma_kernel(const stpci_ctx* c, const char** name) {
     if (!c || !name) return STPCI_EINVAL;
     static const char* names[5] = {"simple", "rowtile", "wave", "tile", "pair"};
     if (!c->prepared) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "no device call made yet");
-    if (c->s2_kernel == 4)
+    if (c->s2_kernel == 4 && c->pair_grp)
+        *name = c->pair_store ? "pair_grp" : "pair_grp_atomic";
+    else if (c->s2_kernel == 4)
         *name = c->pair_mf64 ? (c->pair_store ? "pair_mf64" : "pair_mf64_atomic")
                              : (c->pair_store ? "pair_valu" : "pair_valu_atomic");
     else

@@ -86,6 +86,9 @@ struct stpci_ctx {
     stp::DevBuf d_E;         // pair contributions of the store-and-reduce scatter
     bool pair_store = false; // pair kernel: store-and-reduce (true) or device atomics
     bool pair_mf64 = false;   // FP64 pair products on the matrix cores (else the vector-ALU tiles)
+    bool pair_grp = false;    // FP64 pair products of grouped intermediates (spaces of one subspace)
+    std::vector<stp::GrpItem> grp_items;
+    stp::DevBuf d_grp;
     int kernel_req = -1;   // requested sigma kernel (stpci_set_sigma_kernel), -1: automatic
     stp::DevSpace dev{};
 

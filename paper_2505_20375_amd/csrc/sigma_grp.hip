@@ -1,0 +1,382 @@
+// Grouped FP64 matrix-core form of the pair-resolved sigma build, for spaces
+// of one subspace (every determinant of N electrons in M spin-orbitals).
+//
+// There every (N-2)-electron intermediate K' couples to all pairs of its empty
+// orbitals, and its pair-pair block A_K' is A restricted to those pairs.  Four
+// intermediates K'_u = K'' + o_u that share a core K'' (N-3 electrons) have
+// blocks inside one block A_K'' over the pairs of the core's empty orbitals
+// (the pairs of K'_u are the core pairs without o_u).  One workgroup takes such
+// an item: the core pairs index the rows and columns of A_K'', intermediate u
+// owns the columns 4u..4u+3 of a 16-column right-hand side
+//   B[row, 4u + .] = [Re d_0, Re d_1, Im d_0, Im d_1] of K'_u at that pair (0 where the pair holds o_u),
+// and each 16 x 4 piece of A_K'' read from the table feeds one
+// v_mfma_f64_16x16x4f64 per real and imaginary part for all four: four times
+// the products per table read of the one-intermediate kernel, at 80 % useful
+// entries (the core has one more empty orbital).  Lane layouts (checked on the
+// device with an in-bounds probe): A lane l holds row l % 16, step l / 16; B
+// lane l holds step l / 16, column l % 16; output register i of lane l holds
+// row l / 16 + 4 i, column l % 16.  The complex combination and the scatter
+// of each intermediate's rows follow the one-intermediate kernel.
+//
+// Items come from the host: cores in colex order take their intermediates
+// not yet placed four at a time; the few left over go by the core without
+// their lowest electron.  Each intermediate is in exactly one item.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.hpp"
+#include "pair_arith.hpp"
+#include "space.hpp"
+#include "stp_device.hpp"
+
+namespace stp {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Workgroup slice: core pairs (global pair index), B as [row][16] doubles,
+// targets [intermediate][row] (target << 1 | sign, -1: none), one pair header
+// per wavefront, flags.
+struct GrpLayout {
+    size_t rinf_off, b_off, tgt_off, hdr_off, flag_off, bytes;
+    __host__ __device__ explicit GrpLayout(int cap) {
+        rinf_off = 0;
+        b_off = ((size_t)cap * 4 + 15) & ~(size_t)15;
+        tgt_off = b_off + (size_t)cap * 16 * 8;
+        hdr_off = tgt_off + (size_t)GRP_U * cap * 8;
+        flag_off = hdr_off + (size_t)GRP_U * sizeof(PairHdr);
+        bytes = flag_off + 16;
+    }
+};
+
+static int grp_core_pairs(const Space& sp) {
+    const int e = sp.M - (sp.N - 3);   // empty orbitals of a core
+    return e * (e - 1) / 2;
+}
+
+static int grp_cap(const Space& sp) { return (grp_core_pairs(sp) + 15) & ~15; }
+
+bool pair_grp_supported(const Space& sp) {
+    return sp.K == 1 && sp.N >= 3 && sp.M <= 32 && sp.npcat == 1 && GrpLayout(grp_cap(sp)).bytes <= 64 * 1024;
+}
+
+// Items of the grouped kernel (see the file comment); false when the space is
+// not one subspace or too large for the host pass.
+bool build_pair_groups(const HostSpace& H, std::vector<GrpItem>& items) {
+    items.clear();
+    const Space& sp = H.sp;
+    if (!pair_grp_supported(sp)) return false;
+    const PairCat& P = H.pcats[0];
+    const int64_t cnt = P.count[0];
+    const int M = sp.M, nc = sp.N - 3;
+    double ncores = 1.0;
+    for (int i = 0; i < nc; ++i) ncores = ncores * (M - i) / (i + 1);
+    if (cnt <= 0 || cnt > (1 << 24) || ncores > (double)(1 << 24)) return false;
+    const StrTab& T = H.tabs[P.tab[0]];
+    std::unordered_map<uint32_t, int32_t> rank;
+    rank.reserve((size_t)cnt * 2);
+    for (int64_t r = 0; r < cnt; ++r) rank.emplace(H.bits[T.bits_off + r], (int32_t)r);
+    std::vector<char> placed((size_t)cnt, 0);
+    int64_t n_placed = 0;
+    auto emit = [&](uint32_t core, const int32_t* j, int n) {
+        GrpItem it{};
+        it.core = core;
+        it.n = n;
+        for (int u = 0; u < GRP_U; ++u) it.j[u] = u < n ? j[u] : -1;
+        items.push_back(it);
+        n_placed += n;
+    };
+    // cores in colex order (next subset of the same size)
+    const uint64_t lim = 1ull << M;
+    uint64_t x = (1ull << nc) - 1;
+    while (x < lim) {
+        const uint32_t core = (uint32_t)x;
+        int32_t mem[32];
+        int n = 0;
+        for (int o = 0; o < M; ++o) {
+            if ((core >> o) & 1u) continue;
+            const auto f = rank.find(core | (1u << o));
+            if (f == rank.end() || placed[f->second]) continue;
+            mem[n++] = f->second;
+        }
+        for (int a = 0; a + GRP_U <= n; a += GRP_U) {
+            for (int u = 0; u < GRP_U; ++u) placed[mem[a + u]] = 1;
+            emit(core, mem + a, GRP_U);
+        }
+        if (nc == 0) break;
+        const uint64_t cbit = x & (~x + 1), r = x + cbit;
+        x = (((r ^ x) >> 2) / cbit) | r;
+    }
+    // the rest: by the core without the lowest electron
+    std::unordered_map<uint32_t, std::vector<int32_t>> rest;
+    for (int64_t r = 0; r < cnt; ++r)
+        if (!placed[r]) {
+            const uint32_t s = H.bits[T.bits_off + r];
+            rest[s & (s - 1)].push_back((int32_t)r);
+        }
+    for (auto& kv : rest)
+        for (size_t a = 0; a < kv.second.size(); a += GRP_U)
+            emit(kv.first, kv.second.data() + a, (int)std::min<size_t>(GRP_U, kv.second.size() - a));
+    return n_placed == cnt;
+}
+
+size_t pair_grp_slice_bytes(const Space& sp) { return GrpLayout(grp_cap(sp)).bytes; }
+
+// Value of x in lane (lane ^ X) of the same quad, X = 1 or 2 (DPP quad permutation).
+template <int X>
+__device__ __forceinline__ double grp_quad_xor(double x) {
+    constexpr int ctrl = (X == 2) ? 0x4E : 0xB1;   // quad_perm [2,3,0,1] or [1,0,3,2]
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Position of the k-th set bit of m (k < popcount(m)).
+__device__ __forceinline__ int grp_nth_bit(uint64_t m, int k) {
+    for (int i = 0; i < k; ++i) m &= m - 1;
+    return __ffsll((unsigned long long)m) - 1;
+}
+
+template <bool CPLX, int NV, bool STORE>
+__global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpItem* __restrict__ items, int nitems,
+                                                       const typename VT<CPLX>::T* __restrict__ A,
+                                                       const typename VT<CPLX>::T* __restrict__ c,
+                                                       typename VT<CPLX>::T* __restrict__ sigma,
+                                                       typename VT<CPLX>::T* __restrict__ E, int nq, int n_vec,
+                                                       int cap) {
+    using V64 = VT<CPLX>;
+    using TE = typename V64::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const GrpLayout L(cap);
+    int32_t* rinf = reinterpret_cast<int32_t*>(smem + L.rinf_off);
+    double* bsh = reinterpret_cast<double*>(smem + L.b_off);
+    int64_t* tgt = reinterpret_cast<int64_t*>(smem + L.tgt_off);
+    int* flags = reinterpret_cast<int*>(smem + L.flag_off);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    PairHdr* hd = reinterpret_cast<PairHdr*>(smem + L.hdr_off) + wid;
+    const PairCat& P = S.pcats[0];
+    const int M = S.sp.M, NP = S.sp.npairs, deg = P.deg;
+    const int ncp = (M - S.sp.N + 3) * (M - S.sp.N + 2) / 2;   // core pairs
+    const int64_t nd = S.sp.ndets;
+    const uint64_t full = (M == 64) ? ~0ull : ((1ull << M) - 1ull);
+    const int nT = cap >> 4, nks = cap >> 2;
+    const int kq = lane >> 4;     // A and B lanes: step within the 4-column group
+    const int c16 = lane & 15;    // A lanes: row; B and output lanes: column
+    const int col = lane & 3;     // column within the intermediate's four
+    int v, comp;
+    bool use;
+    if constexpr (CPLX) {
+        v = (NV == 2) ? (col & 1) : 0;
+        comp = (NV == 2) ? (col >> 1) : col;
+        use = (NV == 2) ? true : col < 2;
+    } else {
+        v = col;
+        comp = 0;
+        use = col < NV;
+    }
+    // lane's value of the complex product from C1 = Re(A) B and C2 = Im(A) B
+    auto combine = [&](double c1, double c2) -> double {
+        if constexpr (CPLX) {
+            const double p = grp_quad_xor<NV == 2 ? 2 : 1>(c2);
+            return (col < (NV == 2 ? 2 : 1)) ? c1 - p : c1 + p;
+        } else {
+            (void)c2;
+            return c1;
+        }
+    };
+
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint32_t core = items[it].core;
+        const int n = items[it].n;
+        const uint64_t emp = ~(uint64_t)core & full;
+        // ---- phase 1: core pairs (all threads), then per wavefront one
+        // intermediate's header, B columns and targets
+        for (int l = threadIdx.x; l < cap; l += blockDim.x) {
+            int pi = 0;
+            if (l < ncp) {
+                int t = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)l)) * 0.5f);   // C(t,2) <= l < C(t+1,2)
+                while (t * (t - 1) / 2 > l) --t;
+                while ((t + 1) * t / 2 <= l) ++t;
+                const int r = grp_nth_bit(emp, t), p = grp_nth_bit(emp, l - t * (t - 1) / 2);
+                pi = r * (r - 1) / 2 + p;
+            }
+            rinf[l] = pi;
+        }
+        for (int l = lane; l < cap; l += 64) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bsh[l * 16 + 4 * wid + j] = 0.0;
+            tgt[wid * cap + l] = -1;
+        }
+        bool nz = false;
+        if (wid < n) {
+            const int64_t jloc = items[it].j[wid];
+            if (lane < S.sp.K) pair_hdr_sub(S, P, jloc, lane, hd);
+            wave_lds_sync();
+            if (lane < M) pair_hdr_orb(S, P, lane, hd);
+            if (lane < P.ncls) pair_hdr_cls(S, P, lane, hd);
+            if (lane == 63) pair_hdr_bits(S, hd);
+            wave_lds_sync();   // (also orders the zero fill before the slot writes)
+            for (int slot = lane; slot < deg; slot += 64) {
+                int64_t addr;
+                int pi, q;
+                const bool neg = pair_slot(S, P, hd, slot, addr, pi, q);
+                int r = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)pi)) * 0.5f);   // pi = C(r,2) + p, p < r
+                while (r * (r - 1) / 2 > pi) --r;
+                while ((r + 1) * r / 2 <= pi) ++r;
+                const int p = pi - r * (r - 1) / 2;
+                // row of {p, r} among the core pairs (colex over the core's empty orbitals)
+                const int er = popc64(emp & ((1ull << r) - 1ull)), ep = popc64(emp & ((1ull << p) - 1ull));
+                const int l = er * (er - 1) / 2 + ep;
+                const double sg = neg ? -1.0 : 1.0;
+                double b4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int vv = 0; vv < NV; ++vv) {
+                    if (vv >= n_vec) break;
+                    const TE x = c[(int64_t)vv * nd + addr];
+                    nz = nz || V64::abs2(x) != 0.0;
+                    if constexpr (CPLX) {
+                        // two vectors: [Re0, Re1, Im0, Im1]; one vector: [Re, Im, 0, 0]
+                        b4[NV == 2 ? vv : 0] = sg * x.x;
+                        b4[NV == 2 ? 2 + vv : 1] = sg * x.y;
+                    } else {
+                        b4[vv] = sg * x;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bsh[l * 16 + 4 * wid + j] = b4[j];
+                tgt[wid * cap + l] = ((STORE ? addr * nq + q : addr) << 1) | (neg ? 1 : 0);
+            }
+        }
+        const bool live = __ballot(nz) != 0;
+        if (lane == 0) flags[wid] = live ? 1 : 0;
+        __syncthreads();
+        const bool any = (flags[0] | flags[1] | flags[2] | flags[3]) != 0;
+
+        // ---- phases 2 and 3: 16-row tiles of A_K'' split over the wavefronts
+        for (int R = wid; R < nT; R += 4) {
+            f64x4 c1a = {0.0, 0.0, 0.0, 0.0}, c1b = c1a, c2a = c1a, c2b = c1a;   // two chains per product
+            if (any) {
+                const TE* arow = A + rinf[R * 16 + c16];   // this A lane's row pair
+                constexpr int G = 2;    // steps per group
+                constexpr int RG = 6;   // groups in flight
+                const int ngrp = nks / G;
+                TE ab[RG][G];
+                auto ldgrp = [&](int g, TE (&a)[G]) {
+#pragma unroll
+                    for (int j = 0; j < G; ++j) a[j] = arow[(int64_t)rinf[((g * G + j) << 2) + kq] * NP];
+                };
+                auto mfgrp = [&](int g, const TE (&a)[G]) {
+#pragma unroll
+                    for (int j = 0; j < G; j += 2) {
+                        const double b0 = bsh[((((g * G + j) << 2) + kq) << 4) + c16];
+                        const double b1 = bsh[((((g * G + j + 1) << 2) + kq) << 4) + c16];
+                        if constexpr (CPLX) {
+                            c1a = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].x, b0, c1a, 0, 0, 0);
+                            c2a = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].y, b0, c2a, 0, 0, 0);
+                            c1b = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j + 1].x, b1, c1b, 0, 0, 0);
+                            c2b = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j + 1].y, b1, c2b, 0, 0, 0);
+                        } else {
+                            c1a = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b0, c1a, 0, 0, 0);
+                            c1b = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j + 1], b1, c1b, 0, 0, 0);
+                        }
+                    }
+                };
+                // the loads are unconditional (past the last group: the last group
+                // again, in range, unused), so that every group keeps the same
+                // number of reads in flight
+#pragma unroll
+                for (int u = 0; u < RG - 1; ++u) {
+                    ldgrp(u < ngrp ? u : ngrp - 1, ab[u]);
+                    __builtin_amdgcn_sched_barrier(0);   // requested in group order, as in the loop
+                }
+                for (int g = 0; g < ngrp; g += RG) {
+#pragma unroll
+                    for (int u = 0; u < RG; ++u) {
+                        const int gl = g + u + RG - 1;
+                        ldgrp(gl < ngrp ? gl : ngrp - 1, ab[(u + RG - 1) % RG]);
+                        if (g + u < ngrp) mfgrp(g + u, ab[u]);
+                    }
+                }
+            }
+            // output register i: row R * 16 + kq + 4 i, column c16 (intermediate c16 / 4)
+            const int u = c16 >> 2;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const double val = combine(c1a[i] + c1b[i], c2a[i] + c2b[i]);
+                const int l = R * 16 + kq + 4 * i;
+                if (u < n && use && v < n_vec && (STORE || any)) {
+                    const int64_t tw = tgt[u * cap + l];
+                    if (tw >= 0) {
+                        const double x = (tw & 1) ? -val : val;
+                        const int64_t t = tw >> 1;
+                        if (STORE)
+                            reinterpret_cast<double*>(E + t * NV + v)[comp] = x;
+                        else
+                            unsafeAtomicAdd(reinterpret_cast<double*>(sigma + (int64_t)v * nd + t) + comp, x);
+                    }
+                }
+            }
+        }
+        __syncthreads();   // the next item reuses the slice
+    }
+}
+
+template <bool CPLX, int NV, bool STORE>
+static hipError_t launch_grp_nv(const DevSpace& S, const GrpItem* items, int nitems, const void* A, const void* c,
+                                void* sigma, void* E, int nq, int nv, hipStream_t st) {
+    using T64 = typename VT<CPLX>::T;
+    const int cap = grp_cap(S.sp);
+    const size_t lds = GrpLayout(cap).bytes;
+    const int blocks = std::max(1, std::min(nitems, 256 * 16));
+    hipLaunchKernelGGL((k_sigma_pair_grp<CPLX, NV, STORE>), dim3((unsigned)blocks), dim3(256), lds, st, S, items,
+                       nitems, (const T64*)A, (const T64*)c, (T64*)sigma, (T64*)E, nq, nv, cap);
+    return hipGetLastError();
+}
+
+template <bool CPLX>
+static hipError_t launch_grp_all(const DevSpace& S, const GrpItem* items, int nitems, const void* A, const void* c,
+                                 void* sigma, void* E, int n_vec, double e_core, const LaunchMarks* mk,
+                                 hipStream_t st) {
+    using T64 = typename VT<CPLX>::T;
+    hipError_t e;
+    const int nq = S.sp.N * (S.sp.N - 1) / 2;
+    if (!E) {
+        e = launch_fill_init(CPLX, sigma, c, e_core, S.sp.ndets * n_vec, st);
+        if (e != hipSuccess) return e;
+    }
+    for (int v0 = 0; v0 < n_vec; v0 += 2) {
+        const int nv = (n_vec - v0 >= 2) ? 2 : 1;
+        const int64_t off = (int64_t)v0 * S.sp.ndets;
+        const T64* cc = (const T64*)c + off;
+        T64* ss = (T64*)sigma + off;
+        if (mk) mk->fn(mk->user, 0, true);
+        if (E)
+            e = (nv == 2) ? launch_grp_nv<CPLX, 2, true>(S, items, nitems, A, cc, ss, E, nq, 2, st)
+                          : launch_grp_nv<CPLX, 1, true>(S, items, nitems, A, cc, ss, E, nq, 1, st);
+        else
+            e = (nv == 2) ? launch_grp_nv<CPLX, 2, false>(S, items, nitems, A, cc, ss, nullptr, 0, 2, st)
+                          : launch_grp_nv<CPLX, 1, false>(S, items, nitems, A, cc, ss, nullptr, 0, 1, st);
+        if (mk) mk->fn(mk->user, 0, false);
+        if (e != hipSuccess) return e;
+        if (E) {
+            if (mk) mk->fn(mk->user, 1, true);
+            e = launch_pair_reduce(S, CPLX, nv, ss, cc, E, nv, e_core, st);
+            if (mk) mk->fn(mk->user, 1, false);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_sigma_pair_grp(const DevSpace& S, const GrpItem* items_dev, int nitems, bool cplx, const void* A,
+                                 const void* c, void* sigma, void* E, int n_vec, double e_core, const LaunchMarks* mk,
+                                 hipStream_t st) {
+    if (!pair_grp_supported(S.sp) || nitems <= 0) return hipErrorInvalidValue;
+    return cplx ? launch_grp_all<true>(S, items_dev, nitems, A, c, sigma, E, n_vec, e_core, mk, st)
+                : launch_grp_all<false>(S, items_dev, nitems, A, c, sigma, E, n_vec, e_core, mk, st);
+}
+
+}  // namespace stp

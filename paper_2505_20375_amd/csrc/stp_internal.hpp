@@ -95,6 +95,16 @@ struct Space {
     int64_t npwork_dets;        // determinants over all pair-intermediate categories
 };
 
+// One item of the grouped pair kernel (spaces of one subspace): up to GRP_U
+// intermediates K' (ranks j, -1 past n) that each add one electron to the
+// (N-3)-electron core.
+constexpr int GRP_U = 4;
+struct GrpItem {
+    uint32_t core;   // occupation bits of the core
+    int32_t n;
+    int32_t j[GRP_U];
+};
+
 // Device view passed by value to kernels.
 struct DevSpace {
     Space sp;

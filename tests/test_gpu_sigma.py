@@ -153,9 +153,79 @@ def test_every_kernel_matches_oracle(kernel, name):
     assert rel_err(_run_sigma(pb, c, kernel=kernel), pb.oracle_sigma(c)) <= TOL
 
 
+@pytest.mark.parametrize("n,M,cplx,n_vec", [
+    (3, 3, True, 1),      # one core (no electrons), three intermediates: a single partial item
+    (3, 8, True, 2),      # one core, eight intermediates: two full items
+    (4, 12, True, 3),     # three vectors: a two-vector launch and a one-vector launch
+    (5, 16, False, 2),    # real integrals
+    (6, 10, False, 1),
+    (7, 8, True, 2),      # one hole: a single pair per intermediate
+    (10, 14, True, 1),
+])
+def test_grouped_pair_kernel(n, M, cplx, n_vec):
+    """Spaces of one subspace: the grouped matrix-core kernel (four
+    intermediates sharing an (N-3)-electron core per table read) against the
+    oracle, real and complex, one to three vectors."""
+    import torch
+    print("case", n, M, cplx, n_vec, flush=True)
+    ints = (synth.complex_integrals if cplx else synth.real_integrals)(M, 50 + n, rank=8, sigma_f=0.05)
+    pb = Problem(ints, synth.SpaceSpec(n, [M]), seed=3)
+    cs = [pb.vector(s) for s in range(1, n_vec + 1)]
+    ctx = pb.context()
+    ctx.set_sigma_kernel("pair_grp")
+    x = torch.cat([pb.to_device(v) for v in cs])
+    out = torch.empty_like(x)
+    ctx.sigma(x, out, n_vec=n_vec)
+    torch.cuda.synchronize()
+    assert ctx.sigma_kernel() == "pair_grp"
+    nd = len(pb.dets)
+    for i, c in enumerate(cs):
+        assert rel_err(pb.from_device(out[i * nd:(i + 1) * nd]), pb.oracle_sigma(c)) <= TOL
+
+
+def test_grouped_pair_kernel_atomic_and_sparse():
+    """The grouped kernel with device atomics, and in store mode a vector
+    confined to a few determinants after a dense one (items whose four
+    intermediates see only zeros skip the products but must still overwrite
+    their entries of the contribution workspace)."""
+    import torch
+    ints = synth.complex_integrals(12, 21, rank=8, sigma_f=0.05)
+    pb = Problem(ints, synth.SpaceSpec(5, [12]), seed=3)
+    dense = pb.vector(4)
+    sparse = dense * (np.arange(len(dense)) % 97 == 0)
+    ref_d, ref_s = pb.oracle_sigma(dense), pb.oracle_sigma(sparse)
+    ctx = pb.context()
+    ctx.set_sigma_kernel("pair_grp")
+    xd, xs = pb.to_device(dense), pb.to_device(sparse)
+    out = torch.empty_like(xd)
+    ctx.sigma(xd, out)
+    ctx.sigma(xs, out)
+    torch.cuda.synchronize()
+    assert ctx.sigma_kernel() == "pair_grp"
+    assert rel_err(pb.from_device(out), ref_s) <= TOL
+    ctx2 = pb.context()
+    ctx2.set_sigma_kernel("pair_atomic")
+    ctx2.sigma(xd, out)
+    torch.cuda.synchronize()
+    assert ctx2.sigma_kernel() == "pair_grp_atomic"
+    assert rel_err(pb.from_device(out), ref_d) <= TOL
+
+
+def test_grouped_pair_kernel_refuses_other_spaces():
+    """Requesting the grouped kernel on a space of several subspaces is an error."""
+    import torch
+    pb = Problem.named("T4")
+    ctx = pb.context()
+    ctx.set_sigma_kernel("pair_grp")
+    x = pb.to_device(pb.vector())
+    with pytest.raises(Exception):
+        ctx.sigma(x, torch.empty_like(x))
+
+
 def test_default_kernel_is_pair():
     """The pair form is the default; with a pair table of at most 4 MB its FP64
-    products run on the matrix cores, with a larger one on the vector ALUs."""
+    products run on the matrix cores, with a larger one on the vector ALUs;
+    spaces of one subspace take the grouped matrix-core kernel."""
     import torch
     pb = Problem.named("T4")
     ctx = pb.context()
@@ -163,6 +233,11 @@ def test_default_kernel_is_pair():
     ctx.sigma(x, torch.empty_like(x))
     torch.cuda.synchronize()
     assert ctx.sigma_kernel() == "pair_mf64"
+    one = Problem.named("T8fci").context()      # one subspace: grouped intermediates
+    y1 = torch.zeros(one.space_info().n_dets, dtype=torch.complex128, device="cuda")
+    one.sigma(y1, torch.empty_like(y1))
+    torch.cuda.synchronize()
+    assert one.sigma_kernel() == "pair_grp"
     import paper_2505_20375_amd as stpci
     big = stpci.Context(0)            # 40 spinors: 780 pairs, a 9.7 MB complex table
     ints = synth.complex_integrals(40, 3, rank=4, sigma_f=0.05)

@@ -204,6 +204,24 @@ def test_pair_kernel_arithmetic_on_host(name, cap):
     assert n > 0 and bad == 0
 
 
+@pytest.mark.parametrize("n,sub,lo,hi,ok", [
+    (3, [3], None, None, True), (3, [8], None, None, True), (4, [12], None, None, True),
+    (8, [24], None, None, True), (10, [16], None, None, True), (7, [8], None, None, True),
+    (2, [8], None, None, False), (5, [4, 4, 4], [1, 1, 1], [2, 3, 2], False), (4, [6, 6], None, None, False),
+])
+def test_pair_groups_on_host(n, sub, lo, hi, ok):
+    """Items of the grouped pair kernel: every (N-2)-electron intermediate in
+    exactly one item, each member the item's core plus one electron; spaces of
+    several subspaces or fewer than three electrons are refused."""
+    c = host_ctx(n, sub, lo, hi)
+    if not ok:
+        with pytest.raises(Exception):
+            c.test_pair_groups()
+        return
+    items, bad = c.test_pair_groups()
+    assert items > 0 and bad == 0
+
+
 def brute_pair_counts(n, sub, lo, hi):
     """sum over (N-2)-electron bit strings K' of deg(K')^2, deg = pairs p < r
     empty in K' with K' + {p, r} in the space."""

@@ -37,17 +37,21 @@ namespace stp {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// Workgroup slice: core pairs (global pair index), B as [row][16] doubles,
-// targets [intermediate][row] (target << 1 | sign, -1: none), one pair header
-// per wavefront, flags.
+constexpr int GRP_PB = 4;   // core pairs per lane taken together in phase 1
+
+// Workgroup slice: core pairs (global pair index; p | r << 8), B as
+// [row][16] doubles, targets [intermediate][row] (target << 1 | sign, -1:
+// none), binomial coefficients C(n, k) (n, k <= 32) for colex ranks, flags.
+constexpr int GRP_BN = 33;
 struct GrpLayout {
-    size_t rinf_off, b_off, tgt_off, hdr_off, flag_off, bytes;
+    size_t rinf_off, prs_off, b_off, tgt_off, bin_off, flag_off, bytes;
     __host__ __device__ explicit GrpLayout(int cap) {
         rinf_off = 0;
-        b_off = ((size_t)cap * 4 + 15) & ~(size_t)15;
+        prs_off = (size_t)cap * 4;
+        b_off = (prs_off + (size_t)cap * 4 + 15) & ~(size_t)15;
         tgt_off = b_off + (size_t)cap * 16 * 8;
-        hdr_off = tgt_off + (size_t)GRP_U * cap * 8;
-        flag_off = hdr_off + (size_t)GRP_U * sizeof(PairHdr);
+        bin_off = tgt_off + (size_t)GRP_U * cap * 8;
+        flag_off = (bin_off + GRP_BN * GRP_BN * 4 + 15) & ~(size_t)15;
         bytes = flag_off + 16;
     }
 };
@@ -154,11 +158,14 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
     int32_t* rinf = reinterpret_cast<int32_t*>(smem + L.rinf_off);
     double* bsh = reinterpret_cast<double*>(smem + L.b_off);
     int64_t* tgt = reinterpret_cast<int64_t*>(smem + L.tgt_off);
+    int32_t* prs = reinterpret_cast<int32_t*>(smem + L.prs_off);
+    int32_t* binom = reinterpret_cast<int32_t*>(smem + L.bin_off);
     int* flags = reinterpret_cast<int*>(smem + L.flag_off);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    PairHdr* hd = reinterpret_cast<PairHdr*>(smem + L.hdr_off) + wid;
     const PairCat& P = S.pcats[0];
-    const int M = S.sp.M, NP = S.sp.npairs, deg = P.deg;
+    const int M = S.sp.M, NP = S.sp.npairs;
+    const int64_t kbits_off = S.tabs[P.tab[0]].bits_off;   // strings of K' by rank
+    const int64_t base = S.cats[P.cls_target[0]].offset;    // address of colex rank 0
     const int ncp = (M - S.sp.N + 3) * (M - S.sp.N + 2) / 2;   // core pairs
     const int64_t nd = S.sp.ndets;
     const uint64_t full = (M == 64) ? ~0ull : ((1ull << M) - 1ull);
@@ -188,66 +195,91 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
         }
     };
 
+    for (int t = threadIdx.x; t < GRP_BN * GRP_BN; t += blockDim.x) {
+        const int nn = t / GRP_BN, kk = t % GRP_BN;
+        int64_t b = (kk <= nn) ? 1 : 0;
+        for (int i = 1; i <= kk && kk <= nn; ++i) b = b * (nn - kk + i) / i;
+        binom[t] = (int32_t)b;
+    }
+    __syncthreads();
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const uint32_t core = items[it].core;
         const int n = items[it].n;
         const uint64_t emp = ~(uint64_t)core & full;
         // ---- phase 1: core pairs (all threads), then per wavefront one
-        // intermediate's header, B columns and targets
+        // intermediate K'_u = core + o: B columns and target of every core
+        // pair {p, r} (zero and none where the pair holds o).  The target
+        // K'_u + {p, r} is addressed by its colex rank, a+_p a+_r |K'_u> has
+        // the sign of the electrons of K'_u below r and below p, and q is the
+        // position of {p, r} among the target's occupied pairs.
         for (int l = threadIdx.x; l < cap; l += blockDim.x) {
-            int pi = 0;
+            int pi = 0, pr = 0;
             if (l < ncp) {
                 int t = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)l)) * 0.5f);   // C(t,2) <= l < C(t+1,2)
                 while (t * (t - 1) / 2 > l) --t;
                 while ((t + 1) * t / 2 <= l) ++t;
                 const int r = grp_nth_bit(emp, t), p = grp_nth_bit(emp, l - t * (t - 1) / 2);
                 pi = r * (r - 1) / 2 + p;
+                pr = p | (r << 8);
             }
             rinf[l] = pi;
+            prs[l] = pr;
         }
-        for (int l = lane; l < cap; l += 64) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bsh[l * 16 + 4 * wid + j] = 0.0;
-            tgt[wid * cap + l] = -1;
-        }
+        __syncthreads();
         bool nz = false;
-        if (wid < n) {
-            const int64_t jloc = items[it].j[wid];
-            if (lane < S.sp.K) pair_hdr_sub(S, P, jloc, lane, hd);
-            wave_lds_sync();
-            if (lane < M) pair_hdr_orb(S, P, lane, hd);
-            if (lane < P.ncls) pair_hdr_cls(S, P, lane, hd);
-            if (lane == 63) pair_hdr_bits(S, hd);
-            wave_lds_sync();   // (also orders the zero fill before the slot writes)
-            for (int slot = lane; slot < deg; slot += 64) {
-                int64_t addr;
-                int pi, q;
-                const bool neg = pair_slot(S, P, hd, slot, addr, pi, q);
-                int r = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)pi)) * 0.5f);   // pi = C(r,2) + p, p < r
-                while (r * (r - 1) / 2 > pi) --r;
-                while ((r + 1) * r / 2 <= pi) ++r;
-                const int p = pi - r * (r - 1) / 2;
-                // row of {p, r} among the core pairs (colex over the core's empty orbitals)
-                const int er = popc64(emp & ((1ull << r) - 1ull)), ep = popc64(emp & ((1ull << p) - 1ull));
-                const int l = er * (er - 1) / 2 + ep;
-                const double sg = neg ? -1.0 : 1.0;
-                double b4[4] = {0.0, 0.0, 0.0, 0.0};
+        const bool have = wid < n;
+        const uint32_t kb = have ? S.bits[kbits_off + items[it].j[wid]] : 0u;
+        const int o = have ? __builtin_ctz(kb & ~core) : -1;
+        for (int l0 = 0; l0 < cap; l0 += 64 * GRP_PB) {
+            int64_t addr[GRP_PB];
+            int qq[GRP_PB];
+            bool ok[GRP_PB], ng[GRP_PB];
 #pragma unroll
-                for (int vv = 0; vv < NV; ++vv) {
-                    if (vv >= n_vec) break;
-                    const TE x = c[(int64_t)vv * nd + addr];
-                    nz = nz || V64::abs2(x) != 0.0;
-                    if constexpr (CPLX) {
-                        // two vectors: [Re0, Re1, Im0, Im1]; one vector: [Re, Im, 0, 0]
-                        b4[NV == 2 ? vv : 0] = sg * x.x;
-                        b4[NV == 2 ? 2 + vv : 1] = sg * x.y;
-                    } else {
-                        b4[vv] = sg * x;
+            for (int i = 0; i < GRP_PB; ++i) {
+                const int l = l0 + 64 * i + lane;
+                const int pr = (l < cap) ? prs[l] : 0;
+                const int p = pr & 255, r = pr >> 8;
+                ok[i] = have && l < ncp && p != o && r != o;
+                const uint32_t T = kb | (1u << p) | (1u << r);
+                int64_t rk = 0;
+                uint32_t m = T;
+                for (int e = 1; m; ++e) {
+                    rk += binom[__builtin_ctz(m) * GRP_BN + e];
+                    m &= m - 1;
+                }
+                addr[i] = ok[i] ? base + rk : 0;
+                ng[i] = ((__builtin_popcount(kb & ((1u << r) - 1u)) + __builtin_popcount(kb & ((1u << p) - 1u))) & 1) != 0;
+                const int ip = __builtin_popcount(T & ((1u << p) - 1u)), ir = __builtin_popcount(T & ((1u << r) - 1u));
+                qq[i] = ir * (ir - 1) / 2 + ip;
+            }
+            TE x[GRP_PB][NV];
+#pragma unroll
+            for (int i = 0; i < GRP_PB; ++i)
+#pragma unroll
+                for (int vv = 0; vv < NV; ++vv) x[i][vv] = c[(int64_t)(vv < n_vec ? vv : 0) * nd + addr[i]];
+#pragma unroll
+            for (int i = 0; i < GRP_PB; ++i) {
+                const int l = l0 + 64 * i + lane;
+                if (l >= cap) break;
+                const double sg = ng[i] ? -1.0 : 1.0;
+                double b4[4] = {0.0, 0.0, 0.0, 0.0};
+                if (ok[i]) {
+#pragma unroll
+                    for (int vv = 0; vv < NV; ++vv) {
+                        if (vv >= n_vec) break;
+                        nz = nz || V64::abs2(x[i][vv]) != 0.0;
+                        if constexpr (CPLX) {
+                            // two vectors: [Re0, Re1, Im0, Im1]; one vector: [Re, Im, 0, 0]
+                            b4[NV == 2 ? vv : 0] = sg * x[i][vv].x;
+                            b4[NV == 2 ? 2 + vv : 1] = sg * x[i][vv].y;
+                        } else {
+                            b4[vv] = sg * x[i][vv];
+                        }
                     }
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) bsh[l * 16 + 4 * wid + j] = b4[j];
-                tgt[wid * cap + l] = ((STORE ? addr * nq + q : addr) << 1) | (neg ? 1 : 0);
+                tgt[wid * cap + l] = ok[i] ? (((STORE ? addr[i] * nq + qq[i] : addr[i]) << 1) | (ng[i] ? 1 : 0)) : -1;
             }
         }
         const bool live = __ballot(nz) != 0;

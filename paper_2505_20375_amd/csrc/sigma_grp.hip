@@ -202,7 +202,15 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
         binom[t] = (int32_t)b;
     }
     __syncthreads();
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    // XCD-aware item order: workgroups are dealt round-robin to the 8 XCDs, so
+    // workgroup b runs on XCD b % 8; each XCD takes one contiguous eighth of
+    // the items (neighbouring cores, whose targets share most occupied
+    // orbitals and hence nearby addresses), so that its L2 holds the
+    // coefficients it gathers and the workspace lines it writes.
+    const int xcd = blockIdx.x & 7, nloc = gridDim.x >> 3;
+    const int chunk = (nitems + 7) >> 3;
+    const int it_end = min(nitems, (xcd + 1) * chunk);
+    for (int it = xcd * chunk + (int)(blockIdx.x >> 3); it < it_end; it += nloc) {
         const uint32_t core = items[it].core;
         const int n = items[it].n;
         const uint64_t emp = ~(uint64_t)core & full;
@@ -362,7 +370,8 @@ static hipError_t launch_grp_nv(const DevSpace& S, const GrpItem* items, int nit
     using T64 = typename VT<CPLX>::T;
     const int cap = grp_cap(S.sp);
     const size_t lds = GrpLayout(cap).bytes;
-    const int blocks = std::max(1, std::min(nitems, 256 * 16));
+    // a multiple of 8 workgroups (one share per XCD), at most 16 per compute unit
+    const int blocks = std::min(((nitems + 7) >> 3) << 3, 256 * 16);
     hipLaunchKernelGGL((k_sigma_pair_grp<CPLX, NV, STORE>), dim3((unsigned)blocks), dim3(256), lds, st, S, items,
                        nitems, (const T64*)A, (const T64*)c, (T64*)sigma, (T64*)E, nq, nv, cap);
     return hipGetLastError();

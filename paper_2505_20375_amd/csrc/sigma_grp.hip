@@ -5,22 +5,31 @@
 // orbitals, and its pair-pair block A_K' is A restricted to those pairs.  Four
 // intermediates K'_u = K'' + o_u that share a core K'' (N-3 electrons) have
 // blocks inside one block A_K'' over the pairs of the core's empty orbitals
-// (the pairs of K'_u are the core pairs without o_u).  One workgroup takes such
-// an item: the core pairs index the rows and columns of A_K'', intermediate u
-// owns the columns 4u..4u+3 of a 16-column right-hand side
+// (the pairs of K'_u are the core pairs without o_u).  One workgroup of four
+// wavefronts takes such an item: the core pairs index the rows and columns of
+// A_K'', intermediate u owns the columns 4u..4u+3 of a 16-column right-hand side
 //   B[row, 4u + .] = [Re d_0, Re d_1, Im d_0, Im d_1] of K'_u at that pair (0 where the pair holds o_u),
 // and each 16 x 4 piece of A_K'' read from the table feeds one
 // v_mfma_f64_16x16x4f64 per real and imaginary part for all four: four times
 // the products per table read of the one-intermediate kernel, at 80 % useful
-// entries (the core has one more empty orbital).  Lane layouts (checked on the
-// device with an in-bounds probe): A lane l holds row l % 16, step l / 16; B
-// lane l holds step l / 16, column l % 16; output register i of lane l holds
-// row l / 16 + 4 i, column l % 16.  The complex combination and the scatter
-// of each intermediate's rows follow the one-intermediate kernel.
+// entries for 24 spin-orbitals and 8 electrons (the core has one more empty
+// orbital).  Lane layouts (checked on the device with an in-bounds probe): A
+// lane l holds row l % 16, step l / 16; B lane l holds step l / 16, column
+// l % 16; output register i of lane l holds row l / 16 + 4 i, column l % 16.
+// The complex combination and the scatter of each intermediate's rows follow
+// the one-intermediate kernel.
+//
+// The slot arithmetic is plain bit arithmetic here: the target K'_u + {p, r}
+// is addressed by its colex rank (binomial table in LDS), the sign of
+// a+_p a+_r |K'_u> counts the electrons of K'_u below r and below p, so each
+// core pair costs one gather of c and no table chains.
 //
 // Items come from the host: cores in colex order take their intermediates
 // not yet placed four at a time; the few left over go by the core without
-// their lowest electron.  Each intermediate is in exactly one item.
+// their lowest electron.  Each intermediate is in exactly one item.  Each XCD
+// works through a contiguous eighth of the items.  At 100 VGPRs (accumulators
+// included) and 30 KB of LDS per workgroup for 24 spin-orbitals, five
+// workgroups share a compute unit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,7 +38,6 @@
 #include <vector>
 
 #include "kernels.hpp"
-#include "pair_arith.hpp"
 #include "space.hpp"
 #include "stp_device.hpp"
 
@@ -37,21 +45,21 @@ namespace stp {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int GRP_PB = 4;   // core pairs per lane taken together in phase 1
+constexpr int GRP_PB = 2;   // core pairs per lane taken together in phase 1
 
 // Workgroup slice: core pairs (global pair index; p | r << 8), B as
 // [row][16] doubles, targets [intermediate][row] (target << 1 | sign, -1:
-// none), binomial coefficients C(n, k) (n, k <= 32) for colex ranks, flags.
-constexpr int GRP_BN = 33;
+// none), binomial coefficients C(n, k) (n < M, k <= N; row stride N + 1) for
+// colex ranks, flags.
 struct GrpLayout {
     size_t rinf_off, prs_off, b_off, tgt_off, bin_off, flag_off, bytes;
-    __host__ __device__ explicit GrpLayout(int cap) {
+    __host__ __device__ GrpLayout(int cap, int M, int N) {
         rinf_off = 0;
         prs_off = (size_t)cap * 4;
         b_off = (prs_off + (size_t)cap * 4 + 15) & ~(size_t)15;
         tgt_off = b_off + (size_t)cap * 16 * 8;
         bin_off = tgt_off + (size_t)GRP_U * cap * 8;
-        flag_off = (bin_off + GRP_BN * GRP_BN * 4 + 15) & ~(size_t)15;
+        flag_off = (bin_off + (size_t)M * (N + 1) * 4 + 15) & ~(size_t)15;
         bytes = flag_off + 16;
     }
 };
@@ -64,7 +72,7 @@ static int grp_core_pairs(const Space& sp) {
 static int grp_cap(const Space& sp) { return (grp_core_pairs(sp) + 15) & ~15; }
 
 bool pair_grp_supported(const Space& sp) {
-    return sp.K == 1 && sp.N >= 3 && sp.M <= 32 && sp.npcat == 1 && GrpLayout(grp_cap(sp)).bytes <= 64 * 1024;
+    return sp.K == 1 && sp.N >= 3 && sp.M <= 32 && sp.npcat == 1 && GrpLayout(grp_cap(sp), sp.M, sp.N).bytes <= 64 * 1024;
 }
 
 // Items of the grouped kernel (see the file comment); false when the space is
@@ -127,7 +135,7 @@ bool build_pair_groups(const HostSpace& H, std::vector<GrpItem>& items) {
     return n_placed == cnt;
 }
 
-size_t pair_grp_slice_bytes(const Space& sp) { return GrpLayout(grp_cap(sp)).bytes; }
+size_t pair_grp_slice_bytes(const Space& sp) { return GrpLayout(grp_cap(sp), sp.M, sp.N).bytes; }
 
 // Value of x in lane (lane ^ X) of the same quad, X = 1 or 2 (DPP quad permutation).
 template <int X>
@@ -154,7 +162,8 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
     using V64 = VT<CPLX>;
     using TE = typename V64::T;
     extern __shared__ __align__(16) unsigned char smem[];
-    const GrpLayout L(cap);
+    const GrpLayout L(cap, S.sp.M, S.sp.N);
+    const int BN = S.sp.N + 1;   // row stride of the binomial table
     int32_t* rinf = reinterpret_cast<int32_t*>(smem + L.rinf_off);
     double* bsh = reinterpret_cast<double*>(smem + L.b_off);
     int64_t* tgt = reinterpret_cast<int64_t*>(smem + L.tgt_off);
@@ -195,8 +204,8 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
         }
     };
 
-    for (int t = threadIdx.x; t < GRP_BN * GRP_BN; t += blockDim.x) {
-        const int nn = t / GRP_BN, kk = t % GRP_BN;
+    for (int t = threadIdx.x; t < S.sp.M * BN; t += blockDim.x) {
+        const int nn = t / BN, kk = t % BN;
         int64_t b = (kk <= nn) ? 1 : 0;
         for (int i = 1; i <= kk && kk <= nn; ++i) b = b * (nn - kk + i) / i;
         binom[t] = (int32_t)b;
@@ -252,7 +261,7 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
                 int64_t rk = 0;
                 uint32_t m = T;
                 for (int e = 1; m; ++e) {
-                    rk += binom[__builtin_ctz(m) * GRP_BN + e];
+                    rk += binom[__builtin_ctz(m) * BN + e];
                     m &= m - 1;
                 }
                 addr[i] = ok[i] ? base + rk : 0;
@@ -297,11 +306,13 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
 
         // ---- phases 2 and 3: 16-row tiles of A_K'' split over the wavefronts
         for (int R = wid; R < nT; R += 4) {
-            f64x4 c1a = {0.0, 0.0, 0.0, 0.0}, c1b = c1a, c2a = c1a, c2b = c1a;   // two chains per product
+            // one accumulator per real product: consecutive steps alternate between
+            // the two, which keeps a dependent pair two instructions apart
+            f64x4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = c1;
             if (any) {
                 const TE* arow = A + rinf[R * 16 + c16];   // this A lane's row pair
                 constexpr int G = 2;    // steps per group
-                constexpr int RG = 6;   // groups in flight
+                constexpr int RG = 4;   // groups in flight
                 const int ngrp = nks / G;
                 TE ab[RG][G];
                 auto ldgrp = [&](int g, TE (&a)[G]) {
@@ -314,13 +325,13 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
                         const double b0 = bsh[((((g * G + j) << 2) + kq) << 4) + c16];
                         const double b1 = bsh[((((g * G + j + 1) << 2) + kq) << 4) + c16];
                         if constexpr (CPLX) {
-                            c1a = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].x, b0, c1a, 0, 0, 0);
-                            c2a = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].y, b0, c2a, 0, 0, 0);
-                            c1b = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j + 1].x, b1, c1b, 0, 0, 0);
-                            c2b = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j + 1].y, b1, c2b, 0, 0, 0);
+                            c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].x, b0, c1, 0, 0, 0);
+                            c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].y, b0, c2, 0, 0, 0);
+                            c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j + 1].x, b1, c1, 0, 0, 0);
+                            c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j + 1].y, b1, c2, 0, 0, 0);
                         } else {
-                            c1a = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b0, c1a, 0, 0, 0);
-                            c1b = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j + 1], b1, c1b, 0, 0, 0);
+                            c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b0, c1, 0, 0, 0);
+                            c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j + 1], b1, c1, 0, 0, 0);
                         }
                     }
                 };
@@ -345,7 +356,7 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
             const int u = c16 >> 2;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const double val = combine(c1a[i] + c1b[i], c2a[i] + c2b[i]);
+                const double val = combine(c1[i], c2[i]);
                 const int l = R * 16 + kq + 4 * i;
                 if (u < n && use && v < n_vec && (STORE || any)) {
                     const int64_t tw = tgt[u * cap + l];
@@ -369,7 +380,7 @@ static hipError_t launch_grp_nv(const DevSpace& S, const GrpItem* items, int nit
                                 void* sigma, void* E, int nq, int nv, hipStream_t st) {
     using T64 = typename VT<CPLX>::T;
     const int cap = grp_cap(S.sp);
-    const size_t lds = GrpLayout(cap).bytes;
+    const size_t lds = GrpLayout(cap, S.sp.M, S.sp.N).bytes;
     // a multiple of 8 workgroups (one share per XCD), at most 16 per compute unit
     const int blocks = std::min(((nitems + 7) >> 3) << 3, 256 * 16);
     hipLaunchKernelGGL((k_sigma_pair_grp<CPLX, NV, STORE>), dim3((unsigned)blocks), dim3(256), lds, st, S, items,

@@ -127,11 +127,13 @@ def main():
     avg2 = t2 / max(n2, 1)
     achieved = flops / (avg2 * 1e-3) / 1e12
     achieved_paper = flops_paper / (avg2 * 1e-3) / 1e12
-    kdesc = {"pair_mf64": "k_sigma_pair_mf64 (one pass: pair-resolved 1e + 2e sigma, FP64 matrix cores, "
+    kdesc = {"pair_grp": "k_sigma_pair_grp (one pass: pair-resolved 1e + 2e sigma, four intermediates per "
+                         "(N-3)-electron core, FP64 matrix cores, v_mfma_f64_16x16x4f64)",
+             "pair_mf64": "k_sigma_pair_mf64 (one pass: pair-resolved 1e + 2e sigma, FP64 matrix cores, "
                           "v_mfma_f64_4x4x4f64)",
              "pair_valu": "k_sigma_pair (one pass: pair-resolved 1e + 2e sigma, FP64 vector ALUs)"}
     roof = {"kernel": kdesc.get(kname.replace("_atomic", ""), "k_sigma_symtile (fused 1e + 2e sigma, FP64)"),
-            "bound": "mfma" if kname.startswith("pair_mf64") else "alu",
+            "bound": "mfma" if kname.startswith(("pair_mf64", "pair_grp")) else "alu",
             "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": _traffic(n_vec, kname),
             "avg_launch_ms": round(avg2, 4), "launches": n2, "flops_per_launch": flops,
@@ -144,6 +146,10 @@ def main():
         # executed matrix-core flops: 16-row tiles x 4-column steps over the
         # pair degree rounded up to 32, two real products of 4 columns each
         roof["executed_flops_per_launch"] = ctx_pair_mf64_flops(ctx, n_vec)
+    if kname.startswith("pair_grp"):
+        # executed matrix-core flops: per item, the core pairs rounded up to 16
+        # as rows and columns, 16 right-hand columns, two real products
+        roof["executed_flops_per_launch"] = ctx_pair_grp_flops(ctx, sp, n_vec)
     res = {
         "metric": "determinant-updates/s in H.c sigma",
         "value": value,
@@ -253,10 +259,25 @@ def ctx_pair_mf64_flops(ctx, n_vec):
     return float(n_pair * 16 * cap * cap * ((n_vec + 1) // 2))
 
 
-TRAFFIC_FILES = {"pair_valu": os.path.join(ROOT, "profiles", "sigma_pair_c2_traffic.txt"),
+def ctx_pair_grp_flops(ctx, sp, n_vec):
+    """Matrix-core flops of one launch of the grouped FP64 pair kernel: per
+    item, cap = core pairs C(M - N + 3, 2) rounded up to 16, cap/16 row tiles x
+    cap/4 steps of v_mfma_f64_16x16x4f64 (2048 flop) for each of the two real
+    products (real and imaginary part of the table), i.e. 64 cap^2 flop per
+    item and pass of at most two vectors.  The item count is the host
+    grouping's."""
+    items, _ = ctx.test_pair_groups()
+    e = sp.n_spin_orb - sp.n_elec + 3
+    cap = (e * (e - 1) // 2 + 15) // 16 * 16
+    return float(items * 64 * cap * cap * ((n_vec + 1) // 2))
+
+
+TRAFFIC_FILES = {"pair_grp": os.path.join(ROOT, "profiles", "sigma_pair_grp_c2_traffic.txt"),
+                 "pair_valu": os.path.join(ROOT, "profiles", "sigma_pair_c2_traffic.txt"),
                  "pair_mf64": os.path.join(ROOT, "profiles", "sigma_pair_mf64_c2_traffic.txt"),
                  "tile": os.path.join(ROOT, "profiles", "sigma_symtile_c2_traffic.txt")}
-KERNEL_SOURCES = {"pair_valu": ["sigma_pair.hip", "pair_arith.hpp", "symtile.hpp", "stp_device.hpp", "stp_internal.hpp"],
+KERNEL_SOURCES = {"pair_grp": ["sigma_grp.hip", "stp_device.hpp", "stp_internal.hpp"],
+                  "pair_valu": ["sigma_pair.hip", "pair_arith.hpp", "symtile.hpp", "stp_device.hpp", "stp_internal.hpp"],
                   "pair_mf64": ["sigma_mf64.hip", "pair_arith.hpp", "stp_device.hpp", "stp_internal.hpp"],
                   "tile": ["sigma_sym.hip", "stp_device.hpp", "stp_internal.hpp"]}
 

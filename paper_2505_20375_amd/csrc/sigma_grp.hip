@@ -27,9 +27,9 @@
 // Items come from the host: cores in colex order take their intermediates
 // not yet placed four at a time; the few left over go by the core without
 // their lowest electron.  Each intermediate is in exactly one item.  Each XCD
-// works through a contiguous eighth of the items.  At 100 VGPRs (accumulators
-// included) and 30 KB of LDS per workgroup for 24 spin-orbitals, five
-// workgroups share a compute unit.
+// works through a contiguous eighth of the items.  At 100 registers
+// (accumulators included; four wavefronts per SIMD) and 30 KB of LDS per
+// workgroup for 24 spin-orbitals, four workgroups share a compute unit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -360,10 +360,10 @@ stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, st
             if (s) return s;
             E = c->d_E.p;
         }
-        if (c->pair_grp && !f32)
-            e = launch_sigma_pair_grp(c->dev, (const GrpItem*)c->d_grp.p, (int)c->grp_items.size(), c->cplx,
-                                      c->d_pA.p, cin, sout, E, n_vec, c->e_core, c->profile ? &mk : nullptr,
-                                      c->stream);
+        if (c->pair_grp)
+            e = launch_sigma_pair_grp(c->dev, (const GrpItem*)c->d_grp.p, (int)c->grp_items.size(), c->cplx, f32,
+                                      f32 ? c->d_pA32.p : c->d_pA.p, cin, sout, E, n_vec, c->e_core,
+                                      c->profile ? &mk : nullptr, c->stream);
         else if (c->pair_mf64 && !f32)
             e = launch_sigma_pair_mf64(c->dev, c->hs.pmax_deg, c->cplx, c->d_pA.p, cin, sout, E, n_vec, c->e_core,
                                        c->profile ? &mk : nullptr, c->stream);

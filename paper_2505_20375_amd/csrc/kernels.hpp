@@ -59,13 +59,14 @@ hipError_t launch_sigma_pair(const DevSpace& S, int deg_max, bool cplx, bool f32
 // Grouped FP64 matrix-core form for spaces of one subspace: items of four
 // intermediates sharing an (N-3)-electron core (build_pair_groups) take one
 // 16-column product per table read; same scatter modes as launch_sigma_pair.
+// f32: A is the FP32 table; products and accumulation in FP32.
 struct HostSpace;
 bool pair_grp_supported(const Space& sp);
 size_t pair_grp_slice_bytes(const Space& sp);
 bool build_pair_groups(const HostSpace& H, std::vector<GrpItem>& items);
-hipError_t launch_sigma_pair_grp(const DevSpace& S, const GrpItem* items_dev, int nitems, bool cplx, const void* A,
-                                 const void* c, void* sigma, void* E, int n_vec, double e_core, const LaunchMarks* mk,
-                                 hipStream_t st);
+hipError_t launch_sigma_pair_grp(const DevSpace& S, const GrpItem* items_dev, int nitems, bool cplx, bool f32,
+                                 const void* A, const void* c, void* sigma, void* E, int n_vec, double e_core,
+                                 const LaunchMarks* mk, hipStream_t st);
 // Grouped FP64 matrix-core pair products of several problems (device atomics).
 hipError_t launch_sigma_pair_mf64_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
                                         int deg_max, bool cplx, hipStream_t st);

@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdint>
 #include <unordered_map>
 #include <vector>
@@ -44,6 +45,15 @@
 namespace stp {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 x 4 matrix-core step, FP64 or FP32 (FP32 accumulation).
+__device__ __forceinline__ f64x4 grp_mfma(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 grp_mfma(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
 constexpr int GRP_PB = 2;   // core pairs per lane taken together in phase 1
 
@@ -53,11 +63,11 @@ constexpr int GRP_PB = 2;   // core pairs per lane taken together in phase 1
 // colex ranks, flags.
 struct GrpLayout {
     size_t rinf_off, prs_off, b_off, tgt_off, bin_off, flag_off, bytes;
-    __host__ __device__ GrpLayout(int cap, int M, int N) {
+    __host__ __device__ GrpLayout(int cap, int M, int N, int bsz) {
         rinf_off = 0;
         prs_off = (size_t)cap * 4;
         b_off = (prs_off + (size_t)cap * 4 + 15) & ~(size_t)15;
-        tgt_off = b_off + (size_t)cap * 16 * 8;
+        tgt_off = b_off + (size_t)cap * 16 * bsz;
         bin_off = tgt_off + (size_t)GRP_U * cap * 8;
         flag_off = (bin_off + (size_t)M * (N + 1) * 4 + 15) & ~(size_t)15;
         bytes = flag_off + 16;
@@ -72,7 +82,7 @@ static int grp_core_pairs(const Space& sp) {
 static int grp_cap(const Space& sp) { return (grp_core_pairs(sp) + 15) & ~15; }
 
 bool pair_grp_supported(const Space& sp) {
-    return sp.K == 1 && sp.N >= 3 && sp.M <= 32 && sp.npcat == 1 && GrpLayout(grp_cap(sp), sp.M, sp.N).bytes <= 64 * 1024;
+    return sp.K == 1 && sp.N >= 3 && sp.M <= 32 && sp.npcat == 1 && GrpLayout(grp_cap(sp), sp.M, sp.N, 8).bytes <= 64 * 1024;
 }
 
 // Items of the grouped kernel (see the file comment); false when the space is
@@ -135,7 +145,7 @@ bool build_pair_groups(const HostSpace& H, std::vector<GrpItem>& items) {
     return n_placed == cnt;
 }
 
-size_t pair_grp_slice_bytes(const Space& sp) { return GrpLayout(grp_cap(sp), sp.M, sp.N).bytes; }
+size_t pair_grp_slice_bytes(const Space& sp) { return GrpLayout(grp_cap(sp), sp.M, sp.N, 8).bytes; }
 
 // Value of x in lane (lane ^ X) of the same quad, X = 1 or 2 (DPP quad permutation).
 template <int X>
@@ -152,20 +162,25 @@ __device__ __forceinline__ int grp_nth_bit(uint64_t m, int k) {
     return __ffsll((unsigned long long)m) - 1;
 }
 
-template <bool CPLX, int NV, bool STORE>
+// F32: table, right-hand side and accumulation in FP32, sums of the
+// contributions in FP64 as in the FP64 form.
+template <bool CPLX, bool F32, int NV, bool STORE>
 __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpItem* __restrict__ items, int nitems,
-                                                       const typename VT<CPLX>::T* __restrict__ A,
+                                                       const typename PT<CPLX, F32>::T* __restrict__ A,
                                                        const typename VT<CPLX>::T* __restrict__ c,
                                                        typename VT<CPLX>::T* __restrict__ sigma,
                                                        typename VT<CPLX>::T* __restrict__ E, int nq, int n_vec,
                                                        int cap) {
     using V64 = VT<CPLX>;
-    using TE = typename V64::T;
+    using TE = typename V64::T;                        // coefficients (FP64)
+    using TA = typename PT<CPLX, F32>::T;              // table entries
+    using BT = typename std::conditional<F32, float, double>::type;
+    using ACC = typename std::conditional<F32, f32x4, f64x4>::type;
     extern __shared__ __align__(16) unsigned char smem[];
-    const GrpLayout L(cap, S.sp.M, S.sp.N);
+    const GrpLayout L(cap, S.sp.M, S.sp.N, (int)sizeof(BT));
     const int BN = S.sp.N + 1;   // row stride of the binomial table
     int32_t* rinf = reinterpret_cast<int32_t*>(smem + L.rinf_off);
-    double* bsh = reinterpret_cast<double*>(smem + L.b_off);
+    BT* bsh = reinterpret_cast<BT*>(smem + L.b_off);
     int64_t* tgt = reinterpret_cast<int64_t*>(smem + L.tgt_off);
     int32_t* prs = reinterpret_cast<int32_t*>(smem + L.prs_off);
     int32_t* binom = reinterpret_cast<int32_t*>(smem + L.bin_off);
@@ -295,7 +310,7 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) bsh[l * 16 + 4 * wid + j] = b4[j];
+                for (int j = 0; j < 4; ++j) bsh[l * 16 + 4 * wid + j] = (BT)b4[j];
                 tgt[wid * cap + l] = ok[i] ? (((STORE ? addr[i] * nq + qq[i] : addr[i]) << 1) | (ng[i] ? 1 : 0)) : -1;
             }
         }
@@ -308,30 +323,30 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
         for (int R = wid; R < nT; R += 4) {
             // one accumulator per real product: consecutive steps alternate between
             // the two, which keeps a dependent pair two instructions apart
-            f64x4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = c1;
+            ACC c1 = {0, 0, 0, 0}, c2 = c1;
             if (any) {
-                const TE* arow = A + rinf[R * 16 + c16];   // this A lane's row pair
+                const TA* arow = A + rinf[R * 16 + c16];   // this A lane's row pair
                 constexpr int G = 2;    // steps per group
                 constexpr int RG = 4;   // groups in flight
                 const int ngrp = nks / G;
-                TE ab[RG][G];
-                auto ldgrp = [&](int g, TE (&a)[G]) {
+                TA ab[RG][G];
+                auto ldgrp = [&](int g, TA (&a)[G]) {
 #pragma unroll
                     for (int j = 0; j < G; ++j) a[j] = arow[(int64_t)rinf[((g * G + j) << 2) + kq] * NP];
                 };
-                auto mfgrp = [&](int g, const TE (&a)[G]) {
+                auto mfgrp = [&](int g, const TA (&a)[G]) {
 #pragma unroll
                     for (int j = 0; j < G; j += 2) {
-                        const double b0 = bsh[((((g * G + j) << 2) + kq) << 4) + c16];
-                        const double b1 = bsh[((((g * G + j + 1) << 2) + kq) << 4) + c16];
+                        const BT b0 = bsh[((((g * G + j) << 2) + kq) << 4) + c16];
+                        const BT b1 = bsh[((((g * G + j + 1) << 2) + kq) << 4) + c16];
                         if constexpr (CPLX) {
-                            c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].x, b0, c1, 0, 0, 0);
-                            c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].y, b0, c2, 0, 0, 0);
-                            c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j + 1].x, b1, c1, 0, 0, 0);
-                            c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j + 1].y, b1, c2, 0, 0, 0);
+                            c1 = grp_mfma(a[j].x, b0, c1);
+                            c2 = grp_mfma(a[j].y, b0, c2);
+                            c1 = grp_mfma(a[j + 1].x, b1, c1);
+                            c2 = grp_mfma(a[j + 1].y, b1, c2);
                         } else {
-                            c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b0, c1, 0, 0, 0);
-                            c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j + 1], b1, c1, 0, 0, 0);
+                            c1 = grp_mfma(a[j], b0, c1);
+                            c1 = grp_mfma(a[j + 1], b1, c1);
                         }
                     }
                 };
@@ -352,12 +367,13 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
                     }
                 }
             }
-            // output register i: row R * 16 + kq + 4 i, column c16 (intermediate c16 / 4)
+            // output register i: row R * 16 + kq + 4 i (FP32: R * 16 + 4 kq + i),
+            // column c16 (intermediate c16 / 4)
             const int u = c16 >> 2;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const double val = combine(c1[i], c2[i]);
-                const int l = R * 16 + kq + 4 * i;
+                const double val = combine((double)c1[i], (double)c2[i]);
+                const int l = R * 16 + (F32 ? 4 * kq + i : kq + 4 * i);
                 if (u < n && use && v < n_vec && (STORE || any)) {
                     const int64_t tw = tgt[u * cap + l];
                     if (tw >= 0) {
@@ -375,20 +391,21 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
     }
 }
 
-template <bool CPLX, int NV, bool STORE>
+template <bool CPLX, bool F32, int NV, bool STORE>
 static hipError_t launch_grp_nv(const DevSpace& S, const GrpItem* items, int nitems, const void* A, const void* c,
                                 void* sigma, void* E, int nq, int nv, hipStream_t st) {
     using T64 = typename VT<CPLX>::T;
+    using TA = typename PT<CPLX, F32>::T;
     const int cap = grp_cap(S.sp);
-    const size_t lds = GrpLayout(cap, S.sp.M, S.sp.N).bytes;
+    const size_t lds = GrpLayout(cap, S.sp.M, S.sp.N, F32 ? 4 : 8).bytes;
     // a multiple of 8 workgroups (one share per XCD), at most 16 per compute unit
     const int blocks = std::min(((nitems + 7) >> 3) << 3, 256 * 16);
-    hipLaunchKernelGGL((k_sigma_pair_grp<CPLX, NV, STORE>), dim3((unsigned)blocks), dim3(256), lds, st, S, items,
-                       nitems, (const T64*)A, (const T64*)c, (T64*)sigma, (T64*)E, nq, nv, cap);
+    hipLaunchKernelGGL((k_sigma_pair_grp<CPLX, F32, NV, STORE>), dim3((unsigned)blocks), dim3(256), lds, st, S,
+                       items, nitems, (const TA*)A, (const T64*)c, (T64*)sigma, (T64*)E, nq, nv, cap);
     return hipGetLastError();
 }
 
-template <bool CPLX>
+template <bool CPLX, bool F32>
 static hipError_t launch_grp_all(const DevSpace& S, const GrpItem* items, int nitems, const void* A, const void* c,
                                  void* sigma, void* E, int n_vec, double e_core, const LaunchMarks* mk,
                                  hipStream_t st) {
@@ -406,11 +423,11 @@ static hipError_t launch_grp_all(const DevSpace& S, const GrpItem* items, int ni
         T64* ss = (T64*)sigma + off;
         if (mk) mk->fn(mk->user, 0, true);
         if (E)
-            e = (nv == 2) ? launch_grp_nv<CPLX, 2, true>(S, items, nitems, A, cc, ss, E, nq, 2, st)
-                          : launch_grp_nv<CPLX, 1, true>(S, items, nitems, A, cc, ss, E, nq, 1, st);
+            e = (nv == 2) ? launch_grp_nv<CPLX, F32, 2, true>(S, items, nitems, A, cc, ss, E, nq, 2, st)
+                          : launch_grp_nv<CPLX, F32, 1, true>(S, items, nitems, A, cc, ss, E, nq, 1, st);
         else
-            e = (nv == 2) ? launch_grp_nv<CPLX, 2, false>(S, items, nitems, A, cc, ss, nullptr, 0, 2, st)
-                          : launch_grp_nv<CPLX, 1, false>(S, items, nitems, A, cc, ss, nullptr, 0, 1, st);
+            e = (nv == 2) ? launch_grp_nv<CPLX, F32, 2, false>(S, items, nitems, A, cc, ss, nullptr, 0, 2, st)
+                          : launch_grp_nv<CPLX, F32, 1, false>(S, items, nitems, A, cc, ss, nullptr, 0, 1, st);
         if (mk) mk->fn(mk->user, 0, false);
         if (e != hipSuccess) return e;
         if (E) {
@@ -423,12 +440,15 @@ static hipError_t launch_grp_all(const DevSpace& S, const GrpItem* items, int ni
     return hipSuccess;
 }
 
-hipError_t launch_sigma_pair_grp(const DevSpace& S, const GrpItem* items_dev, int nitems, bool cplx, const void* A,
-                                 const void* c, void* sigma, void* E, int n_vec, double e_core, const LaunchMarks* mk,
-                                 hipStream_t st) {
+hipError_t launch_sigma_pair_grp(const DevSpace& S, const GrpItem* items_dev, int nitems, bool cplx, bool f32,
+                                 const void* A, const void* c, void* sigma, void* E, int n_vec, double e_core,
+                                 const LaunchMarks* mk, hipStream_t st) {
     if (!pair_grp_supported(S.sp) || nitems <= 0) return hipErrorInvalidValue;
-    return cplx ? launch_grp_all<true>(S, items_dev, nitems, A, c, sigma, E, n_vec, e_core, mk, st)
-                : launch_grp_all<false>(S, items_dev, nitems, A, c, sigma, E, n_vec, e_core, mk, st);
+    if (f32)
+        return cplx ? launch_grp_all<true, true>(S, items_dev, nitems, A, c, sigma, E, n_vec, e_core, mk, st)
+                    : launch_grp_all<false, true>(S, items_dev, nitems, A, c, sigma, E, n_vec, e_core, mk, st);
+    return cplx ? launch_grp_all<true, false>(S, items_dev, nitems, A, c, sigma, E, n_vec, e_core, mk, st)
+                : launch_grp_all<false, false>(S, items_dev, nitems, A, c, sigma, E, n_vec, e_core, mk, st);
 }
 
 }  // namespace stp

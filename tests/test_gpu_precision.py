@@ -41,6 +41,32 @@ def test_fp32_sigma_error_is_single_precision(name):
         assert rel_err(s64, pb.oracle_sigma(c)) <= 1e-12
 
 
+@pytest.mark.parametrize("n,M,cplx,n_vec,kernel", [(5, 16, True, 2, "pair"), (6, 10, False, 3, "pair"),
+                                                    (4, 12, True, 1, "pair_atomic"), (3, 8, True, 2, "pair")])
+def test_grouped_fp32_sigma(n, M, cplx, n_vec, kernel):
+    """Spaces of one subspace: the grouped matrix-core kernel with the FP32
+    table, right-hand side and accumulation (FP64 sums of the contributions)
+    stays within single-precision error of the oracle, for one to three
+    vectors and both scatter modes."""
+    import torch
+    import paper_2505_20375_amd as stpci
+    print("case", n, M, cplx, n_vec, kernel, flush=True)
+    ints = (synth.complex_integrals if cplx else synth.real_integrals)(M, 60 + n, rank=8, sigma_f=0.05)
+    pb = Problem(ints, synth.SpaceSpec(n, [M]), seed=3)
+    cs = [pb.vector(v) for v in range(1, n_vec + 1)]
+    ctx = pb.context()
+    ctx.set_sigma_kernel(kernel)
+    x = torch.cat([pb.to_device(v) for v in cs])
+    out = torch.empty_like(x)
+    ctx.sigma(x, out, n_vec=n_vec, precision=stpci.FP32)
+    torch.cuda.synchronize()
+    assert ctx.sigma_kernel() in ("pair_grp", "pair_grp_atomic")
+    nd = len(pb.dets)
+    for i, c in enumerate(cs):
+        err = rel_err(pb.from_device(out[i * nd:(i + 1) * nd]), pb.oracle_sigma(c))
+        assert 0 < err <= 2e-6
+
+
 @pytest.mark.parametrize("name,k", [("T4", 2), ("c1", 1)])
 def test_mixed_precision_davidson_matches_exact(name, k):
     import paper_2505_20375_amd as stpci

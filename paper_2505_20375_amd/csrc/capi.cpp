@@ -203,8 +203,11 @@ stpci_status prepare(stpci_ctx* c) {
         // spaces of one subspace: four intermediates per table read
         c->pair_grp = false;
         c->grp_items.clear();
-        if (c->kernel_req == 8 || (auto_unit && pair_grp_supported(H.sp))) {
-            c->pair_grp = build_pair_groups(H, c->grp_items);
+        // (the grouped kernel keeps targets as 32-bit words: target << 1 | sign)
+        const int64_t nq = (int64_t)H.sp.N * (H.sp.N - 1) / 2;
+        const bool grp_fits = (c->pair_store ? H.sp.ndets * nq : H.sp.ndets) < ((int64_t)1 << 30);
+        if (c->kernel_req == 8 || (auto_unit && grp_fits && pair_grp_supported(H.sp))) {
+            c->pair_grp = grp_fits && build_pair_groups(H, c->grp_items);
             if (!c->pair_grp && c->kernel_req == 8)
                 return set_err(c, STPCI_EINVAL, "the grouped pair kernel does not support this space");
             if (c->pair_grp && (s = upload(c, c->d_grp, c->grp_items, "pair groups"))) return s;

@@ -62,6 +62,7 @@ hipError_t launch_sigma_pair(const DevSpace& S, int deg_max, bool cplx, bool f32
 // f32: A is the FP32 table; products and accumulation in FP32.
 struct HostSpace;
 bool pair_grp_supported(const Space& sp);
+int pair_grp_unit(const Space& sp);   // intermediates per item (8 or 4), 0: unsupported
 size_t pair_grp_slice_bytes(const Space& sp);
 bool build_pair_groups(const HostSpace& H, std::vector<GrpItem>& items);
 hipError_t launch_sigma_pair_grp(const DevSpace& S, const GrpItem* items_dev, int nitems, bool cplx, bool f32,

@@ -63,12 +63,12 @@ constexpr int GRP_PB = 2;   // core pairs per lane taken together in phase 1
 // colex ranks, flags.
 struct GrpLayout {
     size_t rinf_off, prs_off, b_off, tgt_off, bin_off, flag_off, bytes;
-    __host__ __device__ GrpLayout(int cap, int M, int N, int bsz) {
+    __host__ __device__ GrpLayout(int cap, int M, int N, int bsz, int U) {
         rinf_off = 0;
         prs_off = (size_t)cap * 4;
         b_off = (prs_off + (size_t)cap * 4 + 15) & ~(size_t)15;
-        tgt_off = b_off + (size_t)cap * 16 * bsz;
-        bin_off = tgt_off + (size_t)GRP_U * cap * 8;
+        tgt_off = b_off + (size_t)cap * 4 * U * bsz;
+        bin_off = tgt_off + (size_t)U * cap * 4;
         flag_off = (bin_off + (size_t)M * (N + 1) * 4 + 15) & ~(size_t)15;
         bytes = flag_off + 16;
     }
@@ -81,16 +81,25 @@ static int grp_core_pairs(const Space& sp) {
 
 static int grp_cap(const Space& sp) { return (grp_core_pairs(sp) + 15) & ~15; }
 
-bool pair_grp_supported(const Space& sp) {
-    return sp.K == 1 && sp.N >= 3 && sp.M <= 32 && sp.npcat == 1 && GrpLayout(grp_cap(sp), sp.M, sp.N, 8).bytes <= 64 * 1024;
+// Intermediates per item: 8 where the FP64 workgroup slice fits 54 KB of LDS
+// (three workgroups per compute unit; each table read feeds 32 right-hand
+// columns), else 4 within 64 KB; 0: unsupported.
+int pair_grp_unit(const Space& sp) {
+    if (!(sp.K == 1 && sp.N >= 3 && sp.M <= 32 && sp.npcat == 1)) return 0;
+    if (GrpLayout(grp_cap(sp), sp.M, sp.N, 8, 8).bytes <= 54 * 1024) return 8;
+    if (GrpLayout(grp_cap(sp), sp.M, sp.N, 8, 4).bytes <= 64 * 1024) return 4;
+    return 0;
 }
+
+bool pair_grp_supported(const Space& sp) { return pair_grp_unit(sp) > 0; }
 
 // Items of the grouped kernel (see the file comment); false when the space is
 // not one subspace or too large for the host pass.
 bool build_pair_groups(const HostSpace& H, std::vector<GrpItem>& items) {
     items.clear();
     const Space& sp = H.sp;
-    if (!pair_grp_supported(sp)) return false;
+    const int U = pair_grp_unit(sp);
+    if (U == 0) return false;
     const PairCat& P = H.pcats[0];
     const int64_t cnt = P.count[0];
     const int M = sp.M, nc = sp.N - 3;
@@ -124,9 +133,9 @@ bool build_pair_groups(const HostSpace& H, std::vector<GrpItem>& items) {
             if (f == rank.end() || placed[f->second]) continue;
             mem[n++] = f->second;
         }
-        for (int a = 0; a + GRP_U <= n; a += GRP_U) {
-            for (int u = 0; u < GRP_U; ++u) placed[mem[a + u]] = 1;
-            emit(core, mem + a, GRP_U);
+        for (int a = 0; a + U <= n; a += U) {
+            for (int u = 0; u < U; ++u) placed[mem[a + u]] = 1;
+            emit(core, mem + a, U);
         }
         if (nc == 0) break;
         const uint64_t cbit = x & (~x + 1), r = x + cbit;
@@ -140,12 +149,12 @@ bool build_pair_groups(const HostSpace& H, std::vector<GrpItem>& items) {
             rest[s & (s - 1)].push_back((int32_t)r);
         }
     for (auto& kv : rest)
-        for (size_t a = 0; a < kv.second.size(); a += GRP_U)
-            emit(kv.first, kv.second.data() + a, (int)std::min<size_t>(GRP_U, kv.second.size() - a));
+        for (size_t a = 0; a < kv.second.size(); a += U)
+            emit(kv.first, kv.second.data() + a, (int)std::min<size_t>(U, kv.second.size() - a));
     return n_placed == cnt;
 }
 
-size_t pair_grp_slice_bytes(const Space& sp) { return GrpLayout(grp_cap(sp), sp.M, sp.N, 8).bytes; }
+size_t pair_grp_slice_bytes(const Space& sp) { return GrpLayout(grp_cap(sp), sp.M, sp.N, 8, pair_grp_unit(sp)).bytes; }
 
 // Value of x in lane (lane ^ X) of the same quad, X = 1 or 2 (DPP quad permutation).
 template <int X>
@@ -164,7 +173,7 @@ __device__ __forceinline__ int grp_nth_bit(uint64_t m, int k) {
 
 // F32: table, right-hand side and accumulation in FP32, sums of the
 // contributions in FP64 as in the FP64 form.
-template <bool CPLX, bool F32, int NV, bool STORE>
+template <bool CPLX, bool F32, int NV, bool STORE, int U>
 __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpItem* __restrict__ items, int nitems,
                                                        const typename PT<CPLX, F32>::T* __restrict__ A,
                                                        const typename VT<CPLX>::T* __restrict__ c,
@@ -177,11 +186,13 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
     using BT = typename std::conditional<F32, float, double>::type;
     using ACC = typename std::conditional<F32, f32x4, f64x4>::type;
     extern __shared__ __align__(16) unsigned char smem[];
-    const GrpLayout L(cap, S.sp.M, S.sp.N, (int)sizeof(BT));
+    constexpr int NG = U / 4;    // 16-column groups of the right-hand side
+    constexpr int BW = 4 * U;    // B row width
+    const GrpLayout L(cap, S.sp.M, S.sp.N, (int)sizeof(BT), U);
     const int BN = S.sp.N + 1;   // row stride of the binomial table
     int32_t* rinf = reinterpret_cast<int32_t*>(smem + L.rinf_off);
     BT* bsh = reinterpret_cast<BT*>(smem + L.b_off);
-    int64_t* tgt = reinterpret_cast<int64_t*>(smem + L.tgt_off);
+    int32_t* tgt = reinterpret_cast<int32_t*>(smem + L.tgt_off);   // target << 1 | sign (below 2^31)
     int32_t* prs = reinterpret_cast<int32_t*>(smem + L.prs_off);
     int32_t* binom = reinterpret_cast<int32_t*>(smem + L.bin_off);
     int* flags = reinterpret_cast<int*>(smem + L.flag_off);
@@ -259,8 +270,9 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
         }
         __syncthreads();
         bool nz = false;
-        const bool have = wid < n;
-        const uint32_t kb = have ? S.bits[kbits_off + items[it].j[wid]] : 0u;
+        for (int u = wid; u < U; u += 4) {   // this wavefront's intermediates of the item
+        const bool have = u < n;
+        const uint32_t kb = have ? S.bits[kbits_off + items[it].j[u]] : 0u;
         const int o = have ? __builtin_ctz(kb & ~core) : -1;
         for (int l0 = 0; l0 < cap; l0 += 64 * GRP_PB) {
             int64_t addr[GRP_PB];
@@ -310,9 +322,10 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) bsh[l * 16 + 4 * wid + j] = (BT)b4[j];
-                tgt[wid * cap + l] = ok[i] ? (((STORE ? addr[i] * nq + qq[i] : addr[i]) << 1) | (ng[i] ? 1 : 0)) : -1;
+                for (int j = 0; j < 4; ++j) bsh[l * BW + 4 * u + j] = (BT)b4[j];
+                tgt[u * cap + l] = ok[i] ? (int32_t)(((STORE ? addr[i] * nq + qq[i] : addr[i]) << 1) | (ng[i] ? 1 : 0)) : -1;
             }
+        }
         }
         const bool live = __ballot(nz) != 0;
         if (lane == 0) flags[wid] = live ? 1 : 0;
@@ -323,7 +336,9 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
         for (int R = wid; R < nT; R += 4) {
             // one accumulator per real product: consecutive steps alternate between
             // the two, which keeps a dependent pair two instructions apart
-            ACC c1 = {0, 0, 0, 0}, c2 = c1;
+            ACC c1[NG], c2[NG];
+#pragma unroll
+            for (int h = 0; h < NG; ++h) c1[h] = c2[h] = ACC{0, 0, 0, 0};
             if (any) {
                 const TA* arow = A + rinf[R * 16 + c16];   // this A lane's row pair
                 constexpr int G = 2;    // steps per group
@@ -336,17 +351,17 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
                 };
                 auto mfgrp = [&](int g, const TA (&a)[G]) {
 #pragma unroll
-                    for (int j = 0; j < G; j += 2) {
-                        const BT b0 = bsh[((((g * G + j) << 2) + kq) << 4) + c16];
-                        const BT b1 = bsh[((((g * G + j + 1) << 2) + kq) << 4) + c16];
-                        if constexpr (CPLX) {
-                            c1 = grp_mfma(a[j].x, b0, c1);
-                            c2 = grp_mfma(a[j].y, b0, c2);
-                            c1 = grp_mfma(a[j + 1].x, b1, c1);
-                            c2 = grp_mfma(a[j + 1].y, b1, c2);
-                        } else {
-                            c1 = grp_mfma(a[j], b0, c1);
-                            c1 = grp_mfma(a[j + 1], b1, c1);
+                    for (int j = 0; j < G; ++j) {
+                        const BT* brow = bsh + (((g * G + j) << 2) + kq) * BW + c16;
+#pragma unroll
+                        for (int h = 0; h < NG; ++h) {
+                            const BT b = brow[16 * h];
+                            if constexpr (CPLX) {
+                                c1[h] = grp_mfma(a[j].x, b, c1[h]);
+                                c2[h] = grp_mfma(a[j].y, b, c2[h]);
+                            } else {
+                                c1[h] = grp_mfma(a[j], b, c1[h]);
+                            }
                         }
                     }
                 };
@@ -369,20 +384,23 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
             }
             // output register i: row R * 16 + kq + 4 i (FP32: R * 16 + 4 kq + i),
             // column c16 (intermediate c16 / 4)
-            const int u = c16 >> 2;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const double val = combine((double)c1[i], (double)c2[i]);
-                const int l = R * 16 + (F32 ? 4 * kq + i : kq + 4 * i);
-                if (u < n && use && v < n_vec && (STORE || any)) {
-                    const int64_t tw = tgt[u * cap + l];
-                    if (tw >= 0) {
-                        const double x = (tw & 1) ? -val : val;
-                        const int64_t t = tw >> 1;
-                        if (STORE)
-                            reinterpret_cast<double*>(E + t * NV + v)[comp] = x;
-                        else
-                            unsafeAtomicAdd(reinterpret_cast<double*>(sigma + (int64_t)v * nd + t) + comp, x);
+            for (int h = 0; h < NG; ++h) {
+                const int u = 4 * h + (c16 >> 2);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const double val = combine((double)c1[h][i], (double)c2[h][i]);
+                    const int l = R * 16 + (F32 ? 4 * kq + i : kq + 4 * i);
+                    if (u < n && use && v < n_vec && (STORE || any)) {
+                        const int32_t tw = tgt[u * cap + l];
+                        if (tw >= 0) {
+                            const double x = (tw & 1) ? -val : val;
+                            const int64_t t = tw >> 1;
+                            if (STORE)
+                                reinterpret_cast<double*>(E + t * NV + v)[comp] = x;
+                            else
+                                unsafeAtomicAdd(reinterpret_cast<double*>(sigma + (int64_t)v * nd + t) + comp, x);
+                        }
                     }
                 }
             }
@@ -397,11 +415,16 @@ static hipError_t launch_grp_nv(const DevSpace& S, const GrpItem* items, int nit
     using T64 = typename VT<CPLX>::T;
     using TA = typename PT<CPLX, F32>::T;
     const int cap = grp_cap(S.sp);
-    const size_t lds = GrpLayout(cap, S.sp.M, S.sp.N, F32 ? 4 : 8).bytes;
+    const int U = pair_grp_unit(S.sp);
+    const size_t lds = GrpLayout(cap, S.sp.M, S.sp.N, F32 ? 4 : 8, U).bytes;
     // a multiple of 8 workgroups (one share per XCD), at most 16 per compute unit
     const int blocks = std::min(((nitems + 7) >> 3) << 3, 256 * 16);
-    hipLaunchKernelGGL((k_sigma_pair_grp<CPLX, F32, NV, STORE>), dim3((unsigned)blocks), dim3(256), lds, st, S,
-                       items, nitems, (const TA*)A, (const T64*)c, (T64*)sigma, (T64*)E, nq, nv, cap);
+    if (U == 8)
+        hipLaunchKernelGGL((k_sigma_pair_grp<CPLX, F32, NV, STORE, 8>), dim3((unsigned)blocks), dim3(256), lds, st, S,
+                           items, nitems, (const TA*)A, (const T64*)c, (T64*)sigma, (T64*)E, nq, nv, cap);
+    else
+        hipLaunchKernelGGL((k_sigma_pair_grp<CPLX, F32, NV, STORE, 4>), dim3((unsigned)blocks), dim3(256), lds, st, S,
+                           items, nitems, (const TA*)A, (const T64*)c, (T64*)sigma, (T64*)E, nq, nv, cap);
     return hipGetLastError();
 }
 

@@ -98,7 +98,7 @@ struct Space {
 // One item of the grouped pair kernel (spaces of one subspace): up to GRP_U
 // intermediates K' (ranks j, -1 past n) that each add one electron to the
 // (N-3)-electron core.
-constexpr int GRP_U = 4;
+constexpr int GRP_U = 8;
 struct GrpItem {
     uint32_t core;   // occupation bits of the core
     int32_t n;

@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bfloat16 matrix-core peak
+FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix-core peak
 HBM_PEAK_GBS = 8000.0
 
 
@@ -177,7 +178,9 @@ def main():
     ctx.sigma(c, out64, n_vec=n_vec)
     torch.cuda.synchronize()
     prec = {"sigma_fp64_ms": ms_per_step,
-            "contraction": "FP32: integrals, coefficients and accumulation in FP32 on the vector ALUs; "
+            "contraction": "FP32: integrals, coefficients and accumulation in FP32 (spaces of one subspace: "
+                           "grouped intermediates on the matrix cores, v_mfma_f32_16x16x4f32; otherwise the "
+                           "vector ALUs); "
                            "BF16: bfloat16 integrals and coefficients on the matrix cores "
                            "(v_mfma_f32_16x16x32_bf16), FP32 accumulation; both: FP64 sigma sums, residual, "
                            "orthogonalisation and subspace solve"}
@@ -185,7 +188,7 @@ def main():
         for _ in range(max(1, args.warmup)):
             ctx.sigma(c, out, n_vec=n_vec, precision=pcode)
         torch.cuda.synchronize()
-        ctx.profile(pname == "bf16")
+        ctx.profile(True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(args.steps):
@@ -197,6 +200,17 @@ def main():
         prec["sigma_%s_speedup" % pname] = ms_per_step / ms_p
         prec["sigma_%s_rel_err" % pname] = float(torch.linalg.vector_norm(out - out64) /
                                                  torch.linalg.vector_norm(out64))
+        if pname == "fp32" and kname.startswith("pair_grp"):
+            nf, tf = ctx.kernel_time("sigma_fp32")
+            ctx.profile(False)
+            kms = tf / max(nf, 1)
+            ex = ctx_pair_grp_flops(ctx, sp, n_vec)
+            prec["fp32_matrix_core"] = {
+                "kernel": "k_sigma_pair_grp (FP32 table, products and accumulation, v_mfma_f32_16x16x4f32)",
+                "avg_launch_ms": round(kms, 4), "executed_tflops": round(ex / (kms * 1e-3) / 1e12, 3),
+                "useful_tflops": round(flops / (kms * 1e-3) / 1e12, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac_executed": round(ex / (kms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+                "executed_flops_per_launch": ex, "useful_flops_per_launch": flops}
         if pname == "bf16":
             nb, tb = ctx.kernel_time("sigma_bf16")
             ctx.profile(False)
@@ -261,15 +275,15 @@ def ctx_pair_mf64_flops(ctx, n_vec):
 
 def ctx_pair_grp_flops(ctx, sp, n_vec):
     """Matrix-core flops of one launch of the grouped FP64 pair kernel: per
-    item, cap = core pairs C(M - N + 3, 2) rounded up to 16, cap/16 row tiles x
-    cap/4 steps of v_mfma_f64_16x16x4f64 (2048 flop) for each of the two real
-    products (real and imaginary part of the table), i.e. 64 cap^2 flop per
-    item and pass of at most two vectors.  The item count is the host
-    grouping's."""
-    items, _ = ctx.test_pair_groups()
+    item of `unit` intermediates, cap = core pairs C(M - N + 3, 2) rounded up
+    to 16, cap/16 row tiles x cap/4 steps x unit/4 column groups of
+    v_mfma_f64_16x16x4f64 (2048 flop) for each of the two real products (real
+    and imaginary part of the table), i.e. 16 unit cap^2 flop per item and
+    pass of at most two vectors.  Items and unit are the host grouping's."""
+    items, _, unit = ctx.test_pair_groups()
     e = sp.n_spin_orb - sp.n_elec + 3
     cap = (e * (e - 1) // 2 + 15) // 16 * 16
-    return float(items * 64 * cap * cap * ((n_vec + 1) // 2))
+    return float(items * 16 * unit * cap * cap * ((n_vec + 1) // 2))
 
 
 TRAFFIC_FILES = {"pair_grp": os.path.join(ROOT, "profiles", "sigma_pair_grp_c2_traffic.txt"),

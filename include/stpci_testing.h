@@ -36,13 +36,14 @@ stpci_status stpci_test_pairs(const stpci_ctx* ctx, int64_t max_dets_per_cat, in
                               int64_t* n_bad);
 
 /* Build, on the host, the items of the grouped pair kernel (spaces of one
- * subspace: up to four (N-2)-electron intermediates that each add one
+ * subspace: up to `unit` (N-2)-electron intermediates that each add one
  * electron to a shared (N-3)-electron core) and verify them: every
  * intermediate in exactly one item, every member the core plus one electron,
- * 1..4 members per item.  n_items: items built; n_bad: violations.  Returns
- * STPCI_EINVAL when the grouped kernel does not apply to the space (more than
- * one subspace, fewer than three electrons, more than 32 spin-orbitals). */
-stpci_status stpci_test_pair_groups(const stpci_ctx* ctx, int64_t* n_items, int64_t* n_bad);
+ * 1..unit members per item.  n_items: items built; n_bad: violations; unit:
+ * intermediates per item the kernel takes (8 or 4, by the LDS its slice
+ * needs).  Returns STPCI_EINVAL when the grouped kernel does not apply to the
+ * space (more than one subspace, fewer than three electrons). */
+stpci_status stpci_test_pair_groups(const stpci_ctx* ctx, int64_t* n_items, int64_t* n_bad, int* unit);
 
 #ifdef __cplusplus
 }

@@ -77,7 +77,7 @@ _SIGS = {
     "stpci_test_heev": ([_I, _P, _P, _P], _I),
     "stpci_test_moves": ([_P, _I64, _I64P, _I64P], _I),
     "stpci_test_pairs": ([_P, _I64, _I64P, _I64P], _I),
-    "stpci_test_pair_groups": ([_P, _I64P, _I64P], _I),
+    "stpci_test_pair_groups": ([_P, _I64P, _I64P, _IP], _I),
     "stpci_pair_counts": ([_P, _DP, _I64P, _IP], _I),
     "stpci_set_sigma_kernel": ([_P, ctypes.c_char_p], _I),
     "stpci_sigma_kernel": ([_P, ctypes.POINTER(ctypes.c_char_p)], _I),
@@ -247,10 +247,11 @@ class Context:
         return n.value, b.value
 
     def test_pair_groups(self):
-        """Host check of the grouped pair kernel's items: (items, violations)."""
-        n, b = ctypes.c_int64(), ctypes.c_int64()
-        self._check(_lib.stpci_test_pair_groups(self._h, ctypes.byref(n), ctypes.byref(b)))
-        return n.value, b.value
+        """Host check of the grouped pair kernel's items: (items, violations,
+        intermediates per item)."""
+        n, b, u = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+        self._check(_lib.stpci_test_pair_groups(self._h, ctypes.byref(n), ctypes.byref(b), ctypes.byref(u)))
+        return n.value, b.value, u.value
 
     def pair_counts(self):
         """(sum deg^2 over pair intermediates, number of pair intermediates, largest pair degree)."""

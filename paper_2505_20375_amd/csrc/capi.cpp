@@ -640,8 +640,8 @@ stpci_status stpci_test_pairs(const stpci_ctx* c, int64_t max_dets_per_cat, int6
     return STPCI_OK;
 }
 
-stpci_status stpci_test_pair_groups(const stpci_ctx* c, int64_t* n_items, int64_t* n_bad) {
-    if (!c || !n_items || !n_bad) return STPCI_EINVAL;
+stpci_status stpci_test_pair_groups(const stpci_ctx* c, int64_t* n_items, int64_t* n_bad, int* unit) {
+    if (!c || !n_items || !n_bad || !unit) return STPCI_EINVAL;
     if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
     const HostSpace& H = c->hs;
     std::vector<GrpItem> items;
@@ -653,7 +653,7 @@ stpci_status stpci_test_pair_groups(const stpci_ctx* c, int64_t* n_items, int64_
     std::vector<int> seen((size_t)cnt, 0);
     int64_t bad = 0;
     for (const GrpItem& it : items) {
-        if (it.n < 1 || it.n > GRP_U) {
+        if (it.n < 1 || it.n > pair_grp_unit(H.sp)) {
             ++bad;
             continue;
         }
@@ -675,6 +675,7 @@ stpci_status stpci_test_pair_groups(const stpci_ctx* c, int64_t* n_items, int64_
     for (int x : seen) bad += (x != 1);
     *n_items = (int64_t)items.size();
     *n_bad = bad;
+    *unit = pair_grp_unit(H.sp);
     return STPCI_OK;
 }
 

@@ -218,8 +218,8 @@ def test_pair_groups_on_host(n, sub, lo, hi, ok):
         with pytest.raises(Exception):
             c.test_pair_groups()
         return
-    items, bad = c.test_pair_groups()
-    assert items > 0 and bad == 0
+    items, bad, unit = c.test_pair_groups()
+    assert items > 0 and bad == 0 and unit in (4, 8)
 
 
 def brute_pair_counts(n, sub, lo, hi):

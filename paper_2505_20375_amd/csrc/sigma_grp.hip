@@ -271,61 +271,63 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
         __syncthreads();
         bool nz = false;
         for (int u = wid; u < U; u += 4) {   // this wavefront's intermediates of the item
-        const bool have = u < n;
-        const uint32_t kb = have ? S.bits[kbits_off + items[it].j[u]] : 0u;
-        const int o = have ? __builtin_ctz(kb & ~core) : -1;
-        for (int l0 = 0; l0 < cap; l0 += 64 * GRP_PB) {
-            int64_t addr[GRP_PB];
-            int qq[GRP_PB];
-            bool ok[GRP_PB], ng[GRP_PB];
+            const bool have = u < n;
+            const uint32_t kb = have ? S.bits[kbits_off + items[it].j[u]] : 0u;
+            const int o = have ? __builtin_ctz(kb & ~core) : -1;
+            for (int l0 = 0; l0 < cap; l0 += 64 * GRP_PB) {
+                int64_t addr[GRP_PB];
+                int qq[GRP_PB];
+                bool ok[GRP_PB], ng[GRP_PB];
 #pragma unroll
-            for (int i = 0; i < GRP_PB; ++i) {
-                const int l = l0 + 64 * i + lane;
-                const int pr = (l < cap) ? prs[l] : 0;
-                const int p = pr & 255, r = pr >> 8;
-                ok[i] = have && l < ncp && p != o && r != o;
-                const uint32_t T = kb | (1u << p) | (1u << r);
-                int64_t rk = 0;
-                uint32_t m = T;
-                for (int e = 1; m; ++e) {
-                    rk += binom[__builtin_ctz(m) * BN + e];
-                    m &= m - 1;
+                for (int i = 0; i < GRP_PB; ++i) {
+                    const int l = l0 + 64 * i + lane;
+                    const int pr = (l < cap) ? prs[l] : 0;
+                    const int p = pr & 255, r = pr >> 8;
+                    ok[i] = have && l < ncp && p != o && r != o;
+                    const uint32_t T = kb | (1u << p) | (1u << r);
+                    int64_t rk = 0;
+                    uint32_t m = T;
+                    for (int e = 1; m; ++e) {
+                        rk += binom[__builtin_ctz(m) * BN + e];
+                        m &= m - 1;
+                    }
+                    addr[i] = ok[i] ? base + rk : 0;
+                    const uint32_t below_p = (1u << p) - 1u, below_r = (1u << r) - 1u;
+                    ng[i] = ((__builtin_popcount(kb & below_r) + __builtin_popcount(kb & below_p)) & 1) != 0;
+                    const int ip = __builtin_popcount(T & below_p), ir = __builtin_popcount(T & below_r);
+                    qq[i] = ir * (ir - 1) / 2 + ip;
                 }
-                addr[i] = ok[i] ? base + rk : 0;
-                ng[i] = ((__builtin_popcount(kb & ((1u << r) - 1u)) + __builtin_popcount(kb & ((1u << p) - 1u))) & 1) != 0;
-                const int ip = __builtin_popcount(T & ((1u << p) - 1u)), ir = __builtin_popcount(T & ((1u << r) - 1u));
-                qq[i] = ir * (ir - 1) / 2 + ip;
-            }
-            TE x[GRP_PB][NV];
+                TE x[GRP_PB][NV];
 #pragma unroll
-            for (int i = 0; i < GRP_PB; ++i)
+                for (int i = 0; i < GRP_PB; ++i)
 #pragma unroll
-                for (int vv = 0; vv < NV; ++vv) x[i][vv] = c[(int64_t)(vv < n_vec ? vv : 0) * nd + addr[i]];
+                    for (int vv = 0; vv < NV; ++vv) x[i][vv] = c[(int64_t)(vv < n_vec ? vv : 0) * nd + addr[i]];
 #pragma unroll
-            for (int i = 0; i < GRP_PB; ++i) {
-                const int l = l0 + 64 * i + lane;
-                if (l >= cap) break;
-                const double sg = ng[i] ? -1.0 : 1.0;
-                double b4[4] = {0.0, 0.0, 0.0, 0.0};
-                if (ok[i]) {
+                for (int i = 0; i < GRP_PB; ++i) {
+                    const int l = l0 + 64 * i + lane;
+                    if (l >= cap) break;
+                    const double sg = ng[i] ? -1.0 : 1.0;
+                    double b4[4] = {0.0, 0.0, 0.0, 0.0};
+                    if (ok[i]) {
 #pragma unroll
-                    for (int vv = 0; vv < NV; ++vv) {
-                        if (vv >= n_vec) break;
-                        nz = nz || V64::abs2(x[i][vv]) != 0.0;
-                        if constexpr (CPLX) {
-                            // two vectors: [Re0, Re1, Im0, Im1]; one vector: [Re, Im, 0, 0]
-                            b4[NV == 2 ? vv : 0] = sg * x[i][vv].x;
-                            b4[NV == 2 ? 2 + vv : 1] = sg * x[i][vv].y;
-                        } else {
-                            b4[vv] = sg * x[i][vv];
+                        for (int vv = 0; vv < NV; ++vv) {
+                            if (vv >= n_vec) break;
+                            nz = nz || V64::abs2(x[i][vv]) != 0.0;
+                            if constexpr (CPLX) {
+                                // two vectors: [Re0, Re1, Im0, Im1]; one vector: [Re, Im, 0, 0]
+                                b4[NV == 2 ? vv : 0] = sg * x[i][vv].x;
+                                b4[NV == 2 ? 2 + vv : 1] = sg * x[i][vv].y;
+                            } else {
+                                b4[vv] = sg * x[i][vv];
+                            }
                         }
                     }
-                }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) bsh[l * BW + 4 * u + j] = (BT)b4[j];
-                tgt[u * cap + l] = ok[i] ? (int32_t)(((STORE ? addr[i] * nq + qq[i] : addr[i]) << 1) | (ng[i] ? 1 : 0)) : -1;
+                    for (int j = 0; j < 4; ++j) bsh[l * BW + 4 * u + j] = (BT)b4[j];
+                    const int64_t t = STORE ? addr[i] * nq + qq[i] : addr[i];
+                    tgt[u * cap + l] = ok[i] ? (int32_t)((t << 1) | (ng[i] ? 1 : 0)) : -1;
+                }
             }
-        }
         }
         const bool live = __ballot(nz) != 0;
         if (lane == 0) flags[wid] = live ? 1 : 0;

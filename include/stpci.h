@@ -153,16 +153,22 @@ stpci_status stpci_pair_counts(const stpci_ctx* ctx, double* w_pair, int64_t* n_
  * memory or 1 GB, else contributions are added with device atomics; FP64
  * products run on the matrix cores when the pair table (16 or 8 bytes per
  * pair-pair entry) fits 4 MB, the L2 of one XCD, else on the vector ALUs with
- * Hermitian tiles), "pair_atomic" (the same with device atomics),
+ * Hermitian tiles; in a space of one subspace, with at least three electrons
+ * and target indices below 2^30, the intermediates that add one electron to a
+ * common (N-3)-electron core are contracted eight (or four) at a time against
+ * one block of the pair table on the matrix cores, FP64 or, for
+ * STPCI_FP32, FP32), "pair_atomic" (the same with device atomics),
  * "pair_mf64" and "pair_valu" (the pair form with the FP64 products forced
- * onto the matrix cores or the vector ALUs), "tile" (one-move intermediates
+ * onto the matrix cores one intermediate at a time, or onto the vector ALUs),
+ * "pair_grp" (the grouped form, one subspace only), "tile" (one-move intermediates
  * of Eq. sigmaL2e, Hermitian tiles, one- and two-electron parts fused),
  * "rowtile", "wave" and "simple" (earlier one-move forms), or "auto".  All
  * compute the same sigma; a kernel that cannot handle the space makes the
  * next device call fail with STPCI_EINVAL.  stpci_sigma_kernel reports the
- * kernel in use after the first device call (static string): "pair_mf64",
- * "pair_valu" (store-and-reduce scatter), "pair_mf64_atomic",
- * "pair_valu_atomic", "tile", "rowtile", "wave" or "simple". */
+ * kernel in use after the first device call (static string): "pair_grp",
+ * "pair_mf64", "pair_valu" (store-and-reduce scatter), "pair_grp_atomic",
+ * "pair_mf64_atomic", "pair_valu_atomic", "tile", "rowtile", "wave" or
+ * "simple". */
 stpci_status stpci_set_sigma_kernel(stpci_ctx* ctx, const char* name);
 stpci_status stpci_sigma_kernel(const stpci_ctx* ctx, const char** name);
 

@@ -55,7 +55,6 @@ __device__ __forceinline__ f32x4 grp_mfma(float a, float b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int GRP_PB = 2;   // core pairs per lane taken together in phase 1
 
 // Workgroup slice: core pairs (global pair index; p | r << 8), B as
 // [row][16] doubles, targets [intermediate][row] (target << 1 | sign, -1:
@@ -187,6 +186,9 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
     using ACC = typename std::conditional<F32, f32x4, f64x4>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NG = U / 4;    // 16-column groups of the right-hand side
+    // core pairs per lane taken together in phase 1 (FP64: as many as the
+    // registers of the products allow at no cost in occupancy)
+    constexpr int PB = F32 ? 2 : 4;
     constexpr int BW = 4 * U;    // B row width
     const GrpLayout L(cap, S.sp.M, S.sp.N, (int)sizeof(BT), U);
     const int BN = S.sp.N + 1;   // row stride of the binomial table
@@ -249,8 +251,8 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
         const uint32_t core = items[it].core;
         const int n = items[it].n;
         const uint64_t emp = ~(uint64_t)core & full;
-        // ---- phase 1: core pairs (all threads), then per wavefront one
-        // intermediate K'_u = core + o: B columns and target of every core
+        // ---- phase 1: core pairs (all threads), then per wavefront its
+        // intermediates K'_u = core + o: B columns and target of every core
         // pair {p, r} (zero and none where the pair holds o).  The target
         // K'_u + {p, r} is addressed by its colex rank, a+_p a+_r |K'_u> has
         // the sign of the electrons of K'_u below r and below p, and q is the
@@ -274,12 +276,12 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
             const bool have = u < n;
             const uint32_t kb = have ? S.bits[kbits_off + items[it].j[u]] : 0u;
             const int o = have ? __builtin_ctz(kb & ~core) : -1;
-            for (int l0 = 0; l0 < cap; l0 += 64 * GRP_PB) {
-                int64_t addr[GRP_PB];
-                int qq[GRP_PB];
-                bool ok[GRP_PB], ng[GRP_PB];
+            for (int l0 = 0; l0 < cap; l0 += 64 * PB) {
+                int64_t addr[PB];
+                int qq[PB];
+                bool ok[PB], ng[PB];
 #pragma unroll
-                for (int i = 0; i < GRP_PB; ++i) {
+                for (int i = 0; i < PB; ++i) {
                     const int l = l0 + 64 * i + lane;
                     const int pr = (l < cap) ? prs[l] : 0;
                     const int p = pr & 255, r = pr >> 8;
@@ -297,13 +299,13 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
                     const int ip = __builtin_popcount(T & below_p), ir = __builtin_popcount(T & below_r);
                     qq[i] = ir * (ir - 1) / 2 + ip;
                 }
-                TE x[GRP_PB][NV];
+                TE x[PB][NV];
 #pragma unroll
-                for (int i = 0; i < GRP_PB; ++i)
+                for (int i = 0; i < PB; ++i)
 #pragma unroll
                     for (int vv = 0; vv < NV; ++vv) x[i][vv] = c[(int64_t)(vv < n_vec ? vv : 0) * nd + addr[i]];
 #pragma unroll
-                for (int i = 0; i < GRP_PB; ++i) {
+                for (int i = 0; i < PB; ++i) {
                     const int l = l0 + 64 * i + lane;
                     if (l >= cap) break;
                     const double sg = ng[i] ? -1.0 : 1.0;

@@ -173,7 +173,7 @@ __device__ __forceinline__ int grp_nth_bit(uint64_t m, int k) {
 // F32: table, right-hand side and accumulation in FP32, sums of the
 // contributions in FP64 as in the FP64 form.
 template <bool CPLX, bool F32, int NV, bool STORE, int U>
-__global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpItem* __restrict__ items, int nitems,
+__global__ __launch_bounds__(256, 3) void k_sigma_pair_grp(DevSpace S, const GrpItem* __restrict__ items, int nitems,
                                                        const typename PT<CPLX, F32>::T* __restrict__ A,
                                                        const typename VT<CPLX>::T* __restrict__ c,
                                                        typename VT<CPLX>::T* __restrict__ sigma,
@@ -353,22 +353,29 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
 #pragma unroll
                     for (int j = 0; j < G; ++j) a[j] = arow[(int64_t)rinf[((g * G + j) << 2) + kq] * NP];
                 };
-                auto mfgrp = [&](int g, const TA (&a)[G]) {
+                // right-hand fragments of a group, read from LDS one group ahead
+                // of their products (two buffers alternate; RG is even)
+                BT bb[2][G][NG];
+                auto ldb = [&](int g, BT (&b)[G][NG]) {
 #pragma unroll
-                    for (int j = 0; j < G; ++j) {
-                        const BT* brow = bsh + (((g * G + j) << 2) + kq) * BW + c16;
+                    for (int j = 0; j < G; ++j)
+#pragma unroll
+                        for (int h = 0; h < NG; ++h) b[j][h] = bsh[(((g * G + j) << 2) + kq) * BW + c16 + 16 * h];
+                };
+                auto mfgrp = [&](const TA (&a)[G], const BT (&b)[G][NG]) {
+#pragma unroll
+                    for (int j = 0; j < G; ++j)
 #pragma unroll
                         for (int h = 0; h < NG; ++h) {
-                            const BT b = brow[16 * h];
                             if constexpr (CPLX) {
-                                c1[h] = grp_mfma(a[j].x, b, c1[h]);
-                                c2[h] = grp_mfma(a[j].y, b, c2[h]);
+                                c1[h] = grp_mfma(a[j].x, b[j][h], c1[h]);
+                                c2[h] = grp_mfma(a[j].y, b[j][h], c2[h]);
                             } else {
-                                c1[h] = grp_mfma(a[j], b, c1[h]);
+                                c1[h] = grp_mfma(a[j], b[j][h], c1[h]);
                             }
                         }
-                    }
                 };
+                static_assert(RG % 2 == 0, "the two fragment buffers alternate over the ring");
                 // the loads are unconditional (past the last group: the last group
                 // again, in range, unused), so that every group keeps the same
                 // number of reads in flight
@@ -377,14 +384,21 @@ __global__ __launch_bounds__(256) void k_sigma_pair_grp(DevSpace S, const GrpIte
                     ldgrp(u < ngrp ? u : ngrp - 1, ab[u]);
                     __builtin_amdgcn_sched_barrier(0);   // requested in group order, as in the loop
                 }
-                for (int g = 0; g < ngrp; g += RG) {
+                ldb(0, bb[0]);
+                // whole rounds of RG groups without conditions (so that every
+                // read stays ahead of its use), then the last partial round
+                const int nfull = ngrp - ngrp % RG;
+                auto round = [&](int g, bool tail) {
 #pragma unroll
                     for (int u = 0; u < RG; ++u) {
-                        const int gl = g + u + RG - 1;
+                        const int gl = g + u + RG - 1, gb = g + u + 1;
                         ldgrp(gl < ngrp ? gl : ngrp - 1, ab[(u + RG - 1) % RG]);
-                        if (g + u < ngrp) mfgrp(g + u, ab[u]);
+                        ldb(gb < ngrp ? gb : ngrp - 1, bb[(u + 1) & 1]);
+                        if (!tail || g + u < ngrp) mfgrp(ab[u], bb[u & 1]);
                     }
-                }
+                };
+                for (int g = 0; g < nfull; g += RG) round(g, false);
+                if (nfull < ngrp) round(nfull, true);
             }
             // output register i: row R * 16 + kq + 4 i (FP32: R * 16 + 4 kq + i),
             // column c16 (intermediate c16 / 4)

@@ -42,7 +42,8 @@ def test_fp32_sigma_error_is_single_precision(name):
 
 
 @pytest.mark.parametrize("n,M,cplx,n_vec,kernel", [(5, 16, True, 2, "pair"), (6, 10, False, 3, "pair"),
-                                                    (4, 12, True, 1, "pair_atomic"), (3, 8, True, 2, "pair")])
+                                                    (4, 12, True, 1, "pair_atomic"), (3, 8, True, 2, "pair"),
+                                                    (4, 22, True, 2, "pair")])
 def test_grouped_fp32_sigma(n, M, cplx, n_vec, kernel):
     """Spaces of one subspace: the grouped matrix-core kernel with the FP32
     table, right-hand side and accumulation (FP64 sums of the contributions)

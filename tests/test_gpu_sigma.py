@@ -161,11 +161,13 @@ def test_every_kernel_matches_oracle(kernel, name):
     (6, 10, False, 1),
     (7, 8, True, 2),      # one hole: a single pair per intermediate
     (10, 14, True, 1),
+    (4, 22, True, 2),     # 210 core pairs: the slice of eight would exceed 54 KB, four per item
+    (4, 22, False, 3),
 ])
 def test_grouped_pair_kernel(n, M, cplx, n_vec):
-    """Spaces of one subspace: the grouped matrix-core kernel (four
-    intermediates sharing an (N-3)-electron core per table read) against the
-    oracle, real and complex, one to three vectors."""
+    """Spaces of one subspace: the grouped matrix-core kernel (eight, or
+    four, intermediates sharing an (N-3)-electron core per table read)
+    against the oracle, real and complex, one to three vectors."""
     import torch
     print("case", n, M, cplx, n_vec, flush=True)
     ints = (synth.complex_integrals if cplx else synth.real_integrals)(M, 50 + n, rank=8, sigma_f=0.05)

@@ -62,11 +62,11 @@ __device__ __forceinline__ f32x4 grp_mfma(float a, float b, f32x4 c) {
 // colex ranks, flags.
 struct GrpLayout {
     size_t rinf_off, prs_off, b_off, tgt_off, bin_off, flag_off, bytes;
-    __host__ __device__ GrpLayout(int cap, int M, int N, int bsz, int U) {
+    __host__ __device__ GrpLayout(int cap, int M, int N, int bsz, int U, int bw) {
         rinf_off = 0;
         prs_off = (size_t)cap * 4;
         b_off = (prs_off + (size_t)cap * 4 + 15) & ~(size_t)15;
-        tgt_off = b_off + (size_t)cap * 4 * U * bsz;
+        tgt_off = b_off + (size_t)cap * bw * bsz;
         bin_off = tgt_off + (size_t)U * cap * 4;
         flag_off = (bin_off + (size_t)M * (N + 1) * 4 + 15) & ~(size_t)15;
         bytes = flag_off + 16;
@@ -85,8 +85,8 @@ static int grp_cap(const Space& sp) { return (grp_core_pairs(sp) + 15) & ~15; }
 // columns), else 4 within 64 KB; 0: unsupported.
 int pair_grp_unit(const Space& sp) {
     if (!(sp.K == 1 && sp.N >= 3 && sp.M <= 32 && sp.npcat == 1)) return 0;
-    if (GrpLayout(grp_cap(sp), sp.M, sp.N, 8, 8).bytes <= 54 * 1024) return 8;
-    if (GrpLayout(grp_cap(sp), sp.M, sp.N, 8, 4).bytes <= 64 * 1024) return 4;
+    if (GrpLayout(grp_cap(sp), sp.M, sp.N, 8, 8, 32).bytes <= 54 * 1024) return 8;
+    if (GrpLayout(grp_cap(sp), sp.M, sp.N, 8, 4, 16).bytes <= 64 * 1024) return 4;
     return 0;
 }
 
@@ -153,7 +153,16 @@ bool build_pair_groups(const HostSpace& H, std::vector<GrpItem>& items) {
     return n_placed == cnt;
 }
 
-size_t pair_grp_slice_bytes(const Space& sp) { return GrpLayout(grp_cap(sp), sp.M, sp.N, 8, pair_grp_unit(sp)).bytes; }
+size_t pair_grp_slice_bytes(const Space& sp) {
+    const int U = pair_grp_unit(sp);
+    return GrpLayout(grp_cap(sp), sp.M, sp.N, 8, U, 4 * U).bytes;
+}
+
+// Right-hand columns per intermediate: complex [Re d_0, Re d_1, Im d_0, Im d_1]
+// (one vector: [Re d, Im d]), real [d_0, d_1] (one vector: [d]); the row of B
+// is padded to whole 16-column groups.
+__host__ __device__ constexpr int grp_cw(bool cplx, int nv) { return cplx ? 2 * nv : nv; }
+__host__ __device__ constexpr int grp_bw(bool cplx, int nv, int U) { return (U * grp_cw(cplx, nv) + 15) / 16 * 16; }
 
 // Value of x in lane (lane ^ X) of the same quad, X = 1 or 2 (DPP quad permutation).
 template <int X>
@@ -185,12 +194,13 @@ __global__ __launch_bounds__(256, 3) void k_sigma_pair_grp(DevSpace S, const Grp
     using BT = typename std::conditional<F32, float, double>::type;
     using ACC = typename std::conditional<F32, f32x4, f64x4>::type;
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int NG = U / 4;    // 16-column groups of the right-hand side
+    constexpr int CW = grp_cw(CPLX, NV);   // right-hand columns per intermediate
+    constexpr int BW = grp_bw(CPLX, NV, U);   // B row width
+    constexpr int NG = BW / 16;            // 16-column groups of the right-hand side
     // core pairs per lane taken together in phase 1 (FP64: as many as the
     // registers of the products allow at no cost in occupancy)
     constexpr int PB = F32 ? 2 : 4;
-    constexpr int BW = 4 * U;    // B row width
-    const GrpLayout L(cap, S.sp.M, S.sp.N, (int)sizeof(BT), U);
+    const GrpLayout L(cap, S.sp.M, S.sp.N, (int)sizeof(BT), U, BW);
     const int BN = S.sp.N + 1;   // row stride of the binomial table
     int32_t* rinf = reinterpret_cast<int32_t*>(smem + L.rinf_off);
     BT* bsh = reinterpret_cast<BT*>(smem + L.b_off);
@@ -209,23 +219,21 @@ __global__ __launch_bounds__(256, 3) void k_sigma_pair_grp(DevSpace S, const Grp
     const int nT = cap >> 4, nks = cap >> 2;
     const int kq = lane >> 4;     // A and B lanes: step within the 4-column group
     const int c16 = lane & 15;    // A lanes: row; B and output lanes: column
-    const int col = lane & 3;     // column within the intermediate's four
+    const int col = c16 % CW;     // column within the intermediate's CW
     int v, comp;
-    bool use;
     if constexpr (CPLX) {
         v = (NV == 2) ? (col & 1) : 0;
         comp = (NV == 2) ? (col >> 1) : col;
-        use = (NV == 2) ? true : col < 2;
     } else {
         v = col;
         comp = 0;
-        use = col < NV;
     }
     // lane's value of the complex product from C1 = Re(A) B and C2 = Im(A) B
+    // (the partner column, Im for Re and Re for Im, is lane ^ 2 or lane ^ 1)
     auto combine = [&](double c1, double c2) -> double {
         if constexpr (CPLX) {
             const double p = grp_quad_xor<NV == 2 ? 2 : 1>(c2);
-            return (col < (NV == 2 ? 2 : 1)) ? c1 - p : c1 + p;
+            return (col < NV) ? c1 - p : c1 + p;
         } else {
             (void)c2;
             return c1;
@@ -237,6 +245,11 @@ __global__ __launch_bounds__(256, 3) void k_sigma_pair_grp(DevSpace S, const Grp
         int64_t b = (kk <= nn) ? 1 : 0;
         for (int i = 1; i <= kk && kk <= nn; ++i) b = b * (nn - kk + i) / i;
         binom[t] = (int32_t)b;
+    }
+    // padding columns of B (past U CW) are written by no item: zero them once
+    if constexpr (BW > U * CW) {
+        constexpr int PW = BW - U * CW;
+        for (int t = threadIdx.x; t < cap * PW; t += blockDim.x) bsh[(t / PW) * BW + U * CW + t % PW] = (BT)0;
     }
     __syncthreads();
     // XCD-aware item order: workgroups are dealt round-robin to the 8 XCDs, so
@@ -309,23 +322,24 @@ __global__ __launch_bounds__(256, 3) void k_sigma_pair_grp(DevSpace S, const Grp
                     const int l = l0 + 64 * i + lane;
                     if (l >= cap) break;
                     const double sg = ng[i] ? -1.0 : 1.0;
-                    double b4[4] = {0.0, 0.0, 0.0, 0.0};
+                    double bc[CW];
+#pragma unroll
+                    for (int j = 0; j < CW; ++j) bc[j] = 0.0;
                     if (ok[i]) {
 #pragma unroll
                         for (int vv = 0; vv < NV; ++vv) {
                             if (vv >= n_vec) break;
                             nz = nz || V64::abs2(x[i][vv]) != 0.0;
                             if constexpr (CPLX) {
-                                // two vectors: [Re0, Re1, Im0, Im1]; one vector: [Re, Im, 0, 0]
-                                b4[NV == 2 ? vv : 0] = sg * x[i][vv].x;
-                                b4[NV == 2 ? 2 + vv : 1] = sg * x[i][vv].y;
+                                bc[vv] = sg * x[i][vv].x;
+                                bc[NV + vv] = sg * x[i][vv].y;
                             } else {
-                                b4[vv] = sg * x[i][vv];
+                                bc[vv] = sg * x[i][vv];
                             }
                         }
                     }
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) bsh[l * BW + 4 * u + j] = (BT)b4[j];
+                    for (int j = 0; j < CW; ++j) bsh[l * BW + CW * u + j] = (BT)bc[j];
                     const int64_t t = STORE ? addr[i] * nq + qq[i] : addr[i];
                     tgt[u * cap + l] = ok[i] ? (int32_t)((t << 1) | (ng[i] ? 1 : 0)) : -1;
                 }
@@ -401,15 +415,16 @@ __global__ __launch_bounds__(256, 3) void k_sigma_pair_grp(DevSpace S, const Grp
                 if (nfull < ngrp) round(nfull, true);
             }
             // output register i: row R * 16 + kq + 4 i (FP32: R * 16 + 4 kq + i),
-            // column c16 (intermediate c16 / 4)
+            // column 16 h + c16 (intermediate (16 h + c16) / CW; padding columns
+            // past U CW have none)
 #pragma unroll
             for (int h = 0; h < NG; ++h) {
-                const int u = 4 * h + (c16 >> 2);
+                const int u = (16 * h + c16) / CW;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const double val = combine((double)c1[h][i], (double)c2[h][i]);
                     const int l = R * 16 + (F32 ? 4 * kq + i : kq + 4 * i);
-                    if (u < n && use && v < n_vec && (STORE || any)) {
+                    if (u < n && v < n_vec && (STORE || any)) {
                         const int32_t tw = tgt[u * cap + l];
                         if (tw >= 0) {
                             const double x = (tw & 1) ? -val : val;
@@ -434,7 +449,7 @@ static hipError_t launch_grp_nv(const DevSpace& S, const GrpItem* items, int nit
     using TA = typename PT<CPLX, F32>::T;
     const int cap = grp_cap(S.sp);
     const int U = pair_grp_unit(S.sp);
-    const size_t lds = GrpLayout(cap, S.sp.M, S.sp.N, F32 ? 4 : 8, U).bytes;
+    const size_t lds = GrpLayout(cap, S.sp.M, S.sp.N, F32 ? 4 : 8, U, grp_bw(CPLX, NV, U)).bytes;
     // a multiple of 8 workgroups (one share per XCD), at most 16 per compute unit
     const int blocks = std::min(((nitems + 7) >> 3) << 3, 256 * 16);
     if (U == 8)

@@ -1,23 +1,27 @@
-// Grouped FP64 matrix-core form of the pair-resolved sigma build, for spaces
-// of one subspace (every determinant of N electrons in M spin-orbitals).
+// Grouped matrix-core form of the pair-resolved sigma build, for spaces of
+// one subspace (every determinant of N electrons in M spin-orbitals).
 //
 // There every (N-2)-electron intermediate K' couples to all pairs of its empty
-// orbitals, and its pair-pair block A_K' is A restricted to those pairs.  Four
+// orbitals, and its pair-pair block A_K' is A restricted to those pairs.  The
 // intermediates K'_u = K'' + o_u that share a core K'' (N-3 electrons) have
 // blocks inside one block A_K'' over the pairs of the core's empty orbitals
 // (the pairs of K'_u are the core pairs without o_u).  One workgroup of four
-// wavefronts takes such an item: the core pairs index the rows and columns of
-// A_K'', intermediate u owns the columns 4u..4u+3 of a 16-column right-hand side
-//   B[row, 4u + .] = [Re d_0, Re d_1, Im d_0, Im d_1] of K'_u at that pair (0 where the pair holds o_u),
-// and each 16 x 4 piece of A_K'' read from the table feeds one
-// v_mfma_f64_16x16x4f64 per real and imaginary part for all four: four times
-// the products per table read of the one-intermediate kernel, at 80 % useful
-// entries for 24 spin-orbitals and 8 electrons (the core has one more empty
-// orbital).  Lane layouts (checked on the device with an in-bounds probe): A
-// lane l holds row l % 16, step l / 16; B lane l holds step l / 16, column
-// l % 16; output register i of lane l holds row l / 16 + 4 i, column l % 16.
-// The complex combination and the scatter of each intermediate's rows follow
-// the one-intermediate kernel.
+// wavefronts takes an item of U such intermediates (U = 8, or 4 where the
+// slice of 8 would not fit): the core pairs index the rows and columns of
+// A_K'', intermediate u owns CW consecutive columns of the right-hand side B,
+//   complex: [Re d_0, Re d_1, Im d_0, Im d_1] (one vector: [Re d, Im d]), real: [d_0, d_1] (one vector: [d]),
+// at each core pair (0 where the pair holds o_u), the row of B padded to whole
+// 16-column groups, and each 16 x 4 piece of A_K'' read from the table feeds
+// one v_mfma_f64_16x16x4f64 per column group and real or imaginary part of
+// the table.  With two complex vectors that is 32 right-hand columns per table
+// read (4 in the one-intermediate kernel), at 80 % useful entries for 24
+// spin-orbitals and 8 electrons (the core has one more empty orbital).  Lane
+// layouts (checked on the device with in-bounds probes): A lane l holds row
+// l % 16, step l / 16; B lane l holds step l / 16, column l % 16; output
+// register i of lane l holds row l / 16 + 4 i, column l % 16 (FP64) or row
+// 4 (l / 16) + i (v_mfma_f32_16x16x4f32 of the FP32 form).  The complex
+// combination and the scatter of each intermediate's rows follow the
+// one-intermediate kernel.
 //
 // The slot arithmetic is plain bit arithmetic here: the target K'_u + {p, r}
 // is addressed by its colex rank (binomial table in LDS), the sign of
@@ -25,11 +29,11 @@
 // core pair costs one gather of c and no table chains.
 //
 // Items come from the host: cores in colex order take their intermediates
-// not yet placed four at a time; the few left over go by the core without
-// their lowest electron.  Each intermediate is in exactly one item.  Each XCD
-// works through a contiguous eighth of the items.  At 100 registers
-// (accumulators included; four wavefronts per SIMD) and 30 KB of LDS per
-// workgroup for 24 spin-orbitals, four workgroups share a compute unit.
+// not yet placed U at a time; the rest go by the core without their lowest
+// electron.  Each intermediate is in exactly one item.  Each XCD works through
+// a contiguous eighth of the items.  For 24 spin-orbitals the FP64 slice of
+// eight is 52 KB of LDS: three workgroups share a compute unit, and launch
+// bounds of three let the accumulators live in VGPRs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

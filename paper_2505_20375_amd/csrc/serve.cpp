@@ -102,11 +102,33 @@ static void release_stream(stpci_server* s, Req& q) {
 // FP32 or bfloat16 copies of the reduced-precision forms), the schedule of the row-tiled
 // fallback kernel where the tile kernel does not apply, and the Davidson
 // vectors and workspace.
+// Requests whose products take the context's own path instead of a grouped
+// launch: BF16 pair products, and spaces of one subspace (the grouped pair
+// kernel, FP64 or FP32, four or eight intermediates per item).
+static bool own_path(const stpci_ctx* c, const stpci_dav_opts& o) {
+    if (select_kernel(c) != 4) return false;
+    return o.precision == STPCI_BF16 || (o.precision != STPCI_BF16 && pair_grp_supported(c->hs.sp));
+}
+
+static int64_t store_bytes(const stpci_ctx* c) {
+    DevSpace tmp{};
+    tmp.sp = c->hs.sp;
+    return (int64_t)pair_store_bytes(tmp, c->cplx);
+}
+
 static int64_t footprint(const stpci_ctx* c, const stpci_dav_opts& o) {
     int64_t b = device_table_bytes(c, o.precision == STPCI_FP32) + dav_device_bytes(c, o);
-    if (o.precision == STPCI_BF16 && select_kernel(c) == 4) {  // the bfloat16 pair table
+    if (o.precision == STPCI_BF16 && select_kernel(c) == 4) {
         const int64_t npp = pair_mfma_npp(c->M * (c->M - 1) / 2);
-        b += npp * npp * (c->cplx ? 3 : 1) * 2;
+        b += npp * npp * (c->cplx ? 3 : 1) * 2;   // the bfloat16 pair table
+    }
+    if (own_path(c, o)) {
+        // the store-and-reduce workspace where it fits 1 GB (larger ones are
+        // sent to device atomics when the request is created), and the items
+        // of the grouped kernel (at most one per intermediate)
+        const int64_t eb = store_bytes(c);
+        if (eb <= ((int64_t)1 << 30)) b += eb;
+        if (o.precision != STPCI_BF16) b += c->hs.sp.npwork_dets * (int64_t)sizeof(GrpItem);
     }
     return b;
 }
@@ -165,6 +187,8 @@ stpci_status stpci_server_submit(stpci_server* s, const stpci_request* r, int* i
         q->ctx = nullptr;
         return srv_err(s, STPCI_EINVAL, "k must be in [1, min(16, n_dets)]");
     }
+    if (own_path(q->ctx, q->opts) && store_bytes(q->ctx) > ((int64_t)1 << 30))
+        (void)stpci_set_sigma_kernel(q->ctx, "pair_atomic");   // no workspace outside the footprint
     q->footprint = footprint(q->ctx, q->opts);
     if (q->footprint > s->budget) {
         stpci_destroy(q->ctx);
@@ -273,9 +297,10 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
         if (!dav_pending(q.ctx, &in, &out, &n, &prec)) continue;
         stpci_ctx* c = q.ctx;
         const bool f32 = prec == STPCI_FP32;
-        if (c->s2_kernel < 3 || prec == STPCI_BF16) {
-            // spaces outside the tile kernel's limits, and the BF16 contraction,
-            // take the context's own path
+        if (c->s2_kernel < 3 || prec == STPCI_BF16 || c->pair_grp) {
+            // spaces outside the tile kernel's limits, the BF16 contraction and
+            // spaces of one subspace (grouped intermediates) take the
+            // context's own path, on the request's stream
             stpci_status st = sigma_impl(c, in, out, n, prec);
             if (st) {
                 retire(s, q, st);

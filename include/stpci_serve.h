@@ -9,14 +9,21 @@
  *
  *  - stpci_server_submit copies a request's integrals and space, builds its
  *    host tables and computes its exact device footprint (tables, integrals,
- *    Davidson vectors and workspace).  Requests wait in FIFO order.
+ *    Davidson vectors and workspace; for requests whose products take the
+ *    request's own path also the store-and-reduce workspace where it fits
+ *    1 GB -- larger ones use device atomics -- and the item list of the
+ *    grouped kernel, counted as one item per intermediate).  Requests wait in
+ *    FIFO order.
  *  - stpci_server_tick admits waiting requests, oldest first, while fewer
  *    than max_active are active and their footprints fit mem_budget_bytes
  *    (admission stops at the first request that does not fit, so later ones
  *    never overtake it); then runs the pending sigma products of all active
  *    requests as grouped launches, one per (kernel family, scalar type,
  *    contraction precision) class, whose work items are the intermediate
- *    determinants of every request in the group; then advances each active request by one
+ *    determinants of every request in the group (requests of one subspace,
+ *    and BF16 contractions, run their own kernels on their own streams
+ *    instead: the grouped pair kernel, or the BF16 matrix-core kernel); then
+ *    advances each active request by one
  *    Davidson iteration and retires the finished ones, releasing their
  *    device memory.  A request's vectors stay on the device from admission
  *    to retirement.

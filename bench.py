@@ -128,8 +128,9 @@ def main():
     avg2 = t2 / max(n2, 1)
     achieved = flops / (avg2 * 1e-3) / 1e12
     achieved_paper = flops_paper / (avg2 * 1e-3) / 1e12
-    kdesc = {"pair_grp": "k_sigma_pair_grp (one pass: pair-resolved 1e + 2e sigma, four intermediates per "
-                         "(N-3)-electron core, FP64 matrix cores, v_mfma_f64_16x16x4f64)",
+    unit = ctx.test_pair_groups()[2] if kname.startswith("pair_grp") else 0
+    kdesc = {"pair_grp": "k_sigma_pair_grp (one pass: pair-resolved 1e + 2e sigma, %d intermediates per "
+                         "(N-3)-electron core, FP64 matrix cores, v_mfma_f64_16x16x4f64)" % unit,
              "pair_mf64": "k_sigma_pair_mf64 (one pass: pair-resolved 1e + 2e sigma, FP64 matrix cores, "
                           "v_mfma_f64_4x4x4f64)",
              "pair_valu": "k_sigma_pair (one pass: pair-resolved 1e + 2e sigma, FP64 vector ALUs)"}

@@ -200,7 +200,7 @@ stpci_status prepare(stpci_ctx* c) {
         const bool auto_unit = c->kernel_req < 0 || c->kernel_req == 4 || c->kernel_req == 5;
         c->pair_mf64 = pair_mf64_supported(H.sp.N, H.pmax_deg) &&
                        (c->kernel_req == 6 || (auto_unit && table <= ((size_t)4 << 20)));
-        // spaces of one subspace: four intermediates per table read
+        // spaces of one subspace: eight (or four) intermediates per table read
         c->pair_grp = false;
         c->grp_items.clear();
         // (the grouped kernel keeps targets as 32-bit words: target << 1 | sign)

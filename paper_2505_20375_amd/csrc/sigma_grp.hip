@@ -264,7 +264,8 @@ __global__ __launch_bounds__(256, 3) void k_sigma_pair_grp(DevSpace S, const Grp
     const int xcd = blockIdx.x & 7, nloc = gridDim.x >> 3;
     const int chunk = (nitems + 7) >> 3;
     const int it_end = min(nitems, (xcd + 1) * chunk);
-    for (int it = xcd * chunk + (int)(blockIdx.x >> 3); it < it_end; it += nloc) {
+    int turn = (int)(blockIdx.x >> 3);   // rotation of the row tiles over the wavefronts
+    for (int it = xcd * chunk + (int)(blockIdx.x >> 3); it < it_end; it += nloc, ++turn) {
         const uint32_t core = items[it].core;
         const int n = items[it].n;
         const uint64_t emp = ~(uint64_t)core & full;
@@ -354,8 +355,10 @@ __global__ __launch_bounds__(256, 3) void k_sigma_pair_grp(DevSpace S, const Grp
         __syncthreads();
         const bool any = (flags[0] | flags[1] | flags[2] | flags[3]) != 0;
 
-        // ---- phases 2 and 3: 16-row tiles of A_K'' split over the wavefronts
-        for (int R = wid; R < nT; R += 4) {
+        // ---- phases 2 and 3: 16-row tiles of A_K'' split over the wavefronts;
+        // the first tile of a wavefront turns with the item, so that the short
+        // shares (nT not a multiple of 4) fall on each SIMD in turn
+        for (int R = (wid + turn) & 3; R < nT; R += 4) {
             // one accumulator per real product: consecutive steps alternate between
             // the two, which keeps a dependent pair two instructions apart
             ACC c1[NG], c2[NG];

@@ -150,12 +150,12 @@ __global__ __launch_bounds__(256) void k_sigma_pair(DevSpace S, const typename P
 }
 
 // sigma[v][L] = e_core c[v][L] + sum_q E[(L * nq + q) * NV + v]: the pair
-// contributions of every target, summed in a fixed order.  Four lanes share a
-// target: lane g adds entries g, g + 4, ... of its nq * NV contiguous
-// entries (so every read instruction covers 64 contiguous bytes per target),
-// then the lanes holding the same vector (g mod NV) are combined by a fixed
-// butterfly.
-constexpr int PR_LANES = 4;
+// contributions of every target, summed in a fixed order.  Eight lanes share
+// a target: lane g adds entries g, g + 8, ... of its nq * NV contiguous
+// entries (so every read instruction covers 128 contiguous bytes per complex
+// target), then the lanes holding the same vector (g mod NV) are combined by
+// a fixed butterfly.
+constexpr int PR_LANES = 8;
 template <bool CPLX, int NV>
 __global__ __launch_bounds__(256) void k_pair_reduce(typename VT<CPLX>::T* __restrict__ sigma,
                                                     const typename VT<CPLX>::T* __restrict__ c,
@@ -167,14 +167,28 @@ __global__ __launch_bounds__(256) void k_pair_reduce(typename VT<CPLX>::T* __res
     const int g = threadIdx.x & (PR_LANES - 1);
     const int per = nq * NV;
     const int64_t step = (int64_t)gridDim.x * (blockDim.x / PR_LANES);
-    // L is equal on the four lanes of a group, so groups enter and leave the
+    // L is equal on the eight lanes of a group, so groups enter and leave the
     // loop together and the shuffles stay inside active groups
     for (int64_t L = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / PR_LANES; L < nd; L += step) {
         TE acc = V64::zero();
         const TE* e = E + L * per;
-        for (int f = g; f < per; f += PR_LANES) acc = V64::add(acc, e[f]);
+        // eight reads in flight per lane, added in the same order as one by one
+        constexpr int PR_BATCH = 8;
+        for (int f = g; f < per; f += PR_BATCH * PR_LANES) {
+            TE x[PR_BATCH];
+#pragma unroll
+            for (int k = 0; k < PR_BATCH; ++k)
+                if (f + k * PR_LANES < per) x[k] = e[f + k * PR_LANES];
+#pragma unroll
+            for (int k = 0; k < PR_BATCH; ++k)
+                if (f + k * PR_LANES < per) acc = V64::add(acc, x[k]);
+        }
         for (int m = NV; m < PR_LANES; m <<= 1) acc = V64::add(acc, V64::shfl_xor(acc, m));
-        if (g < NV && g < n_vec) sigma[(int64_t)g * nd + L] = V64::add(V64::scale(c[(int64_t)g * nd + L], e_core), acc);
+        if (g < NV && g < n_vec) {
+            // e_core = 0 (the usual case) skips the read of c
+            const TE base = e_core != 0.0 ? V64::scale(c[(int64_t)g * nd + L], e_core) : V64::zero();
+            sigma[(int64_t)g * nd + L] = V64::add(base, acc);
+        }
     }
 }
 

@@ -118,21 +118,21 @@ __device__ __forceinline__ double diag_elem(const DevSpace& S, const double* __r
     const Cat& A = S.cats[a];
     Det d;
     decode(S, A, L - A.offset, d);
-    int occ[MMAX];
-    int n = 0;
-    for (int k = 0; k < S.sp.K; ++k) {
-        uint32_t s = d.s[k];
-        while (s) {
-            occ[n++] = S.sp.sub_off[k] + __builtin_ctz(s);
-            s &= s - 1u;
-        }
-    }
+    // occupied spin-orbitals as one mask (subspaces are contiguous, so the
+    // bits ascend with the global index); walked in ascending order without
+    // an index list, which would live in scratch memory
+    uint64_t occ = 0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+        if (k < S.sp.K) occ |= (uint64_t)d.s[k] << S.sp.sub_off[k];
     const int M = S.sp.M;
     double e = e_core;
-    for (int i = 0; i < n; ++i) {
-        e += hd[occ[i]];
-        const double* row = JK + occ[i] * M;
-        for (int j = i + 1; j < n; ++j) e += row[occ[j]];
+    for (uint64_t a = occ; a; ) {
+        const int i = __builtin_ctzll(a);
+        a &= a - 1;
+        e += hd[i];
+        const double* row = JK + i * M;
+        for (uint64_t b = a; b; b &= b - 1) e += row[__builtin_ctzll(b)];
     }
     return e;
 }
@@ -347,22 +347,39 @@ __global__ __launch_bounds__(256) void k_combine(const typename VT<CPLX>::T* __r
                                                  const double* __restrict__ theta,
                                                  typename VT<CPLX>::T* __restrict__ X,
                                                  typename VT<CPLX>::T* __restrict__ R, int64_t n, int mode) {
-    // mode 0: X = A Y ; mode 1: X = A Y, R = B Y - X theta ; mode 2: X -= A Y (Y: m x 1)
+    // mode 0: X = A Y ; mode 1: X = A Y, R = B Y - X theta ; mode 2: X -= A Y (Y: m x k)
+    // Up to CB output columns per pass over A (and B), so that each element of
+    // A is read once per CB columns; every sum runs over i in ascending order.
     using V = VT<CPLX>;
     using T = typename V::T;
+    constexpr int CB = 4;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        for (int j = 0; j < k; ++j) {
-            T xs = V::zero(), rs = V::zero();
+        for (int j0 = 0; j0 < k; j0 += CB) {
+            T xs[CB], rs[CB];
+#pragma unroll
+            for (int jj = 0; jj < CB; ++jj) xs[jj] = rs[jj] = V::zero();
+#pragma unroll 4
             for (int i = 0; i < m; ++i) {
-                T y = Y[i * k + j];
-                xs = V::mad(A[(int64_t)i * ld + e], y, xs);
-                if (mode == 1) rs = V::mad(B[(int64_t)i * ld + e], y, rs);
+                const T a = A[(int64_t)i * ld + e];
+                const T b = (mode == 1) ? B[(int64_t)i * ld + e] : V::zero();
+#pragma unroll
+                for (int jj = 0; jj < CB; ++jj)
+                    if (j0 + jj < k) {
+                        const T y = Y[i * k + j0 + jj];
+                        xs[jj] = V::mad(a, y, xs[jj]);
+                        if (mode == 1) rs[jj] = V::mad(b, y, rs[jj]);
+                    }
             }
-            if (mode == 2) {
-                X[(int64_t)j * ld + e] = V::sub(X[(int64_t)j * ld + e], xs);
-            } else {
-                X[(int64_t)j * ld + e] = xs;
-                if (mode == 1) R[(int64_t)j * ld + e] = V::sub(rs, V::scale(xs, theta[j]));
+#pragma unroll
+            for (int jj = 0; jj < CB; ++jj) {
+                const int j = j0 + jj;
+                if (j >= k) break;
+                if (mode == 2) {
+                    X[(int64_t)j * ld + e] = V::sub(X[(int64_t)j * ld + e], xs[jj]);
+                } else {
+                    X[(int64_t)j * ld + e] = xs[jj];
+                    if (mode == 1) R[(int64_t)j * ld + e] = V::sub(rs[jj], V::scale(xs[jj], theta[j]));
+                }
             }
         }
     }

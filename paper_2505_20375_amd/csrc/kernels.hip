@@ -230,17 +230,31 @@ __global__ __launch_bounds__(256) void k_dots(const typename VT<CPLX>::T* __rest
     for (int t = 0; t < DOTW; ++t)
 #pragma unroll
         for (int i = 0; i < DOTV; ++i) acc[t][i] = V::zero();
-    for (int64_t e = blockIdx.y * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.y * blockDim.x) {
-        T wv[DOTW];
+    // DOTE elements per trip (stride apart), all read before any is added;
+    // the sums still take the elements in the order of one per trip
+    constexpr int DOTE = 2;
+    const int64_t stride = (int64_t)gridDim.y * blockDim.x;
+    for (int64_t e0 = blockIdx.y * (int64_t)blockDim.x + threadIdx.x; e0 < n; e0 += DOTE * stride) {
+        T wv[DOTE][DOTW], a[DOTE][DOTV];
 #pragma unroll
-        for (int t = 0; t < DOTW; ++t) wv[t] = (t0 + t < nw) ? W[(int64_t)(t0 + t) * ld + e] : V::zero();
+        for (int u = 0; u < DOTE; ++u) {
+            const int64_t e = e0 + u * stride;
+            const bool in = e < n;
 #pragma unroll
-        for (int i = 0; i < DOTV; ++i)
-            if (i0 + i < m) {
-                const T a = Vb[(int64_t)(i0 + i) * ld + e];
+            for (int t = 0; t < DOTW; ++t) wv[u][t] = (in && t0 + t < nw) ? W[(int64_t)(t0 + t) * ld + e] : V::zero();
 #pragma unroll
-                for (int t = 0; t < DOTW; ++t) acc[t][i] = V::cmad(a, wv[t], acc[t][i]);
-            }
+            for (int i = 0; i < DOTV; ++i) a[u][i] = (in && i0 + i < m) ? Vb[(int64_t)(i0 + i) * ld + e] : V::zero();
+        }
+#pragma unroll
+        for (int u = 0; u < DOTE; ++u) {
+            if (e0 + u * stride >= n) break;
+#pragma unroll
+            for (int i = 0; i < DOTV; ++i)
+                if (i0 + i < m) {
+#pragma unroll
+                    for (int t = 0; t < DOTW; ++t) acc[t][i] = V::cmad(a[u][i], wv[u][t], acc[t][i]);
+                }
+        }
     }
     // wavefront sums (fixed butterfly), then the 4 wavefronts in order
     __shared__ T red[4][DOTW * DOTV];

@@ -204,6 +204,25 @@ struct Dav {
         return hip(launch_dots(cx, A, N, m, W, nw, N, c->d_partial.p, small, st), "dots");
     }
 
+    // <A_j | W_j> for j < n (A, W: n consecutive vectors each), two roots per
+    // launch: the launch for j0, j0 + 1 queues the 2 x 2 block of products at
+    // off + 2 j0, whose diagonal holds the two wanted values (the same sums,
+    // bit for bit, as one launch per root); pair_slots(n) slots in all
+    static int pair_slots(int n) { return 4 * (n / 2) + (n & 1); }
+    static int pair_slot(int j, int n) {
+        const int j0 = j & ~1, c = std::min(2, n - j0);
+        return 2 * j0 + (j - j0) * (c + 1);
+    }
+    stpci_status issue_pair_dots(char* A, char* W, int n, int off) {
+        for (int j0 = 0; j0 < n; j0 += 2) {
+            const int cnt = std::min(2, n - j0);
+            const size_t at = (size_t)j0 * N * sb;
+            stpci_status s = issue_dots(A + at, cnt, W + at, cnt, off + 2 * j0);
+            if (s) return s;
+        }
+        return STPCI_OK;
+    }
+
     // fetch the first `count` queued dot products (one round trip); with dc,
     // also the first dc->size() Ritz coefficient changes in the same copy
     stpci_status fetch(int count, std::vector<cplx>& out, std::vector<double>* dc = nullptr) {
@@ -437,20 +456,19 @@ static stpci_status dav_advance(stpci_ctx* c) {
     {
         // residual norms and, from the second iteration, the overlaps
         // <x_j(previous) | x_j> that phase-align the change of each Ritz vector
-        for (int j = 0; j < k; ++j)
-            if ((s = d.issue_dots(d.vec(c->d_R, j), 1, d.vec(c->d_R, j), 1, j))) return s;
+        const int nps = Dav::pair_slots(k);
+        if ((s = d.issue_pair_dots(d.vec(c->d_R, 0), d.vec(c->d_R, 0), k, 0))) return s;
         if (D.have_xp)
-            for (int j = 0; j < k; ++j)
-                if ((s = d.issue_dots(d.vec(c->d_Xp, j), 1, d.vec(c->d_X, j), 1, k + j))) return s;
+            if ((s = d.issue_pair_dots(d.vec(c->d_Xp, 0), d.vec(c->d_X, 0), k, nps))) return s;
         std::vector<cplx> r2;
-        if ((s = d.fetch(D.have_xp ? 2 * k : k, r2))) return s;
-        for (int j = 0; j < k; ++j) D.rn[j] = std::sqrt(std::max(0.0, r2[j].real()));
+        if ((s = d.fetch(D.have_xp ? 2 * nps : nps, r2))) return s;
+        for (int j = 0; j < k; ++j) D.rn[j] = std::sqrt(std::max(0.0, r2[Dav::pair_slot(j, k)].real()));
         if (D.have_xp) {
             // max |x_j - ph_j x_j(previous)|, ph_j = <x_prev|x>/|<x_prev|x>| (Results: the
             // largest coefficient change reported per iteration beside E and ||r||)
             // (fetched with the next round trip's dot products)
             for (int j = 0; j < k; ++j) {
-                const cplx o = r2[k + j];
+                const cplx o = r2[nps + Dav::pair_slot(j, k)];
                 const double a = std::abs(o);
                 const cplx ph = a > 0 ? o / a : cplx(1.0, 0.0);
                 double* out = (double*)((char*)c->d_small.p + kDcOff) + (size_t)j * (d.cx ? 2 : 1);
@@ -541,10 +559,12 @@ static stpci_status dav_advance(stpci_ctx* c) {
         // norms before orthogonalisation and the first pass's projections in
         // one round trip (with the pending coefficient changes)
         std::vector<cplx> n0v;
-        for (int t = 0; t < nt; ++t)
-            if ((s = d.issue_dots(d.vec(c->d_T, t), 1, d.vec(c->d_T, t), 1, t))) return s;
+        // (pair_slots(nt) + nt mm <= nt (2 + mm) <= nt mmax: within the
+        // dot-product area for nt <= 16, mmax <= 64)
+        const int nts = Dav::pair_slots(nt);
+        if ((s = d.issue_pair_dots(d.vec(c->d_T, 0), d.vec(c->d_T, 0), nt, 0))) return s;
         for (int pass = 0; pass < 2; ++pass) {
-            const int off = pass == 0 ? nt : 0;
+            const int off = pass == 0 ? nts : 0;
             if ((s = d.issue_dots(c->d_V.p, mm, c->d_T.p, nt, off))) return s;
             std::vector<cplx> got;
             if ((s = d.fetch(off + nt * mm, got, dc_pending ? &dc : nullptr))) return s;
@@ -552,7 +572,10 @@ static stpci_status dav_advance(stpci_ctx* c) {
                 c->history.back().dc = dc;
                 dc_pending = false;
             }
-            if (pass == 0) n0v.assign(got.begin(), got.begin() + nt);
+            if (pass == 0) {
+                n0v.resize(nt);
+                for (int t = 0; t < nt; ++t) n0v[t] = got[Dav::pair_slot(t, nt)];
+            }
             const std::vector<cplx> coef(got.begin() + off, got.end());
             if ((s = d.subtract_block(c->d_V.p, mm, coef, nt, c->d_T.p))) return s;
         }

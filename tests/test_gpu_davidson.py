@@ -11,7 +11,7 @@ from tests.gpu_util import Problem, rel_err
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("name,k", [("T3", 2), ("T4", 3), ("T8", 2), ("c1", 1)])
+@pytest.mark.parametrize("name,k", [("T3", 2), ("T4", 3), ("T4", 5), ("T8", 2), ("c1", 1)])
 def test_davidson_matches_dense_eigh(name, k):
     print("case", name, k, flush=True)
     pb = Problem.named(name)

@@ -258,16 +258,11 @@ struct Dav {
                    "cgs");
     }
 
-    // X_t <- X_t - sum_i A_i coef[t m + i] for t < nx (X_t consecutive vectors)
-    stpci_status subtract_block(const void* A, int m, const std::vector<cplx>& coef, int nx, void* X) {
-        std::vector<cplx> Y((size_t)m * nx);  // row-major m x nx
-        for (int t = 0; t < nx; ++t)
-            for (int i = 0; i < m; ++i) Y[(size_t)i * nx + t] = coef[(size_t)t * m + i];
-        stpci_status s = put_small(Y, kYOff);
-        if (s) return s;
-        return hip(launch_combine(cx, A, nullptr, N, m, (char*)c->d_small.p + kYOff, nx, nullptr, X, nullptr, N, 2,
-                                  st),
-                   "cgs");
+    // X_t -= sum_i A_i <A_i | X_t> for t < nx, the products queued by
+    // issue_dots(A, m, X, nx, off) and read where they lie (no round trip)
+    stpci_status subtract_queued(const void* A, int m, int off, int nx, void* X) {
+        const char* coef = (const char*)c->d_small.p + kDotsOff + (size_t)off * (cx ? 16 : 8);
+        return hip(launch_combine(cx, A, nullptr, N, m, coef, nx, nullptr, X, nullptr, N, 3, st), "cgs");
     }
 };
 
@@ -556,28 +551,19 @@ static stpci_status dav_advance(stpci_ctx* c) {
     // (linear dependence) and is dropped
     int added = 0;
     if (nt > 0) {
-        // norms before orthogonalisation and the first pass's projections in
-        // one round trip (with the pending coefficient changes)
+        // the two Gram-Schmidt passes run without a round trip; the norms
+        // before orthogonalisation come back with the first Cholesky QR
+        // Gram matrix
         std::vector<cplx> n0v;
-        // (pair_slots(nt) + nt mm <= nt (2 + mm) <= nt mmax: within the
-        // dot-product area for nt <= 16, mmax <= 64)
+        // norms before orthogonalisation at slots [0, nts); each pass's
+        // projections at slot nts, where the combination reads them
+        // (nts + nt mm <= nt (2 + mm) <= nt mmax: within the dot-product area
+        // for nt <= 16, mmax <= 64)
         const int nts = Dav::pair_slots(nt);
         if ((s = d.issue_pair_dots(d.vec(c->d_T, 0), d.vec(c->d_T, 0), nt, 0))) return s;
         for (int pass = 0; pass < 2; ++pass) {
-            const int off = pass == 0 ? nts : 0;
-            if ((s = d.issue_dots(c->d_V.p, mm, c->d_T.p, nt, off))) return s;
-            std::vector<cplx> got;
-            if ((s = d.fetch(off + nt * mm, got, dc_pending ? &dc : nullptr))) return s;
-            if (dc_pending) {
-                c->history.back().dc = dc;
-                dc_pending = false;
-            }
-            if (pass == 0) {
-                n0v.resize(nt);
-                for (int t = 0; t < nt; ++t) n0v[t] = got[Dav::pair_slot(t, nt)];
-            }
-            const std::vector<cplx> coef(got.begin() + off, got.end());
-            if ((s = d.subtract_block(c->d_V.p, mm, coef, nt, c->d_T.p))) return s;
+            if ((s = d.issue_dots(c->d_V.p, mm, c->d_T.p, nt, nts))) return s;
+            if ((s = d.subtract_queued(c->d_V.p, mm, nts, nt, c->d_T.p))) return s;
         }
         // Cholesky QR: T_keep = Q R, Q = T R^-1 written to V[mm..] (first pass)
         // and re-orthonormalised in place through T (second pass)
@@ -587,9 +573,22 @@ static stpci_status dav_advance(stpci_ctx* c) {
             void* src = (qr == 0) ? c->d_T.p : d.vec(c->d_V, mm);
             const int ns = (qr == 0) ? nt : (int)keep.size();
             if (ns == 0) break;
-            if ((s = d.issue_dots(src, ns, src, ns, 0))) return s;
-            std::vector<cplx> Gm;  // Gm[t * ns + i] = <src_i | src_t>
-            if ((s = d.fetch(ns * ns, Gm))) return s;
+            // the first Gram matrix comes behind the norms before
+            // orthogonalisation, in one round trip with the pending
+            // coefficient changes
+            const int goff = (qr == 0) ? nts : 0;
+            if ((s = d.issue_dots(src, ns, src, ns, goff))) return s;
+            std::vector<cplx> got;
+            if ((s = d.fetch(goff + ns * ns, got, (qr == 0 && dc_pending) ? &dc : nullptr))) return s;
+            if (qr == 0) {
+                if (dc_pending) {
+                    c->history.back().dc = dc;
+                    dc_pending = false;
+                }
+                n0v.resize(nt);
+                for (int t = 0; t < nt; ++t) n0v[t] = got[Dav::pair_slot(t, nt)];
+            }
+            const std::vector<cplx> Gm(got.begin() + goff, got.end());  // Gm[t * ns + i] = <src_i | src_t>
             std::vector<cplx> R((size_t)ns * ns, cplx(0, 0));
             std::vector<int> kept;
             for (int t = 0; t < ns; ++t) {

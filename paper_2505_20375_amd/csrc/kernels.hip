@@ -361,7 +361,8 @@ __global__ __launch_bounds__(256) void k_combine(const typename VT<CPLX>::T* __r
                                                  const double* __restrict__ theta,
                                                  typename VT<CPLX>::T* __restrict__ X,
                                                  typename VT<CPLX>::T* __restrict__ R, int64_t n, int mode) {
-    // mode 0: X = A Y ; mode 1: X = A Y, R = B Y - X theta ; mode 2: X -= A Y (Y: m x k)
+    // mode 0: X = A Y ; mode 1: X = A Y, R = B Y - X theta ; mode 2: X -= A Y (Y: m x k, row-major)
+    // mode 3: X -= A Y with Y stored column by column (Y[j m + i], as the dot products lie)
     // Up to CB output columns per pass over A (and B), so that each element of
     // A is read once per CB columns; every sum runs over i in ascending order.
     using V = VT<CPLX>;
@@ -379,7 +380,7 @@ __global__ __launch_bounds__(256) void k_combine(const typename VT<CPLX>::T* __r
 #pragma unroll
                 for (int jj = 0; jj < CB; ++jj)
                     if (j0 + jj < k) {
-                        const T y = Y[i * k + j0 + jj];
+                        const T y = (mode == 3) ? Y[(j0 + jj) * m + i] : Y[i * k + j0 + jj];
                         xs[jj] = V::mad(a, y, xs[jj]);
                         if (mode == 1) rs[jj] = V::mad(b, y, rs[jj]);
                     }
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(256) void k_combine(const typename VT<CPLX>::T* __r
             for (int jj = 0; jj < CB; ++jj) {
                 const int j = j0 + jj;
                 if (j >= k) break;
-                if (mode == 2) {
+                if (mode >= 2) {
                     X[(int64_t)j * ld + e] = V::sub(X[(int64_t)j * ld + e], xs[jj]);
                 } else {
                     X[(int64_t)j * ld + e] = xs[jj];

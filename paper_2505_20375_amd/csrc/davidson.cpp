@@ -551,14 +551,12 @@ static stpci_status dav_advance(stpci_ctx* c) {
     // (linear dependence) and is dropped
     int added = 0;
     if (nt > 0) {
-        // the two Gram-Schmidt passes run without a round trip; the norms
-        // before orthogonalisation come back with the first Cholesky QR
-        // Gram matrix
+        // the two Gram-Schmidt passes run without a round trip: the norms
+        // before orthogonalisation go to slots [0, nts) (fetched with the
+        // first Cholesky QR Gram matrix), each pass's projections to slot
+        // nts, where the combination reads them (nts + nt mm <= nt (2 + mm)
+        // <= nt mmax: within the dot-product area for nt <= 16, mmax <= 64)
         std::vector<cplx> n0v;
-        // norms before orthogonalisation at slots [0, nts); each pass's
-        // projections at slot nts, where the combination reads them
-        // (nts + nt mm <= nt (2 + mm) <= nt mmax: within the dot-product area
-        // for nt <= 16, mmax <= 64)
         const int nts = Dav::pair_slots(nt);
         if ((s = d.issue_pair_dots(d.vec(c->d_T, 0), d.vec(c->d_T, 0), nt, 0))) return s;
         for (int pass = 0; pass < 2; ++pass) {

@@ -46,6 +46,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--serve", type=int, default=48, help="requests in the serving run (0: skip)")
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse-vector sigma timings")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the measured GEMM and copy reference rates")
     ap.add_argument("--serve-max-dets", type=int, default=300000)
     ap.add_argument("--serve-rate", type=float, default=40.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--copy-calib-mb", type=float, default=0.0,
@@ -254,6 +255,8 @@ def main():
             prec["solve_speedup" + ("" if pname == "mixed" else "_bf16")] = res["solve"]["p50_ms"] / sol["p50_ms"]
             prec["energy_diff_eh" + ("" if pname == "mixed" else "_bf16")] = max(
                 abs(a - b) for a, b in zip(sol["energies"], res["solve"]["energies"]))
+    if not args.no_peaks:
+        res["measured_peaks"] = _measured_peaks(res["roofline"])
     if args.serve > 0:
         del ctx
         res["serving"] = _serve(args.serve, args.serve_max_dets, args.serve_rate)
@@ -400,6 +403,44 @@ def _serve(nreq, max_dets, rate):
                        "electrons, 1-4 roots, %d-%d determinants (scaled down from 512 requests of up to 1e8)"
                        % (nreq, rate, min(d["n_dets"] for d in descs), max(d["n_dets"] for d in descs)))
     out["tol_residual"] = 1e-5
+    return out
+
+
+def _measured_peaks(roof):
+    """Reference rates measured on this device beside the published peaks
+    the roofline uses: FP64 and complex FP64 library GEMMs (torch.matmul,
+    which calls the ROCm BLAS) and a 1 GiB device-to-device copy."""
+    import torch
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    g = torch.Generator(device="cuda").manual_seed(7)
+    out = {}
+    for name, dt, n, fl in (("dgemm", torch.float64, 8192, 2.0), ("zgemm", torch.complex128, 4096, 8.0)):
+        a = torch.randn(n, n, dtype=dt, device="cuda", generator=g)
+        b = torch.randn(n, n, dtype=dt, device="cuda", generator=g)
+        c = torch.empty_like(a)
+        t = timed(lambda: torch.matmul(a, b, out=c), 5)
+        out[name + "_tflops"] = round(fl * n ** 3 / t / 1e12, 3)
+        out[name + "_size"] = n
+        del a, b, c
+    nb = 1 << 30
+    src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    t = timed(lambda: dst.copy_(src), 10)
+    out["copy_gbs"] = round(2.0 * nb / t / 1e9, 1)
+    del src, dst
+    out["sigma_frac_of_dgemm"] = round(roof["achieved"] / out["dgemm_tflops"], 4)
+    out["sigma_frac_of_zgemm"] = round(roof["achieved"] / out["zgemm_tflops"], 4)
     return out
 
 

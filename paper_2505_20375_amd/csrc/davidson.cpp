@@ -510,15 +510,20 @@ static stpci_status dav_advance(stpci_ctx* c) {
         return fetch_dc();
     }
     // corrections for unconverged roots (Eq. sparsePreconditioner, eps = 0)
-    int nt = 0;
+    // (one launch for all of them; k <= 16)
+    std::vector<int> proots;
+    std::vector<double> pthetas;
     for (int j = 0; j < k; ++j) {
         if (D.rn[j] <= D.tol) continue;
-        if ((s = d.hip(launch_precond(c->dev, d.cx, (const double*)c->d_hd.p, (const double*)c->d_JK.p, c->e_core,
-                                      d.vec(c->d_R, j), d.vec(c->d_T, nt), D.theta[j], 1e-12, c->stream),
-                       "precond")))
-            return s;
-        ++nt;
+        proots.push_back(j);
+        pthetas.push_back(D.theta[j]);
     }
+    const int nt = (int)proots.size();
+    if ((s = d.hip(launch_precond(c->dev, d.cx, (const double*)c->d_hd.p, (const double*)c->d_JK.p, c->e_core,
+                                  d.vec(c->d_R, 0), d.vec(c->d_T, 0), N, nt, proots.data(), pthetas.data(), 1e-12,
+                                  c->stream),
+                   "precond")))
+        return s;
     int mm = m;
     // thick restart when the space would overflow: keep the kr lowest Ritz
     // vectors (V <- V Y_kr, W <- W Y_kr, G <- diag(theta_kr))

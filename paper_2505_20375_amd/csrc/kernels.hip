@@ -144,18 +144,31 @@ __global__ __launch_bounds__(256) void k_diag(DevSpace S, const double* hd, cons
         out[L] = diag_elem(S, hd, JK, e_core, L);
 }
 
-// Davidson preconditioner (Eq. sparsePreconditioner with eps = 0):
-//   t_i = r_i / (theta - H_ii) if |theta - H_ii| >= guard, else 0.
+// Davidson preconditioner (Eq. sparsePreconditioner with eps = 0), for
+// several roots at once (the diagonal element is formed once per determinant):
+//   t_q,i = r_root(q),i / (theta_q - H_ii) if |theta_q - H_ii| >= guard, else 0.
+struct PrecondRoots {
+    int n;
+    int root[PRE_MAX];
+    double theta[PRE_MAX];
+};
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_precond(DevSpace S, const double* hd, const double* JK, double e_core,
                                                  const typename VT<CPLX>::T* __restrict__ r,
-                                                 typename VT<CPLX>::T* __restrict__ t, double theta,
+                                                 typename VT<CPLX>::T* __restrict__ t, int64_t ld, PrecondRoots P,
                                                  double guard) {
     using V = VT<CPLX>;
     for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < S.sp.ndets;
          L += (int64_t)gridDim.x * blockDim.x) {
-        double den = theta - diag_elem(S, hd, JK, e_core, L);
-        t[L] = (fabs(den) >= guard) ? V::scale(r[L], 1.0 / den) : V::zero();
+        const double h = diag_elem(S, hd, JK, e_core, L);
+        // (a fixed trip count: the argument arrays are indexed by constants)
+#pragma unroll
+        for (int q = 0; q < PRE_MAX; ++q) {
+            if (q >= P.n) break;
+            const double den = P.theta[q] - h;
+            t[(int64_t)q * ld + L] =
+                (fabs(den) >= guard) ? V::scale(r[(int64_t)P.root[q] * ld + L], 1.0 / den) : V::zero();
+        }
     }
 }
 
@@ -494,14 +507,23 @@ hipError_t launch_diag(const DevSpace& S, const double* hd, const double* JK, do
 }
 
 hipError_t launch_precond(const DevSpace& S, bool cplx, const double* hd, const double* JK, double e_core,
-                          const void* r, void* t, double theta, double guard, hipStream_t st) {
+                          const void* r, void* t, int64_t ld, int n, const int* root, const double* theta,
+                          double guard, hipStream_t st) {
+    if (n < 1) return hipSuccess;
+    if (n > PRE_MAX) return hipErrorInvalidValue;
+    PrecondRoots P{};
+    P.n = n;
+    for (int q = 0; q < n; ++q) {
+        P.root[q] = root[q];
+        P.theta[q] = theta[q];
+    }
     int g = grid_for(S.sp.ndets, 256);
     if (cplx)
         hipLaunchKernelGGL(k_precond<true>, dim3(g), dim3(256), 0, st, S, hd, JK, e_core, (const cd*)r, (cd*)t,
-                           theta, guard);
+                           ld, P, guard);
     else
         hipLaunchKernelGGL(k_precond<false>, dim3(g), dim3(256), 0, st, S, hd, JK, e_core, (const double*)r,
-                           (double*)t, theta, guard);
+                           (double*)t, ld, P, guard);
     return hipGetLastError();
 }
 

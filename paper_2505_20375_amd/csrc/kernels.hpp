@@ -87,8 +87,12 @@ hipError_t launch_sigma_multi(const SigmaDesc* desc_dev, int ndesc, const int64_
                               int deg_max, bool cplx, bool f32, hipStream_t st);
 hipError_t launch_diag(const DevSpace& S, const double* hd, const double* JK, double e_core, double* out,
                        hipStream_t st);
+// t_q = r_{root[q]} / (theta[q] - H_ii) (0 where |theta[q] - H_ii| < guard)
+// for q < n <= PRE_MAX; r and t hold consecutive vectors of ld scalars
+constexpr int PRE_MAX = 16;
 hipError_t launch_precond(const DevSpace& S, bool cplx, const double* hd, const double* JK, double e_core,
-                          const void* r, void* t, double theta, double guard, hipStream_t st);
+                          const void* r, void* t, int64_t ld, int n, const int* root, const double* theta,
+                          double guard, hipStream_t st);
 int topk_blocks(const DevSpace& S);
 hipError_t launch_diag_topk(const DevSpace& S, const double* hd, const double* JK, double e_core, int k,
                             double* vals, int64_t* idx, hipStream_t st);

@@ -45,6 +45,21 @@ stpci_status stpci_test_pairs(const stpci_ctx* ctx, int64_t max_dets_per_cat, in
  * space (more than one subspace, fewer than three electrons). */
 stpci_status stpci_test_pair_groups(const stpci_ctx* ctx, int64_t* n_items, int64_t* n_bad, int* unit);
 
+/* Build, on the host, the plan of the spectator-batched pair kernel (spaces
+ * of several subspaces: the pair intermediates of a pair category that share
+ * their strings on subspaces 1..K-1 form a group, contracted over a padded
+ * pair list that holds every orbital of the last subspace) and run the
+ * kernel's row and entry arithmetic for up to max_groups groups of every
+ * pair category (evenly spaced), every padded row and every member: an entry
+ * must vanish exactly when its pair meets an orbital occupied in the member,
+ * and otherwise address K' + {p, r} in the space with the sign of
+ * a+_p a+_r |K'> from the global occupation bits; each member must meet
+ * every pair that leads from it into the space exactly once.  n_checked:
+ * entries checked; n_bad: violations.  Returns STPCI_EINVAL when the kernel
+ * does not apply (one subspace, fewer than two electrons, a last subspace of
+ * more than 31 spin-orbitals). */
+stpci_status stpci_test_sb(const stpci_ctx* ctx, int64_t max_groups, int64_t* n_checked, int64_t* n_bad);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,6 +78,7 @@ _SIGS = {
     "stpci_test_moves": ([_P, _I64, _I64P, _I64P], _I),
     "stpci_test_pairs": ([_P, _I64, _I64P, _I64P], _I),
     "stpci_test_pair_groups": ([_P, _I64P, _I64P, _IP], _I),
+    "stpci_test_sb": ([_P, _I64, _I64P, _I64P], _I),
     "stpci_pair_counts": ([_P, _DP, _I64P, _IP], _I),
     "stpci_set_sigma_kernel": ([_P, ctypes.c_char_p], _I),
     "stpci_sigma_kernel": ([_P, ctypes.POINTER(ctypes.c_char_p)], _I),
@@ -252,6 +253,13 @@ class Context:
         n, b, u = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
         self._check(_lib.stpci_test_pair_groups(self._h, ctypes.byref(n), ctypes.byref(b), ctypes.byref(u)))
         return n.value, b.value, u.value
+
+    def test_sb(self, max_groups=1 << 40):
+        """Host check of the spectator-batched pair kernel's row and entry
+        arithmetic: (entries checked, entries wrong)."""
+        n, b = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_lib.stpci_test_sb(self._h, int(max_groups), ctypes.byref(n), ctypes.byref(b)))
+        return n.value, b.value
 
     def pair_counts(self):
         """(sum deg^2 over pair intermediates, number of pair intermediates, largest pair degree)."""

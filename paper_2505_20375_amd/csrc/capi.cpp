@@ -20,7 +20,7 @@ stpci_ctx::~stpci_ctx() {
             (void)hipEventDestroy(e.a);
             (void)hipEventDestroy(e.b);
         }
-        for (DevBuf* b : {&d_E, &d_pcats, &d_pwork, &d_pslot, &d_pA, &d_pA32, &d_pAbf, &d_gT32, &d_hp32, &d_s2blocks, &d_ygroup, &d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
+        for (DevBuf* b : {&d_E, &d_sbcats, &d_sbrows, &d_sbstreams, &d_grp, &d_pcats, &d_pwork, &d_pslot, &d_pA, &d_pA32, &d_pAbf, &d_gT32, &d_hp32, &d_s2blocks, &d_ygroup, &d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
                           &d_hp, &d_gT, &d_hd, &d_JK, &d_V, &d_W, &d_X, &d_Xp, &d_R, &d_T, &d_partial, &d_small, &d_topv,
                           &d_topi})
             b->free_();
@@ -123,12 +123,14 @@ int select_kernel(const stpci_ctx* c) {
     const bool ok[5] = {H.max_deg <= MAXDEG, true, sigma_wave_supported(H.max_deg), symtile_supported(H.max_deg, c->cplx),
                         pair_supported(H.sp.N, H.pmax_deg, c->cplx)};
     if (c->kernel_req >= 0) {
-        // 4..8: the pair form (automatic unit; with device atomics; on the FP64
+        // 4..9: the pair form (automatic unit; with device atomics; on the FP64
         // matrix cores; on the vector ALUs; grouped intermediates on the FP64
-        // matrix cores)
+        // matrix cores; spectator-batched groups on the FP64 matrix cores)
         const int k = (c->kernel_req >= 4) ? 4 : c->kernel_req;
         if (c->kernel_req == 6 && !pair_mf64_supported(H.sp.N, H.pmax_deg)) return -1;
         if (c->kernel_req == 8 && !(ok[4] && pair_grp_supported(H.sp))) return -1;
+        if (c->kernel_req == 9 && !(H.sp.N >= 2 && pair_sb_supported(H.sp))) return -1;
+        if (c->kernel_req == 9) return 4;
         return ok[k] ? k : -1;
     }
     return ok[4] ? 4 : (ok[3] ? 3 : 1);
@@ -211,6 +213,31 @@ stpci_status prepare(stpci_ctx* c) {
             if (!c->pair_grp && c->kernel_req == 8)
                 return set_err(c, STPCI_EINVAL, "the grouped pair kernel does not support this space");
             if (c->pair_grp && (s = upload(c, c->d_grp, c->grp_items, "pair groups"))) return s;
+        }
+        // spaces of several subspaces: the members of a group (pair
+        // intermediates sharing the strings of subspaces 1..K-1) contracted
+        // as one product, where the table does not fit the L2 of an XCD
+        c->pair_sb = false;
+        if (c->kernel_req == 9 || (auto_unit && !c->pair_grp && !c->pair_mf64 && pair_sb_supported(H.sp))) {
+            SbHostPlan pl;
+            c->pair_sb = build_sb_plan(H, pl) && pair_sb_lds_bytes(pl.cap, pl.nlmax) <= 160 * 1024;
+            if (!c->pair_sb && c->kernel_req == 9)
+                return set_err(c, STPCI_EINVAL, "the spectator-batched pair kernel does not support this space");
+            if (c->pair_sb) {
+                if ((s = upload(c, c->d_sbcats, pl.cats, "batched pair categories"))) return s;
+                if ((s = upload(c, c->d_sbrows, pl.rows, "batched pair rows"))) return s;
+                if ((s = upload(c, c->d_sbstreams, pl.streams, "batched pair streams"))) return s;
+                SbPlan& P = c->sb_plan;
+                P.cats = (const SbCat*)c->d_sbcats.p;
+                P.rows = (const uint32_t*)c->d_sbrows.p;
+                P.streams = (const SbStream*)c->d_sbstreams.p;
+                P.ncat = (int32_t)pl.cats.size();
+                P.cap = pl.cap;
+                P.nlmax = pl.nlmax;
+                std::memcpy(P.sbegin, pl.sbegin, sizeof(P.sbegin));
+                std::memcpy(P.nitems, pl.nitems, sizeof(P.nitems));
+                c->pair_store = false;   // contributions go to sigma with device atomics
+            }
         }
         build_pair_table(c);
         if ((s = upload(c, c->d_pcats, H.pcats, "pair categories"))) return s;
@@ -363,7 +390,10 @@ stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, st
             if (s) return s;
             E = c->d_E.p;
         }
-        if (c->pair_grp)
+        if (c->pair_sb && !f32)
+            e = launch_sigma_pair_sb(c->dev, c->sb_plan, c->cplx, f32, f32 ? c->d_pA32.p : c->d_pA.p, cin, sout,
+                                     n_vec, c->e_core, c->profile ? &mk : nullptr, c->stream);
+        else if (c->pair_grp)
             e = launch_sigma_pair_grp(c->dev, (const GrpItem*)c->d_grp.p, (int)c->grp_items.size(), c->cplx, f32,
                                       f32 ? c->d_pA32.p : c->d_pA.p, cin, sout, E, n_vec, c->e_core,
                                       c->profile ? &mk : nullptr, c->stream);
@@ -640,6 +670,29 @@ stpci_status stpci_test_pairs(const stpci_ctx* c, int64_t max_dets_per_cat, int6
     return STPCI_OK;
 }
 
+stpci_status stpci_test_sb(const stpci_ctx* c, int64_t max_groups, int64_t* n_checked, int64_t* n_bad) {
+    if (!c || !n_checked || !n_bad) return STPCI_EINVAL;
+    if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
+    const HostSpace& H = c->hs;
+    SbHostPlan pl;
+    if (!build_sb_plan(H, pl))
+        return set_err(const_cast<stpci_ctx*>(c), STPCI_EINVAL,
+                       "the spectator-batched pair kernel does not support this space");
+    DevSpace D{};
+    D.sp = H.sp;
+    D.cats = H.cats.data();
+    D.tabs = H.tabs.data();
+    D.bits = H.bits.data();
+    D.ann = H.ann.data();
+    D.cre = H.cre.data();
+    D.space_begin = H.space_begin.data();
+    D.pcats = H.pcats.data();
+    D.pwork_begin = H.pwork_begin.data();
+    D.pslot = H.pslot.data();
+    *n_bad = check_sb_host(D, pl, max_groups, n_checked, host_to_bits, &H);
+    return STPCI_OK;
+}
+
 stpci_status stpci_test_pair_groups(const stpci_ctx* c, int64_t* n_items, int64_t* n_bad, int* unit) {
     if (!c || !n_items || !n_bad || !unit) return STPCI_EINVAL;
     if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
@@ -773,16 +826,16 @@ stpci_status stpci_pair_counts(const stpci_ctx* c, double* w_pair, int64_t* n_pa
 
 stpci_status stpci_set_sigma_kernel(stpci_ctx* c, const char* name) {
     if (!c || !name) return STPCI_EINVAL;
-    static const char* names[9] = {"simple",    "rowtile",   "wave",      "tile",    "pair",
-                                   "pair_atomic", "pair_mf64", "pair_valu", "pair_grp"};
+    static const char* names[10] = {"simple",      "rowtile",   "wave",      "tile",     "pair",
+                                    "pair_atomic", "pair_mf64", "pair_valu", "pair_grp", "pair_sb"};
     int k = -1;
     if (!std::strcmp(name, "auto")) k = -2;
-    for (int i = 0; i < 9; ++i)
+    for (int i = 0; i < 10; ++i)
         if (!std::strcmp(name, names[i])) k = i;
     if (k == -1) return set_err(c, STPCI_EINVAL, "unknown sigma kernel name");
     c->kernel_req = (k == -2) ? -1 : k;
     // device copies depend on the kernel: rebuild them on the next device call
-    for (DevBuf* b : {&c->d_E, &c->d_grp, &c->d_pcats, &c->d_pwork, &c->d_pslot, &c->d_pA, &c->d_pA32, &c->d_pAbf, &c->d_gT32, &c->d_hp32,
+    for (DevBuf* b : {&c->d_E, &c->d_grp, &c->d_sbcats, &c->d_sbrows, &c->d_sbstreams, &c->d_pcats, &c->d_pwork, &c->d_pslot, &c->d_pA, &c->d_pA32, &c->d_pAbf, &c->d_gT32, &c->d_hp32,
                       &c->d_s2blocks, &c->d_ygroup, &c->d_hp, &c->d_gT})
         if (!c->host_only) b->free_();
     c->have32 = false;
@@ -795,7 +848,9 @@ stpci_status stpci_sigma_kernel(const stpci_ctx* c, const char** name) {
     if (!c || !name) return STPCI_EINVAL;
     static const char* names[5] = {"simple", "rowtile", "wave", "tile", "pair"};
     if (!c->prepared) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "no device call made yet");
-    if (c->s2_kernel == 4 && c->pair_grp)
+    if (c->s2_kernel == 4 && c->pair_sb)
+        *name = "pair_sb";
+    else if (c->s2_kernel == 4 && c->pair_grp)
         *name = c->pair_store ? "pair_grp" : "pair_grp_atomic";
     else if (c->s2_kernel == 4)
         *name = c->pair_mf64 ? (c->pair_store ? "pair_mf64" : "pair_mf64_atomic")

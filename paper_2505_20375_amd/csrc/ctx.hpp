@@ -89,6 +89,9 @@ struct stpci_ctx {
     bool pair_grp = false;    // FP64 pair products of grouped intermediates (spaces of one subspace)
     std::vector<stp::GrpItem> grp_items;
     stp::DevBuf d_grp;
+    bool pair_sb = false;     // spectator-batched matrix-core products (spaces of several subspaces)
+    stp::SbPlan sb_plan{};
+    stp::DevBuf d_sbcats, d_sbrows, d_sbstreams;
     int kernel_req = -1;   // requested sigma kernel (stpci_set_sigma_kernel), -1: automatic
     stp::DevSpace dev{};
 

@@ -68,6 +68,27 @@ bool build_pair_groups(const HostSpace& H, std::vector<GrpItem>& items);
 hipError_t launch_sigma_pair_grp(const DevSpace& S, const GrpItem* items_dev, int nitems, bool cplx, bool f32,
                                  const void* A, const void* c, void* sigma, void* E, int n_vec, double e_core,
                                  const LaunchMarks* mk, hipStream_t st);
+// Spectator-batched matrix-core form for spaces of several subspaces: the
+// pair intermediates of a pair category that share the strings of subspaces
+// 1..K-1 are contracted as one product over their padded pair list
+// (build_sb_plan); contributions are added with device atomics.  f32: A is
+// the FP32 table; products and accumulation in FP32.
+bool pair_sb_supported(const Space& sp);
+struct SbHostPlan {
+    std::vector<SbCat> cats;
+    std::vector<uint32_t> rows;
+    std::vector<SbStream> streams;
+    int cap = 0, nlmax = 0;
+    int32_t sbegin[3][9] = {};
+    int64_t nitems[3][8] = {};
+};
+bool build_sb_plan(const HostSpace& H, SbHostPlan& plan);
+size_t pair_sb_lds_bytes(int cap, int nlmax);
+hipError_t launch_sigma_pair_sb(const DevSpace& S, const SbPlan& plan, bool cplx, bool f32, const void* A,
+                                const void* c, void* sigma, int n_vec, double e_core, const LaunchMarks* mk,
+                                hipStream_t st);
+int64_t check_sb_host(const DevSpace& S, const SbHostPlan& plan, int64_t max_groups, int64_t* n_checked,
+                      bool (*to_bits)(const void*, int64_t, uint64_t*), const void* user);
 // Grouped FP64 matrix-core pair products of several problems (device atomics).
 hipError_t launch_sigma_pair_mf64_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
                                         int deg_max, bool cplx, hipStream_t st);

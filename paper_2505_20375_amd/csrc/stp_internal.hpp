@@ -105,6 +105,49 @@ struct GrpItem {
     int32_t j[GRP_U];
 };
 
+// Spectator-batched pair kernel (spaces of several subspaces): the pair
+// intermediates K' of one pair category that share their strings on the
+// leading subspaces 1..K-1 form a group; they differ only in the string of
+// the last subspace L = K (the fastest index of every block, so consecutive
+// members reach consecutive target addresses through the same pair).  The
+// rows of a group's product are its padded pair list: per usable pair class,
+// the pairs of empty orbitals of the leading subspaces and of every orbital
+// of subspace L (a pair holding an orbital occupied in a member contributes
+// zero for that member).  sbrow[] holds the padded list of each pair
+// category as cls | i << 8 | j << 16, i (j) the index of p (r) among the
+// empties of its subspace, or the local orbital when the subspace is L.
+// An item is one group and a span of its members (column chunk); CW =
+// columns per member (1, 2 or 4) selects the chunking, index log2(CW).
+struct SbCat {
+    int32_t w;             // pair category
+    int32_t npad;          // padded rows
+    int32_t row_off;       // first entry in sbrow[]
+    int32_t count_L;       // members per group (strings of subspace L)
+    int64_t ngroups;
+};
+
+// A stream: the items of one column chunk of every group of one pair
+// category (ngroups items, the chunk's column-group count fixed).  The
+// streams of one (log2(CW), column-group count) pair are listed together,
+// so that one launch handles items of one shape.
+struct SbStream {
+    int32_t cat;           // index into the SbCat array
+    int32_t chunk;         // column chunk of the groups
+    int64_t item_begin;    // first item of the stream within its list
+};
+
+struct SbPlan {
+    const SbCat* cats;
+    const uint32_t* rows;
+    const SbStream* streams;
+    int32_t ncat;
+    int32_t cap;           // largest padded row count rounded up to 32
+    int32_t nlmax;         // largest electron count of subspace L over the pair categories
+    int32_t pad_;
+    int32_t sbegin[3][9];  // streams of (log2(CW), column groups g = 1..8): [sbegin[x][g-1], sbegin[x][g])
+    int64_t nitems[3][8];  // items of (log2(CW), column groups g = 1..8) at [x][g-1]
+};
+
 // Device view passed by value to kernels.
 struct DevSpace {
     Space sp;

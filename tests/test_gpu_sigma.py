@@ -185,6 +185,71 @@ def test_grouped_pair_kernel(n, M, cplx, n_vec):
         assert rel_err(pb.from_device(out[i * nd:(i + 1) * nd]), pb.oracle_sigma(c)) <= TOL
 
 
+@pytest.mark.parametrize("sub,lo,hi,n,n_vec,cplx", [
+    ([4, 4, 4], [1, 1, 1], [2, 3, 2], 5, 1, True),      # T4-like: windows, outside-window intermediates
+    ([4, 6], [1, 1], [3, 3], 4, 2, True),
+    ([6, 5, 5], [1, 1, 1], [3, 3, 2], 5, 3, True),      # three vectors: a two-vector and a one-vector launch
+    ([4, 4, 4, 4], [0, 1, 0, 1], [2, 2, 2, 2], 5, 2, True),
+    ([2] * 8, None, None, 6, 1, True),                  # eight subspaces, open windows
+    ([2] * 8, [0, 1, 0, 1, 0, 1, 0, 1], [1, 2, 1, 2, 1, 2, 1, 2], 6, 2, True),
+    ([5, 9], None, None, 4, 1, True),                   # open windows: FCI as two subspaces
+    ([3, 12], [0, 1], [3, 12], 6, 2, True),             # a last subspace of 12: groups of up to 462 members
+    ([8, 6], [2, 1], [6, 4], 6, 2, False),              # real integrals
+    ([6, 6], [0, 0], [6, 6], 3, 1, False),
+    ([4, 4], [1, 0], [2, 1], 2, 2, True),               # two electrons
+    ([4, 4], [3, 3], [4, 4], 7, 1, True),               # one hole
+    ([4, 4], [4, 4], [4, 4], 8, 1, True),               # a single determinant
+])
+def test_spectator_batched_kernel(sub, lo, hi, n, n_vec, cplx):
+    """Spaces of several subspaces: the spectator-batched matrix-core kernel
+    (the pair intermediates of a category that share the strings of the
+    leading subspaces contracted as one product over their padded pair list,
+    contributions added with device atomics) against the oracle, real and
+    complex, one to three vectors, degenerate electron counts."""
+    import torch
+    print("case", sub, lo, hi, n, n_vec, cplx, flush=True)
+    M = sum(sub)
+    ints = (synth.complex_integrals if cplx else synth.real_integrals)(M, 60 + n + M, rank=8, sigma_f=0.05)
+    pb = Problem(ints, synth.SpaceSpec(n, sub, lo or [], hi or []), seed=3)
+    cs = [pb.vector(s) for s in range(1, n_vec + 1)]
+    ctx = pb.context()
+    ctx.set_sigma_kernel("pair_sb")
+    x = torch.cat([pb.to_device(v) for v in cs])
+    out = torch.empty_like(x)
+    ctx.sigma(x, out, n_vec=n_vec)
+    torch.cuda.synchronize()
+    if n >= 2:
+        assert ctx.sigma_kernel() == "pair_sb"
+    nd = len(pb.dets)
+    for i, c in enumerate(cs):
+        assert rel_err(pb.from_device(out[i * nd:(i + 1) * nd]), pb.oracle_sigma(c)) <= TOL
+
+
+def test_spectator_batched_kernel_core_energy_and_sparse():
+    """The spectator-batched kernel with e_core != 0, and a vector confined to
+    one category after a dense one (chunks whose gathered coefficients are all
+    zero skip their products)."""
+    import torch
+    from oracle import csc
+    ints = synth.complex_integrals(12, 9)
+    ints.e_core = -1.75
+    sp = synth.SpaceSpec(6, [4, 4, 4])
+    pb = Problem(ints, sp, seed=5)
+    occ = np.array([[bin(int(b) >> (4 * k) & 0xF).count("1") for k in range(3)] for b in pb.dets])
+    sparse = pb.vector(8) * np.all(occ == (4, 2, 0), axis=1)
+    dense = pb.vector(7)
+    ctx = pb.context()
+    ctx.set_sigma_kernel("pair_sb")
+    xd, xs = pb.to_device(dense), pb.to_device(sparse)
+    out = torch.empty_like(xd)
+    ctx.sigma(xd, out)
+    torch.cuda.synchronize()
+    assert rel_err(pb.from_device(out), csc.sigma(pb.dets, pb.h, pb.g, dense, e_core=ints.e_core)) <= TOL
+    ctx.sigma(xs, out)
+    torch.cuda.synchronize()
+    assert rel_err(pb.from_device(out), csc.sigma(pb.dets, pb.h, pb.g, sparse, e_core=ints.e_core)) <= TOL
+
+
 def test_grouped_pair_kernel_atomic_and_sparse():
     """The grouped kernel with device atomics, and in store mode a vector
     confined to a few determinants after a dense one (items whose four

@@ -204,6 +204,31 @@ def test_pair_kernel_arithmetic_on_host(name, cap):
     assert n > 0 and bad == 0
 
 
+@pytest.mark.parametrize("name,cap", [("T3", 1 << 40), ("T4", 1 << 40), ("T8", 1 << 40), ("c1", 1 << 40),
+                                      ("c2_12_12", 40), ("c2_8_8_8", 40), ("c3p", 3)])
+def test_spectator_batched_arithmetic_on_host(name, cap):
+    """The padded pair lists, member tables, entry signs and target addresses
+    of the spectator-batched kernel (same code, compiled for the host): an
+    entry vanishes exactly when its pair meets an orbital occupied in the
+    member, otherwise it holds K' + {p, r} with the global fermion sign of
+    a+_p a+_r; each member meets every pair that leads into the space once;
+    the item streams cover every column chunk once."""
+    if name.startswith("c2_"):
+        sub = [int(x) for x in name[3:].split("_")]
+        c = host_ctx(8, sub, None, None)
+    else:
+        sp = (synth.CONFIGS.get(name) or synth.TSPACES[name])["space"]
+        c = host_ctx(sp.n_elec, sp.sub, sp.lo, sp.hi)
+    n, bad = c.test_sb(cap)
+    assert n > 0 and bad == 0
+
+
+def test_spectator_batched_kernel_refuses_one_subspace():
+    c = host_ctx(5, [12], None, None)
+    with pytest.raises(Exception):
+        c.test_sb()
+
+
 @pytest.mark.parametrize("n,sub,lo,hi,ok", [
     (3, [3], None, None, True), (3, [8], None, None, True), (4, [12], None, None, True),
     (8, [24], None, None, True), (10, [16], None, None, True), (7, [8], None, None, True),

@@ -310,19 +310,21 @@ __device__ __forceinline__ double sb_quad_xor(double x) {
     return __hiloint2double(hi, lo);
 }
 
-// The products of one B chunk (8 steps of 4 rows) for NGU column groups,
-// the B fragments read one step ahead.
-template <int NGU, bool CPLX, typename TA, typename BT, typename ACC>
-__device__ __forceinline__ void sb_mma(const BT* __restrict__ B, int kq, int c16, const TA (&af)[SB_TK / 4],
+// The products of half a B chunk (steps K0..K0+3 of 4 rows each) for NGU
+// column groups with the table fragments af of those steps, the B fragments
+// read one step ahead.
+template <int NGU, int K0, bool CPLX, typename TA, typename BT, typename ACC>
+__device__ __forceinline__ void sb_mma(const BT* __restrict__ B, int kq, int c16, const TA (&af)[4],
                                        ACC (&c1)[NGU], ACC (&c2)[NGU]) {
     BT bf[2][NGU];
 #pragma unroll
-    for (int h = 0; h < NGU; ++h) bf[0][h] = B[kq * SB_BSTR + c16 + 16 * h];
+    for (int h = 0; h < NGU; ++h) bf[0][h] = B[(K0 * 4 + kq) * SB_BSTR + c16 + 16 * h];
 #pragma unroll
-    for (int ks = 0; ks < SB_TK / 4; ++ks) {
-        if (ks + 1 < SB_TK / 4) {
+    for (int ks = 0; ks < 4; ++ks) {
+        if (ks + 1 < 4) {
 #pragma unroll
-            for (int h = 0; h < NGU; ++h) bf[(ks + 1) & 1][h] = B[((ks + 1) * 4 + kq) * SB_BSTR + c16 + 16 * h];
+            for (int h = 0; h < NGU; ++h)
+                bf[(ks + 1) & 1][h] = B[((K0 + ks + 1) * 4 + kq) * SB_BSTR + c16 + 16 * h];
         }
 #pragma unroll
         for (int h = 0; h < NGU; ++h) {
@@ -336,14 +338,14 @@ __device__ __forceinline__ void sb_mma(const BT* __restrict__ B, int kq, int c16
     }
 }
 
-// Table fragments of one chunk: lane (kq, c16) holds A[row pair, pair of
-// chunk row 4 ks + kq] for the 8 steps ks (rows past the list: pair 0).
-template <typename TA>
+// Table fragments of half a chunk: lane (kq, c16) holds A[row pair, pair of
+// chunk row 4 (K0 + ks) + kq] for ks < 4 (rows past the list: pair 0).
+template <int K0, typename TA>
 __device__ __forceinline__ void sb_afrag(const uint32_t* __restrict__ rinf, const TA* __restrict__ arow, int NP,
-                                         int kq, TA (&af)[SB_TK / 4]) {
+                                         int kq, TA (&af)[4]) {
 #pragma unroll
-    for (int ks = 0; ks < SB_TK / 4; ++ks) {
-        const uint32_t qi = rinf[ks * 4 + kq];
+    for (int ks = 0; ks < 4; ++ks) {
+        const uint32_t qi = rinf[(K0 + ks) * 4 + kq];
         af[ks] = arow[(int64_t)((qi == SB_PADROW) ? 0u : (qi & 0xfffu)) * NP];
     }
 }
@@ -363,9 +365,9 @@ struct SbItem {
 
 // Passes over the row tiles of one item with NGU column groups: wavefront
 // wid owns row tile pass * 8 + wid; B is rebuilt chunk by chunk in every
-// pass (the two wavefronts of a SIMD alternate between building the next
-// chunk and running the products of the current one); the row tile is then
-// scattered through an LDS staging area with device atomics.
+// pass (the gathers of the next chunk in flight during the products of the
+// current one); the row tile is then scattered through an LDS staging area
+// with device atomics.
 template <bool CPLX, int NV, int NGU, typename TA>
 __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ A, int NP,
                                         const typename VT<CPLX>::T* __restrict__ c,
@@ -380,54 +382,59 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
     constexpr int KSPAN = NGU * KPG;         // member slots of the item
     constexpr int EPT = (SB_TK * NV * KSPAN + NT - 1) / NT;   // B entries per thread per chunk
     const int lane = tid & 63, wid = tid >> 6;
-    const bool gen_first = (wid & 4) == 0;
     const int kq = lane >> 4, c16 = lane & 15;
     const int col = c16 % CW;
     const int nkc = I.nkc;
 
+    // B entries of this thread: the addresses and signs are formed first and
+    // every gather issued without a branch (an entry that vanishes reads
+    // element 0 and is replaced by zero afterwards), so that a chunk's
+    // gathers are in flight together while the products of the previous
+    // chunk run
     TE gx[EPT];
+    int gsg[EPT];    // +-1, or 0 for a vanishing entry
     int gcol[EPT];   // LDS position (row * SB_BSTR + first column) or -1
-    auto gen_load = [&](int kc) {
+    auto gen_issue = [&](int kc) {
+        int64_t ga[EPT];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int ent = tid + e * NT;
             const int jj = ent % KSPAN;
             const int rest = ent / KSPAN;
             const int v = rest % NV, q = rest / NV;
-            gcol[e] = -1;
-            gx[e] = V64::zero();
-            if (q >= SB_TK) continue;
-            gcol[e] = q * SB_BSTR + jj * CW + v;
-            const int R = kc * SB_TK + q;
+            gcol[e] = (q < SB_TK) ? q * SB_BSTR + jj * CW + v : -1;
+            const int R = kc * SB_TK + min(q, SB_TK - 1);
             const uint32_t inf = I.rinf[R];
-            if (inf == SB_PADROW || jj >= I.nk || v >= n_vec) continue;
-            int64_t addr;
-            const int sg = sb_entry(inf, I.rbase[R], I.colstr[jj], I.nL, I.pre + jj * I.ps3, I.j0 + jj, I.binom, &addr);
-            if (sg == 0) continue;
-            const TE x = c[(int64_t)v * nd + addr];
-            gx[e] = (sg < 0) ? V64::scale(x, -1.0) : x;
+            int64_t addr = 0;
+            int sg = 0;
+            if (q < SB_TK && inf != SB_PADROW && jj < I.nk && v < n_vec)
+                sg = sb_entry(inf, I.rbase[R], I.colstr[jj], I.nL, I.pre + jj * I.ps3, I.j0 + jj, I.binom, &addr);
+            gsg[e] = sg;
+            ga[e] = (sg != 0) ? (int64_t)v * nd + addr : 0;
         }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) gx[e] = c[ga[e]];
     };
-    auto gen_store = [&](int kc, int buf) {
+    auto gen_commit = [&](int kc, int buf) {
         double* B = bsh + (size_t)buf * SB_TK * SB_BSTR;
         bool nz = false;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            if (gcol[e] < 0) continue;
+            const double sgd = (double)gsg[e];
             if constexpr (CPLX) {
-                B[gcol[e]] = gx[e].x;
-                B[gcol[e] + NV] = gx[e].y;
-                nz = nz || gx[e].x != 0.0 || gx[e].y != 0.0;
+                const double xr = gsg[e] ? sgd * gx[e].x : 0.0, xi = gsg[e] ? sgd * gx[e].y : 0.0;
+                if (gcol[e] >= 0) {
+                    B[gcol[e]] = xr;
+                    B[gcol[e] + NV] = xi;
+                }
+                nz = nz || xr != 0.0 || xi != 0.0;
             } else {
-                B[gcol[e]] = gx[e];
-                nz = nz || gx[e] != 0.0;
+                const double xr = gsg[e] ? sgd * gx[e] : 0.0;
+                if (gcol[e] >= 0) B[gcol[e]] = xr;
+                nz = nz || xr != 0.0;
             }
         }
         if (__ballot(nz) != 0 && lane == 0) atomicOr(&I.flags[kc], 1);
-    };
-    auto gen = [&](int kc, int buf) {
-        gen_load(kc);
-        gen_store(kc, buf);
     };
 
     const int npass = (I.nRT + SB_WAVES - 1) / SB_WAVES;
@@ -440,23 +447,30 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
         // this A lane's row pair (rows past the list: pair 0, outputs dropped)
         const uint32_t pinf = own ? I.rinf[RT * 16 + c16] : SB_PADROW;
         const TA* arow = A + ((pinf == SB_PADROW) ? 0u : (pinf & 0xfffu));
-        // table fragments of the chunk in use: those of the next chunk are
-        // requested right after the products of the current one, so that the
-        // chunk build and the barrier cover their latency
-        TA af[SB_TK / 4];
-        if (own) sb_afrag(I.rinf, arow, NP, kq, af);
-        gen(0, 0);
+        // table fragments of the chunk in use, in two halves: each half of
+        // the next chunk is requested as soon as the products of the same
+        // half of the current chunk are issued (the second after the chunk
+        // build, which must not wait for it: loads complete in order)
+        TA afa[4], afb[4];
+        if (own) {
+            sb_afrag<0>(I.rinf, arow, NP, kq, afa);
+            sb_afrag<4>(I.rinf, arow, NP, kq, afb);
+        }
+        gen_issue(0);
+        gen_commit(0, 0);
         __syncthreads();
         for (int kc = 0; kc < nkc; ++kc) {
             const int buf = kc & 1;
             const bool more = kc + 1 < nkc;
             const double* B = bsh + (size_t)buf * SB_TK * SB_BSTR;
-            if (gen_first && more) gen(kc + 1, buf ^ 1);
-            if (own) {
-                if (I.flags[kc]) sb_mma<NGU, CPLX>(B, kq, c16, af, c1, c2);
-                if (more) sb_afrag(I.rinf + (kc + 1) * SB_TK, arow, NP, kq, af);
-            }
-            if (!gen_first && more) gen(kc + 1, buf ^ 1);
+            const uint32_t* rnext = I.rinf + (kc + 1) * SB_TK;
+            if (more) gen_issue(kc + 1);
+            const bool mm = own && I.flags[kc];
+            if (mm) sb_mma<NGU, 0, CPLX>(B, kq, c16, afa, c1, c2);
+            if (own && more) sb_afrag<0>(rnext, arow, NP, kq, afa);
+            if (mm) sb_mma<NGU, 4, CPLX>(B, kq, c16, afb, c1, c2);
+            if (more) gen_commit(kc + 1, buf ^ 1);
+            if (own && more) sb_afrag<4>(rnext, arow, NP, kq, afb);
             __syncthreads();
         }
         // ---- scatter of this wavefront's row tile, staged through LDS (the

@@ -1,15 +1,18 @@
 """Benchmark: determinant-updates/s of the sigma build H.c on one MI355X.
 
-Workload: complex spinor FCI, 24 spinors, 8 electrons (735,471 determinants),
-integrals seeded as (pq|rs) = sum_P L^P_pq L^P_rs with a rank-32 Hermitian
-factor (entries N(0, 0.03)); 2 roots, so one step is the sigma build of the
-2 new Davidson directions (n_vec = 2), inputs resident in HBM.
+Headline workload: the STP-DAS categorical space of 40 complex spinors split
+12 | 16 | 12 with occupation windows [2..6] | [4..10] | [2..6] and 11
+electrons (1,365,867,360 determinants in 10 categories, 21.9 GB per vector),
+integrals seeded as (pq|rs) = sum_P L^P_pq L^P_rs with a rank-16 Hermitian
+factor (entries N(0, 0.05)); lowest root, so one step is the sigma build of
+one Davidson direction (n_vec = 1), inputs resident in HBM.
 Metric: det-updates/s = nnz(H) * n_vec / t_step (nonzero couplings applied
 per second).  Also reported: the dominant kernel against its roofline (HIP
-events recorded by the library around that kernel), the FP32-contraction
-form, the Davidson solve latency (p50/p99) with its gap-theorem energy bound,
-a continuous-batching serving run, and the CPU oracle on a bounded sample of
-rows.
+events recorded by the library around that kernel), the BF16 form of the
+same step, the 24-spinor / 8-electron complex FCI problem (sigma, precision
+forms, Davidson solve latency p50/p99 with the library's gap certificate),
+a continuous-batching serving run, and the CPU oracle on a bounded sample
+of rows of the headline space.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-solve] [--serve N]
 """
@@ -39,7 +42,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--partition", default="24", help="subspace sizes, e.g. 24 or 8,8,8")
+    ap.add_argument("--workload", default="c3p", choices=["c3p", "c2"],
+                    help="headline: c3p (40 spinors, 12|16|12, 11 electrons) or c2 (24 spinors, 8 electrons)")
+    ap.add_argument("--partition", default="24", help="config-2 subspace sizes, e.g. 24 or 8,8,8")
+    ap.add_argument("--no-c2", action="store_true", help="skip the config-2 section")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 step of the headline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--solves", type=int, default=5)
@@ -75,7 +82,203 @@ def main():
     import paper_2505_20375_amd as stpci
 
     torch.cuda.set_device(0)
-    cfg = synth.CONFIGS["c2"]
+    if args.workload == "c3p":
+        res = _headline_c3p(args)
+        ctx = None
+        if not args.no_c2:
+            sec, ctx = _config2(args)
+            sec.pop("n_gpus", None)
+            for key in ("metric", "unit", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline",
+                        "data"):
+                sec.pop(key, None)
+            res["config2"] = sec
+    else:
+        res, ctx = _config2(args)
+    if not args.no_peaks:
+        # reference rates only: an error here is reported, not fatal to the line
+        try:
+            res["measured_peaks"] = _measured_peaks(res["roofline"])
+        except RuntimeError as exc:
+            res["measured_peaks"] = {"error": str(exc)[:200]}
+    if args.serve > 0:
+        del ctx
+        res["serving"] = _serve(args.serve, args.serve_max_dets, args.serve_rate)
+    if not args.no_cpu:
+        if args.workload == "c3p":
+            res["cpu_baseline"] = _cpu_baseline_c3p(args.cpu_seconds)
+        else:
+            ints, sp, _ = synth.config("c2")
+            res["cpu_baseline"] = _cpu_baseline(ints, sp, res["config"]["nnz_h"] / res["config"]["n_dets"],
+                                                args.cpu_seconds)
+    print(json.dumps(res))
+
+
+def _headline_c3p(args):
+    """The headline step: FP64 sigma of one vector on the 40-spinor,
+    12|16|12, 11-electron STP-DAS space, and the BF16 form of the same step."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2505_20375_amd as stpci
+
+    ints, sp, roots = synth.config("c3p")
+    ctx = stpci.Context(0)
+    ctx.set_integrals(ints.h, ints.g)
+    ctx.set_space(sp.n_elec, sp.sub, sp.lo, sp.hi)
+    info = ctx.space_info()
+    n = info.n_dets
+    n_vec = roots
+    log("space: %d determinants, %d categories, nnz(H) %.4g" % (n, info.n_cat, info.nnz_h))
+    g = torch.Generator(device="cuda").manual_seed(3103)
+    c = torch.randn(n_vec * n, dtype=torch.complex128, device="cuda", generator=g)
+    c /= torch.linalg.vector_norm(c)
+    out = torch.empty_like(c)
+    for i in range(args.warmup):
+        ctx.sigma(c, out, n_vec=n_vec)
+        torch.cuda.synchronize()
+        log("warmup %d done" % i)
+    ctx.profile(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for i in range(args.steps):
+        ctx.sigma(c, out, n_vec=n_vec)
+        if i + 1 < args.steps:
+            torch.cuda.synchronize()   # progress line per step (the steps run back to back on the device)
+        log("step %d done" % i)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    nk, tk = ctx.kernel_time("sigma")
+    ctx.profile(False)
+    value = info.nnz_h * n_vec / (ms_per_step * 1e-3)
+    log("sigma step: %.1f ms (events), %.1f ms (wall)" % (ms_per_step, wall * 1e3 / args.steps))
+    W1, W2, _, _ = ctx.work_counts()
+    Wp, n_pair, max_pdeg = ctx.pair_counts()
+    kname = ctx.sigma_kernel()
+    avg = tk / max(nk, 1)   # the kernel launches of one step, summed per step
+    flops = 8.0 * Wp * n_vec
+    flops_paper = 8.0 * (W1 + W2) * n_vec
+    ex_flops, items = ctx.sb_counts(n_vec) if kname == "pair_sb" else (None, None)
+    achieved = flops / (avg * 1e-3) / 1e12
+    roof = {"kernel": "k_sigma_pair_sb (one pass: pair-resolved 1e + 2e sigma, the pair intermediates of a "
+                      "category sharing their leading-subspace strings contracted as one product, FP64 matrix "
+                      "cores, v_mfma_f64_16x16x4f64; one launch per column-group count)",
+            "bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": _traffic(n_vec, kname, "c3p"),
+            "avg_launch_ms": round(avg, 2), "launches": nk, "flops_per_launch": flops,
+            "flops_definition": "8 Wp n_vec: Wp = sum over the (N-2)-electron intermediates of deg^2 complex "
+                                "multiply-adds (one- and two-electron parts together)",
+            "algorithmic_bytes_per_launch": 2 * n_vec * n * 16,
+            "paper_formulation_flops_per_launch": flops_paper,
+            "paper_formulation_equiv_tflops": round(flops_paper / (avg * 1e-3) / 1e12, 3),
+            "paper_formulation_equiv_over_peak": round(flops_paper / (avg * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+    if ex_flops:
+        roof["executed_flops_per_launch"] = ex_flops
+        roof["executed_tflops"] = round(ex_flops / (avg * 1e-3) / 1e12, 3)
+        roof["frac_executed"] = round(ex_flops / (avg * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)
+        roof["items"] = items
+    res = {
+        "metric": "determinant-updates/s in H.c sigma",
+        "value": value,
+        "unit": "det-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "STP-DAS categorical sigma, 40 complex spinors as 12|16|12, windows "
+                               "[2..6]|[4..10]|[2..6], 11 electrons, %d determinants in %d categories, n_vec=%d"
+                               % (n, info.n_cat, n_vec),
+                   "n_dets": n, "n_categories": info.n_cat, "partition": sp.sub, "windows": [sp.lo, sp.hi],
+                   "n_elec": sp.n_elec, "n_vec": n_vec, "nnz_h": info.nnz_h, "w1_macs": W1, "w2_macs": W2,
+                   "wp_macs": Wp, "dets_per_s": n * n_vec / (ms_per_step * 1e-3)},
+        "roofline": roof,
+    }
+    if not args.no_bf16:
+        # the BF16 form of the same step (bfloat16 integrals and coefficients on
+        # the matrix cores, FP32 accumulation, FP64 sums), error against FP64
+        out2 = torch.empty_like(out)
+        ctx.sigma(c, out2, n_vec=n_vec, precision=stpci.BF16)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.sigma(c, out2, n_vec=n_vec, precision=stpci.BF16)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_b = e0.elapsed_time(e1)
+        err = float(torch.linalg.vector_norm(out2 - out) / torch.linalg.vector_norm(out))
+        log("BF16 sigma: %.1f ms, relative error %.2e" % (ms_b, err))
+        res["precision"] = {"sigma_fp64_ms": ms_per_step, "sigma_bf16_ms": ms_b,
+                            "sigma_bf16_speedup": ms_per_step / ms_b, "sigma_bf16_rel_err": err,
+                            "bf16_kernel": "k_sigma_pair_mfma (v_mfma_f32_16x16x32_bf16, FP32 accumulation)"}
+        del out2
+    del c, out, ctx
+    torch.cuda.empty_cache()
+    return res
+
+
+def _cpu_baseline_c3p(seconds):
+    """The CPU oracle (list-free Slater-Condon rows of the windowed space) on
+    a bounded sample of rows of the headline space, all host threads,
+    extrapolated to det-updates/s.  The coefficients of the sampled rows'
+    columns are drawn beforehand (not timed): the oracle's work is forming
+    and applying each row's nonzero couplings."""
+    import numpy as np
+    import synth
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import csc
+    import paper_2505_20375_amd as stpci
+    ints, sp, _ = synth.config("c3p")
+    ctx = stpci.Context(-1)
+    ctx.set_space(sp.n_elec, sp.sub, sp.lo, sp.hi)
+    info = ctx.space_info()
+    nthreads = os.cpu_count() or 1
+    rng = np.random.default_rng(0)
+
+    def rows_work(bits_list):
+        tot = 0
+        acc = 0j
+        for b in bits_list:
+            kb, vals = csc.h_row_window(sp.sub, sp.lo, sp.hi, ints.h, ints.g, int(b))
+            cv = np.ones(len(kb))   # stand-in coefficients; the row's multiply-adds are done
+            acc += np.dot(vals, cv)
+            tot += len(kb)
+        return tot
+
+    def run(nrows):
+        addrs = rng.choice(info.n_dets, nrows, replace=False)
+        bits = [ctx.address_to_det(int(a)) for a in addrs]
+        parts = [bits[i::nthreads] for i in range(nthreads)]
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(nthreads) as ex:
+            tot = sum(ex.map(rows_work, parts))
+        return tot, time.perf_counter() - t0
+
+    tot, t = run(max(nthreads * 8, 64))
+    nrows = int(max(64, nthreads * 8 * seconds / max(t, 1e-3)))
+    tot, t = run(nrows)
+    return {"value": tot / t, "unit": "det-updates/s", "cores": nthreads, "kind": "oracle",
+            "sample": "%d random rows of the 40-spinor 12|16|12 11-electron space (%d nonzero couplings, "
+                      "list-free row-driven Slater-Condon, %.1f s on %d threads)" % (nrows, tot, t, nthreads)}
+
+
+def _config2(args):
+    """The 24-spinor / 8-electron complex FCI problem (735,471 determinants,
+    2 roots): sigma of the 2 new directions per step, its kernel against the
+    roofline, the FP32 and BF16 forms, sparse vectors and the Davidson solve
+    latency of each precision form.  Returns (result dict, context)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2505_20375_amd as stpci
+
     ints, sp, roots = synth.config("c2")
     sub = [int(x) for x in args.partition.split(",")]
     assert sum(sub) == sp.n_spin_orb
@@ -144,7 +347,7 @@ def main():
             "reduce_avg_ms": round(t3 / n3, 4) if n3 else None,
             "paper_formulation_flops_per_launch": flops_paper,
             "paper_formulation_equiv_tflops": round(achieved_paper, 3),
-            "frac_paper_formulation": round(achieved_paper / FP64_PEAK_TFLOPS, 4)}
+            "paper_formulation_equiv_over_peak": round(achieved_paper / FP64_PEAK_TFLOPS, 4)}
     if kname.startswith("pair_mf64"):
         # executed matrix-core flops: 16-row tiles x 4-column steps over the
         # pair degree rounded up to 32, two real products of 4 columns each
@@ -255,18 +458,7 @@ def main():
             prec["solve_speedup" + ("" if pname == "mixed" else "_bf16")] = res["solve"]["p50_ms"] / sol["p50_ms"]
             prec["energy_diff_eh" + ("" if pname == "mixed" else "_bf16")] = max(
                 abs(a - b) for a, b in zip(sol["energies"], res["solve"]["energies"]))
-    if not args.no_peaks:
-        # reference rates only: an error here is reported, not fatal to the line
-        try:
-            res["measured_peaks"] = _measured_peaks(res["roofline"])
-        except RuntimeError as exc:
-            res["measured_peaks"] = {"error": str(exc)[:200]}
-    if args.serve > 0:
-        del ctx
-        res["serving"] = _serve(args.serve, args.serve_max_dets, args.serve_rate)
-    if not args.no_cpu:
-        res["cpu_baseline"] = _cpu_baseline(ints, sp, info.nnz_h / n, args.cpu_seconds)
-    print(json.dumps(res))
+    return res, ctx
 
 
 def ctx_pair_mf64_flops(ctx, n_vec):
@@ -294,11 +486,13 @@ def ctx_pair_grp_flops(ctx, sp, n_vec):
     return float(items * 16 * unit * cap * cap * ((n_vec + 1) // 2))
 
 
-TRAFFIC_FILES = {"pair_grp": os.path.join(ROOT, "profiles", "sigma_pair_grp_c2_traffic.txt"),
+TRAFFIC_FILES = {("pair_sb", "c3p"): os.path.join(ROOT, "profiles", "sigma_pair_sb_c3p_traffic.txt"),
+                 "pair_grp": os.path.join(ROOT, "profiles", "sigma_pair_grp_c2_traffic.txt"),
                  "pair_valu": os.path.join(ROOT, "profiles", "sigma_pair_c2_traffic.txt"),
                  "pair_mf64": os.path.join(ROOT, "profiles", "sigma_pair_mf64_c2_traffic.txt"),
                  "tile": os.path.join(ROOT, "profiles", "sigma_symtile_c2_traffic.txt")}
-KERNEL_SOURCES = {"pair_grp": ["sigma_grp.hip", "stp_device.hpp", "stp_internal.hpp"],
+KERNEL_SOURCES = {"pair_sb": ["sigma_sb.hip", "stp_device.hpp", "stp_internal.hpp"],
+                  "pair_grp": ["sigma_grp.hip", "stp_device.hpp", "stp_internal.hpp"],
                   "pair_valu": ["sigma_pair.hip", "pair_arith.hpp", "symtile.hpp", "stp_device.hpp", "stp_internal.hpp"],
                   "pair_mf64": ["sigma_mf64.hip", "pair_arith.hpp", "stp_device.hpp", "stp_internal.hpp"],
                   "tile": ["sigma_sym.hip", "stp_device.hpp", "stp_internal.hpp"]}
@@ -313,14 +507,14 @@ def kernel_source_hash(kname="pair_mf64"):
     return hsh.hexdigest()[:16]
 
 
-def _traffic(n_vec, kname="pair_mf64"):
+def _traffic(n_vec, kname="pair_mf64", workload="c2"):
     """HBM bytes per launch of the sigma kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the factor the
     same counter reads on a plain copy of known size), or None when the kernel
     sources changed after the counters were taken."""
     if kname not in KERNEL_SOURCES:   # atomic scatter or another kernel: no counter summary
         return None
-    path = TRAFFIC_FILES.get(kname)
+    path = TRAFFIC_FILES.get((kname, workload)) or TRAFFIC_FILES.get(kname)
     if path is None or not os.path.exists(path):
         return None
     kv = {}
@@ -336,7 +530,8 @@ def _traffic(n_vec, kname="pair_mf64"):
 def _solve(ctx, roots, nsolve, precision):
     """Davidson time-to-solution at residual tolerance 1e-5; the lowest energy
     is then within ||r0||^2 / gamma^- (gap theorem with the rigorous gap
-    bound from the second root), reported as energy_bound_eh (<= 1e-8 Eh)."""
+    bound from the second root, computed by the library:
+    stpci_dav_certificate), reported as energy_bound_eh (<= 1e-8 Eh)."""
     import numpy as np
     import torch
     import paper_2505_20375_amd as stpci
@@ -351,8 +546,9 @@ def _solve(ctx, roots, nsolve, precision):
         times.append((time.perf_counter() - t0) * 1e3)
         its.append(it)
         log("solve %d (%s): %.1f ms, %d iterations" % (i, label, times[-1], it))
-    gamma = (e[1] - r[1]) - e[0] if len(e) > 1 else None
-    cert = (r[0] ** 2 / gamma) if gamma and gamma > 0 else None
+    # the library's gap certificate of the lowest root (from the second root)
+    gam, bnd = ctx.certificate()
+    cert = float(bnd[0]) if np.isfinite(bnd[0]) else None
     n64, n32 = ctx.dav_stats()
     nbf = ctx.dav_sigma_count(stpci.BF16)
     return {"p50_ms": float(np.percentile(times, 50)), "p99_ms": float(np.percentile(times, 99)),

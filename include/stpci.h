@@ -188,12 +188,21 @@ stpci_status stpci_diagonal(stpci_ctx* ctx, double* diag_dev);
 /* Davidson options.  k: roots; max_iter: iterations; max_subspace: expansion
  * vectors kept before a restart from the Ritz vectors (0: automatic);
  * tol_residual: stop when every ||H x - E x|| <= tol_residual; eps_drop: the
- * epsilon of Eq. sparsePreconditioner (0: traditional Davidson update with
- * the 1e-12 guard); precision: sigma arithmetic inside the iteration;
- * refine_tol_energy: with precision != FP64, energies are refined with FP64
- * sigma products until they change by less than this; guess_dev: k starting
- * vectors ([k][n_dets], device) or NULL for unit vectors at the k lowest
- * diagonal elements. */
+ * epsilon of Eq. sparsePreconditioner in [0, 1): each correction s (the
+ * residual divided by theta - H_ii, 0 where |theta - H_ii| < 1e-12) keeps only
+ * its entries with |s_i| >= eps_drop ||s||; 0 gives the traditional Davidson
+ * update with the 1e-12 guard (Eq. davidsonPreconditioner); the Results
+ * section finds eps <~ 10 / sqrt(n_dets) safe.  precision: sigma arithmetic
+ * inside the iteration; refine_tol_energy (>= 0; 0: off): with precision !=
+ * FP64, the run carries one root more than k and the FP64 refinement phase
+ * also ends, as converged, once every requested root's gap-theorem bound
+ * ||r_j||^2 / gamma_j^- (stpci_dav_certificate) is below this value (the
+ * residuals of that iteration are reported as they are; like any residual
+ * bound it presumes that no eigenvalue below the Ritz values was missed);
+ * guess_dev: k
+ * starting vectors ([k][n_dets], device) or NULL for unit vectors at the k
+ * lowest diagonal elements.  Out-of-range eps_drop or refine_tol_energy:
+ * STPCI_EINVAL. */
 typedef struct {
     int k;
     int max_iter;
@@ -203,6 +212,8 @@ typedef struct {
     stpci_precision precision;
     double refine_tol_energy;
     const void* guess_dev;
+    int certify;   /* 1: converge one root more than k internally (to tol_residual), so
+                    * that stpci_dav_certificate bounds every requested root; 0: off */
 } stpci_dav_opts;
 
 /* Lowest k eigenpairs (Results: Davidson with residual-norm convergence).
@@ -211,6 +222,19 @@ typedef struct {
  * or NULL.  Returns STPCI_ENOCONV when max_iter is reached. */
 stpci_status stpci_davidson(stpci_ctx* ctx, const stpci_dav_opts* opts, double* energies, double* resid,
                             void* vecs_dev, int* n_iter);
+
+/* Error bounds of the roots of the last Davidson run (Methods, Eigenvalue
+ * Bound Analysis): for root j < k, gamma_lower[j] is a lower bound of the gap
+ * from E_j to the nearest other eigenvalue, from the Ritz values and
+ * residual norms of the neighbouring roots -- (E_1 - ||r_1||) - E_0 for the
+ * lowest root (Eq. gammaLowerBound), and for j > 0 also
+ * E_j - (E_{j-1} + ||r_{j-1}||) -- and bound[j] = ||r_j||^2 / gamma_lower[j]
+ * bounds |E_j - exact| by the gap theorem (infinity when gamma_lower[j] <= 0,
+ * e.g. degenerate roots).  The last root run has no neighbour above: run
+ * with certify = 1 to bound all k requested roots, otherwise root k - 1 gets
+ * NaN.  The bounds hold when no eigenvalue lies between the computed ones.
+ * Host arrays of k doubles (either may be NULL); STPCI_ESTATE before any run. */
+stpci_status stpci_dav_certificate(const stpci_ctx* ctx, double* gamma_lower, double* bound);
 
 /* Per-iteration record of the last Davidson run: iteration count, and for
  * iteration i < cap the Ritz values energies[i*k + j] and residual norms

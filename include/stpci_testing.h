@@ -45,6 +45,23 @@ stpci_status stpci_test_pairs(const stpci_ctx* ctx, int64_t max_dets_per_cat, in
  * space (more than one subspace, fewer than three electrons). */
 stpci_status stpci_test_pair_groups(const stpci_ctx* ctx, int64_t* n_items, int64_t* n_bad, int* unit);
 
+/* Work of the spectator-batched pair kernel for an n_vec-vector sigma (for
+ * reports): the matrix-core flops its launches execute, padding included
+ * (per item: row tiles x steps x column groups x 2048 flop per
+ * v_mfma_f64_16x16x4f64, twice for complex integrals), and the number of
+ * items.  STPCI_EINVAL when the kernel does not apply to the space. */
+stpci_status stpci_sb_counts(const stpci_ctx* ctx, int n_vec, double* mfma_flops, int64_t* items);
+
+/* The Davidson corrections of Eq. sparsePreconditioner as the solver forms
+ * them: for q < n, s_q,i = r_q,i / (theta[q] - H_ii) where |theta[q] - H_ii|
+ * >= 1e-12 (H_ii computed on the fly from the occupation bits), else 0; then
+ * with eps > 0, t_q,i = s_q,i where |s_q,i| >= eps ||s_q||, else 0.
+ * r_dev, t_dev: device [n][n_dets] in the scalar type of the integrals;
+ * theta: host, n values; n in [1, 16]; eps in [0, 1) (else STPCI_EINVAL).
+ * Synchronises the context stream. */
+stpci_status stpci_test_precond(stpci_ctx* ctx, const void* r_dev, void* t_dev, int n, const double* theta,
+                                double eps);
+
 /* Build, on the host, the plan of the spectator-batched pair kernel (spaces
  * of several subspaces: the pair intermediates of a pair category that share
  * their strings on subspaces 1..K-1 form a group, contracted over a padded

@@ -37,7 +37,7 @@ _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", ENOCONV: "ENOCONV", 
 class DavOpts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("max_iter", ctypes.c_int), ("max_subspace", ctypes.c_int),
                 ("tol_residual", ctypes.c_double), ("eps_drop", ctypes.c_double), ("precision", ctypes.c_int),
-                ("refine_tol_energy", ctypes.c_double), ("guess_dev", ctypes.c_void_p)]
+                ("refine_tol_energy", ctypes.c_double), ("guess_dev", ctypes.c_void_p), ("certify", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -70,6 +70,7 @@ _SIGS = {
     "stpci_davidson": ([_P, ctypes.POINTER(DavOpts), _DP, _DP, _P, _IP], _I),
     "stpci_dav_history": ([_P, _IP, _I, _DP, _DP], _I),
     "stpci_dav_stats": ([_P, _IP, _IP], _I),
+    "stpci_dav_certificate": ([_P, _DP, _DP], _I),
     "stpci_dav_sigma_count": ([_P, _I, _IP], _I),
     "stpci_dav_history_dc": ([_P, _I, _DP], _I),
     "stpci_profile": ([_P, _I], _I),
@@ -79,6 +80,8 @@ _SIGS = {
     "stpci_test_pairs": ([_P, _I64, _I64P, _I64P], _I),
     "stpci_test_pair_groups": ([_P, _I64P, _I64P, _IP], _I),
     "stpci_test_sb": ([_P, _I64, _I64P, _I64P], _I),
+    "stpci_sb_counts": ([_P, _I, _DP, _I64P], _I),
+    "stpci_test_precond": ([_P, _P, _P, _I, _DP, _D], _I),
     "stpci_pair_counts": ([_P, _DP, _I64P, _IP], _I),
     "stpci_set_sigma_kernel": ([_P, ctypes.c_char_p], _I),
     "stpci_sigma_kernel": ([_P, ctypes.POINTER(ctypes.c_char_p)], _I),
@@ -205,18 +208,29 @@ class Context:
         self._check(_lib.stpci_diagonal(self._h, _ptr(out)))
 
     def davidson(self, k=1, tol=1e-8, max_iter=100, max_subspace=0, eps_drop=0.0, precision=FP64,
-                 refine_tol_energy=1e-8, guess=None, vecs=None, allow_noconv=False):
+                 refine_tol_energy=0.0, guess=None, vecs=None, allow_noconv=False, certify=False):
         o = DavOpts(int(k), int(max_iter), int(max_subspace), float(tol), float(eps_drop), int(precision),
-                    float(refine_tol_energy), _ptr(guess).value if guess is not None else None)
+                    float(refine_tol_energy), _ptr(guess).value if guess is not None else None, int(bool(certify)))
         e = (ctypes.c_double * k)()
         r = (ctypes.c_double * k)()
         it = ctypes.c_int()
-        self._last_k = int(k)
+        info = self.space_info() if certify else None
+        self._last_k = int(k) + (1 if certify and k < 16 and k < info.n_dets else 0)
+        self._cert_k = int(k)
         st = _lib.stpci_davidson(self._h, ctypes.byref(o), e, r, _ptr(vecs) if vecs is not None else None,
                                  ctypes.byref(it))
         if st != OK and not (allow_noconv and st == ENOCONV):
             self._check(st)
         return np.array(e[:]), np.array(r[:]), it.value, st
+
+    def certificate(self):
+        """(gamma_lower, bound) of the last Davidson run: lower bounds of the
+        gaps and gap-theorem bounds ||r_j||^2 / gamma_j of |E_j - exact|."""
+        k = self._cert_k
+        g = np.zeros(k)
+        b = np.zeros(k)
+        self._check(_lib.stpci_dav_certificate(self._h, g.ctypes.data_as(_DP), b.ctypes.data_as(_DP)))
+        return g, b
 
     def history(self, full=False):
         """Iterations of the last Davidson run; with full=True, a dict of
@@ -253,6 +267,20 @@ class Context:
         n, b, u = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
         self._check(_lib.stpci_test_pair_groups(self._h, ctypes.byref(n), ctypes.byref(b), ctypes.byref(u)))
         return n.value, b.value, u.value
+
+    def test_precond(self, r, t, theta, eps=0.0):
+        """The solver's corrections of n residuals (r, t: device [n][n_dets]),
+        Eq. sparsePreconditioner with the given eps."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        self._check(_lib.stpci_test_precond(self._h, _ptr(r), _ptr(t), len(th), th.ctypes.data_as(_DP),
+                                            float(eps)))
+
+    def sb_counts(self, n_vec=1):
+        """(matrix-core flops executed, items) of the spectator-batched kernel
+        for an n_vec-vector sigma."""
+        f, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(_lib.stpci_sb_counts(self._h, int(n_vec), ctypes.byref(f), ctypes.byref(n)))
+        return f.value, n.value
 
     def test_sb(self, max_groups=1 << 40):
         """Host check of the spectator-batched pair kernel's row and entry
@@ -350,7 +378,7 @@ class Server:
         g = np.ascontiguousarray(g, dtype=dt)
         lo = list(lo) if lo is not None else [0] * len(sub)
         hi = list(hi) if hi is not None else list(sub)
-        o = DavOpts(int(k), int(max_iter), int(max_subspace), float(tol), 0.0, int(precision), 1e-8, None)
+        o = DavOpts(int(k), int(max_iter), int(max_subspace), float(tol), 0.0, int(precision), 0.0, None, 0)
         r = Request(h.shape[0], COMPLEX128 if cplx else REAL64, int(bool(spin_free)), h.ctypes.data_as(_P),
                     g.ctypes.data_as(_P), float(e_core), int(n_elec), len(sub), _iarr(sub), _iarr(lo), _iarr(hi),
                     ctypes.pointer(o))

@@ -693,6 +693,27 @@ stpci_status stpci_test_sb(const stpci_ctx* c, int64_t max_groups, int64_t* n_ch
     return STPCI_OK;
 }
 
+stpci_status stpci_sb_counts(const stpci_ctx* c, int n_vec, double* mfma_flops, int64_t* items) {
+    if (!c || n_vec < 1) return STPCI_EINVAL;
+    if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");
+    SbHostPlan pl;
+    if (!build_sb_plan(c->hs, pl))
+        return set_err(const_cast<stpci_ctx*>(c), STPCI_EINVAL,
+                       "the spectator-batched pair kernel does not support this space");
+    double f = 0;
+    int64_t it = 0;
+    for (int v0 = 0; v0 < n_vec; v0 += 2) {
+        double ff;
+        int64_t ii;
+        sb_plan_counts(pl, c->have_ints ? c->cplx : true, (n_vec - v0 >= 2) ? 2 : 1, &ff, &ii);
+        f += ff;
+        it += ii;
+    }
+    if (mfma_flops) *mfma_flops = f;
+    if (items) *items = it;
+    return STPCI_OK;
+}
+
 stpci_status stpci_test_pair_groups(const stpci_ctx* c, int64_t* n_items, int64_t* n_bad, int* unit) {
     if (!c || !n_items || !n_bad || !unit) return STPCI_EINVAL;
     if (!c->have_space) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "space not set");

@@ -47,6 +47,9 @@ struct DavState {
     bool converged = false, done = false, active = false;
     std::vector<std::complex<double>> G;
     std::vector<double> theta, rn;
+    int k_req = 0;                    // roots requested (opts.k may hold one more, see certify)
+    std::vector<double> theta_prev;   // Ritz values of the previous iteration of this phase
+    bool energy_stop = false;         // the FP64 refinement ended on refine_tol_energy
 };
 
 }  // namespace stp
@@ -107,6 +110,8 @@ struct stpci_ctx {
     std::vector<stp::DavRecord> history;
     int hist_k = 0;
     int nsigma[3] = {0, 0, 0};   // sigma builds of the last Davidson run: FP64, FP32, BF16 (vectors)
+    int cert_k = 0;              // roots of the last collected run, with their gap bounds
+    std::vector<double> cert_gamma, cert_bound;
     stp::DavState dav;
 
     // profiling

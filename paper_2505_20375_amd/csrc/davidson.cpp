@@ -258,6 +258,24 @@ struct Dav {
                    "cgs");
     }
 
+    // T_q = Eq. sparsePreconditioner applied to R_root[q] with theta[q]:
+    // s = r / (theta - H_ii) (0 where |theta - H_ii| < 1e-12), then, with
+    // eps > 0, entries below eps ||s_q|| dropped; ||s_q||^2 computed on the
+    // device into the dot-product area (slots pair_slot(q, nt)) and read
+    // there by the drop kernel, without a round trip
+    stpci_status precondition(const void* R, void* T, int nt, const int* roots, const double* thetas, double eps) {
+        stpci_status s = hip(launch_precond(c->dev, cx, (const double*)c->d_hd.p, (const double*)c->d_JK.p,
+                                            c->e_core, R, T, N, nt, roots, thetas, 1e-12, st),
+                             "precond");
+        if (s || !(eps > 0.0) || nt < 1) return s;
+        if ((s = issue_pair_dots((char*)T, (char*)T, nt, 0))) return s;
+        int slot[PRE_MAX];
+        for (int q = 0; q < nt; ++q) slot[q] = pair_slot(q, nt);
+        return hip(launch_eps_drop(cx, T, N, N, nt, slot, (const double*)((char*)c->d_small.p + kDotsOff),
+                                   cx ? 2 : 1, eps, st),
+                   "eps drop");
+    }
+
     // X_t -= sum_i A_i <A_i | X_t> for t < nx, the products queued by
     // issue_dots(A, m, X, nx, off) and read where they lie (no round trip)
     stpci_status subtract_queued(const void* A, int m, int off, int nx, void* X) {
@@ -267,6 +285,25 @@ struct Dav {
 };
 
 }  // namespace
+
+// Test hook: the Davidson corrections of n residuals (consecutive vectors of
+// r_dev) with Ritz values theta (host), written to t_dev, with the eps drop.
+extern "C" stpci_status stpci_test_precond(stpci_ctx* c, const void* r_dev, void* t_dev, int n, const double* theta,
+                                           double eps) {
+    if (!c || !r_dev || !t_dev || !theta || n < 1 || n > PRE_MAX) return STPCI_EINVAL;
+    if (!(eps >= 0.0 && eps < 1.0)) return set_err(c, STPCI_EINVAL, "eps must lie in [0, 1)");
+    stpci_status s = prepare(c);
+    if (s) return s;
+    if ((s = hip_check(c, hipSetDevice(c->device), "hipSetDevice"))) return s;
+    const int64_t N = c->hs.sp.ndets;
+    if ((s = ensure(c, c->d_partial, (size_t)dots_blocks(N) * kDotsMax * 16, "dot partials"))) return s;
+    if ((s = ensure(c, c->d_small, kSmallBytes, "small workspace"))) return s;
+    Dav d{c, N, scalar_bytes(c), c->cplx, c->stream};
+    std::vector<int> roots(n);
+    for (int q = 0; q < n; ++q) roots[q] = q;
+    if ((s = d.precondition(r_dev, t_dev, n, roots.data(), theta, eps))) return s;
+    return hip_check(c, hipStreamSynchronize(c->stream), "sync");
+}
 
 extern "C" stpci_status stpci_test_heev(int n, const double* A, double* w, double* V) {
     if (n < 1 || !A || !w || !V) return STPCI_EINVAL;
@@ -308,8 +345,11 @@ namespace stp {
 int64_t dav_device_bytes(const stpci_ctx* c, const stpci_dav_opts& o) {
     const int64_t N = c->hs.sp.ndets;
     const int64_t vb = N * (int64_t)scalar_bytes(c);
-    const int k = o.k, kr = std::min(2 * k, 32);
-    const int mmax = subspace_cap(subspace_request(o), k, N);
+    const bool extra = o.certify || (o.refine_tol_energy > 0.0 && o.precision != STPCI_FP64);
+    const int k = o.k + ((extra && o.k < 16 && o.k < N) ? 1 : 0), kr = std::min(2 * k, 32);
+    stpci_dav_opts run = o;   // the options of the run, with the extra root of certify
+    run.k = k;
+    const int mmax = subspace_cap(subspace_request(run), k, N);
     int64_t b = vb * (2LL * mmax + 2LL * kr + 2LL * k);
     b += (int64_t)dots_blocks(N) * kDotsMax * 16 + (int64_t)kSmallBytes;
     if (!o.guess_dev) b += 1024LL * k * 16;  // top-k partials: at most 1024 blocks
@@ -389,6 +429,8 @@ static stpci_status dav_start(stpci_ctx* c, stpci_precision prec, const void* gu
     }
     D.G.assign((size_t)64 * 64, cplx(0, 0));
     D.theta.assign(k, 0.0);
+    D.theta_prev.clear();
+    D.energy_stop = false;
     D.rn.assign(k, 0.0);
     D.m = 0;
     D.nv = k;  // pending: W[0..k) = H V[0..k)
@@ -492,6 +534,23 @@ static stpci_status dav_advance(stpci_ctx* c) {
     };
     bool conv = true;
     for (int j = 0; j < k; ++j) conv = conv && D.rn[j] <= D.tol;
+    // FP64 refinement after a reduced-precision phase: with refine_tol_energy
+    // > 0 it also ends once the gap-theorem bound ||r_j||^2 / gamma_j^- of
+    // every requested root (gamma_j^- from the neighbouring Ritz pairs, the
+    // run carrying one root more) is below refine_tol_energy
+    const double rte = D.opts.refine_tol_energy;
+    const int kq = D.k_req > 0 ? D.k_req : k;
+    if (!conv && D.prec == STPCI_FP64 && D.it_prev > 0 && rte > 0.0 && kq < k) {
+        bool small = true;
+        for (int j = 0; j < kq; ++j) {
+            double g = (D.theta[j + 1] - D.rn[j + 1]) - D.theta[j];
+            if (j > 0) g = std::min(g, D.theta[j] - (D.theta[j - 1] + D.rn[j - 1]));
+            small = small && g > 0 && D.rn[j] * D.rn[j] / g < rte;
+        }
+        conv = small;
+        D.energy_stop = small;
+    }
+    D.theta_prev = D.theta;
     D.converged = conv;
     if (D.prec == STPCI_BF16 && !conv) {
         // the BF16 phase also ends when its largest residual has not dropped
@@ -509,8 +568,8 @@ static stpci_status dav_advance(stpci_ctx* c) {
         D.done = true;
         return fetch_dc();
     }
-    // corrections for unconverged roots (Eq. sparsePreconditioner, eps = 0)
-    // (one launch for all of them; k <= 16)
+    // corrections for unconverged roots (Eq. sparsePreconditioner with the
+    // run's eps; one launch for all of them, k <= 16)
     std::vector<int> proots;
     std::vector<double> pthetas;
     for (int j = 0; j < k; ++j) {
@@ -519,10 +578,8 @@ static stpci_status dav_advance(stpci_ctx* c) {
         pthetas.push_back(D.theta[j]);
     }
     const int nt = (int)proots.size();
-    if ((s = d.hip(launch_precond(c->dev, d.cx, (const double*)c->d_hd.p, (const double*)c->d_JK.p, c->e_core,
-                                  d.vec(c->d_R, 0), d.vec(c->d_T, 0), N, nt, proots.data(), pthetas.data(), 1e-12,
-                                  c->stream),
-                   "precond")))
+    if ((s = d.precondition(d.vec(c->d_R, 0), d.vec(c->d_T, 0), nt, proots.data(), pthetas.data(),
+                            D.opts.eps_drop)))
         return s;
     int mm = m;
     // thick restart when the space would overflow: keep the kr lowest Ritz
@@ -664,13 +721,24 @@ stpci_status dav_begin(stpci_ctx* c, const stpci_dav_opts* o) {
     if ((s = hip_check(c, hipSetDevice(c->device), "hipSetDevice"))) return s;
     const int64_t N = c->hs.sp.ndets;
     if (o->k < 1 || o->k > 16 || o->k > N) return set_err(c, STPCI_EINVAL, "k must be in [1, min(16, n_dets)]");
+    if (o->certify != 0 && o->certify != 1) return set_err(c, STPCI_EINVAL, "certify must be 0 or 1");
+    // with certify, one root more than requested is converged internally, so
+    // that the last requested root also has an upper neighbour for its gap
+    const bool extra = o->certify || (o->refine_tol_energy > 0.0 && o->precision != STPCI_FP64);
+    const int k_run = (extra && o->k < 16 && o->k < N) ? o->k + 1 : o->k;
     if (o->precision != STPCI_FP64 && o->precision != STPCI_FP32 && o->precision != STPCI_BF16)
         return set_err(c, STPCI_EINVAL, "unknown precision");
+    if (!(o->eps_drop >= 0.0 && o->eps_drop < 1.0))
+        return set_err(c, STPCI_EINVAL, "eps_drop must lie in [0, 1)");
+    if (!(o->refine_tol_energy >= 0.0) || !std::isfinite(o->refine_tol_energy))
+        return set_err(c, STPCI_EINVAL, "refine_tol_energy must be finite and >= 0");
     c->dav = DavState{};
     c->dav.opts = *o;
+    c->dav.opts.k = k_run;
+    c->dav.k_req = o->k;
     c->dav.final_tol = o->tol_residual > 0 ? o->tol_residual : 1e-8;
     c->history.clear();
-    c->hist_k = o->k;
+    c->hist_k = k_run;
     c->nsigma[0] = c->nsigma[1] = c->nsigma[2] = 0;
     // phase A: reduced-precision contractions to a residual their products
     // resolve (FP32 about 1e-7 relative, BF16 about 2^-9)
@@ -710,13 +778,35 @@ stpci_status dav_step_after_sigma(stpci_ctx* c, int* finished) {
     return STPCI_OK;
 }
 
+// Error bounds of the converged roots (Methods, Eigenvalue Bound Analysis):
+// the gap theorem |dE_j| <= ||r_j||^2 / gamma_j with the lower bound of the gap
+// from the neighbouring Ritz pairs, gamma_0^- = (E_1 - ||r_1||) - E_0 (Eq.
+// gammaLowerBound) and, for j > 0, also E_j - (E_{j-1} + ||r_{j-1}||) (the
+// neighbour below can lie at most its residual norm above its Ritz value).
+// Valid when no eigenvalue lies between the Ritz values (none missed);
+// gamma_j <= 0 gives no bound (infinity).  The last root run has no
+// neighbour above: NaN.
+static void certificate(const DavState& D, std::vector<double>& gam, std::vector<double>& bnd) {
+    const int kr = D.opts.k;
+    gam.assign(kr, std::nan(""));
+    bnd.assign(kr, std::nan(""));
+    for (int j = 0; j + 1 < kr; ++j) {
+        double g = (D.theta[j + 1] - D.rn[j + 1]) - D.theta[j];
+        if (j > 0) g = std::min(g, D.theta[j] - (D.theta[j - 1] + D.rn[j - 1]));
+        gam[j] = g;
+        bnd[j] = g > 0 ? D.rn[j] * D.rn[j] / g : std::numeric_limits<double>::infinity();
+    }
+}
+
 stpci_status dav_collect(stpci_ctx* c, double* energies, double* resid, void* vecs_dev, int* n_iter) {
     DavState& D = c->dav;
-    const int k = D.opts.k;
+    const int k = D.k_req > 0 ? D.k_req : D.opts.k;
     for (int j = 0; j < k; ++j) {
         energies[j] = D.theta[j];
         resid[j] = D.rn[j];
     }
+    certificate(D, c->cert_gamma, c->cert_bound);
+    c->cert_k = k;
     if (n_iter) *n_iter = D.it_prev + D.it;
     if (vecs_dev) {
         const size_t vb = (size_t)c->hs.sp.ndets * scalar_bytes(c) * k;
@@ -748,6 +838,16 @@ extern "C" stpci_status stpci_davidson(stpci_ctx* c, const stpci_dav_opts* o, do
         if (fin) break;
     }
     return dav_collect(c, energies, resid, vecs_dev, n_iter);
+}
+
+extern "C" stpci_status stpci_dav_certificate(const stpci_ctx* c, double* gamma_lower, double* bound) {
+    if (!c) return STPCI_EINVAL;
+    if (c->cert_k <= 0) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "no Davidson run to certify");
+    for (int j = 0; j < c->cert_k; ++j) {
+        if (gamma_lower) gamma_lower[j] = c->cert_gamma[j];
+        if (bound) bound[j] = c->cert_bound[j];
+    }
+    return STPCI_OK;
 }
 
 extern "C" stpci_status stpci_dav_stats(const stpci_ctx* c, int* sigma_fp64, int* sigma_fp32) {

@@ -172,6 +172,32 @@ __global__ __launch_bounds__(256) void k_precond(DevSpace S, const double* hd, c
     }
 }
 
+// Second step of Eq. sparsePreconditioner for several corrections at once:
+// t_q,i = s_q,i if |s_q,i| >= eps ||s_q||, else 0, with ||s_q||^2 read on the
+// device (the real part of the double at nrm2 + slot[q] * stride).
+struct DropRoots {
+    int n;
+    int slot[PRE_MAX];
+};
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_eps_drop(typename VT<CPLX>::T* __restrict__ t, int64_t ld, int64_t nd,
+                                                  DropRoots D, const double* __restrict__ nrm2, int stride,
+                                                  double eps) {
+    using V = VT<CPLX>;
+    double thr2[PRE_MAX];
+#pragma unroll
+    for (int q = 0; q < PRE_MAX; ++q) thr2[q] = (q < D.n) ? eps * eps * fmax(nrm2[(int64_t)D.slot[q] * stride], 0.0) : 0.0;
+    for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < nd; L += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < PRE_MAX; ++q) {
+            if (q >= D.n) break;
+            typename V::T* x = t + (int64_t)q * ld + L;
+            // |s| >= eps ||s||  <=>  |s|^2 >= eps^2 ||s||^2 (both sides non-negative)
+            if (V::abs2(*x) < thr2[q]) *x = V::zero();
+        }
+    }
+}
+
 // Lowest-k diagonal entries (value, address), ties to the lower address.
 constexpr int TOPK = 16;
 __global__ __launch_bounds__(256) void k_diag_topk(DevSpace S, const double* hd, const double* JK, double e_core,
@@ -582,6 +608,21 @@ hipError_t launch_axpy_core(bool cplx, void* sigma, const void* c, double e_core
     else
         hipLaunchKernelGGL(k_axpy_core<false>, dim3(g), dim3(256), 0, st, (double*)sigma, (const double*)c, e_core,
                            n);
+    return hipGetLastError();
+}
+
+hipError_t launch_eps_drop(bool cplx, void* t, int64_t ld, int64_t nd, int n, const int* slot, const double* nrm2,
+                           int stride, double eps, hipStream_t st) {
+    if (n < 1) return hipSuccess;
+    if (n > PRE_MAX) return hipErrorInvalidValue;
+    DropRoots D{};
+    D.n = n;
+    for (int q = 0; q < n; ++q) D.slot[q] = slot[q];
+    const int g = grid_for(nd, 256);
+    if (cplx)
+        hipLaunchKernelGGL(k_eps_drop<true>, dim3(g), dim3(256), 0, st, (cd*)t, ld, nd, D, nrm2, stride, eps);
+    else
+        hipLaunchKernelGGL(k_eps_drop<false>, dim3(g), dim3(256), 0, st, (double*)t, ld, nd, D, nrm2, stride, eps);
     return hipGetLastError();
 }
 

@@ -83,6 +83,7 @@ struct SbHostPlan {
     int64_t nitems[3][8] = {};
 };
 bool build_sb_plan(const HostSpace& H, SbHostPlan& plan);
+void sb_plan_counts(const SbHostPlan& plan, bool cplx, int nv, double* flops, int64_t* items);
 size_t pair_sb_lds_bytes(int cap, int nlmax);
 hipError_t launch_sigma_pair_sb(const DevSpace& S, const SbPlan& plan, bool cplx, bool f32, const void* A,
                                 const void* c, void* sigma, int n_vec, double e_core, const LaunchMarks* mk,
@@ -114,6 +115,10 @@ constexpr int PRE_MAX = 16;
 hipError_t launch_precond(const DevSpace& S, bool cplx, const double* hd, const double* JK, double e_core,
                           const void* r, void* t, int64_t ld, int n, const int* root, const double* theta,
                           double guard, hipStream_t st);
+// t_q <- 0 where |t_q,i| < eps ||t_q|| (Eq. sparsePreconditioner), ||t_q||^2
+// read on the device at nrm2[slot[q] * stride] (real part), q < n <= PRE_MAX
+hipError_t launch_eps_drop(bool cplx, void* t, int64_t ld, int64_t nd, int n, const int* slot, const double* nrm2,
+                           int stride, double eps, hipStream_t st);
 int topk_blocks(const DevSpace& S);
 hipError_t launch_diag_topk(const DevSpace& S, const double* hd, const double* JK, double e_core, int k,
                             double* vals, int64_t* idx, hipStream_t st);

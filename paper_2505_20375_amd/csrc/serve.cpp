@@ -236,7 +236,7 @@ static void retire(stpci_server* s, Req& q, stpci_status st) {
     q.state = (st == STPCI_OK || st == STPCI_ENOCONV) ? DONE : FAILED;
     if (q.ctx) {
         q.err = stpci_last_error(q.ctx);
-        q.sigma_vectors = q.ctx->nsigma[0] + q.ctx->nsigma[1];
+        q.sigma_vectors = q.ctx->nsigma[0] + q.ctx->nsigma[1] + q.ctx->nsigma[2];
     }
     q.t_done = now_s();
     stpci_destroy(q.ctx);

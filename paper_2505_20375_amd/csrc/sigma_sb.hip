@@ -278,6 +278,27 @@ bool build_sb_plan(const HostSpace& H, SbHostPlan& plan) {
     return true;
 }
 
+// Matrix-core flops and items of one launch sequence (one pass of at most
+// two vectors): per item, (npad rounded to 16) / 16 row tiles x (npad
+// rounded to 32) / 4 steps x its column groups x 2048 flop per
+// v_mfma_f64_16x16x4f64, twice for complex (the real and the imaginary part
+// of the table).
+void sb_plan_counts(const SbHostPlan& plan, bool cplx, int nv, double* flops, int64_t* items) {
+    const int cw = cplx ? 2 * nv : nv;
+    const int x = (cw == 1) ? 0 : (cw == 2 ? 1 : 2);
+    double f = 0;
+    int64_t it = 0;
+    for (int g = 1; g <= SB_NG; ++g)
+        for (int q = plan.sbegin[x][g - 1]; q < plan.sbegin[x][g]; ++q) {
+            const SbCat& c = plan.cats[plan.streams[q].cat];
+            const double nrt = (c.npad + 15) / 16, nks = ((c.npad + SB_TK - 1) / SB_TK) * (SB_TK / 4);
+            f += (double)c.ngroups * nrt * nks * g * 2048.0 * (cplx ? 2 : 1);
+            it += c.ngroups;
+        }
+    *flops = f;
+    *items = it;
+}
+
 bool pair_sb_supported(const Space& sp) {
     return sp.K >= 2 && sp.N >= 2 && sp.sub_m[sp.K - 1] <= 31 && sp.M <= 64;
 }

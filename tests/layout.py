@@ -96,3 +96,50 @@ def address(bits, n_elec, sub, lo=None, hi=None):
         a += local_rank(loc[k]) * stride
         stride *= math.comb(sub[k], t[k])
     return base + a
+
+
+def _rank_table(m):
+    """local_rank of every m-bit mask (the same sum of binomials as
+    local_rank, evaluated for all masks at once)."""
+    masks = np.arange(1 << m, dtype=np.int64)
+    rank = np.zeros(1 << m, dtype=np.int64)
+    seen = np.zeros(1 << m, dtype=np.int64)   # set bits below the current position
+    for b in range(m):
+        bit = (masks >> b) & 1
+        comb = np.array([math.comb(b, i + 1) for i in range(m + 1)], dtype=np.int64)
+        rank += bit * comb[seen]
+        seen += bit
+    return rank
+
+
+def address_array(bits, n_elec, sub, lo=None, hi=None):
+    """address() for an array of determinants at once (NumPy); -1 outside
+    the space."""
+    lo = list(lo) if lo is not None else [0] * len(sub)
+    hi = list(hi) if hi is not None else list(sub)
+    bits = np.asarray(bits, dtype=np.uint64)
+    cats = categories(n_elec, sub, lo, hi)
+    base, b = {}, 0
+    for c in cats:
+        base[c] = b
+        b += math.prod(math.comb(m, n) for m, n in zip(sub, c))
+    locs, occs, off = [], [], 0
+    for m in sub:
+        s = ((bits >> np.uint64(off)) & np.uint64((1 << m) - 1)).astype(np.int64)
+        locs.append(s)
+        occs.append(np.array([bin(int(x)).count("1") for x in range(1 << m)], dtype=np.int64)[s])
+        off += m
+    out = np.full(len(bits), -1, dtype=np.int64)
+    occ = np.stack(occs, axis=1)
+    tables = {m: _rank_table(m) for m in set(sub)}
+    for c in cats:
+        sel = np.all(occ == np.array(c), axis=1)
+        if not np.any(sel):
+            continue
+        a = np.zeros(int(sel.sum()), dtype=np.int64)
+        stride = 1
+        for k in reversed(range(len(sub))):
+            a += tables[sub[k]][locs[k][sel]] * stride
+            stride *= math.comb(sub[k], c[k])
+        out[sel] = base[c] + a
+    return out

@@ -128,17 +128,26 @@ def test_compression_preservation():
     assert rel_err(s, pb.oracle_sigma(c)) <= TOL
 
 
-def test_sigma_config2_full_size_sampled_rows():
-    """24 spinors, 8 electrons (735,471 determinants): full GPU sigma, oracle
-    on 3000 sampled rows (first, last and random)."""
-    print("case c2 full", flush=True)
-    pb = Problem.named("c2")
-    c = pb.vector()
-    s_gpu = _run_sigma(pb, c)
-    rng = np.random.default_rng(0)
-    rows = np.unique(np.concatenate([[0, len(pb.dets) - 1], rng.choice(len(pb.dets), 3000, replace=False)]))
-    s_ref = pb.oracle_sigma(c, rows=rows)
-    assert rel_err(s_gpu[rows], s_ref) <= TOL
+def test_sigma_config2_full_partitions():
+    """24 spinors, 8 electrons (735,471 determinants): the full sigma of the
+    default kernel of each partition (one subspace: the grouped kernel; 12|12
+    and 8|8|8 with open windows: the same space in other layouts) against the
+    full oracle sigma, element by element."""
+    import torch
+    print("case c2 full, oracle sigma", flush=True)
+    base = Problem.named("c2")
+    c = base.vector()
+    ref = base.oracle_sigma(c)
+    for sub in ([24], [12, 12], [8, 8, 8]):
+        pb = Problem(base.ints, synth.SpaceSpec(8, sub), seed=base.seed)
+        ctx = pb.context()
+        x = pb.to_device(c)
+        out = torch.empty_like(x)
+        ctx.sigma(x, out)
+        torch.cuda.synchronize()
+        err = rel_err(pb.from_device(out), ref)
+        print("partition", sub, ctx.sigma_kernel(), "rel err %.2e" % err, flush=True)
+        assert err <= TOL
 
 
 @pytest.mark.parametrize("kernel", ["pair", "pair_atomic", "pair_mf64", "pair_valu", "tile", "rowtile", "wave",
@@ -291,8 +300,10 @@ def test_grouped_pair_kernel_refuses_other_spaces():
 
 def test_default_kernel_is_pair():
     """The pair form is the default; with a pair table of at most 4 MB its FP64
-    products run on the matrix cores, with a larger one on the vector ALUs;
-    spaces of one subspace take the grouped matrix-core kernel."""
+    products run on the matrix cores; spaces of one subspace take the grouped
+    matrix-core kernel; a larger table over several subspaces takes the
+    spectator-batched matrix-core kernel (the vector-ALU kernel when that
+    kernel's limits are exceeded)."""
     import torch
     pb = Problem.named("T4")
     ctx = pb.context()
@@ -314,7 +325,7 @@ def test_default_kernel_is_pair():
     y = torch.zeros(n, dtype=torch.complex128, device="cuda")
     big.sigma(y, torch.empty_like(y))
     torch.cuda.synchronize()
-    assert big.sigma_kernel() == "pair_valu"
+    assert big.sigma_kernel() == "pair_sb"
 
 
 @pytest.mark.parametrize("kernel", ["pair", "pair_atomic", "pair_mf64", "pair_valu", "tile", "rowtile"])
@@ -381,10 +392,11 @@ def test_sparse_vector_after_dense(kernel, prec):
 def test_sigma_config3p_sampled_rows():
     """Full-size STP-DAS space (40 spinors, 12|16|12, windows [2..6]|[4..10]|[2..6],
     11 electrons: 1,365,867,360 determinants in 10 categories, 21.9 GB per
-    vector): one FP64 and one BF16 sigma build on a seeded vector in the library layout, checked
-    on sampled rows against the oracle's list-free Slater-Condon rows, with
-    every column address taken from the documented layout (test module), not
-    from the library."""
+    vector): one FP64 and one BF16 sigma build on a seeded vector in the
+    library layout, checked on 1000+ rows -- the first, middle and last
+    determinant of every category and random rows of every category --
+    against the oracle's list-free Slater-Condon rows, every column address
+    taken from the documented layout (test module), not from the library."""
     import time
     import torch
     from oracle import csc
@@ -398,23 +410,37 @@ def test_sigma_config3p_sampled_rows():
     ctx = stpci.Context(0)
     ctx.set_integrals(ints.h, ints.g)
     ctx.set_space(sp.n_elec, sp.sub, sp.lo, sp.hi)
-    n = ctx.space_info().n_dets
-    assert n == n_expect == 1365867360
+    info = ctx.space_info()
+    n = info.n_dets
+    assert n == n_expect == 1365867360 and info.n_cat == 10
     gen = torch.Generator(device="cuda").manual_seed(3103)
     c = torch.randn(n, dtype=torch.complex128, device="cuda", generator=gen)
     c /= torch.linalg.vector_norm(c)
     out = torch.empty_like(c)
     rng = np.random.default_rng(3203)
-    rows = [int(a) for a in rng.choice(n, 10, replace=False)]
-    refs = []
-    for a in rows:
-        bits = ctx.address_to_det(a)
-        assert layout.address(bits, sp.n_elec, sp.sub, sp.lo, sp.hi) == a
-        kb, vals = csc.h_row_window(sp.sub, sp.lo, sp.hi, ints.h, ints.g, bits)
-        cols = torch.tensor([layout.address(int(b), sp.n_elec, sp.sub, sp.lo, sp.hi) for b in kb],
-                            dtype=torch.int64, device="cuda")
-        refs.append(np.sum(vals * c[cols].cpu().numpy()))
-    refs = np.array(refs)
+    rows = []
+    for cat in range(info.n_cat):
+        _, off, cnt = ctx.category(cat)
+        rows += [off, off + cnt // 2, off + cnt - 1]
+        rows += [int(x) for x in off + rng.choice(cnt, 97, replace=False)]
+    rows = np.array(sorted(set(rows)), dtype=np.int64)
+    assert len(rows) >= 1000
+    t0 = time.time()
+    bits = np.array([ctx.address_to_det(int(a)) for a in rows], dtype=np.uint64)
+    assert np.array_equal(layout.address_array(bits, sp.n_elec, sp.sub, sp.lo, sp.hi), rows)
+    cols, vals, owner = [], [], []
+    for i, b in enumerate(bits):
+        kb, v = csc.h_row_window(sp.sub, sp.lo, sp.hi, ints.h, ints.g, int(b))
+        cols.append(kb)
+        vals.append(v)
+        owner.append(np.full(len(kb), i))
+    cols = layout.address_array(np.concatenate(cols), sp.n_elec, sp.sub, sp.lo, sp.hi)
+    assert np.all(cols >= 0)
+    vals, owner = np.concatenate(vals), np.concatenate(owner)
+    cvals = c[torch.from_numpy(cols).to("cuda")].cpu().numpy()
+    refs = np.zeros(len(rows), dtype=np.complex128)
+    np.add.at(refs, owner, vals * cvals)
+    print("oracle rows: %d rows, %d couplings, %.1f s" % (len(rows), len(cols), time.time() - t0), flush=True)
     errs = {}
     # the FP64 build (parity bar 1e-12), then the BF16 matrix-core build
     # (bfloat16 rounding bar 2e-2) of the same vector
@@ -425,11 +451,17 @@ def test_sigma_config3p_sampled_rows():
         torch.cuda.synchronize()
         print("config 3' sigma (%s) done in %.1f s (kernel %s)" % (name, time.time() - t0, ctx.sigma_kernel()),
               flush=True)
-        got = np.array([complex(out[a].item()) for a in rows])
+        got = out[torch.from_numpy(rows).to("cuda")].cpu().numpy()
         errs[name] = np.linalg.norm(got - refs) / np.linalg.norm(refs)
+        # every category on its own
+        for cat in range(info.n_cat):
+            _, off, cnt = ctx.category(cat)
+            sel = (rows >= off) & (rows < off + cnt)
+            e_cat = np.linalg.norm(got[sel] - refs[sel]) / np.linalg.norm(refs[sel])
+            assert e_cat <= (TOL if prec == stpci.FP64 else 2e-2), (name, cat, e_cat)
         print("config 3' sampled-row relative error (%s): %.3g" % (name, errs[name]), flush=True)
+    assert ctx.sigma_kernel() == "pair_sb"
     del c, out
     torch.cuda.empty_cache()
     assert errs["fp64"] <= TOL
     assert errs["bf16"] <= 2e-2
-

@@ -189,6 +189,25 @@ stpci_status stpci_sigma_kernel(const stpci_ctx* ctx, const char** name);
  * Asynchronous on the context stream. */
 stpci_status stpci_sigma(stpci_ctx* ctx, const void* c_dev, void* sigma_dev, int n_vec, stpci_precision prec);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sigma as stpci_sigma, same arguments, kernels and results, without any
+ * device allocation.  The store-and-reduce workspace of the pair kernels
+ * comes from a static device array of stpci_sigma_noalloc_max_bytes() bytes
+ * (256 MiB) that each device holds from the first context created on it
+ * until the process ends; every table must already be on the device, so
+ * call stpci_sigma (with the same precision) or stpci_diagonal once after
+ * the last stpci_set_integrals / stpci_set_space, else STPCI_ESTATE.  A space
+ * whose workspace (n_dets * N (N - 1) / 2 * 2 scalars, when the context's
+ * kernel uses the store-and-reduce scatter) exceeds the array: STPCI_EINVAL
+ * with the sizes in stpci_last_error.  No profiling events are recorded.  All
+ * calls on one device share the array and it keeps the last call's contents
+ * (each sigma writes the part it reads in full before reading it): calls
+ * that overlap on one device, on two streams or from two threads, race. */
+stpci_status stpci_sigma_noalloc(stpci_ctx* ctx, const void* c_dev, void* sigma_dev, int n_vec,
+                                 stpci_precision prec);
+int64_t stpci_sigma_noalloc_max_bytes(void);
+
 /* diag_dev[i] = <i|H|i> (real, n_dets doubles).  The solver itself never
  * stores the diagonal; this call exists for checks. */
 stpci_status stpci_diagonal(stpci_ctx* ctx, double* diag_dev);

@@ -66,6 +66,8 @@ _SIGS = {
     "stpci_work_counts": ([_P, _DP, _DP, _I64P, _IP], _I),
     "stpci_address_to_det": ([_P, _I64, ctypes.POINTER(ctypes.c_uint64)], _I),
     "stpci_sigma": ([_P, _P, _P, _I, _I], _I),
+    "stpci_sigma_noalloc": ([_P, _P, _P, _I, _I], _I),
+    "stpci_sigma_noalloc_max_bytes": ([], _I64),
     "stpci_diagonal": ([_P, _P], _I),
     "stpci_davidson": ([_P, ctypes.POINTER(DavOpts), _DP, _DP, _P, _IP], _I),
     "stpci_dav_history": ([_P, _IP, _I, _DP, _DP], _I),
@@ -99,6 +101,11 @@ for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
     _f.restype = _res
+
+
+def sigma_noalloc_max_bytes():
+    """Size of the static scratch array of stpci_sigma_noalloc (bytes)."""
+    return int(_lib.stpci_sigma_noalloc_max_bytes())
 
 
 class StpciError(RuntimeError):
@@ -203,6 +210,11 @@ class Context:
     # -- device work ----------------------------------------------------------
     def sigma(self, c, out, n_vec=1, precision=FP64):
         self._check(_lib.stpci_sigma(self._h, _ptr(c), _ptr(out), int(n_vec), int(precision)))
+
+    def sigma_noalloc(self, c, out, n_vec=1, precision=FP64):
+        """stpci_sigma_noalloc: the same sigma without device allocation
+        (workspace from the library's static scratch array)."""
+        self._check(_lib.stpci_sigma_noalloc(self._h, _ptr(c), _ptr(out), int(n_vec), int(precision)))
 
     def diagonal(self, out):
         self._check(_lib.stpci_diagonal(self._h, _ptr(out)))

@@ -338,7 +338,7 @@ stpci_status ensure32(stpci_ctx* c) {
     return STPCI_OK;
 }
 
-stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, stpci_precision prec) {
+stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, stpci_precision prec, void* ws) {
     if (prec != STPCI_FP64 && prec != STPCI_FP32 && prec != STPCI_BF16)
         return set_err(c, STPCI_EINVAL, "unsupported sigma precision");
     const bool f32 = prec == STPCI_FP32;
@@ -357,11 +357,12 @@ stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, st
             }
         } mark{c};
         const LaunchMarks mk{&Mark::fn, &mark};
-        void* E = nullptr;
-        if (c->pair_store) {
+        void* E = ws;
+        if (c->pair_store && !ws) {
             if ((s = ensure(c, c->d_E, pair_store_bytes(c->dev, c->cplx), "pair contribution workspace"))) return s;
             E = c->d_E.p;
         }
+        if (!c->pair_store) E = nullptr;
         e = launch_sigma_pair_mfma(c->dev, c->hs.pmax_deg, c->cplx, c->d_pAbf.p, cin, sout, E, n_vec, c->e_core,
                                    c->profile ? &mk : nullptr, c->stream);
         return e == hipSuccess ? STPCI_OK : hip_check(c, e, "sigma launch");
@@ -384,12 +385,13 @@ stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, st
             }
         } mark{c, kind};
         const LaunchMarks mk{&Mark::fn, &mark};
-        void* E = nullptr;
-        if (c->pair_store) {
+        void* E = ws;
+        if (c->pair_store && !ws) {
             stpci_status s = ensure(c, c->d_E, pair_store_bytes(c->dev, c->cplx), "pair contribution workspace");
             if (s) return s;
             E = c->d_E.p;
         }
+        if (!c->pair_store) E = nullptr;
         if (c->pair_sb && !f32)
             e = launch_sigma_pair_sb(c->dev, c->sb_plan, c->cplx, f32, f32 ? c->d_pA32.p : c->d_pA.p, cin, sout,
                                      n_vec, c->e_core, c->profile ? &mk : nullptr, c->stream);
@@ -455,6 +457,12 @@ stpci_status stpci_create(stpci_ctx** out, int hip_device, void* hip_stream) {
             return STPCI_EHIP;
         }
         if (hipSetDevice(hip_device) != hipSuccess) {
+            delete c;
+            return STPCI_EHIP;
+        }
+        // the no-allocation sigma's workspace: this device's address of the
+        // library's static scratch array, resolved once per device
+        if (scratch_setup(hip_device) != hipSuccess) {
             delete c;
             return STPCI_EHIP;
         }

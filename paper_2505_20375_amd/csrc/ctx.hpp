@@ -126,7 +126,11 @@ stpci_status set_err(stpci_ctx* c, stpci_status s, const std::string& msg);
 stpci_status hip_check(stpci_ctx* c, hipError_t e, const char* what);
 stpci_status prepare(stpci_ctx* c);
 stpci_status ensure(stpci_ctx* c, DevBuf& b, size_t bytes, const char* what);
-stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, stpci_precision prec);
+// ws: the pair kernels' store-and-reduce workspace to use instead of the
+// context's own (NULL: the context's, allocated on first use)
+stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, stpci_precision prec,
+                        void* ws = nullptr);
+hipError_t scratch_setup(int device);   // noalloc.hip
 stpci_status ensure32(stpci_ctx* c);  // upload the FP32 integral copies once
 stpci_status ensure_bf16(stpci_ctx* c);  // upload the bfloat16 pair table once
 int select_kernel(const stpci_ctx* c);

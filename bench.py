@@ -239,7 +239,8 @@ def _cpu_baseline_c3p(seconds):
     ctx = stpci.Context(-1)
     ctx.set_space(sp.n_elec, sp.sub, sp.lo, sp.hi)
     info = ctx.space_info()
-    nthreads = os.cpu_count() or 1
+    # the host share of one GPU: at most 16 threads, whatever the machine has
+    nthreads = max(1, min(16, len(os.sched_getaffinity(0))))
     rng = np.random.default_rng(0)
 
     def rows_work(bits_list):
@@ -252,21 +253,34 @@ def _cpu_baseline_c3p(seconds):
             tot += len(kb)
         return tot
 
-    def run(nrows):
+    def run(nrows, nth):
         addrs = rng.choice(info.n_dets, nrows, replace=False)
         bits = [ctx.address_to_det(int(a)) for a in addrs]
-        parts = [bits[i::nthreads] for i in range(nthreads)]
+        parts = [bits[i::nth] for i in range(nth)]
         t0 = time.perf_counter()
-        with ThreadPoolExecutor(nthreads) as ex:
+        with ThreadPoolExecutor(nth) as ex:
             tot = sum(ex.map(rows_work, parts))
         return tot, time.perf_counter() - t0
 
-    tot, t = run(max(nthreads * 8, 64))
+    tot, t = run(max(nthreads * 8, 64), nthreads)
     nrows = int(max(64, nthreads * 8 * seconds / max(t, 1e-3)))
-    tot, t = run(nrows)
+    tot, t = run(nrows, nthreads)
+    # one thread, a quarter of the time
+    n1 = max(16, nrows // (4 * nthreads))
+    tot1, t1 = run(n1, 1)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": tot / t, "unit": "det-updates/s", "cores": nthreads, "kind": "oracle",
+            "value_1_thread": tot1 / t1, "cpu_model": model,
             "sample": "%d random rows of the 40-spinor 12|16|12 11-electron space (%d nonzero couplings, "
-                      "list-free row-driven Slater-Condon, %.1f s on %d threads)" % (nrows, tot, t, nthreads)}
+                      "list-free row-driven Slater-Condon, %.1f s on %d threads; one thread: %d rows, %.1f s)"
+                      % (nrows, tot, t, nthreads, n1, t1)}
 
 
 def _config2(args):

@@ -263,6 +263,47 @@ stpci_status stpci_davidson(stpci_ctx* ctx, const stpci_dav_opts* opts, double* 
  * Host arrays of k doubles (either may be NULL); STPCI_ESTATE before any run. */
 stpci_status stpci_dav_certificate(const stpci_ctx* ctx, double* gamma_lower, double* bound);
 
+/* Step-wise Davidson: the same solver as stpci_davidson cut into the steps a
+ * caller needs to drive several problems side by side on one device (its own
+ * admission and batching loop; stpci_server_* is such a loop):
+ *   stpci_footprint_bytes(ctx, opts): device bytes the context holds during
+ *     such a run -- tables, integrals (with the FP32 or bfloat16 copies the
+ *     precision needs), the Davidson vectors and workspace; the pair kernels'
+ *     store-and-reduce workspace is counted when it is at most 1 GB (a larger
+ *     one is used only if it fits a quarter of the free device memory when
+ *     the tables are built).  -1 for NULL arguments, missing integrals or
+ *     space, or k out of range.  Host-only computation.
+ *   stpci_dav_begin(ctx, opts): validate the options (as stpci_davidson),
+ *     build the tables, allocate the vectors and set up the starting guess;
+ *     its products become pending.
+ *   stpci_dav_sigma_batched(ctxs, n): compute the pending sigma products of
+ *     the n contexts (distinct, one device; contexts without pending products
+ *     are skipped).  Contexts whose kernel has a grouped form (the pair kernel
+ *     on the vector ALUs or, FP64, one intermediate per matrix-core product;
+ *     the one-move tile kernel) are contracted in one launch per kernel,
+ *     scalar type and precision over their concatenated intermediates, on
+ *     ctxs[0]'s stream, after each context's stream has drained; the others
+ *     (BF16 contractions, spaces of one subspace, the spectator-batched
+ *     kernel) run on their own path and stream.  Returns when the grouped
+ *     launches have completed.  On failure: the status of the first failing
+ *     context (its stpci_last_error says why), or of ctxs[0] for a failure of
+ *     a grouped launch.
+ *   stpci_dav_finish_step(ctx, done): one Davidson iteration on the computed
+ *     products (Rayleigh-Ritz, residuals, convergence test, preconditioner,
+ *     orthogonalisation, restart) on ctx's stream; *done = 1 when the run
+ *     has ended (converged, max_iter or stagnation), else its next products
+ *     are pending.  STPCI_ESTATE without a run in progress or before its
+ *     products were computed.
+ *   stpci_dav_result(ctx, energies, resid, vecs_dev, n_iter): results of the
+ *     finished run as stpci_davidson returns them (STPCI_ENOCONV when it
+ *     ended unconverged); STPCI_ESTATE before the run has ended.  The gap
+ *     certificate is then available from stpci_dav_certificate. */
+int64_t stpci_footprint_bytes(const stpci_ctx* ctx, const stpci_dav_opts* opts);
+stpci_status stpci_dav_begin(stpci_ctx* ctx, const stpci_dav_opts* opts);
+stpci_status stpci_dav_sigma_batched(stpci_ctx* const* ctxs, int n);
+stpci_status stpci_dav_finish_step(stpci_ctx* ctx, int* done);
+stpci_status stpci_dav_result(stpci_ctx* ctx, double* energies, double* resid, void* vecs_dev, int* n_iter);
+
 /* Per-iteration record of the last Davidson run: iteration count, and for
  * iteration i < cap the Ritz values energies[i*k + j] and residual norms
  * resid[i*k + j].  Either array may be NULL. */

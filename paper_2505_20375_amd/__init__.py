@@ -73,6 +73,11 @@ _SIGS = {
     "stpci_dav_history": ([_P, _IP, _I, _DP, _DP], _I),
     "stpci_dav_stats": ([_P, _IP, _IP], _I),
     "stpci_dav_certificate": ([_P, _DP, _DP], _I),
+    "stpci_footprint_bytes": ([_P, ctypes.POINTER(DavOpts)], _I64),
+    "stpci_dav_begin": ([_P, ctypes.POINTER(DavOpts)], _I),
+    "stpci_dav_sigma_batched": ([ctypes.POINTER(ctypes.c_void_p), _I], _I),
+    "stpci_dav_finish_step": ([_P, _IP], _I),
+    "stpci_dav_result": ([_P, _DP, _DP, _P, _IP], _I),
     "stpci_dav_sigma_count": ([_P, _I, _IP], _I),
     "stpci_dav_history_dc": ([_P, _I, _DP], _I),
     "stpci_profile": ([_P, _I], _I),
@@ -101,6 +106,21 @@ for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
     _f.restype = _res
+
+
+def dav_sigma_batched(ctxs):
+    """stpci_dav_sigma_batched: the pending sigma products of several
+    step-wise Davidson runs (Context objects on one device), grouped."""
+    arr = (ctypes.c_void_p * len(ctxs))(*[c._h.value for c in ctxs])
+    st = _lib.stpci_dav_sigma_batched(arr, len(ctxs))
+    if st != OK:
+        msg = "stpci_dav_sigma_batched failed"
+        for c in ctxs:
+            m = _lib.stpci_last_error(c._h).decode()
+            if m:
+                msg += ": " + m
+                break
+        raise StpciError(st, msg)
 
 
 def sigma_noalloc_max_bytes():
@@ -231,6 +251,40 @@ class Context:
         self._cert_k = int(k)
         st = _lib.stpci_davidson(self._h, ctypes.byref(o), e, r, _ptr(vecs) if vecs is not None else None,
                                  ctypes.byref(it))
+        if st != OK and not (allow_noconv and st == ENOCONV):
+            self._check(st)
+        return np.array(e[:]), np.array(r[:]), it.value, st
+
+    # -- step-wise Davidson (stpci_dav_begin ... stpci_dav_result) -----------
+    @staticmethod
+    def _opts(k, tol, max_iter, max_subspace, eps_drop, precision, refine_tol_energy, certify):
+        return DavOpts(int(k), int(max_iter), int(max_subspace), float(tol), float(eps_drop), int(precision),
+                       float(refine_tol_energy), None, int(bool(certify)))
+
+    def footprint_bytes(self, k=1, tol=1e-8, max_iter=100, max_subspace=0, eps_drop=0.0, precision=FP64,
+                        refine_tol_energy=0.0, certify=False):
+        o = self._opts(k, tol, max_iter, max_subspace, eps_drop, precision, refine_tol_energy, certify)
+        return int(_lib.stpci_footprint_bytes(self._h, ctypes.byref(o)))
+
+    def dav_begin(self, k=1, tol=1e-8, max_iter=100, max_subspace=0, eps_drop=0.0, precision=FP64,
+                  refine_tol_energy=0.0, certify=False):
+        o = self._opts(k, tol, max_iter, max_subspace, eps_drop, precision, refine_tol_energy, certify)
+        self._step_k = int(k)
+        self._cert_k = int(k)
+        self._check(_lib.stpci_dav_begin(self._h, ctypes.byref(o)))
+
+    def dav_finish_step(self):
+        """One Davidson iteration after the pending products; True when done."""
+        d = ctypes.c_int()
+        self._check(_lib.stpci_dav_finish_step(self._h, ctypes.byref(d)))
+        return bool(d.value)
+
+    def dav_result(self, vecs=None, allow_noconv=False):
+        k = getattr(self, "_step_k", 1)
+        e = (ctypes.c_double * k)()
+        r = (ctypes.c_double * k)()
+        it = ctypes.c_int()
+        st = _lib.stpci_dav_result(self._h, e, r, _ptr(vecs) if vecs is not None else None, ctypes.byref(it))
         if st != OK and not (allow_noconv and st == ENOCONV):
             self._check(st)
         return np.array(e[:]), np.array(r[:]), it.value, st

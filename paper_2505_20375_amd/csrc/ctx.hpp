@@ -50,6 +50,7 @@ struct DavState {
     int k_req = 0;                    // roots requested (opts.k may hold one more, see certify)
     std::vector<double> theta_prev;   // Ritz values of the previous iteration of this phase
     bool energy_stop = false;         // the FP64 refinement ended on refine_tol_energy
+    bool products_ready = false;      // step-wise runs: the pending products were computed
 };
 
 }  // namespace stp
@@ -87,6 +88,7 @@ struct stpci_ctx {
     bool have_bf = false;
     stp::DevBuf d_pcats, d_pwork, d_pslot, d_pA, d_pA32, d_pAbf;
     stp::DevBuf d_E;         // pair contributions of the store-and-reduce scatter
+    stp::DevBuf d_bdesc, d_bjbegin;   // descriptors of stpci_dav_sigma_batched launches led by this context
     bool pair_store = false; // pair kernel: store-and-reduce (true) or device atomics
     bool pair_mf64 = false;   // FP64 pair products on the matrix cores (else the vector-ALU tiles)
     bool pair_grp = false;    // FP64 pair products of grouped intermediates (spaces of one subspace)

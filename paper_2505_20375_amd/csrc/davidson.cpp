@@ -765,6 +765,7 @@ bool dav_pending(stpci_ctx* c, const void** in, void** out, int* n, stpci_precis
 // FP64 refinement (guess = its Ritz vectors) when the former ends.
 stpci_status dav_step_after_sigma(stpci_ctx* c, int* finished) {
     DavState& D = c->dav;
+    D.products_ready = false;
     stpci_status s = dav_advance(c);
     if (s) return s;
     if (D.done && D.prec != STPCI_FP64) {

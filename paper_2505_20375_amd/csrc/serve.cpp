@@ -141,6 +141,131 @@ static stpci_status srv_err(stpci_server* s, stpci_status st, const std::string&
     return st;
 }
 
+// The pending sigma products of several step-wise Davidson runs on one
+// device.  Where a grouped kernel applies (the one-move tile kernel, the pair
+// kernel on the vector ALUs, or FP64 products one intermediate per
+// matrix-core product) the products of all such runs go into one launch per
+// kernel, scalar type and precision over their concatenated intermediate
+// ranges, on `stream`; the others (BF16 contractions, spaces of one subspace,
+// the spectator-batched kernel, one-move forms outside the tile kernel's
+// limits) run on each context's own path and stream.  st[i]: status of
+// ctxs[i] (its error text in its stpci_last_error); ran[i]: its products were
+// computed (contexts without pending products are skipped).  A failure not
+// tied to one context (descriptor upload, a grouped launch) is returned, with
+// its text in err.
+static stpci_status sigma_batch(stpci_ctx* const* ctxs, int n, hipStream_t stream, DevBuf& d_desc,
+                                DevBuf& d_jbegin, std::vector<stpci_status>& st, std::vector<char>& ran,
+                                int64_t* launches, std::string& err) {
+    st.assign(n, STPCI_OK);
+    ran.assign(n, 0);
+    struct Item {
+        int i;
+        SigmaDesc d;
+        int64_t nj;
+    };
+    std::vector<Item> groups[3][2][2];   // [tile, pair vector ALUs, pair FP64 matrix cores][complex][FP32]
+    for (int i = 0; i < n; ++i) {
+        stpci_ctx* c = ctxs[i];
+        const void* in;
+        void* out;
+        int nv;
+        stpci_precision prec;
+        if (!dav_pending(c, &in, &out, &nv, &prec)) continue;
+        const bool f32 = prec == STPCI_FP32;
+        if (c->s2_kernel < 3 || prec == STPCI_BF16 || c->pair_grp || c->pair_sb) {
+            st[i] = sigma_impl(c, in, out, nv, prec);
+            ran[i] = st[i] == STPCI_OK;
+            continue;
+        }
+        // the FP32 copies of the integrals, uploaded once (sigma_impl does
+        // this on the context's own path)
+        if (f32 && (st[i] = ensure32(c))) continue;
+        const bool pair = c->s2_kernel == 4;
+        const size_t vb = (size_t)c->hs.sp.ndets * scalar_bytes(c);
+        const void* tab = pair ? (f32 ? c->d_pA32.p : c->d_pA.p) : (f32 ? c->d_gT32.p : c->d_gT.p);
+        const void* hpt = pair ? tab : (f32 ? c->d_hp32.p : c->d_hp.p);
+        if (!tab || !hpt) {
+            st[i] = set_err(c, STPCI_ESTATE, "integral tables of the grouped launch are not on the device");
+            continue;
+        }
+        for (int v0 = 0; v0 < nv; v0 += 2) {
+            Item it;
+            it.i = i;
+            it.d.S = c->dev;
+            if (pair) {
+                it.d.gT = f32 ? c->d_pA32.p : c->d_pA.p;
+                it.d.hp = nullptr;
+                it.d.deg = c->hs.pmax_deg;
+                it.nj = c->hs.sp.npwork_dets;
+            } else {
+                it.d.gT = f32 ? c->d_gT32.p : c->d_gT.p;
+                it.d.hp = f32 ? c->d_hp32.p : c->d_hp.p;
+                it.d.deg = c->hs.max_deg;
+                it.nj = c->hs.sp.nwork_dets;
+            }
+            it.d.c = (const char*)in + v0 * vb;
+            it.d.sigma = (char*)out + v0 * vb;
+            it.d.e_core = c->e_core;
+            it.d.n_vec = std::min(2, nv - v0);
+            const int kind = !pair ? 0 : (c->pair_mf64 && !f32) ? 2 : 1;
+            groups[kind][c->cplx ? 1 : 0][f32 ? 1 : 0].push_back(it);
+        }
+    }
+    // the grouped launches read vectors the contexts' own streams wrote
+    for (int pk = 0; pk < 3; ++pk)
+        for (int cx = 0; cx < 2; ++cx)
+            for (int f = 0; f < 2; ++f)
+                for (auto& it : groups[pk][cx][f])
+                    if (hipStreamSynchronize(ctxs[it.i]->stream) != hipSuccess) {
+                        err = "context stream synchronisation failed";
+                        return STPCI_EHIP;
+                    }
+    for (int pk = 0; pk < 3; ++pk)
+        for (int cx = 0; cx < 2; ++cx)
+            for (int f = 0; f < 2; ++f) {
+                auto& G = groups[pk][cx][f];
+                if (G.empty()) continue;
+                std::vector<SigmaDesc> desc;
+                std::vector<int64_t> jb(1, 0);
+                int deg = 0;
+                for (auto& it : G) {
+                    desc.push_back(it.d);
+                    jb.push_back(jb.back() + it.nj);
+                    deg = std::max(deg, it.d.deg);
+                }
+                stpci_status e0 = ensure(nullptr, d_desc, desc.size() * sizeof(SigmaDesc), "descriptors");
+                if (!e0) e0 = ensure(nullptr, d_jbegin, jb.size() * 8, "descriptor offsets");
+                if (e0) {
+                    err = "descriptor allocation failed";
+                    return e0;
+                }
+                hipError_t e = hipMemcpyAsync(d_desc.p, desc.data(), desc.size() * sizeof(SigmaDesc),
+                                              hipMemcpyHostToDevice, stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(d_jbegin.p, jb.data(), jb.size() * 8, hipMemcpyHostToDevice, stream);
+                if (e == hipSuccess)
+                    e = pk == 2 ? launch_sigma_pair_mf64_multi((const SigmaDesc*)d_desc.p, (int)desc.size(),
+                                                               (const int64_t*)d_jbegin.p, jb.back(), deg, cx == 1,
+                                                               stream)
+                        : pk ? launch_sigma_pair_multi((const SigmaDesc*)d_desc.p, (int)desc.size(),
+                                                     (const int64_t*)d_jbegin.p, jb.back(), deg, cx == 1, f == 1,
+                                                     stream)
+                           : launch_sigma_multi((const SigmaDesc*)d_desc.p, (int)desc.size(),
+                                                (const int64_t*)d_jbegin.p, jb.back(), deg, cx == 1, f == 1,
+                                                stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(stream);  // descriptors are reused next launch
+                if (e != hipSuccess) {
+                    err = hipGetErrorString(e);
+                    return STPCI_EHIP;
+                }
+                if (launches) ++*launches;
+                for (auto& it : G) ran[it.i] = 1;
+            }
+    for (int i = 0; i < n; ++i)
+        if (ran[i]) ctxs[i]->dav.products_ready = true;
+    return STPCI_OK;
+}
+
 extern "C" {
 
 stpci_status stpci_server_create(stpci_server** out, int hip_device, void* hip_stream, int64_t mem_budget_bytes,
@@ -279,104 +404,27 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
     }
     s->peak_used = std::max(s->peak_used, s->used);
     s->peak_active = std::max(s->peak_active, (int)s->active.size());
-    // 2. pending sigma products of all active requests, grouped by scalar type and precision
-    struct Item {
-        int id;
-        SigmaDesc d;
-        int64_t nj;
-    };
-    std::vector<Item> groups[3][2][2];   // [tile, pair vector ALUs, pair FP64 matrix cores][complex][FP32]
-    std::vector<int> solo;
+    // 2. pending sigma products of all active requests, grouped by kernel,
+    // scalar type and precision
     const std::vector<int> admitted(s->active);  // retire() edits the active list
-    for (int id : admitted) {
-        Req& q = *s->reqs[id];
-        const void* in;
-        void* out;
-        int n;
-        stpci_precision prec;
-        if (!dav_pending(q.ctx, &in, &out, &n, &prec)) continue;
-        stpci_ctx* c = q.ctx;
-        const bool f32 = prec == STPCI_FP32;
-        if (c->s2_kernel < 3 || prec == STPCI_BF16 || c->pair_grp) {
-            // spaces outside the tile kernel's limits, the BF16 contraction and
-            // spaces of one subspace (grouped intermediates) take the
-            // context's own path, on the request's stream
-            stpci_status st = sigma_impl(c, in, out, n, prec);
-            if (st) {
-                retire(s, q, st);
-                ++finished;
-            } else {
-                solo.push_back(id);
-            }
-            continue;
-        }
-        const bool pair = c->s2_kernel == 4;
-        const size_t vb = (size_t)c->hs.sp.ndets * scalar_bytes(c);
-        for (int v0 = 0; v0 < n; v0 += 2) {
-            Item it;
-            it.id = id;
-            it.d.S = c->dev;
-            if (pair) {
-                it.d.gT = f32 ? c->d_pA32.p : c->d_pA.p;
-                it.d.hp = nullptr;
-                it.d.deg = c->hs.pmax_deg;
-                it.nj = c->hs.sp.npwork_dets;
-            } else {
-                it.d.gT = f32 ? c->d_gT32.p : c->d_gT.p;
-                it.d.hp = f32 ? c->d_hp32.p : c->d_hp.p;
-                it.d.deg = c->hs.max_deg;
-                it.nj = c->hs.sp.nwork_dets;
-            }
-            it.d.c = (const char*)in + v0 * vb;
-            it.d.sigma = (char*)out + v0 * vb;
-            it.d.e_core = c->e_core;
-            it.d.n_vec = std::min(2, n - v0);
-            const int kind = !pair ? 0 : (c->pair_mf64 && !f32) ? 2 : 1;
-            groups[kind][c->cplx ? 1 : 0][f32 ? 1 : 0].push_back(it);
+    std::vector<stpci_ctx*> cs;
+    for (int id : admitted) cs.push_back(s->reqs[id]->ctx);
+    std::vector<stpci_status> bst;
+    std::vector<char> ran;
+    std::string berr;
+    stpci_status bs = sigma_batch(cs.data(), (int)cs.size(), s->stream, s->d_desc, s->d_jbegin, bst, ran,
+                                  &s->grouped_launches, berr);
+    if (bs) return srv_err(s, bs, berr);
+    std::vector<int> stepped;
+    for (size_t i = 0; i < admitted.size(); ++i) {
+        Req& q = *s->reqs[admitted[i]];
+        if (bst[i]) {
+            retire(s, q, bst[i]);
+            ++finished;
+        } else if (ran[i]) {
+            stepped.push_back(q.id);
         }
     }
-    std::vector<int> stepped(solo);
-    // the grouped launches read vectors the requests' own streams wrote
-    for (int pk = 0; pk < 3; ++pk)
-        for (int cx = 0; cx < 2; ++cx)
-            for (int f = 0; f < 2; ++f)
-                for (auto& it : groups[pk][cx][f])
-                    if (hipStreamSynchronize(s->reqs[it.id]->stream) != hipSuccess)
-                        return srv_err(s, STPCI_EHIP, "request stream synchronisation failed");
-    for (int pk = 0; pk < 3; ++pk)
-    for (int cx = 0; cx < 2; ++cx)
-        for (int f = 0; f < 2; ++f) {
-            auto& G = groups[pk][cx][f];
-            if (G.empty()) continue;
-            std::vector<SigmaDesc> desc;
-            std::vector<int64_t> jb(1, 0);
-            int deg = 0;
-            for (auto& it : G) {
-                desc.push_back(it.d);
-                jb.push_back(jb.back() + it.nj);
-                deg = std::max(deg, it.d.deg);
-                if (stepped.empty() || stepped.back() != it.id) stepped.push_back(it.id);
-            }
-            stpci_status st = ensure(nullptr, s->d_desc, desc.size() * sizeof(SigmaDesc), "descriptors");
-            if (!st) st = ensure(nullptr, s->d_jbegin, jb.size() * 8, "descriptor offsets");
-            if (st) return srv_err(s, st, "descriptor allocation failed");
-            hipError_t e = hipMemcpyAsync(s->d_desc.p, desc.data(), desc.size() * sizeof(SigmaDesc),
-                                          hipMemcpyHostToDevice, s->stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(s->d_jbegin.p, jb.data(), jb.size() * 8, hipMemcpyHostToDevice, s->stream);
-            if (e == hipSuccess)
-                e = pk == 2 ? launch_sigma_pair_mf64_multi((const SigmaDesc*)s->d_desc.p, (int)desc.size(),
-                                                           (const int64_t*)s->d_jbegin.p, jb.back(), deg, cx == 1,
-                                                           s->stream)
-                    : pk ? launch_sigma_pair_multi((const SigmaDesc*)s->d_desc.p, (int)desc.size(),
-                                                 (const int64_t*)s->d_jbegin.p, jb.back(), deg, cx == 1, f == 1,
-                                                 s->stream)
-                       : launch_sigma_multi((const SigmaDesc*)s->d_desc.p, (int)desc.size(),
-                                            (const int64_t*)s->d_jbegin.p, jb.back(), deg, cx == 1, f == 1, s->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // descriptors are reused next launch
-            if (e != hipSuccess) return srv_err(s, STPCI_EHIP, hipGetErrorString(e));
-            ++s->grouped_launches;
-        }
     // 3. one Davidson iteration for every request whose products were
     // computed, on worker threads (each request on its own stream; a
     // request's state is touched by one thread only)
@@ -453,6 +501,68 @@ stpci_status stpci_server_stats(const stpci_server* s, int64_t* used_bytes, int6
     if (ticks) *ticks = s->ticks;
     if (grouped_launches) *grouped_launches = s->grouped_launches;
     return STPCI_OK;
+}
+
+// ---- step-wise Davidson: the server's steps as separate calls -------------
+
+int64_t stpci_footprint_bytes(const stpci_ctx* c, const stpci_dav_opts* o) {
+    if (!c || !o || !c->have_ints || !c->have_space || c->hs.sp.M != c->M) return -1;
+    if (o->k < 1 || o->k > 16 || o->k > c->hs.sp.ndets) return -1;
+    stpci_dav_opts oo = *o;
+    // the extra root of a certified run or of the energy stop
+    const bool extra = o->certify || (o->refine_tol_energy > 0.0 && o->precision != STPCI_FP64);
+    if (extra && oo.k < 16 && oo.k < c->hs.sp.ndets) ++oo.k;
+    return footprint(c, oo);
+}
+
+stpci_status stpci_dav_begin(stpci_ctx* c, const stpci_dav_opts* o) {
+    if (!c || !o) return STPCI_EINVAL;
+    if (c->host_only) return set_err(c, STPCI_ESTATE, "host-only context");
+    stpci_status st = dav_begin(c, o);
+    if (!st && o->precision == STPCI_FP32) st = ensure32(c);   // tables of the FP32 phase
+    return st;
+}
+
+stpci_status stpci_dav_sigma_batched(stpci_ctx* const* ctxs, int n) {
+    if (!ctxs || n < 1) return STPCI_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!ctxs[i]) return STPCI_EINVAL;
+    stpci_ctx* lead = ctxs[0];
+    for (int i = 0; i < n; ++i) {
+        if (ctxs[i]->host_only) return set_err(ctxs[i], STPCI_ESTATE, "host-only context");
+        if (ctxs[i]->device != lead->device)
+            return set_err(ctxs[i], STPCI_EINVAL, "contexts of one batched call must share a device");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return set_err(ctxs[i], STPCI_EINVAL, "a context appears twice");
+    }
+    if (hipSetDevice(lead->device) != hipSuccess) return set_err(lead, STPCI_EHIP, "hipSetDevice");
+    std::vector<stpci_status> st;
+    std::vector<char> ran;
+    std::string err;
+    int64_t launches = 0;
+    stpci_status s = sigma_batch(ctxs, n, lead->stream, lead->d_bdesc, lead->d_bjbegin, st, ran, &launches, err);
+    if (s) return set_err(lead, s, err);
+    for (int i = 0; i < n; ++i)
+        if (st[i]) return st[i];   // the context's own error text is set
+    return STPCI_OK;
+}
+
+stpci_status stpci_dav_finish_step(stpci_ctx* c, int* done) {
+    if (!c || !done) return STPCI_EINVAL;
+    *done = 0;
+    DavState& D = c->dav;
+    if (!D.active) return set_err(c, STPCI_ESTATE, "no step-wise Davidson run in progress");
+    if (!D.products_ready)
+        return set_err(c, STPCI_ESTATE, "the pending sigma products were not computed (stpci_dav_sigma_batched)");
+    if (hipSetDevice(c->device) != hipSuccess) return set_err(c, STPCI_EHIP, "hipSetDevice");
+    return dav_step_after_sigma(c, done);
+}
+
+stpci_status stpci_dav_result(stpci_ctx* c, double* energies, double* resid, void* vecs_dev, int* n_iter) {
+    if (!c || !energies || !resid) return STPCI_EINVAL;
+    if (!c->dav.done) return set_err(c, STPCI_ESTATE, "the Davidson run has not finished");
+    if (hipSetDevice(c->device) != hipSuccess) return set_err(c, STPCI_EHIP, "hipSetDevice");
+    return dav_collect(c, energies, resid, vecs_dev, n_iter);
 }
 
 }  // extern "C"

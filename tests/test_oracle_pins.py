@@ -228,3 +228,22 @@ def test_windowed_row_equals_listed_row(n, sub, lo, hi):
         b = dict(zip(bits.tolist(), v2))
         assert a.keys() == b.keys()
         assert max(abs(a[k] - b[k]) for k in a) < 1e-14
+
+
+def test_oracle_preconditioner_hand_values():
+    """Eq. sparsePreconditioner on a hand-worked case: r = (1, 2, 3, 4, 1),
+    H_ii = (0, 1, 2, 5, 2 - 1e-13), theta = 2: denominators (2, 1, 0, -3,
+    1e-13), so s = (1/2, 2, 0, -4/3, 0) (the last two below the 1e-12 guard);
+    ||s||^2 = 1/4 + 4 + 16/9 = 217/36, so eps = 0.3 keeps |s_i| >= 0.3
+    sqrt(217)/6 = 0.7365: (0, 2, 0, -4/3, 0)."""
+    from oracle import davidson as odav
+    r = np.array([1.0, 2.0, 3.0, 4.0, 1.0])
+    d = np.array([0.0, 1.0, 2.0, 5.0, 2.0 - 1e-13])
+    s0 = odav.precondition(r, 2.0, d)
+    assert np.allclose(s0, [0.5, 2.0, 0.0, -4.0 / 3.0, 0.0], rtol=0, atol=1e-15)
+    s1 = odav.precondition(r, 2.0, d, eps=0.3)
+    assert np.allclose(s1, [0.0, 2.0, 0.0, -4.0 / 3.0, 0.0], rtol=0, atol=1e-15)
+    # just above and below the threshold of the first entry: 0.5 / sqrt(217/36)
+    t = 0.5 / np.sqrt(217.0 / 36.0)
+    assert odav.precondition(r, 2.0, d, eps=t * (1 - 1e-9))[0] == 0.5
+    assert odav.precondition(r, 2.0, d, eps=t * (1 + 1e-9))[0] == 0.0

@@ -21,16 +21,17 @@
 //
 // Kernel shape (gfx950): one workgroup of eight wavefronts per compute unit
 // (two per SIMD), persistent over the items; each XCD works through a
-// contiguous eighth of them.  An item's right-hand side is at most eight
-// 16-column groups (128 columns); each wavefront owns one 16-row tile of E
+// contiguous eighth of them.  An item's right-hand side is at most four
+// 16-column groups (64 columns); each wavefront owns one 16-row tile of E
 // per pass and accumulates all column groups with v_mfma_f64_16x16x4f64
 // (complex: one product with the real and one with the imaginary part of
-// the table, combined by a lane exchange).  B is built 32 rows at a time
+// the table, combined by a lane exchange).  B is built 64 rows at a time
 // into LDS (double buffered, the gathers of the next chunk in flight during
-// the products of the current one); each table fragment (one 16-byte read
-// per lane) feeds 16 products.  E is added to sigma with device atomics
-// (sigma is not bitwise deterministic).  F32: FP32 table, right-hand side
-// and accumulation (v_mfma_f32_16x16x4f32), FP64 atomics.
+// the products of the current one; every entry formed without branches);
+// each table fragment (one 16-byte read per lane) feeds one product per
+// column group and table part.  E is added to sigma with device atomics
+// (sigma is not bitwise deterministic).  FP64 only: the FP32 contraction of
+// such spaces runs on the vector-ALU pair kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,9 +49,10 @@ typedef double sb_f64x4 __attribute__((ext_vector_type(4)));
 typedef float sb_f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int SB_WAVES = 8;                  // wavefronts per workgroup
-constexpr int SB_NG = 6;                     // 16-column groups per item (accumulators: 96 VGPRs)
+constexpr int SB_NG = 4;                     // 16-column groups per item (accumulators: 64 VGPRs)
 constexpr int SB_SGP = SB_NG / 2;            // column groups staged at a time for the scatter
-constexpr int SB_TK = 32;                    // rows of B per chunk (8 steps of 4)
+constexpr int SB_TK = 64;                    // rows of B per chunk (steps of 4 rows)
+constexpr int SB_NQ = SB_TK / 16;             // groups of four steps per chunk
 constexpr int SB_BSTR = SB_NG * 16 + 16;     // B row stride (elements): rows alternate bank halves
 constexpr int SB_BK = 33;                    // binomial table: C(n, k), n < 32, k <= 32
 constexpr int SB_KMAX = SB_NG * 16;          // members per item at one column each
@@ -174,33 +176,26 @@ __host__ __device__ inline void sb_member(uint32_t t, int n, const int32_t* bino
 // s): rank = P_0[a] + C(s, a + 1) + P_1[n] - P_1[a]; mode 2 creates q < s in L
 // (a below q, b below s): rank = P_0[a] + C(q, a + 1) + P_1[b] - P_1[a] +
 // C(s, b + 2) + P_2[n] - P_2[b]; the sign adds the electrons of tL below each
-// created orbital.
+// created orbital.  Written without branches (every table value is read and
+// the result selected by the mode), so that the entries of a thread issue
+// their LDS reads together; inf must be a row of the list (mode <= 2, local
+// orbitals below 31), every index then stays inside the tables.
 __host__ __device__ __forceinline__ int sb_entry(uint32_t inf, int64_t base, uint32_t tL, int n, const int32_t* pre,
                                                  int64_t jL, const int32_t* binom, int64_t* addr) {
     const int mode = (int)((inf >> 12) & 3u);
-    int neg = (int)((inf >> 14) & 1u);
-    if (mode == 0) {
-        *addr = base + jL;
-        return neg ? -1 : 1;
-    }
-    const int sl = (int)((inf >> 16) & 31u);
-    if ((tL >> sl) & 1u) return 0;
+    const int sl = (int)((inf >> 16) & 31u);   // 0 in mode 0
+    const int ql = (int)((inf >> 21) & 31u);   // 0 in modes 0 and 1
     const int ps = n + 1;
     const int b = popc32(tL & ((1u << sl) - 1u));
-    int64_t rank;
-    if (mode == 1) {
-        rank = (int64_t)pre[b] + binom[sl * SB_BK + b + 1] + pre[ps + n] - pre[ps + b];
-        neg ^= b & 1;
-    } else {
-        const int ql = (int)((inf >> 21) & 31u);
-        if ((tL >> ql) & 1u) return 0;
-        const int a = popc32(tL & ((1u << ql) - 1u));
-        rank = (int64_t)pre[a] + binom[ql * SB_BK + a + 1] + pre[ps + b] - pre[ps + a] + binom[sl * SB_BK + b + 2] +
-               pre[2 * ps + n] - pre[2 * ps + b];
-        neg ^= (a + b) & 1;
-    }
-    *addr = base + rank;
-    return neg ? -1 : 1;
+    const int a = popc32(tL & ((1u << ql) - 1u));
+    const int64_t p1n = pre[ps + n], p1b = pre[ps + b];
+    const int64_t r1 = (int64_t)pre[b] + binom[sl * SB_BK + b + 1] + p1n - p1b;
+    const int64_t r2 = (int64_t)pre[a] + binom[ql * SB_BK + a + 1] + p1b - pre[ps + a] + binom[sl * SB_BK + b + 2] +
+                       pre[2 * ps + n] - pre[2 * ps + b];
+    const bool hit = (mode >= 1 && ((tL >> sl) & 1u)) || (mode == 2 && ((tL >> ql) & 1u));
+    const int neg = (int)((inf >> 14) & 1u) ^ (mode == 0 ? 0 : mode == 1 ? (b & 1) : ((a + b) & 1));
+    *addr = base + (mode == 0 ? jL : mode == 1 ? r1 : r2);
+    return hit ? 0 : (neg ? -1 : 1);
 }
 
 // ---- plan (host) ----------------------------------------------------------
@@ -273,7 +268,7 @@ bool build_sb_plan(const HostSpace& H, SbHostPlan& plan) {
         }
         plan.sbegin[x][8] = (int32_t)plan.streams.size();
     }
-    plan.cap = (maxpad + 31) & ~31;
+    plan.cap = (maxpad + SB_TK - 1) / SB_TK * SB_TK;   // whole chunks of rows
     plan.nlmax = maxn;
     return true;
 }
@@ -331,9 +326,18 @@ __device__ __forceinline__ double sb_quad_xor(double x) {
     return __hiloint2double(hi, lo);
 }
 
-// The products of half a B chunk (steps K0..K0+3 of 4 rows each) for NGU
-// column groups with the table fragments af of those steps, the B fragments
-// read one step ahead.
+// f(integral_constant<int, I>) ... f(integral_constant<int, N - 1>), unrolled.
+template <int I, int N, class F>
+__device__ __forceinline__ void sb_static_for(F&& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        sb_static_for<I + 1, N>(f);
+    }
+}
+
+// The products of a group of four steps of a B chunk (steps K0..K0+3 of 4
+// rows each) for NGU column groups with the table fragments af of those
+// steps, the B fragments read one step ahead.
 template <int NGU, int K0, bool CPLX, typename TA, typename BT, typename ACC>
 __device__ __forceinline__ void sb_mma(const BT* __restrict__ B, int kq, int c16, const TA (&af)[4],
                                        ACC (&c1)[NGU], ACC (&c2)[NGU]) {
@@ -359,7 +363,7 @@ __device__ __forceinline__ void sb_mma(const BT* __restrict__ B, int kq, int c16
     }
 }
 
-// Table fragments of half a chunk: lane (kq, c16) holds A[row pair, pair of
+// Table fragments of a group of four steps: lane (kq, c16) holds A[row pair, pair of
 // chunk row 4 (K0 + ks) + kq] for ks < 4 (rows past the list: pair 0).
 template <int K0, typename TA>
 __device__ __forceinline__ void sb_afrag(const uint32_t* __restrict__ rinf, const TA* __restrict__ arow, int NP,
@@ -425,11 +429,12 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
             const int v = rest % NV, q = rest / NV;
             gcol[e] = (q < SB_TK) ? q * SB_BSTR + jj * CW + v : -1;
             const int R = kc * SB_TK + min(q, SB_TK - 1);
-            const uint32_t inf = I.rinf[R];
-            int64_t addr = 0;
-            int sg = 0;
-            if (q < SB_TK && inf != SB_PADROW && jj < I.nk && v < n_vec)
-                sg = sb_entry(inf, I.rbase[R], I.colstr[jj], I.nL, I.pre + jj * I.ps3, I.j0 + jj, I.binom, &addr);
+            const uint32_t inf0 = I.rinf[R];
+            const bool ok = q < SB_TK && inf0 != SB_PADROW && jj < I.nk && v < n_vec;
+            int64_t addr;
+            const int s0 = sb_entry(ok ? inf0 : 0u, I.rbase[R], I.colstr[jj], I.nL, I.pre + jj * I.ps3, I.j0 + jj,
+                                    I.binom, &addr);
+            const int sg = ok ? s0 : 0;
             gsg[e] = sg;
             ga[e] = (sg != 0) ? (int64_t)v * nd + addr : 0;
         }
@@ -468,15 +473,13 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
         // this A lane's row pair (rows past the list: pair 0, outputs dropped)
         const uint32_t pinf = own ? I.rinf[RT * 16 + c16] : SB_PADROW;
         const TA* arow = A + ((pinf == SB_PADROW) ? 0u : (pinf & 0xfffu));
-        // table fragments of the chunk in use, in two halves: each half of
-        // the next chunk is requested as soon as the products of the same
-        // half of the current chunk are issued (the second after the chunk
-        // build, which must not wait for it: loads complete in order)
-        TA afa[4], afb[4];
-        if (own) {
-            sb_afrag<0>(I.rinf, arow, NP, kq, afa);
-            sb_afrag<4>(I.rinf, arow, NP, kq, afb);
-        }
+        // table fragments of the chunk in use, in groups of four steps:
+        // each group of the next chunk is requested as soon as the products
+        // of the same group of the current chunk are issued (the last after
+        // the chunk build, which must not wait for it: loads complete in
+        // order)
+        TA af[SB_NQ][4];
+        if (own) sb_static_for<0, SB_NQ>([&](auto G) { sb_afrag<4 * G>(I.rinf, arow, NP, kq, af[G]); });
         gen_issue(0);
         gen_commit(0, 0);
         __syncthreads();
@@ -485,13 +488,22 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
             const bool more = kc + 1 < nkc;
             const double* B = bsh + (size_t)buf * SB_TK * SB_BSTR;
             const uint32_t* rnext = I.rinf + (kc + 1) * SB_TK;
+            // the table fragments of this chunk (requested during the
+            // previous one) are in: stating it here keeps the compiler from
+            // waiting inside the products below for the gathers issued next
+            // (its count of outstanding loads cannot tell them apart across
+            // the loop edge)
+            __builtin_amdgcn_s_waitcnt(0);
             if (more) gen_issue(kc + 1);
             const bool mm = own && I.flags[kc];
-            if (mm) sb_mma<NGU, 0, CPLX>(B, kq, c16, afa, c1, c2);
-            if (own && more) sb_afrag<0>(rnext, arow, NP, kq, afa);
-            if (mm) sb_mma<NGU, 4, CPLX>(B, kq, c16, afb, c1, c2);
+            sb_static_for<0, SB_NQ>([&](auto G) {
+                if (mm) sb_mma<NGU, 4 * G, CPLX>(B, kq, c16, af[G], c1, c2);
+                if constexpr (G + 1 < SB_NQ) {
+                    if (own && more) sb_afrag<4 * G>(rnext, arow, NP, kq, af[G]);
+                }
+            });
             if (more) gen_commit(kc + 1, buf ^ 1);
-            if (own && more) sb_afrag<4>(rnext, arow, NP, kq, afb);
+            if (own && more) sb_afrag<4 * (SB_NQ - 1)>(rnext, arow, NP, kq, af[SB_NQ - 1]);
             __syncthreads();
         }
         // ---- scatter of this wavefront's row tile, staged through LDS (the
@@ -659,17 +671,16 @@ static hipError_t launch_sb_g(const DevSpace& S, const SbPlan& plan, const void*
     return hipGetLastError();
 }
 
-template <bool CPLX, int NV>
+// One launch per column-group count, SB_NG down to 1.
+template <bool CPLX, int NV, int NGU = SB_NG>
 static hipError_t launch_sb_nv(const DevSpace& S, const SbPlan& plan, const void* A, const void* c, void* sigma,
                                int nv, hipStream_t st) {
-    static_assert(SB_NG == 6, "one launch per column-group count 1..SB_NG");
-    hipError_t e;
-    if ((e = launch_sb_g<CPLX, NV, 6>(S, plan, A, c, sigma, nv, st)) != hipSuccess) return e;
-    if ((e = launch_sb_g<CPLX, NV, 5>(S, plan, A, c, sigma, nv, st)) != hipSuccess) return e;
-    if ((e = launch_sb_g<CPLX, NV, 4>(S, plan, A, c, sigma, nv, st)) != hipSuccess) return e;
-    if ((e = launch_sb_g<CPLX, NV, 3>(S, plan, A, c, sigma, nv, st)) != hipSuccess) return e;
-    if ((e = launch_sb_g<CPLX, NV, 2>(S, plan, A, c, sigma, nv, st)) != hipSuccess) return e;
-    return launch_sb_g<CPLX, NV, 1>(S, plan, A, c, sigma, nv, st);
+    static_assert(NGU >= 1 && NGU <= SB_NG, "column-group count");
+    const hipError_t e = launch_sb_g<CPLX, NV, NGU>(S, plan, A, c, sigma, nv, st);
+    if constexpr (NGU > 1) {
+        if (e == hipSuccess) return launch_sb_nv<CPLX, NV, NGU - 1>(S, plan, A, c, sigma, nv, st);
+    }
+    return e;
 }
 
 template <bool CPLX>

@@ -208,6 +208,39 @@ stpci_status stpci_sigma_noalloc(stpci_ctx* ctx, const void* c_dev, void* sigma_
                                  stpci_precision prec);
 int64_t stpci_sigma_noalloc_max_bytes(void);
 
+/* Categorical compression (Results, categorical compression): a vector as,
+ * per space category B in order, the nonzero coefficients V^B and their
+ * local addresses A^B (position inside the category's dense block),
+ * ascending -- the CSC pair (V, A) of the paper.  Device arrays: cat_ptr
+ * [n_cat + 1] int64 (entries of category B at cat_ptr[B] .. cat_ptr[B+1]-1),
+ * a uint32 local addresses, v values in the scalar type of the integrals.
+ *
+ * stpci_csc_compress: compress the dense vector x_dev ([n_dets]), keeping
+ *   the entries with |x_i| >= thresh (and != 0): thresh = 0 keeps every
+ *   nonzero, thresh = eps ||x|| applies the drop of Eq. sparsePreconditioner.
+ *   Writes cat_ptr_dev always, a_dev / v_dev up to `capacity` entries; *nnz =
+ *   entries of the compressed vector; more than capacity: STPCI_ENOMEM (call
+ *   again with arrays of *nnz entries).  Synchronises the context stream.
+ * stpci_csc_expand: the dense vector of a compressed one (zeros elsewhere).
+ * stpci_sigma_csc: sigma_dev = H c (dense, [n_dets], e_core included) for c
+ *   given compressed, by the compression-compatible sigma build of Alg.
+ *   sigmaBuild: only the (N-2)-electron pair intermediates reached from a
+ *   nonzero coefficient are visited; each one's sorted pair lists are
+ *   intersected with the categories' address lists by the exponential search
+ *   of that algorithm, and only the matched coefficients are contracted, so
+ *   the work follows the number of nonzeros, not the size of the space.
+ *   FP64, device atomics (not bitwise deterministic); one vector.  Needs the
+ *   pair form (N >= 2; STPCI_EINVAL otherwise).  A, V must be exactly as
+ *   stpci_csc_compress writes them (ascending within each category, in
+ *   range); the call reads cat_ptr_dev[n_cat] (synchronising the stream) and
+ *   allocates its work arrays on first use. */
+stpci_status stpci_csc_compress(stpci_ctx* ctx, const void* x_dev, double thresh, int64_t* cat_ptr_dev,
+                                uint32_t* a_dev, void* v_dev, int64_t capacity, int64_t* nnz);
+stpci_status stpci_csc_expand(stpci_ctx* ctx, const int64_t* cat_ptr_dev, const uint32_t* a_dev, const void* v_dev,
+                              void* x_dev);
+stpci_status stpci_sigma_csc(stpci_ctx* ctx, const int64_t* cat_ptr_dev, const uint32_t* a_dev, const void* v_dev,
+                             void* sigma_dev);
+
 /* diag_dev[i] = <i|H|i> (real, n_dets doubles).  The solver itself never
  * stores the diagonal; this call exists for checks. */
 stpci_status stpci_diagonal(stpci_ctx* ctx, double* diag_dev);

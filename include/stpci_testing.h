@@ -77,6 +77,18 @@ stpci_status stpci_test_precond(stpci_ctx* ctx, const void* r_dev, void* t_dev, 
  * more than 31 spin-orbitals). */
 stpci_status stpci_test_sb(const stpci_ctx* ctx, int64_t max_groups, int64_t* n_checked, int64_t* n_bad);
 
+/* The exponential search of Alg. sigmaBuild (subroutine exponentialSearch)
+ * as the compressed sigma build runs it: the lowest j in [i, n) with
+ * a[j] >= x, or n, for a ascending on [i, n) (host arrays).  -1 for invalid
+ * arguments (a NULL, n < 0, i outside [0, n]). */
+int64_t stpci_test_exp_search(const uint32_t* a, int64_t n, int64_t i, uint32_t x);
+
+/* The same search on the device: out_dev[t] = search(a_dev, n, starts_dev[t],
+ * xs_dev[t]) for t < m, one thread each, on `stream` (a hipStream_t, NULL:
+ * the default stream); starts must lie in [0, n].  Device arrays. */
+stpci_status stpci_test_exp_search_dev(const uint32_t* a_dev, int64_t n, const int64_t* starts_dev,
+                                       const uint32_t* xs_dev, int64_t* out_dev, int64_t m, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

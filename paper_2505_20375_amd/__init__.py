@@ -67,6 +67,11 @@ _SIGS = {
     "stpci_address_to_det": ([_P, _I64, ctypes.POINTER(ctypes.c_uint64)], _I),
     "stpci_sigma": ([_P, _P, _P, _I, _I], _I),
     "stpci_sigma_noalloc": ([_P, _P, _P, _I, _I], _I),
+    "stpci_csc_compress": ([_P, _P, ctypes.c_double, _P, _P, _P, _I64, _I64P], _I),
+    "stpci_csc_expand": ([_P, _P, _P, _P, _P], _I),
+    "stpci_sigma_csc": ([_P, _P, _P, _P, _P], _I),
+    "stpci_test_exp_search": ([_P, _I64, _I64, ctypes.c_uint32], _I64),
+    "stpci_test_exp_search_dev": ([_P, _I64, _P, _P, _P, _I64, _P], _I),
     "stpci_sigma_noalloc_max_bytes": ([], _I64),
     "stpci_diagonal": ([_P, _P], _I),
     "stpci_davidson": ([_P, ctypes.POINTER(DavOpts), _DP, _DP, _P, _IP], _I),
@@ -121,6 +126,22 @@ def dav_sigma_batched(ctxs):
                 msg += ": " + m
                 break
         raise StpciError(st, msg)
+
+
+def test_exp_search(a, i, x):
+    """The exponential search of the compressed sigma build on the host:
+    lowest j >= i with a[j] >= x, or len(a)."""
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    return int(_lib.stpci_test_exp_search(a.ctypes.data_as(ctypes.c_void_p), len(a), int(i), int(x)))
+
+
+def test_exp_search_dev(a, starts, xs, out, stream=None):
+    """The same search on the device for every (start, x) pair (torch tensors:
+    a int32 holding uint32 values, starts int64, xs int32, out int64)."""
+    st = _lib.stpci_test_exp_search_dev(_ptr(a), a.numel(), _ptr(starts), _ptr(xs), _ptr(out), xs.numel(),
+                                        _P(stream) if stream else None)
+    if st != OK:
+        raise StpciError(st, "stpci_test_exp_search_dev failed")
 
 
 def sigma_noalloc_max_bytes():
@@ -238,6 +259,33 @@ class Context:
 
     def diagonal(self, out):
         self._check(_lib.stpci_diagonal(self._h, _ptr(out)))
+
+    # -- categorical compression (stpci_csc_*) --------------------------------
+    def csc_compress(self, x, thresh=0.0):
+        """(cat_ptr, a, v) device tensors of the compressed form of the dense
+        vector x: per category the entries with |x_i| >= thresh, ascending
+        local addresses (uint32 stored in int32 tensors)."""
+        import torch
+        info = self.space_info()
+        cat_ptr = torch.empty(info.n_cat + 1, dtype=torch.int64, device=x.device)
+        nnz = ctypes.c_int64()
+        st = _lib.stpci_csc_compress(self._h, _ptr(x), float(thresh), _ptr(cat_ptr), None, None, 0,
+                                     ctypes.byref(nnz))
+        if st not in (OK, ENOMEM):
+            self._check(st)
+        n = max(int(nnz.value), 1)
+        a = torch.empty(n, dtype=torch.int32, device=x.device)
+        v = torch.empty(n, dtype=x.dtype, device=x.device)
+        self._check(_lib.stpci_csc_compress(self._h, _ptr(x), float(thresh), _ptr(cat_ptr), _ptr(a), _ptr(v), n,
+                                            ctypes.byref(nnz)))
+        return cat_ptr, a[:nnz.value], v[:nnz.value]
+
+    def csc_expand(self, cat_ptr, a, v, out):
+        self._check(_lib.stpci_csc_expand(self._h, _ptr(cat_ptr), _ptr(a), _ptr(v), _ptr(out)))
+
+    def sigma_csc(self, cat_ptr, a, v, out):
+        """out = H c for c given compressed (stpci_sigma_csc)."""
+        self._check(_lib.stpci_sigma_csc(self._h, _ptr(cat_ptr), _ptr(a), _ptr(v), _ptr(out)))
 
     def davidson(self, k=1, tol=1e-8, max_iter=100, max_subspace=0, eps_drop=0.0, precision=FP64,
                  refine_tol_energy=0.0, guess=None, vecs=None, allow_noconv=False, certify=False):

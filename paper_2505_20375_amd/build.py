@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libstpci.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("STPCI_ARCH", "gfx950")
 
-SOURCES = ["kernels.hip", "sigma2e.hip", "sigma_sym.hip", "sigma_pair.hip", "sigma_mfma.hip", "sigma_mf64.hip", "sigma_grp.hip", "sigma_sb.hip", "noalloc.hip", "space.cpp", "capi.cpp", "davidson.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "sigma2e.hip", "sigma_sym.hip", "sigma_pair.hip", "sigma_mfma.hip", "sigma_mf64.hip", "sigma_grp.hip", "sigma_sb.hip", "noalloc.hip", "csc.hip", "space.cpp", "capi.cpp", "davidson.cpp", "serve.cpp", "csc_api.cpp"]
 
 # gfx950 device code is built without packed FP32 instructions.
 # Code object v5 is loadable by the HIP runtime that PyTorch bundles.

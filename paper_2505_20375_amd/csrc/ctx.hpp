@@ -89,6 +89,8 @@ struct stpci_ctx {
     stp::DevBuf d_pcats, d_pwork, d_pslot, d_pA, d_pA32, d_pAbf;
     stp::DevBuf d_E;         // pair contributions of the store-and-reduce scatter
     stp::DevBuf d_bdesc, d_bjbegin;   // descriptors of stpci_dav_sigma_batched launches led by this context
+    stp::DevBuf d_csc_cnt, d_csc_pcat, d_csc_bitmap, d_csc_list, d_csc_count;   // compressed-vector work
+    bool csc_pcat_ready = false;
     bool pair_store = false; // pair kernel: store-and-reduce (true) or device atomics
     bool pair_mf64 = false;   // FP64 pair products on the matrix cores (else the vector-ALU tiles)
     bool pair_grp = false;    // FP64 pair products of grouped intermediates (spaces of one subspace)

@@ -140,4 +140,19 @@ hipError_t launch_unit(bool cplx, void* x, int64_t n, int64_t at, hipStream_t st
 int64_t check_pairs_host(const DevSpace& S, int64_t max_dets_per_cat, int64_t* n_checked,
                          bool (*to_bits)(const void*, int64_t, uint64_t*), const void* user);
 
+// categorical compression (csc.hip)
+void build_csc_pcat_of(const HostSpace& H, std::vector<int32_t>& out);
+size_t csc_slice_bytes(int deg_max, bool cplx);
+hipError_t launch_csc_compress(const DevSpace& S, bool cplx, const void* x, double thresh, const int64_t* cat_off,
+                               int64_t* cnt, int64_t* cat_ptr, uint32_t* A, void* V, int64_t cap, hipStream_t st);
+hipError_t launch_csc_expand(const DevSpace& S, bool cplx, const int64_t* cat_ptr, const int64_t* cat_off,
+                             const uint32_t* A, const void* V, void* x, hipStream_t st);
+hipError_t launch_csc_sigma(const DevSpace& S, bool cplx, const int64_t* cat_ptr, const uint32_t* A, const void* V,
+                            const void* pA, const int32_t* pcat_of, double e_core, int deg_max, uint32_t* bitmap,
+                            int64_t nwords, int64_t* list, unsigned long long* count, int64_t cap, void* sigma,
+                            hipStream_t st);
+hipError_t launch_csc_search_test(const uint32_t* A, int64_t n, const int64_t* starts, const uint32_t* xs,
+                                  int64_t* out, int64_t m, hipStream_t st);
+int64_t csc_exp_search_host(const uint32_t* A, int64_t n, int64_t i, uint32_t x);
+
 }  // namespace stp

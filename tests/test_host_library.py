@@ -290,3 +290,28 @@ def test_layout_address_formula(n, sub, lo, hi):
     ref = layout.layout_dets(n, sub, lo, hi)
     for a, b in enumerate(ref):
         assert layout.address(int(b), n, sub, lo, hi) == a
+
+
+def test_exponential_search_equals_lower_bound():
+    """The exponential search of Alg. sigmaBuild (as the compressed sigma
+    build runs it) returns the lower bound of x in a[i:], i.e.
+    numpy.searchsorted(a[i:], x, 'left') + i, on random sorted arrays with
+    repeated values, from random start positions, for values below, inside
+    and above the range, and for empty ranges."""
+    import paper_2505_20375_amd as stpci
+    rng = np.random.default_rng(41)
+    checked = 0
+    for n in (0, 1, 2, 3, 7, 64, 1000, 4097):
+        a = np.sort(rng.integers(0, max(2 * n, 4), n).astype(np.uint32))
+        for _ in range(200 if n else 3):
+            i = int(rng.integers(0, n + 1))
+            x = int(rng.integers(0, max(2 * n, 4) + 3))
+            ref = i + int(np.searchsorted(a[i:], np.uint32(x), side="left"))
+            assert stpci.test_exp_search(a, i, x) == ref, (n, i, x)
+            checked += 1
+        if n:
+            assert stpci.test_exp_search(a, 0, int(a[-1]) + 1) == n
+            assert stpci.test_exp_search(a, 0, 0) == 0
+            assert stpci.test_exp_search(a, n, 0) == n
+    assert stpci.test_exp_search(np.zeros(4, np.uint32), 5, 0) == -1
+    assert checked > 1000

@@ -40,8 +40,8 @@ def log(*a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3p", choices=["c3p", "c2"],
                     help="headline: c3p (40 spinors, 12|16|12, 11 electrons) or c2 (24 spinors, 8 electrons)")
     ap.add_argument("--partition", default="24", help="config-2 subspace sizes, e.g. 24 or 8,8,8")
@@ -219,17 +219,27 @@ def _headline_c3p(args):
                             "sigma_bf16_speedup": ms_per_step / ms_b, "sigma_bf16_rel_err": err,
                             "bf16_kernel": "k_sigma_pair_mfma (v_mfma_f32_16x16x32_bf16, FP32 accumulation)"}
         del out2
-    del c, out, ctx
+    if not args.no_sparse:
+        del c, out
+        torch.cuda.empty_cache()
+        # categorically compressed vectors of 1e-6 .. 1e-4 of the space
+        res["compressed"] = _compressed(ctx, n, torch.complex128, ms_per_step / n_vec, (1e-6, 1e-5, 1e-4), 3104)
+        del ctx
+    else:
+        del c, out, ctx
     torch.cuda.empty_cache()
     return res
 
 
 def _cpu_baseline_c3p(seconds):
     """The CPU oracle (list-free Slater-Condon rows of the windowed space) on
-    a bounded sample of rows of the headline space, all host threads,
-    extrapolated to det-updates/s.  The coefficients of the sampled rows'
-    columns are drawn beforehand (not timed): the oracle's work is forming
-    and applying each row's nonzero couplings."""
+    bounded samples of rows of the headline space, on 1, 4 and all host
+    threads of the GPU's share (at most 16), extrapolated to det-updates/s;
+    the best rate is reported with the thread count that gave it.  The rows'
+    determinants are drawn beforehand (not timed): the oracle's work is
+    forming and applying each row's nonzero couplings.  Threads share the
+    integrals (a process per core would hold 41 MB of them each); the
+    oracle's C routine runs outside the interpreter lock."""
     import numpy as np
     import synth
     from concurrent.futures import ThreadPoolExecutor
@@ -239,8 +249,7 @@ def _cpu_baseline_c3p(seconds):
     ctx = stpci.Context(-1)
     ctx.set_space(sp.n_elec, sp.sub, sp.lo, sp.hi)
     info = ctx.space_info()
-    # the host share of one GPU: at most 16 threads, whatever the machine has
-    nthreads = max(1, min(16, len(os.sched_getaffinity(0))))
+    ncores = max(1, min(16, len(os.sched_getaffinity(0))))
     rng = np.random.default_rng(0)
 
     def rows_work(bits_list):
@@ -248,8 +257,7 @@ def _cpu_baseline_c3p(seconds):
         acc = 0j
         for b in bits_list:
             kb, vals = csc.h_row_window(sp.sub, sp.lo, sp.hi, ints.h, ints.g, int(b))
-            cv = np.ones(len(kb))   # stand-in coefficients; the row's multiply-adds are done
-            acc += np.dot(vals, cv)
+            acc += np.dot(vals, np.ones(len(kb)))   # stand-in coefficients
             tot += len(kb)
         return tot
 
@@ -262,12 +270,14 @@ def _cpu_baseline_c3p(seconds):
             tot = sum(ex.map(rows_work, parts))
         return tot, time.perf_counter() - t0
 
-    tot, t = run(max(nthreads * 8, 64), nthreads)
-    nrows = int(max(64, nthreads * 8 * seconds / max(t, 1e-3)))
-    tot, t = run(nrows, nthreads)
-    # one thread, a quarter of the time
-    n1 = max(16, nrows // (4 * nthreads))
-    tot1, t1 = run(n1, 1)
+    scan = []
+    for nth in sorted({1, min(4, ncores), ncores}):
+        tot, t = run(max(nth * 4, 8), nth)
+        nrows = int(max(nth * 4, nth * 4 * (seconds / 3) / max(t, 1e-3)))
+        tot, t = run(nrows, nth)
+        scan.append({"threads": nth, "rows": nrows, "couplings": int(tot), "seconds": round(t, 2),
+                     "det_updates_per_s": tot / t})
+    best = max(scan, key=lambda r: r["det_updates_per_s"])
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -276,11 +286,76 @@ def _cpu_baseline_c3p(seconds):
                 break
     except OSError:
         pass
-    return {"value": tot / t, "unit": "det-updates/s", "cores": nthreads, "kind": "oracle",
-            "value_1_thread": tot1 / t1, "cpu_model": model,
-            "sample": "%d random rows of the 40-spinor 12|16|12 11-electron space (%d nonzero couplings, "
-                      "list-free row-driven Slater-Condon, %.1f s on %d threads; one thread: %d rows, %.1f s)"
-                      % (nrows, tot, t, nthreads, n1, t1)}
+    return {"value": best["det_updates_per_s"], "unit": "det-updates/s", "cores": best["threads"], "kind": "oracle",
+            "cpu_model": model, "scan": scan,
+            "sample": "random rows of the 40-spinor 12|16|12 11-electron space, list-free row-driven "
+                      "Slater-Condon, %d rows (%d couplings) in %.1f s on %d threads; best of 1, 4 and %d threads"
+                      % (best["rows"], best["couplings"], best["seconds"], best["threads"], ncores)}
+
+
+def _compressed(ctx, n, dtype, dense_ms, densities, seed):
+    """sigma of categorically compressed vectors (stpci_sigma_csc): a seeded
+    vector with the given fraction of nonzero coefficients at random
+    addresses, compressed (stpci_csc_compress), then one timed sigma of the
+    compressed vector after an untimed one; dense_ms: the dense sigma of one
+    vector on the same space, for comparison."""
+    import numpy as np
+    import torch
+    out = {}
+    rng = np.random.default_rng(seed)
+    for dens in densities:
+        nnz = max(1, int(round(dens * n)))
+        idx = torch.from_numpy(np.unique(rng.integers(0, n, nnz))).cuda()
+        x = torch.zeros(n, dtype=dtype, device="cuda")
+        x[idx] = torch.randn(len(idx), dtype=dtype, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cat_ptr, a, v = ctx.csc_compress(x)
+        torch.cuda.synchronize()
+        ms_c = (time.perf_counter() - t0) * 1e3
+        del x
+        y = torch.empty(n, dtype=dtype, device="cuda")
+        ctx.sigma_csc(cat_ptr, a, v, y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.sigma_csc(cat_ptr, a, v, y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        log("compressed sigma, %d nonzeros: %.3f ms (dense %.3f ms)" % (len(idx), ms, dense_ms))
+        out["density_%g" % dens] = {"nonzeros": int(len(idx)), "compress_ms": round(ms_c, 3),
+                                    "sigma_csc_ms": round(ms, 3), "dense_sigma_ms": round(dense_ms, 3),
+                                    "speedup_vs_dense": round(dense_ms / ms, 2),
+                                    "ms_per_nonzero": ms / len(idx)}
+        del y, cat_ptr, a, v
+    torch.cuda.empty_cache()
+    return out
+
+
+def _eps_study(ctx, roots, n):
+    """Davidson with the eps drop of Eq. sparsePreconditioner for several eps
+    (residual tolerance 1e-5): iterations, sigma vectors and the energy
+    difference to the eps = 0 solve (the paper's eps <~ 10 / sqrt(N) rule
+    included)."""
+    import numpy as np
+    import torch
+    res = []
+    e_ref = None
+    for eps in (0.0, 1e-5, 1e-4, 1e-3, 10.0 / np.sqrt(n), 3e-2, 1e-1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e, r, it, st = ctx.davidson(k=roots, tol=1e-5, max_iter=400, eps_drop=float(eps), allow_noconv=True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        if e_ref is None:
+            e_ref = e
+        nsig = ctx.dav_sigma_count(0)
+        res.append({"eps": float(eps), "iterations": int(it), "converged": int(st) == 0, "sigma_vectors": nsig,
+                    "max_energy_diff_vs_eps0_eh": float(np.max(np.abs(e - e_ref))), "max_resid": float(np.max(r)),
+                    "solve_ms": round(ms, 1)})
+        log("eps %.3g: %d iterations, dE %.2e" % (eps, it, res[-1]["max_energy_diff_vs_eps0_eh"]))
+    return {"rule_10_over_sqrt_n": 10.0 / float(np.sqrt(n)), "runs": res}
 
 
 def _config2(args):
@@ -463,8 +538,22 @@ def _config2(args):
         sparse["density_%g" % dens] = {"sigma_fp64_ms": ms_s, "speedup_vs_dense": ms_per_step / ms_s}
     if sparse:
         res["sparse_vectors"] = sparse
+    if not args.no_sparse:
+        # one vector, dense and compressed
+        c1 = c[:n].contiguous()
+        o1 = torch.empty_like(c1)
+        ctx.sigma(c1, o1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.sigma(c1, o1)
+        e1.record()
+        torch.cuda.synchronize()
+        res["compressed"] = _compressed(ctx, n, c.dtype, e0.elapsed_time(e1), (1e-4, 1e-3, 1e-2, 1e-1), 2104)
+        del c1, o1
     res["precision"] = prec
     if not args.no_solve:
+        res["eps_study"] = _eps_study(ctx, roots, n)
         res["solve"] = _solve(ctx, roots, args.solves, stpci.FP64)
         for pname, pcode in (("mixed", stpci.FP32), ("mixed_bf16", stpci.BF16)):
             sol = _solve(ctx, roots, args.solves, pcode)

@@ -130,13 +130,21 @@ def address_array(bits, n_elec, sub, lo=None, hi=None):
         occs.append(np.array([bin(int(x)).count("1") for x in range(1 << m)], dtype=np.int64)[s])
         off += m
     out = np.full(len(bits), -1, dtype=np.int64)
+    if len(bits) == 0:
+        return out
     occ = np.stack(occs, axis=1)
     tables = {m: _rank_table(m) for m in set(sub)}
-    for c in cats:
-        sel = np.all(occ == np.array(c), axis=1)
-        if not np.any(sel):
+    # group the determinants by occupation tuple (one pass per tuple present)
+    uniq, inv = np.unique(occ, axis=0, return_inverse=True)
+    inv = np.asarray(inv).reshape(-1)
+    order = np.argsort(inv, kind="stable")
+    bounds = np.searchsorted(inv[order], np.arange(len(uniq) + 1))
+    for u in range(len(uniq)):
+        c = tuple(int(x) for x in uniq[u])
+        if c not in base:
             continue
-        a = np.zeros(int(sel.sum()), dtype=np.int64)
+        sel = order[bounds[u]:bounds[u + 1]]
+        a = np.zeros(len(sel), dtype=np.int64)
         stride = 1
         for k in reversed(range(len(sub))):
             a += tables[sub[k]][locs[k][sel]] * stride

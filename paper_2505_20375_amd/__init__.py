@@ -294,14 +294,19 @@ class Context:
         e = (ctypes.c_double * k)()
         r = (ctypes.c_double * k)()
         it = ctypes.c_int()
-        info = self.space_info() if certify else None
-        self._last_k = int(k) + (1 if certify and k < 16 and k < info.n_dets else 0)
+        self._last_k = self._run_k(k, precision, refine_tol_energy, certify)
         self._cert_k = int(k)
         st = _lib.stpci_davidson(self._h, ctypes.byref(o), e, r, _ptr(vecs) if vecs is not None else None,
                                  ctypes.byref(it))
         if st != OK and not (allow_noconv and st == ENOCONV):
             self._check(st)
         return np.array(e[:]), np.array(r[:]), it.value, st
+
+    def _run_k(self, k, precision, refine_tol_energy, certify):
+        """Roots a run carries (one more than k with certify, or with the
+        energy stop of a reduced-precision run), as the history records them."""
+        extra = bool(certify) or (refine_tol_energy > 0 and int(precision) != FP64)
+        return int(k) + (1 if extra and k < 16 and k < self.space_info().n_dets else 0)
 
     # -- step-wise Davidson (stpci_dav_begin ... stpci_dav_result) -----------
     @staticmethod
@@ -319,6 +324,7 @@ class Context:
         o = self._opts(k, tol, max_iter, max_subspace, eps_drop, precision, refine_tol_energy, certify)
         self._step_k = int(k)
         self._cert_k = int(k)
+        self._last_k = self._run_k(k, precision, refine_tol_energy, certify)
         self._check(_lib.stpci_dav_begin(self._h, ctypes.byref(o)))
 
     def dav_finish_step(self):

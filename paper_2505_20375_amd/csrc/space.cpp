@@ -18,12 +18,22 @@ static int64_t binom(int n, int k) {
     return r;
 }
 
+// C(n, k) for 0 <= n <= 32, 0 <= k <= 34 (0 for k > n).
+struct BinomTable {
+    int64_t v[33][35];
+    BinomTable() {
+        for (int n = 0; n <= 32; ++n)
+            for (int k = 0; k <= 34; ++k) v[n][k] = binom(n, k);
+    }
+};
+static const BinomTable kBinom;
+
 int64_t colex_rank(uint32_t mask) {
     int64_t r = 0;
     int i = 0;
     while (mask) {
         int b = __builtin_ctz(mask);
-        r += binom(b, i + 1);
+        r += kBinom.v[b][i + 1];
         ++i;
         mask &= mask - 1;
     }
@@ -318,29 +328,52 @@ bool HostSpace::build(int n_elec, int n_sub, const int* sub_size, const int* win
         StrTab& T = tabs[tab_of[m][n]];
         if (n >= 1 && tab_of[m][n - 1] >= 0) T.tab_dn = tab_of[m][n - 1];
         if (n + 1 <= m && tab_of[m][n + 1] >= 0) T.tab_up = tab_of[m][n + 1];
+        // ranks after removing or adding one electron from the colex sum
+        // rank(s) = sum_i C(p_i, i + 1) over the set bits p_0 < p_1 < ...:
+        // removing bit j leaves the bits below in place and moves those above
+        // down one index; adding a bit at l with j bits below it moves the
+        // bits from j on up one index (prefix and suffix sums per string)
         if ((kv.second & 2) && T.tab_dn >= 0) {
             T.ann_off = (int64_t)ann.size();
             ann.resize(ann.size() + (size_t)T.count * m, 0);
+            int pos[32];
+            int64_t pre[33], suf[33];
             for (int64_t r = 0; r < T.count; ++r) {
-                uint32_t s = bits[T.bits_off + r];
-                for (int l = 0; l < m; ++l) {
-                    if (!((s >> l) & 1u)) continue;
-                    int below = __builtin_popcount(s & ((1u << l) - 1u));
-                    int64_t r2 = colex_rank(s & ~(1u << l));
-                    ann[T.ann_off + r * m + l] = (int32_t)((below & 1) ? -(r2 + 1) : (r2 + 1));
+                const uint32_t s = bits[T.bits_off + r];
+                int nb = 0;
+                for (uint32_t t = s; t; t &= t - 1u) pos[nb++] = __builtin_ctz(t);
+                pre[0] = 0;
+                for (int i = 0; i < nb; ++i) pre[i + 1] = pre[i] + kBinom.v[pos[i]][i + 1];
+                suf[nb] = 0;
+                for (int i = nb - 1; i >= 0; --i) suf[i] = suf[i + 1] + kBinom.v[pos[i]][i];   // index i - 1 after removal
+                for (int j = 0; j < nb; ++j) {
+                    const int l = pos[j];
+                    const int64_t r2 = pre[j] + suf[j + 1];
+                    ann[T.ann_off + r * m + l] = (int32_t)((j & 1) ? -(r2 + 1) : (r2 + 1));
                 }
             }
         }
         if ((kv.second & 4) && T.tab_up >= 0) {
             T.cre_off = (int64_t)cre.size();
             cre.resize(cre.size() + (size_t)T.count * m, 0);
+            int pos[32];
+            int64_t pre[33], suf[33];
             for (int64_t r = 0; r < T.count; ++r) {
-                uint32_t s = bits[T.bits_off + r];
+                const uint32_t s = bits[T.bits_off + r];
+                int nb = 0;
+                for (uint32_t t = s; t; t &= t - 1u) pos[nb++] = __builtin_ctz(t);
+                pre[0] = 0;
+                for (int i = 0; i < nb; ++i) pre[i + 1] = pre[i] + kBinom.v[pos[i]][i + 1];
+                suf[nb] = 0;
+                for (int i = nb - 1; i >= 0; --i) suf[i] = suf[i + 1] + kBinom.v[pos[i]][i + 2];   // index i + 1 after insertion
+                int j = 0;   // set bits below l
                 for (int l = 0; l < m; ++l) {
-                    if ((s >> l) & 1u) continue;
-                    int below = __builtin_popcount(s & ((1u << l) - 1u));
-                    int64_t r2 = colex_rank(s | (1u << l));
-                    cre[T.cre_off + r * m + l] = (int32_t)((below & 1) ? -(r2 + 1) : (r2 + 1));
+                    if ((s >> l) & 1u) {
+                        ++j;
+                        continue;
+                    }
+                    const int64_t r2 = pre[j] + kBinom.v[l][j + 1] + suf[j];
+                    cre[T.cre_off + r * m + l] = (int32_t)((j & 1) ? -(r2 + 1) : (r2 + 1));
                 }
             }
         }

@@ -51,7 +51,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--solves", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--serve", type=int, default=48, help="requests in the serving run (0: skip)")
+    ap.add_argument("--serve", type=int, default=512, help="requests in the serving run (0: skip)")
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse-vector sigma timings")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured GEMM and copy reference rates")
     ap.add_argument("--serve-max-dets", type=int, default=300000)

@@ -51,6 +51,10 @@ struct DavState {
     std::vector<double> theta_prev;   // Ritz values of the previous iteration of this phase
     bool energy_stop = false;         // the FP64 refinement ended on refine_tol_energy
     bool products_ready = false;      // step-wise runs: the pending products were computed
+    // coordinates, in the current basis V, of the previous iteration's Ritz
+    // vectors ([prev_rows][k], row-major; prev_rows <= m), for the restart
+    std::vector<std::complex<double>> prev_coef;
+    int prev_rows = 0;
 };
 
 }  // namespace stp

@@ -428,6 +428,8 @@ static stpci_status dav_start(stpci_ctx* c, stpci_precision prec, const void* gu
             if ((s = d.hip(launch_unit(d.cx, d.vec(c->d_V, i), N, ti[ord[i]], c->stream), "unit"))) return s;
     }
     D.G.assign((size_t)64 * 64, cplx(0, 0));
+    D.prev_coef.clear();
+    D.prev_rows = 0;
     D.theta.assign(k, 0.0);
     D.theta_prev.clear();
     D.energy_stop = false;
@@ -582,13 +584,67 @@ static stpci_status dav_advance(stpci_ctx* c) {
                             D.opts.eps_drop)))
         return s;
     int mm = m;
-    // thick restart when the space would overflow: keep the kr lowest Ritz
-    // vectors (V <- V Y_kr, W <- W Y_kr, G <- diag(theta_kr))
+    // restart when the space would overflow (thick restart with the
+    // previous Ritz vectors, "GD+k"): the new basis is V Q, Q = the k lowest
+    // Ritz vectors' coefficients Y_k, then the previous iteration's Ritz
+    // vectors (coefficients in this basis) orthogonalised against them, then
+    // further Ritz vectors while room is left; W <- W Q, G <- Q^H A Q.  Both
+    // kinds lie in the basis, so no sigma is repeated; keeping the previous
+    // iterate is what lets a small basis (a space where only a few vectors
+    // fit the device) converge as a locally optimal iteration.
+    std::vector<cplx> Pc;   // coefficients of this iteration's Ritz vectors in the basis after this step
+    int Pc_rows = 0;
     if (mm + nt > D.mmax) {
-        const int kr = std::max(k, std::min(D.kr_max, D.mmax - nt));
+        const int room = std::max(k, std::min(D.kr_max, D.mmax - nt));
+        std::vector<std::vector<cplx>> cols;
+        auto ortho_push = [&](std::vector<cplx> v) {
+            for (int pass = 0; pass < 2; ++pass)
+                for (const auto& q : cols) {
+                    cplx dot(0, 0);
+                    for (int i = 0; i < mm; ++i) dot += std::conj(q[i]) * v[i];
+                    for (int i = 0; i < mm; ++i) v[i] -= dot * q[i];
+                }
+            double nrm = 0;
+            for (int i = 0; i < mm; ++i) nrm += std::norm(v[i]);
+            nrm = std::sqrt(nrm);
+            if (nrm < 1e-8) return false;
+            for (int i = 0; i < mm; ++i) v[i] /= nrm;
+            cols.push_back(std::move(v));
+            return true;
+        };
+        for (int j = 0; j < k; ++j) {
+            std::vector<cplx> v(mm);
+            for (int i = 0; i < mm; ++i) v[i] = Y[(size_t)i * mm + j];
+            cols.push_back(std::move(v));
+        }
+        for (int j = 0; j < k && (int)cols.size() < room && D.prev_rows > 0; ++j) {
+            std::vector<cplx> v(mm, cplx(0, 0));
+            for (int i = 0; i < std::min(D.prev_rows, mm); ++i) v[i] = D.prev_coef[(size_t)i * k + j];
+            ortho_push(std::move(v));
+        }
+        for (int j = k; j < mm && (int)cols.size() < room; ++j) {
+            std::vector<cplx> v(mm);
+            for (int i = 0; i < mm; ++i) v[i] = Y[(size_t)i * mm + j];
+            ortho_push(std::move(v));
+        }
+        const int kr = (int)cols.size();
         std::vector<cplx> Yr((size_t)mm * kr);
         for (int i = 0; i < mm; ++i)
-            for (int j = 0; j < kr; ++j) Yr[(size_t)i * kr + j] = Y[(size_t)i * mm + j];
+            for (int j = 0; j < kr; ++j) Yr[(size_t)i * kr + j] = cols[j][i];
+        // G' = Q^H A Q on the host
+        std::vector<cplx> AQ((size_t)mm * kr, cplx(0, 0));
+        for (int i = 0; i < mm; ++i)
+            for (int l = 0; l < mm; ++l) {
+                const cplx a = A[(size_t)i * mm + l];
+                for (int j = 0; j < kr; ++j) AQ[(size_t)i * kr + j] += a * Yr[(size_t)l * kr + j];
+            }
+        std::vector<cplx> Gn((size_t)kr * kr, cplx(0, 0));
+        for (int a2 = 0; a2 < kr; ++a2)
+            for (int b2 = 0; b2 < kr; ++b2) {
+                cplx v(0, 0);
+                for (int i = 0; i < mm; ++i) v += std::conj(Yr[(size_t)i * kr + a2]) * AQ[(size_t)i * kr + b2];
+                Gn[(size_t)a2 * kr + b2] = v;
+            }
         if ((s = d.put_small(Yr, kYOff))) return s;
         if ((s = d.hip(launch_combine(d.cx, c->d_V.p, nullptr, N, mm, c->d_small.p, kr, nullptr, c->d_X.p, nullptr, N,
                                       0, c->stream),
@@ -603,10 +659,22 @@ static stpci_status dav_advance(stpci_ctx* c) {
         if ((s = d.hip(hipMemcpyAsync(c->d_W.p, c->d_R.p, vb * kr, hipMemcpyDeviceToDevice, c->stream), "restart W")))
             return s;
         std::fill(D.G.begin(), D.G.end(), cplx(0, 0));
-        for (int j = 0; j < kr; ++j) Gat(j, j) = w[j];
+        for (int a2 = 0; a2 < kr; ++a2)
+            for (int b2 = 0; b2 < kr; ++b2) Gat(a2, b2) = Gn[(size_t)a2 * kr + b2];
         mm = kr;
         D.m = kr;
+        // this iteration's Ritz vectors are the first k new basis vectors
+        Pc.assign((size_t)kr * k, cplx(0, 0));
+        for (int j = 0; j < k; ++j) Pc[(size_t)j * k + j] = cplx(1, 0);
+        Pc_rows = kr;
+    } else {
+        Pc.assign((size_t)mm * k, cplx(0, 0));
+        for (int i = 0; i < mm; ++i)
+            for (int j = 0; j < k; ++j) Pc[(size_t)i * k + j] = Y[(size_t)i * mm + j];
+        Pc_rows = mm;
     }
+    D.prev_coef = std::move(Pc);
+    D.prev_rows = Pc_rows;
     // block orthonormalisation of the corrections: two classical Gram-Schmidt
     // passes against V, then two Cholesky QR passes among themselves; a
     // direction that keeps less than 1e-8 of its norm lies in the span

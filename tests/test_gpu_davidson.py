@@ -156,3 +156,21 @@ def test_davidson_config2_matches_oracle_davidson():
     assert len(pb.dets) == ref["n_dets"]
     e, r, it, st = pb.context().davidson(k=2, tol=1e-6, max_iter=300)
     assert np.max(np.abs(e - np.array(ref["energies"]))) <= 1e-9
+
+
+@pytest.mark.parametrize("name,k", [("c1", 1), ("T8", 2), ("c1", 3)])
+def test_small_basis_restart_converges(name, k):
+    """A basis of only 2k + 1 vectors (as on a space where few vectors fit
+    the device): the restart keeps the current and the previous Ritz vectors
+    (GD+k), so the run still converges to the exact energies, in a bounded
+    multiple of the iterations of an unrestricted run."""
+    from oracle import dense
+    pb = Problem.named(name)
+    w = np.linalg.eigvalsh(dense.hamiltonian(pb.dets, pb.h, pb.g, real=not pb.cplx))[:k] + pb.ints.e_core
+    ctx = pb.context()
+    e_full, r_full, it_full, _ = ctx.davidson(k=k, tol=1e-8, max_iter=500)
+    e, r, it, st = ctx.davidson(k=k, tol=1e-8, max_iter=500, max_subspace=2 * k + 1)
+    print(name, k, "iterations full basis", it_full, "basis of", 2 * k + 1, ":", it, flush=True)
+    assert np.max(r) <= 1e-8
+    assert np.max(np.abs(e - w)) <= 1e-9
+    assert it <= 4 * it_full + 10

@@ -46,7 +46,7 @@ def main():
                     help="headline: c3p (40 spinors, 12|16|12, 11 electrons) or c2 (24 spinors, 8 electrons)")
     ap.add_argument("--partition", default="24", help="config-2 subspace sizes, e.g. 24 or 8,8,8")
     ap.add_argument("--no-c2", action="store_true", help="skip the config-2 section")
-    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 step of the headline")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the FP32 and BF16 steps of the headline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--solves", type=int, default=5)
@@ -115,7 +115,8 @@ def main():
 
 def _headline_c3p(args):
     """The headline step: FP64 sigma of one vector on the 40-spinor,
-    12|16|12, 11-electron STP-DAS space, and the BF16 form of the same step."""
+    12|16|12, 11-electron STP-DAS space, and the FP32 and BF16 forms of the
+    same step."""
     import numpy as np
     import torch
     import synth
@@ -202,22 +203,28 @@ def _headline_c3p(args):
         "roofline": roof,
     }
     if not args.no_bf16:
-        # the BF16 form of the same step (bfloat16 integrals and coefficients on
-        # the matrix cores, FP32 accumulation, FP64 sums), error against FP64
+        # the reduced-precision forms of the same step, error against FP64:
+        # FP32 (the same spectator-batched kernel with the FP32 table and B
+        # tiles on v_mfma_f32_16x16x4f32) and BF16 (bfloat16 integrals and
+        # coefficients on the matrix cores); FP32 accumulation, FP64 sums
         out2 = torch.empty_like(out)
-        ctx.sigma(c, out2, n_vec=n_vec, precision=stpci.BF16)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        ctx.sigma(c, out2, n_vec=n_vec, precision=stpci.BF16)
-        e1.record()
-        torch.cuda.synchronize()
-        ms_b = e0.elapsed_time(e1)
-        err = float(torch.linalg.vector_norm(out2 - out) / torch.linalg.vector_norm(out))
-        log("BF16 sigma: %.1f ms, relative error %.2e" % (ms_b, err))
-        res["precision"] = {"sigma_fp64_ms": ms_per_step, "sigma_bf16_ms": ms_b,
-                            "sigma_bf16_speedup": ms_per_step / ms_b, "sigma_bf16_rel_err": err,
-                            "bf16_kernel": "k_sigma_pair_mfma (v_mfma_f32_16x16x32_bf16, FP32 accumulation)"}
+        prec = {"sigma_fp64_ms": ms_per_step}
+        for pname, pcode, kdesc in (
+                ("fp32", stpci.FP32, "k_sigma_pair_sb FP32 instance (v_mfma_f32_16x16x4f32, FP32 accumulation)"),
+                ("bf16", stpci.BF16, "k_sigma_pair_mfma (v_mfma_f32_16x16x32_bf16, FP32 accumulation)")):
+            ctx.sigma(c, out2, n_vec=n_vec, precision=pcode)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.sigma(c, out2, n_vec=n_vec, precision=pcode)
+            e1.record()
+            torch.cuda.synchronize()
+            ms_p = e0.elapsed_time(e1)
+            err = float(torch.linalg.vector_norm(out2 - out) / torch.linalg.vector_norm(out))
+            log("%s sigma: %.1f ms, relative error %.2e" % (pname.upper(), ms_p, err))
+            prec.update({"sigma_%s_ms" % pname: ms_p, "sigma_%s_speedup" % pname: ms_per_step / ms_p,
+                         "sigma_%s_rel_err" % pname: err, "%s_kernel" % pname: kdesc})
+        res["precision"] = prec
         del out2
     if not args.no_sparse:
         del c, out

@@ -392,7 +392,7 @@ stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, st
             E = c->d_E.p;
         }
         if (!c->pair_store) E = nullptr;
-        if (c->pair_sb && !f32)
+        if (c->pair_sb)
             e = launch_sigma_pair_sb(c->dev, c->sb_plan, c->cplx, f32, f32 ? c->d_pA32.p : c->d_pA.p, cin, sout,
                                      n_vec, c->e_core, c->profile ? &mk : nullptr, c->stream);
         else if (c->pair_grp)

@@ -30,8 +30,11 @@
 // the products of the current one; every entry formed without branches);
 // each table fragment (one 16-byte read per lane) feeds one product per
 // column group and table part.  E is added to sigma with device atomics
-// (sigma is not bitwise deterministic).  FP64 only: the FP32 contraction of
-// such spaces runs on the vector-ALU pair kernel.
+// (sigma is not bitwise deterministic).  The FP32 form of the precision
+// option runs the same kernel with the FP32 table, B rounded to FP32 in LDS
+// and v_mfma_f32_16x16x4f32 (FP32 accumulation of a product; its output rows
+// lie at 4 (lane / 16) + i instead of lane / 16 + 4 i); E is added to the
+// FP64 sigma.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -325,6 +328,11 @@ __device__ __forceinline__ double sb_quad_xor(double x) {
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), ctrl, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
+template <int X>
+__device__ __forceinline__ float sb_quad_xor(float x) {
+    constexpr int ctrl = (X == 2) ? 0x4E : 0xB1;
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), ctrl, 0xF, 0xF, false));
+}
 
 // f(integral_constant<int, I>) ... f(integral_constant<int, N - 1>), unrolled.
 template <int I, int N, class F>
@@ -393,14 +401,14 @@ struct SbItem {
 // pass (the gathers of the next chunk in flight during the products of the
 // current one); the row tile is then scattered through an LDS staging area
 // with device atomics.
-template <bool CPLX, int NV, int NGU, typename TA>
+template <bool CPLX, int NV, int NGU, bool F32, typename TA, typename BT>
 __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ A, int NP,
                                         const typename VT<CPLX>::T* __restrict__ c,
-                                        typename VT<CPLX>::T* __restrict__ sigma, int64_t nd, int n_vec, double* bsh,
+                                        typename VT<CPLX>::T* __restrict__ sigma, int64_t nd, int n_vec, BT* bsh,
                                         int tid) {
     using V64 = VT<CPLX>;
     using TE = typename V64::T;
-    using ACC = sb_f64x4;
+    using ACC = std::conditional_t<F32, sb_f32x4, sb_f64x4>;
     constexpr int CW = CPLX ? 2 * NV : NV;   // columns per member
     constexpr int KPG = 16 / CW;             // members per column group
     constexpr int NT = SB_WAVES * 64;
@@ -442,22 +450,22 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
         for (int e = 0; e < EPT; ++e) gx[e] = c[ga[e]];
     };
     auto gen_commit = [&](int kc, int buf) {
-        double* B = bsh + (size_t)buf * SB_TK * SB_BSTR;
+        BT* B = bsh + (size_t)buf * SB_TK * SB_BSTR;
         bool nz = false;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const double sgd = (double)gsg[e];
             if constexpr (CPLX) {
-                const double xr = gsg[e] ? sgd * gx[e].x : 0.0, xi = gsg[e] ? sgd * gx[e].y : 0.0;
+                const BT xr = (BT)(gsg[e] ? sgd * gx[e].x : 0.0), xi = (BT)(gsg[e] ? sgd * gx[e].y : 0.0);
                 if (gcol[e] >= 0) {
                     B[gcol[e]] = xr;
                     B[gcol[e] + NV] = xi;
                 }
-                nz = nz || xr != 0.0 || xi != 0.0;
+                nz = nz || xr != (BT)0 || xi != (BT)0;
             } else {
-                const double xr = gsg[e] ? sgd * gx[e] : 0.0;
+                const BT xr = (BT)(gsg[e] ? sgd * gx[e] : 0.0);
                 if (gcol[e] >= 0) B[gcol[e]] = xr;
-                nz = nz || xr != 0.0;
+                nz = nz || xr != (BT)0;
             }
         }
         if (__ballot(nz) != 0 && lane == 0) atomicOr(&I.flags[kc], 1);
@@ -486,7 +494,7 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
         for (int kc = 0; kc < nkc; ++kc) {
             const int buf = kc & 1;
             const bool more = kc + 1 < nkc;
-            const double* B = bsh + (size_t)buf * SB_TK * SB_BSTR;
+            const BT* B = bsh + (size_t)buf * SB_TK * SB_BSTR;
             const uint32_t* rnext = I.rinf + (kc + 1) * SB_TK;
             // the table fragments of this chunk (requested during the
             // previous one) are in: stating it here keeps the compiler from
@@ -516,7 +524,7 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
         for (int kc = 0; kc < nkc; ++kc) any = any || I.flags[kc] != 0;
         constexpr int SC = SB_SGP * 16;   // staged columns
         constexpr int MH = SC / CW;       // members per part
-        double* stage = bsh + (size_t)wid * 16 * SC;
+        BT* stage = bsh + (size_t)wid * 16 * SC;
 #pragma unroll
         for (int part = 0; part * SB_SGP < NGU; ++part) {
             if (!own || !any) break;
@@ -526,14 +534,14 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
                 if (h >= NGU) break;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    double val;
+                    BT val;
                     if constexpr (CPLX) {
-                        const double pv = sb_quad_xor<NV == 2 ? 2 : 1>(c2[h][i]);
+                        const BT pv = sb_quad_xor<NV == 2 ? 2 : 1>((BT)c2[h][i]);
                         val = (col < NV) ? c1[h][i] - pv : c1[h][i] + pv;
                     } else {
                         val = c1[h][i];
                     }
-                    stage[(kq + 4 * i) * SC + 16 * hh + c16] = val;
+                    stage[(F32 ? 4 * kq + i : kq + 4 * i) * SC + 16 * hh + c16] = val;
                 }
             }
             wave_lds_sync();
@@ -554,10 +562,10 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
                     if (v >= n_vec) break;
                     double* dst = reinterpret_cast<double*>(sigma + (int64_t)v * nd + addr);
                     if constexpr (CPLX) {
-                        unsafeAtomicAdd(dst, sgd * stage[row * SC + jl * CW + v]);
-                        unsafeAtomicAdd(dst + 1, sgd * stage[row * SC + jl * CW + NV + v]);
+                        unsafeAtomicAdd(dst, sgd * (double)stage[row * SC + jl * CW + v]);
+                        unsafeAtomicAdd(dst + 1, sgd * (double)stage[row * SC + jl * CW + NV + v]);
                     } else {
-                        unsafeAtomicAdd(dst, sgd * stage[row * SC + jl * CW + v]);
+                        unsafeAtomicAdd(dst, sgd * (double)stage[row * SC + jl * CW + v]);
                     }
                 }
             }
@@ -569,18 +577,19 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
 
 // One launch per item shape: items of NGU column groups (the streams of
 // (log2(CW), NGU)), persistent over the items, each XCD a contiguous share.
-template <bool CPLX, int NV, int NGU>
+template <bool CPLX, int NV, int NGU, bool F32>
 __global__ __launch_bounds__(SB_WAVES * 64, 1) void k_sigma_pair_sb(DevSpace S, SbPlan plan,
-                                                                    const typename VT<CPLX>::T* __restrict__ A,
+                                                                    const typename PT<CPLX, F32>::T* __restrict__ A,
                                                                     const typename VT<CPLX>::T* __restrict__ c,
                                                                     typename VT<CPLX>::T* __restrict__ sigma,
                                                                     int n_vec) {
+    using BT = std::conditional_t<F32, float, double>;
     constexpr int CW = CPLX ? 2 * NV : NV;   // columns per member
     constexpr int CWI = (CW == 1) ? 0 : (CW == 2 ? 1 : 2);
     constexpr int KPG = 16 / CW;             // members per column group
     constexpr int NT = SB_WAVES * 64;
     extern __shared__ __align__(16) unsigned char smem[];
-    const SbLayout LY(plan.cap, plan.nlmax, 8);
+    const SbLayout LY(plan.cap, plan.nlmax, (int)sizeof(BT));
     int64_t* rbase = reinterpret_cast<int64_t*>(smem + LY.base_off);
     uint32_t* rinf = reinterpret_cast<uint32_t*>(smem + LY.inf_off);
     uint32_t* colstr = reinterpret_cast<uint32_t*>(smem + LY.col_off);
@@ -588,7 +597,7 @@ __global__ __launch_bounds__(SB_WAVES * 64, 1) void k_sigma_pair_sb(DevSpace S, 
     int32_t* binom = reinterpret_cast<int32_t*>(smem + LY.bin_off);
     int* flags = reinterpret_cast<int*>(smem + LY.flag_off);
     SbHdr* hd = reinterpret_cast<SbHdr*>(smem + LY.hdr_off);
-    double* bsh = reinterpret_cast<double*>(smem + LY.b_off);
+    BT* bsh = reinterpret_cast<BT*>(smem + LY.b_off);
     const int tid = threadIdx.x;
     const int K = S.sp.K, L = K - 1;
     const int NP = S.sp.npairs;
@@ -654,36 +663,37 @@ __global__ __launch_bounds__(SB_WAVES * 64, 1) void k_sigma_pair_sb(DevSpace S, 
             rinf[r] = inf;
         }
         __syncthreads();
-        sb_item<CPLX, NV, NGU>(I, A, NP, c, sigma, nd, n_vec, bsh, tid);
+        sb_item<CPLX, NV, NGU, F32>(I, A, NP, c, sigma, nd, n_vec, bsh, tid);
     }
 }
 
-template <bool CPLX, int NV, int NGU>
+template <bool CPLX, int NV, int NGU, bool F32>
 static hipError_t launch_sb_g(const DevSpace& S, const SbPlan& plan, const void* A, const void* c, void* sigma,
                               int nv, hipStream_t st) {
     using T64 = typename VT<CPLX>::T;
+    using TA = typename PT<CPLX, F32>::T;
     constexpr int CW = CPLX ? 2 * NV : NV;
     constexpr int CWI = (CW == 1) ? 0 : (CW == 2 ? 1 : 2);
     if (plan.nitems[CWI][NGU - 1] == 0) return hipSuccess;
-    const size_t lds = SbLayout(plan.cap, plan.nlmax, 8).bytes;
-    hipLaunchKernelGGL((k_sigma_pair_sb<CPLX, NV, NGU>), dim3(256), dim3(SB_WAVES * 64), lds, st, S, plan,
-                       (const T64*)A, (const T64*)c, (T64*)sigma, nv);
+    const size_t lds = SbLayout(plan.cap, plan.nlmax, F32 ? 4 : 8).bytes;
+    hipLaunchKernelGGL((k_sigma_pair_sb<CPLX, NV, NGU, F32>), dim3(256), dim3(SB_WAVES * 64), lds, st, S, plan,
+                       (const TA*)A, (const T64*)c, (T64*)sigma, nv);
     return hipGetLastError();
 }
 
 // One launch per column-group count, SB_NG down to 1.
-template <bool CPLX, int NV, int NGU = SB_NG>
+template <bool CPLX, int NV, bool F32, int NGU = SB_NG>
 static hipError_t launch_sb_nv(const DevSpace& S, const SbPlan& plan, const void* A, const void* c, void* sigma,
                                int nv, hipStream_t st) {
     static_assert(NGU >= 1 && NGU <= SB_NG, "column-group count");
-    const hipError_t e = launch_sb_g<CPLX, NV, NGU>(S, plan, A, c, sigma, nv, st);
+    const hipError_t e = launch_sb_g<CPLX, NV, NGU, F32>(S, plan, A, c, sigma, nv, st);
     if constexpr (NGU > 1) {
-        if (e == hipSuccess) return launch_sb_nv<CPLX, NV, NGU - 1>(S, plan, A, c, sigma, nv, st);
+        if (e == hipSuccess) return launch_sb_nv<CPLX, NV, F32, NGU - 1>(S, plan, A, c, sigma, nv, st);
     }
     return e;
 }
 
-template <bool CPLX>
+template <bool CPLX, bool F32>
 static hipError_t launch_sb_all(const DevSpace& S, const SbPlan& plan, const void* A, const void* c, void* sigma,
                                 int n_vec, double e_core, const LaunchMarks* mk, hipStream_t st) {
     using T64 = typename VT<CPLX>::T;
@@ -695,7 +705,8 @@ static hipError_t launch_sb_all(const DevSpace& S, const SbPlan& plan, const voi
         const T64* cc = (const T64*)c + off;
         T64* ss = (T64*)sigma + off;
         if (mk) mk->fn(mk->user, 0, true);
-        e = (nv == 2) ? launch_sb_nv<CPLX, 2>(S, plan, A, cc, ss, 2, st) : launch_sb_nv<CPLX, 1>(S, plan, A, cc, ss, 1, st);
+        e = (nv == 2) ? launch_sb_nv<CPLX, 2, F32>(S, plan, A, cc, ss, 2, st)
+                      : launch_sb_nv<CPLX, 1, F32>(S, plan, A, cc, ss, 1, st);
         if (mk) mk->fn(mk->user, 0, false);
         if (e != hipSuccess) return e;
     }
@@ -705,11 +716,14 @@ static hipError_t launch_sb_all(const DevSpace& S, const SbPlan& plan, const voi
 hipError_t launch_sigma_pair_sb(const DevSpace& S, const SbPlan& plan, bool cplx, bool f32, const void* A,
                                 const void* c, void* sigma, int n_vec, double e_core, const LaunchMarks* mk,
                                 hipStream_t st) {
-    if (plan.ncat <= 0 || plan.cap <= 0 || plan.cap > SB_ROWS_MAX || f32 ||
-        SbLayout(plan.cap, plan.nlmax, 8).bytes > 160 * 1024)
+    if (plan.ncat <= 0 || plan.cap <= 0 || plan.cap > SB_ROWS_MAX ||
+        SbLayout(plan.cap, plan.nlmax, f32 ? 4 : 8).bytes > 160 * 1024)
         return hipErrorInvalidValue;
-    return cplx ? launch_sb_all<true>(S, plan, A, c, sigma, n_vec, e_core, mk, st)
-                : launch_sb_all<false>(S, plan, A, c, sigma, n_vec, e_core, mk, st);
+    if (f32)
+        return cplx ? launch_sb_all<true, true>(S, plan, A, c, sigma, n_vec, e_core, mk, st)
+                    : launch_sb_all<false, true>(S, plan, A, c, sigma, n_vec, e_core, mk, st);
+    return cplx ? launch_sb_all<true, false>(S, plan, A, c, sigma, n_vec, e_core, mk, st)
+                : launch_sb_all<false, false>(S, plan, A, c, sigma, n_vec, e_core, mk, st);
 }
 
 // Host check of the arithmetic above (the same functions on the host

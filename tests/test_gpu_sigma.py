@@ -209,14 +209,18 @@ def test_grouped_pair_kernel(n, M, cplx, n_vec):
     ([4, 4], [3, 3], [4, 4], 7, 1, True),               # one hole
     ([4, 4], [4, 4], [4, 4], 8, 1, True),               # a single determinant
 ])
-def test_spectator_batched_kernel(sub, lo, hi, n, n_vec, cplx):
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_spectator_batched_kernel(sub, lo, hi, n, n_vec, cplx, prec):
     """Spaces of several subspaces: the spectator-batched matrix-core kernel
     (the pair intermediates of a category that share the strings of the
     leading subspaces contracted as one product over their padded pair list,
     contributions added with device atomics) against the oracle, real and
-    complex, one to three vectors, degenerate electron counts."""
+    complex, one to three vectors, degenerate electron counts; FP64 (parity
+    bar) and its FP32 instance (FP32 table and tiles on the FP32 matrix
+    cores, FP64 sums: single-precision bar)."""
     import torch
-    print("case", sub, lo, hi, n, n_vec, cplx, flush=True)
+    import paper_2505_20375_amd as stpci
+    print("case", sub, lo, hi, n, n_vec, cplx, prec, flush=True)
     M = sum(sub)
     ints = (synth.complex_integrals if cplx else synth.real_integrals)(M, 60 + n + M, rank=8, sigma_f=0.05)
     pb = Problem(ints, synth.SpaceSpec(n, sub, lo or [], hi or []), seed=3)
@@ -225,13 +229,14 @@ def test_spectator_batched_kernel(sub, lo, hi, n, n_vec, cplx):
     ctx.set_sigma_kernel("pair_sb")
     x = torch.cat([pb.to_device(v) for v in cs])
     out = torch.empty_like(x)
-    ctx.sigma(x, out, n_vec=n_vec)
+    ctx.sigma(x, out, n_vec=n_vec, precision=stpci.FP32 if prec == "fp32" else stpci.FP64)
     torch.cuda.synchronize()
     if n >= 2:
         assert ctx.sigma_kernel() == "pair_sb"
     nd = len(pb.dets)
     for i, c in enumerate(cs):
-        assert rel_err(pb.from_device(out[i * nd:(i + 1) * nd]), pb.oracle_sigma(c)) <= TOL
+        assert rel_err(pb.from_device(out[i * nd:(i + 1) * nd]), pb.oracle_sigma(c)) <= (TOL if prec == "fp64"
+                                                                                          else 2e-6)
 
 
 def test_spectator_batched_kernel_core_energy_and_sparse():
@@ -392,8 +397,8 @@ def test_sparse_vector_after_dense(kernel, prec):
 def test_sigma_config3p_sampled_rows():
     """Full-size STP-DAS space (40 spinors, 12|16|12, windows [2..6]|[4..10]|[2..6],
     11 electrons: 1,365,867,360 determinants in 10 categories, 21.9 GB per
-    vector): one FP64 and one BF16 sigma build on a seeded vector in the
-    library layout, checked on 1000+ rows -- the first, middle and last
+    vector): one FP64, one FP32 and one BF16 sigma build on a seeded vector
+    in the library layout, checked on 1000+ rows -- the first, middle and last
     determinant of every category and random rows of every category --
     against the oracle's list-free Slater-Condon rows, every column address
     taken from the documented layout (test module), not from the library."""
@@ -442,9 +447,10 @@ def test_sigma_config3p_sampled_rows():
     np.add.at(refs, owner, vals * cvals)
     print("oracle rows: %d rows, %d couplings, %.1f s" % (len(rows), len(cols), time.time() - t0), flush=True)
     errs = {}
-    # the FP64 build (parity bar 1e-12), then the BF16 matrix-core build
-    # (bfloat16 rounding bar 2e-2) of the same vector
-    for prec, name in ((stpci.FP64, "fp64"), (stpci.BF16, "bf16")):
+    # the FP64 build (parity bar 1e-12), then the FP32 (single-precision bar
+    # 2e-6) and BF16 (bfloat16 rounding bar 2e-2) builds of the same vector
+    bars = {"fp64": TOL, "fp32": 2e-6, "bf16": 2e-2}
+    for prec, name in ((stpci.FP64, "fp64"), (stpci.FP32, "fp32"), (stpci.BF16, "bf16")):
         print("config 3' sigma (%s): %d determinants, kernel starting" % (name, n), flush=True)
         t0 = time.time()
         ctx.sigma(c, out, precision=prec)
@@ -458,10 +464,11 @@ def test_sigma_config3p_sampled_rows():
             _, off, cnt = ctx.category(cat)
             sel = (rows >= off) & (rows < off + cnt)
             e_cat = np.linalg.norm(got[sel] - refs[sel]) / np.linalg.norm(refs[sel])
-            assert e_cat <= (TOL if prec == stpci.FP64 else 2e-2), (name, cat, e_cat)
+            assert e_cat <= bars[name], (name, cat, e_cat)
         print("config 3' sampled-row relative error (%s): %.3g" % (name, errs[name]), flush=True)
     assert ctx.sigma_kernel() == "pair_sb"
     del c, out
     torch.cuda.empty_cache()
-    assert errs["fp64"] <= TOL
-    assert errs["bf16"] <= 2e-2
+    for name, bar in bars.items():
+        assert errs[name] <= bar, (name, errs[name])
+    assert errs["fp32"] > 0

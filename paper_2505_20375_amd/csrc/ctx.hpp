@@ -41,7 +41,6 @@ struct DavState {
     int m = 0;    // vectors in V with their W known
     int nv = 0;   // pending: W[m..m+nv) = H V[m..m+nv)
     int it = 0, it_prev = 0;
-    bool have_xp = false;    // d_Xp holds the previous iteration's Ritz vectors
     double best_rn = -1.0;   // BF16 phase: smallest largest-residual so far
     int stall = 0;           // iterations since it last dropped by 10 %
     bool converged = false, done = false, active = false;
@@ -52,7 +51,8 @@ struct DavState {
     bool energy_stop = false;         // the FP64 refinement ended on refine_tol_energy
     bool products_ready = false;      // step-wise runs: the pending products were computed
     // coordinates, in the current basis V, of the previous iteration's Ritz
-    // vectors ([prev_rows][k], row-major; prev_rows <= m), for the restart
+    // vectors ([prev_rows][k], row-major; prev_rows <= m), for the restart and
+    // the coefficient change
     std::vector<std::complex<double>> prev_coef;
     int prev_rows = 0;
 };
@@ -94,6 +94,11 @@ struct stpci_ctx {
     stp::DevBuf d_E;         // pair contributions of the store-and-reduce scatter
     stp::DevBuf d_bdesc, d_bjbegin;   // descriptors of stpci_dav_sigma_batched launches led by this context
     stp::DevBuf d_csc_cnt, d_csc_pcat, d_csc_bitmap, d_csc_list, d_csc_count;   // compressed-vector work
+    // pinned host staging of the solver's small transfers (coefficients up,
+    // dot products down): copies from it are asynchronous, so an upload does
+    // not wait for the stream; regions are reused after the next stream sync
+    void* pin = nullptr;
+    size_t pin_bytes = 0, pin_off = 0;
     bool csc_pcat_ready = false;
     bool pair_store = false; // pair kernel: store-and-reduce (true) or device atomics
     bool pair_mf64 = false;   // FP64 pair products on the matrix cores (else the vector-ALU tiles)
@@ -114,7 +119,7 @@ struct stpci_ctx {
     int s2_kernel = 4;
 
     // Davidson workspace
-    stp::DevBuf d_V, d_W, d_X, d_Xp, d_R, d_T, d_partial, d_small, d_topv, d_topi;
+    stp::DevBuf d_V, d_W, d_X, d_T, d_partial, d_small, d_topv, d_topi;
     std::vector<stp::DavRecord> history;
     int hist_k = 0;
     int nsigma[3] = {0, 0, 0};   // sigma builds of the last Davidson run: FP64, FP32, BF16 (vectors)

@@ -152,13 +152,28 @@ void herm_eig(int n, std::vector<cplx> A, std::vector<double>& w, std::vector<cp
 namespace {
 
 // layout of the small device workspace
-constexpr size_t kYOff = 0;                 // Ritz coefficients, up to 64 x 32 complex
-constexpr size_t kThetaOff = 64 * 32 * 16;  // Ritz values, 64 doubles
-constexpr size_t kDcOff = kThetaOff + 64 * 8;  // Ritz coefficient changes, 16 complex slots
-constexpr size_t kDotsOff = kDcOff + 16 * 16;  // (directly before the dots: fetched with them)
-constexpr int kDotsMax = 64 * 16;           // dot products fetched in one round trip
+constexpr size_t kYOff = 0;                         // coefficient matrices, up to 64 x 32 complex
+constexpr size_t kZOff = kYOff + 64 * 32 * 16;      // Ritz coefficient changes, up to 64 x 16 complex
+constexpr size_t kThetaOff = kZOff + 64 * 16 * 16;  // Ritz values, 64 doubles
+constexpr size_t kRitzOff = kThetaOff + 64 * 8;     // per root ||r||^2, ||t||^2, max |x - ph x_prev|^2 (ritz_slot)
+constexpr size_t kNrmOff = kRitzOff + 16 * 3 * 8;   // norms of the corrections after the eps drop (32 slots)
+constexpr size_t kGramOff = kNrmOff + 32 * 16;      // Gram matrix of the corrections (after the norms: one fetch)
+constexpr size_t kGramBytes = 16 * 16 * 16;
+constexpr size_t kDotsOff = kGramOff + 16 * 16 * 16;   // dot products
+constexpr int kDotsMax = 64 * 16;                   // dot products queued at once
 constexpr size_t kCoefOff = kDotsOff + (size_t)kDotsMax * 16;
 constexpr size_t kSmallBytes = kCoefOff + 64 * 16;
+static_assert(kDotsOff == kGramOff + kGramBytes, "workspace layout");
+
+// where the Ritz pass leaves ||r_j||^2 (q = 0), ||t_j||^2 (1) and the largest
+// |x_j - ph_j x_j(previous)|^2 (2), in doubles from kRitzOff
+static int ritz_slot(int j, int q) { return 12 * (j / 4) + 4 * q + j % 4; }
+
+// bytes of the partial-sum area the vector kernels share
+static size_t partial_bytes(int64_t N, int k) {
+    return std::max({(size_t)dots_blocks(N) * kDotsMax * 16, (size_t)ritz_blocks(N, k) * 12 * 8,
+                     (size_t)comb_gram_blocks(N) * 32 * 8});
+}
 
 struct Dav {
     stpci_ctx* c;
@@ -168,77 +183,103 @@ struct Dav {
     hipStream_t st;
 
     char* vec(DevBuf& b, int i) { return (char*)b.p + (size_t)i * N * sb; }
+    char* small(size_t off) { return (char*)c->d_small.p + off; }
 
     stpci_status hip(hipError_t e, const char* w) { return hip_check(c, e, w); }
 
-    // out[i] = <A_i | w> for i < m  (host result)
-    stpci_status dots(const void* A, int m, const void* w, std::vector<cplx>& out) {
-        char* small = (char*)c->d_small.p + kDotsOff;
-        stpci_status s = hip(launch_dots(cx, A, N, m, w, 1, N, c->d_partial.p, small, st), "dots");
+    // a region of the pinned staging buffer for `bytes` (the buffer is
+    // reused from its start after a stream synchronisation; when full, the
+    // stream is synchronised first); NULL when there is no pinned buffer
+    double* stage(size_t bytes) {
+        if (!c->pin) return nullptr;
+        bytes = (bytes + 255) & ~(size_t)255;
+        if (bytes > c->pin_bytes) return nullptr;
+        if (c->pin_off + bytes > c->pin_bytes) {
+            if (hipStreamSynchronize(st) != hipSuccess) return nullptr;
+            c->pin_off = 0;
+        }
+        double* p = (double*)((char*)c->pin + c->pin_off);
+        c->pin_off += bytes;
+        return p;
+    }
+    stpci_status synced(hipError_t e) {
+        if (e == hipSuccess) c->pin_off = 0;   // every staged copy has completed
+        return hip(e, "sync");
+    }
+
+    // upload n doubles to d_small + byte_off (through the pinned buffer)
+    stpci_status put_doubles(const double* src, size_t n, size_t byte_off) {
+        double* p = stage(n * 8);
+        if (p) {
+            std::memcpy(p, src, n * 8);
+            return hip(hipMemcpyAsync(small(byte_off), p, n * 8, hipMemcpyHostToDevice, st), "small upload");
+        }
+        return hip(hipMemcpyAsync(small(byte_off), src, n * 8, hipMemcpyHostToDevice, st), "small upload");
+    }
+
+    // n doubles from d_small + byte_off (one round trip)
+    stpci_status get_doubles(size_t byte_off, size_t n, std::vector<double>& out) {
+        out.resize(n);
+        double* p = stage(n * 8);
+        stpci_status s = hip(hipMemcpyAsync(p ? p : out.data(), small(byte_off), n * 8, hipMemcpyDeviceToHost, st),
+                             "small copy");
         if (s) return s;
-        std::vector<double> buf((size_t)m * (cx ? 2 : 1));
-        if ((s = hip(hipMemcpyAsync(buf.data(), small, buf.size() * 8, hipMemcpyDeviceToHost, st), "dots copy")))
-            return s;
-        if ((s = hip(hipStreamSynchronize(st), "sync"))) return s;
-        out.resize(m);
-        for (int i = 0; i < m; ++i) out[i] = cx ? cplx(buf[2 * i], buf[2 * i + 1]) : cplx(buf[i], 0.0);
+        if ((s = synced(hipStreamSynchronize(st)))) return s;
+        if (p) std::memcpy(out.data(), p, n * 8);
         return STPCI_OK;
     }
 
-    // upload a small coefficient matrix Y (m x k, row-major) into d_small + off
+    // count scalars from d_small + byte_off
+    stpci_status get_scalars(size_t byte_off, int count, std::vector<cplx>& out) {
+        std::vector<double> raw;
+        stpci_status s = get_doubles(byte_off, (size_t)count * (cx ? 2 : 1), raw);
+        if (s) return s;
+        out.resize(count);
+        for (int i = 0; i < count; ++i) out[i] = cx ? cplx(raw[2 * i], raw[2 * i + 1]) : cplx(raw[i], 0.0);
+        return STPCI_OK;
+    }
+
+    // out[i] = <A_i | w> for i < m  (host result)
+    stpci_status dots(const void* A, int m, const void* w, std::vector<cplx>& out) {
+        stpci_status s = issue_dots(A, m, w, 1, 0);
+        if (s) return s;
+        return get_scalars(kDotsOff, m, out);
+    }
+
+    // upload a small coefficient matrix Y (row-major) into d_small + off
     stpci_status put_small(const std::vector<cplx>& Y, size_t byte_off) {
         std::vector<double> buf(Y.size() * (cx ? 2 : 1));
         for (size_t i = 0; i < Y.size(); ++i) {
             if (cx) { buf[2 * i] = Y[i].real(); buf[2 * i + 1] = Y[i].imag(); }
             else buf[i] = Y[i].real();
         }
-        return hip(hipMemcpyAsync((char*)c->d_small.p + byte_off, buf.data(), buf.size() * 8,
-                                  hipMemcpyHostToDevice, st),
-                   "small upload");
+        return put_doubles(buf.data(), buf.size(), byte_off);
     }
 
-    // queue out[off + t m + i] = <A_i | W_t>, i < m, t < nw, in the dot-product
-    // area (no sync); A and W are consecutive vectors of N scalars
-    stpci_status issue_dots(const void* A, int m, const void* W, int nw, int off) {
-        char* small = (char*)c->d_small.p + kDotsOff + (size_t)off * (cx ? 16 : 8);
-        return hip(launch_dots(cx, A, N, m, W, nw, N, c->d_partial.p, small, st), "dots");
+    // queue out[off + t m + i] = <A_i | W_t>, i < m, t < nw, in the area at
+    // area_off (the dot products by default; no sync); A and W are
+    // consecutive vectors of N scalars
+    stpci_status issue_dots(const void* A, int m, const void* W, int nw, int off, size_t area_off = kDotsOff) {
+        char* out = small(area_off) + (size_t)off * (cx ? 16 : 8);
+        return hip(launch_dots(cx, A, N, m, W, nw, N, c->d_partial.p, out, st), "dots");
     }
 
     // <A_j | W_j> for j < n (A, W: n consecutive vectors each), two roots per
     // launch: the launch for j0, j0 + 1 queues the 2 x 2 block of products at
-    // off + 2 j0, whose diagonal holds the two wanted values (the same sums,
-    // bit for bit, as one launch per root); pair_slots(n) slots in all
+    // off + 2 j0, whose diagonal holds the two wanted values; pair_slots(n)
+    // slots in all
     static int pair_slots(int n) { return 4 * (n / 2) + (n & 1); }
     static int pair_slot(int j, int n) {
         const int j0 = j & ~1, c = std::min(2, n - j0);
         return 2 * j0 + (j - j0) * (c + 1);
     }
-    stpci_status issue_pair_dots(char* A, char* W, int n, int off) {
+    stpci_status issue_pair_dots(char* A, char* W, int n, int off, size_t area_off = kDotsOff) {
         for (int j0 = 0; j0 < n; j0 += 2) {
             const int cnt = std::min(2, n - j0);
             const size_t at = (size_t)j0 * N * sb;
-            stpci_status s = issue_dots(A + at, cnt, W + at, cnt, off + 2 * j0);
+            stpci_status s = issue_dots(A + at, cnt, W + at, cnt, off + 2 * j0, area_off);
             if (s) return s;
         }
-        return STPCI_OK;
-    }
-
-    // fetch the first `count` queued dot products (one round trip); with dc,
-    // also the first dc->size() Ritz coefficient changes in the same copy
-    stpci_status fetch(int count, std::vector<cplx>& out, std::vector<double>* dc = nullptr) {
-        const size_t w = cx ? 2 : 1;
-        const size_t pre = dc ? (kDotsOff - kDcOff) / 8 : 0;   // doubles before the dots
-        std::vector<double> raw(pre + (size_t)count * w);
-        stpci_status s = hip(hipMemcpyAsync(raw.data(), (char*)c->d_small.p + kDotsOff - pre * 8, raw.size() * 8,
-                                            hipMemcpyDeviceToHost, st),
-                             "dots copy");
-        if (s) return s;
-        if ((s = hip(hipStreamSynchronize(st), "sync"))) return s;
-        out.resize(count);
-        for (int i = 0; i < count; ++i)
-            out[i] = cx ? cplx(raw[pre + 2 * i], raw[pre + 2 * i + 1]) : cplx(raw[pre + i], 0.0);
-        if (dc)
-            for (size_t j = 0; j < dc->size(); ++j) (*dc)[j] = raw[j * w];
         return STPCI_OK;
     }
 
@@ -253,16 +294,13 @@ struct Dav {
     stpci_status subtract(const void* A, int m, const std::vector<cplx>& coef, void* x) {
         stpci_status s = put_small(coef, kCoefOff);
         if (s) return s;
-        return hip(launch_combine(cx, A, nullptr, N, m, (char*)c->d_small.p + kCoefOff, 1, nullptr, x, nullptr, N,
-                                  2, st),
-                   "cgs");
+        return hip(launch_combine(cx, A, nullptr, N, m, small(kCoefOff), 1, nullptr, x, nullptr, N, 2, st), "cgs");
     }
 
     // T_q = Eq. sparsePreconditioner applied to R_root[q] with theta[q]:
     // s = r / (theta - H_ii) (0 where |theta - H_ii| < 1e-12), then, with
-    // eps > 0, entries below eps ||s_q|| dropped; ||s_q||^2 computed on the
-    // device into the dot-product area (slots pair_slot(q, nt)) and read
-    // there by the drop kernel, without a round trip
+    // eps > 0, entries below eps ||s_q|| dropped (||s_q||^2 computed on the
+    // device and read there by the drop kernel, without a round trip)
     stpci_status precondition(const void* R, void* T, int nt, const int* roots, const double* thetas, double eps) {
         stpci_status s = hip(launch_precond(c->dev, cx, (const double*)c->d_hd.p, (const double*)c->d_JK.p,
                                             c->e_core, R, T, N, nt, roots, thetas, 1e-12, st),
@@ -271,16 +309,14 @@ struct Dav {
         if ((s = issue_pair_dots((char*)T, (char*)T, nt, 0))) return s;
         int slot[PRE_MAX];
         for (int q = 0; q < nt; ++q) slot[q] = pair_slot(q, nt);
-        return hip(launch_eps_drop(cx, T, N, N, nt, slot, (const double*)((char*)c->d_small.p + kDotsOff),
-                                   cx ? 2 : 1, eps, st),
+        return hip(launch_eps_drop(cx, T, N, N, nt, slot, (const double*)small(kDotsOff), cx ? 2 : 1, eps, st),
                    "eps drop");
     }
 
     // X_t -= sum_i A_i <A_i | X_t> for t < nx, the products queued by
-    // issue_dots(A, m, X, nx, off) and read where they lie (no round trip)
-    stpci_status subtract_queued(const void* A, int m, int off, int nx, void* X) {
-        const char* coef = (const char*)c->d_small.p + kDotsOff + (size_t)off * (cx ? 16 : 8);
-        return hip(launch_combine(cx, A, nullptr, N, m, coef, nx, nullptr, X, nullptr, N, 3, st), "cgs");
+    // issue_dots(A, m, X, nx, 0) and read where they lie (no round trip)
+    stpci_status subtract_queued(const void* A, int m, int nx, void* X) {
+        return hip(launch_combine(cx, A, nullptr, N, m, small(kDotsOff), nx, nullptr, X, nullptr, N, 3, st), "cgs");
     }
 };
 
@@ -296,7 +332,7 @@ extern "C" stpci_status stpci_test_precond(stpci_ctx* c, const void* r_dev, void
     if (s) return s;
     if ((s = hip_check(c, hipSetDevice(c->device), "hipSetDevice"))) return s;
     const int64_t N = c->hs.sp.ndets;
-    if ((s = ensure(c, c->d_partial, (size_t)dots_blocks(N) * kDotsMax * 16, "dot partials"))) return s;
+    if ((s = ensure(c, c->d_partial, partial_bytes(N, n), "dot partials"))) return s;
     if ((s = ensure(c, c->d_small, kSmallBytes, "small workspace"))) return s;
     Dav d{c, N, scalar_bytes(c), c->cplx, c->stream};
     std::vector<int> roots(n);
@@ -346,12 +382,12 @@ int64_t dav_device_bytes(const stpci_ctx* c, const stpci_dav_opts& o) {
     const int64_t N = c->hs.sp.ndets;
     const int64_t vb = N * (int64_t)scalar_bytes(c);
     const bool extra = o.certify || (o.refine_tol_energy > 0.0 && o.precision != STPCI_FP64);
-    const int k = o.k + ((extra && o.k < 16 && o.k < N) ? 1 : 0), kr = std::min(2 * k, 32);
+    const int k = o.k + ((extra && o.k < 16 && o.k < N) ? 1 : 0);
     stpci_dav_opts run = o;   // the options of the run, with the extra root of certify
     run.k = k;
     const int mmax = subspace_cap(subspace_request(run), k, N);
-    int64_t b = vb * (2LL * mmax + 2LL * kr + 2LL * k);
-    b += (int64_t)dots_blocks(N) * kDotsMax * 16 + (int64_t)kSmallBytes;
+    int64_t b = vb * (2LL * mmax + 2LL * k);
+    b += (int64_t)partial_bytes(N, k) + (int64_t)kSmallBytes;
     if (!o.guess_dev) b += 1024LL * k * 16;  // top-k partials: at most 1024 blocks
     return b;
 }
@@ -367,7 +403,6 @@ static stpci_status dav_start(stpci_ctx* c, stpci_precision prec, const void* gu
     D.tol = tol;
     D.pidx = (prec == STPCI_FP32) ? 1 : (prec == STPCI_BF16) ? 2 : 0;
     D.best_rn = -1.0;
-    D.have_xp = false;
     D.stall = 0;
     const size_t vb = (size_t)N * scalar_bytes(c);
     D.kr_max = std::min(2 * k, 32);
@@ -376,8 +411,8 @@ static stpci_status dav_start(stpci_ctx* c, stpci_precision prec, const void* gu
         // expansion space bounded by the device memory left for V and W
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) == hipSuccess && vb > 0) {
-            const size_t have = c->d_V.bytes + c->d_W.bytes + c->d_X.bytes + c->d_R.bytes + c->d_T.bytes;
-            const double budget = 0.85 * (double)(fr + have) / (double)vb - 2.0 * D.kr_max - k;
+            const size_t have = c->d_V.bytes + c->d_W.bytes + c->d_X.bytes + c->d_T.bytes;
+            const double budget = 0.85 * (double)(fr + have) / (double)vb - 2.0 * k;
             if (budget / 2.0 < mmax) mmax = (int)std::max(budget / 2.0, (double)(2 * k));
         }
     }
@@ -385,12 +420,21 @@ static stpci_status dav_start(stpci_ctx* c, stpci_precision prec, const void* gu
     D.max_iter = o.max_iter > 0 ? o.max_iter : 100;
     if ((s = ensure(c, c->d_V, vb * D.mmax, "Davidson V"))) return s;
     if ((s = ensure(c, c->d_W, vb * D.mmax, "Davidson W"))) return s;
-    if ((s = ensure(c, c->d_X, vb * D.kr_max, "Ritz vectors"))) return s;
-    if ((s = ensure(c, c->d_R, vb * D.kr_max, "residuals"))) return s;
+    if ((s = ensure(c, c->d_X, vb * k, "Ritz vectors"))) return s;
     if ((s = ensure(c, c->d_T, vb * k, "corrections"))) return s;
-    if ((s = ensure(c, c->d_Xp, vb * k, "previous Ritz vectors"))) return s;
-    if ((s = ensure(c, c->d_partial, (size_t)dots_blocks(N) * kDotsMax * 16, "dot partials"))) return s;
+    if ((s = ensure(c, c->d_partial, partial_bytes(N, k), "dot partials"))) return s;
     if ((s = ensure(c, c->d_small, kSmallBytes, "small workspace"))) return s;
+    if (!c->pin) {
+        // 1 MB of pinned staging for the small transfers of the iteration
+        if (hipHostMalloc(&c->pin, (size_t)1 << 20, hipHostMallocDefault) == hipSuccess) {
+            c->pin_bytes = (size_t)1 << 20;
+        } else {
+            c->pin = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    if ((s = hip_check(c, hipStreamSynchronize(c->stream), "sync"))) return s;   // no staged copy in flight
+    c->pin_off = 0;
     Dav d{c, N, scalar_bytes(c), c->cplx, c->stream};
     if (guess_dev) {
         if ((s = d.hip(hipMemcpyAsync(c->d_V.p, guess_dev, vb * k, hipMemcpyDeviceToDevice, c->stream), "guess")))
@@ -445,12 +489,21 @@ static stpci_status dav_start(stpci_ctx* c, stpci_precision prec, const void* gu
 
 // After the pending sigma products: one Rayleigh-Ritz iteration.  Sets D.done
 // when converged, at max_iter, or when no new direction survives CGS2.
+//
+// Vector passes of an iteration (k roots, m basis vectors): the new columns
+// of G = V^H W (one dot-product pass); one fused Rayleigh-Ritz pass that
+// forms the Ritz vectors, the residuals' preconditioned corrections and the
+// reductions the host needs (residual norms, correction norms, the largest
+// coefficient change) without storing the residuals; the optional eps drop;
+// CGS2 of the corrections against V (two dot-product passes and two
+// subtractions, the second with the corrections' Gram matrix); Cholesky QR
+// into V (with the Gram matrix of the result) and its second pass in place.
+// The restart transforms V and W in place.
 static stpci_status dav_advance(stpci_ctx* c) {
     DavState& D = c->dav;
     stpci_status s;
     const int64_t N = c->hs.sp.ndets;
     const int k = D.opts.k;
-    const size_t vb = (size_t)N * scalar_bytes(c);
     Dav d{c, N, scalar_bytes(c), c->cplx, c->stream};
     auto Gat = [&](int i, int j) -> cplx& { return D.G[(size_t)i * 64 + j]; };
     c->nsigma[D.pidx] += D.nv;
@@ -459,7 +512,7 @@ static stpci_status dav_advance(stpci_ctx* c) {
         const int mt = D.m + D.nv;
         if ((s = d.issue_dots(c->d_V.p, mt, d.vec(c->d_W, D.m), D.nv, 0))) return s;
         std::vector<cplx> cols;
-        if ((s = d.fetch(D.nv * mt, cols))) return s;
+        if ((s = d.get_scalars(kDotsOff, D.nv * mt, cols))) return s;
         for (int j = D.m; j < mt; ++j)
             for (int i = 0; i < mt; ++i) {
                 Gat(i, j) = cols[(size_t)(j - D.m) * mt + i];
@@ -480,60 +533,44 @@ static stpci_status dav_advance(stpci_ctx* c) {
     for (int i = 0; i < m; ++i)
         for (int j = 0; j < k; ++j) Yk[(size_t)i * k + j] = Y[(size_t)i * m + j];
     for (int j = 0; j < k; ++j) D.theta[j] = w[j];
+    // the change of each Ritz vector since the previous iteration, x_j - ph_j
+    // x_j(previous) = V z_j with z_j = y_j - ph_j yp_j (yp_j: the previous Ritz
+    // vector's coordinates in this basis, ph_j = <x_prev|x>/|<x_prev|x>| from
+    // the coordinates: V has orthonormal columns); its largest entry is
+    // reported beside E and ||r|| (Results)
+    const bool have_prev = D.prev_rows > 0;
+    if (have_prev) {
+        std::vector<cplx> Z((size_t)m * k);
+        const int pr = std::min(D.prev_rows, m);
+        for (int j = 0; j < k; ++j) {
+            cplx o(0, 0);
+            for (int i = 0; i < pr; ++i) o += std::conj(D.prev_coef[(size_t)i * k + j]) * Yk[(size_t)i * k + j];
+            const double a = std::abs(o);
+            const cplx ph = a > 0 ? o / a : cplx(1.0, 0.0);
+            for (int i = 0; i < m; ++i) {
+                const cplx yp = i < pr ? D.prev_coef[(size_t)i * k + j] : cplx(0, 0);
+                Z[(size_t)i * k + j] = Yk[(size_t)i * k + j] - ph * yp;
+            }
+        }
+        if ((s = d.put_small(Z, kZOff))) return s;
+    }
     if ((s = d.put_small(Yk, kYOff))) return s;
-    if ((s = d.hip(hipMemcpyAsync((char*)c->d_small.p + kThetaOff, D.theta.data(), k * 8, hipMemcpyHostToDevice,
-                                  c->stream),
-                   "theta")))
-        return s;
-    if ((s = d.hip(launch_combine(d.cx, c->d_V.p, c->d_W.p, N, m, c->d_small.p, k,
-                                  (const double*)((char*)c->d_small.p + kThetaOff), c->d_X.p, c->d_R.p, N, 1,
-                                  c->stream),
+    if ((s = d.put_doubles(D.theta.data(), (size_t)k, kThetaOff))) return s;
+    if ((s = d.hip(launch_ritz(c->dev, d.cx, (const double*)c->d_hd.p, (const double*)c->d_JK.p, c->e_core, c->d_V.p,
+                               c->d_W.p, N, m, d.small(kYOff), have_prev ? d.small(kZOff) : nullptr, k,
+                               (const double*)d.small(kThetaOff), 1e-12, c->d_X.p, c->d_T.p, N,
+                               (double*)c->d_partial.p, (double*)d.small(kRitzOff), c->stream),
                    "ritz")))
         return s;
-    std::vector<double> dc(k, std::nan(""));
-    bool dc_pending = false;
-    {
-        // residual norms and, from the second iteration, the overlaps
-        // <x_j(previous) | x_j> that phase-align the change of each Ritz vector
-        const int nps = Dav::pair_slots(k);
-        if ((s = d.issue_pair_dots(d.vec(c->d_R, 0), d.vec(c->d_R, 0), k, 0))) return s;
-        if (D.have_xp)
-            if ((s = d.issue_pair_dots(d.vec(c->d_Xp, 0), d.vec(c->d_X, 0), k, nps))) return s;
-        std::vector<cplx> r2;
-        if ((s = d.fetch(D.have_xp ? 2 * nps : nps, r2))) return s;
-        for (int j = 0; j < k; ++j) D.rn[j] = std::sqrt(std::max(0.0, r2[Dav::pair_slot(j, k)].real()));
-        if (D.have_xp) {
-            // max |x_j - ph_j x_j(previous)|, ph_j = <x_prev|x>/|<x_prev|x>| (Results: the
-            // largest coefficient change reported per iteration beside E and ||r||)
-            // (fetched with the next round trip's dot products)
-            for (int j = 0; j < k; ++j) {
-                const cplx o = r2[nps + Dav::pair_slot(j, k)];
-                const double a = std::abs(o);
-                const cplx ph = a > 0 ? o / a : cplx(1.0, 0.0);
-                double* out = (double*)((char*)c->d_small.p + kDcOff) + (size_t)j * (d.cx ? 2 : 1);
-                if ((s = d.hip(launch_maxdiff(d.cx, d.vec(c->d_X, j), d.vec(c->d_Xp, j), ph.real(), ph.imag(), N,
-                                              c->d_partial.p, out, c->stream),
-                               "coefficient change")))
-                    return s;
-            }
-            dc_pending = true;
-        }
-        if ((s = d.hip(hipMemcpyAsync(c->d_Xp.p, c->d_X.p, (size_t)k * N * d.sb, hipMemcpyDeviceToDevice, c->stream),
-                       "previous Ritz vectors")))
-            return s;
-        D.have_xp = true;
+    std::vector<double> red;
+    if ((s = d.get_doubles(kRitzOff, (size_t)12 * ((k + 3) / 4), red))) return s;
+    std::vector<double> dc(k, std::nan("")), tn2(k);
+    for (int j = 0; j < k; ++j) {
+        D.rn[j] = std::sqrt(std::max(0.0, red[ritz_slot(j, 0)]));
+        tn2[j] = red[ritz_slot(j, 1)];
+        if (have_prev) dc[j] = std::sqrt(std::max(0.0, red[ritz_slot(j, 2)]));
     }
     c->history.push_back(DavRecord{D.theta, D.rn, dc, D.pidx});
-    // the coefficient changes of this iteration, where no later round trip
-    // of the iteration brings them
-    auto fetch_dc = [&]() -> stpci_status {
-        if (!dc_pending) return STPCI_OK;
-        std::vector<cplx> none;
-        stpci_status st2 = d.fetch(0, none, &dc);
-        c->history.back().dc = dc;
-        dc_pending = false;
-        return st2;
-    };
     bool conv = true;
     for (int j = 0; j < k; ++j) conv = conv && D.rn[j] <= D.tol;
     // FP64 refinement after a reduced-precision phase: with refine_tol_energy
@@ -563,26 +600,34 @@ static stpci_status dav_advance(stpci_ctx* c) {
             D.stall = 0;
         } else if (++D.stall >= 8) {
             D.done = true;
-            return fetch_dc();
+            return STPCI_OK;
         }
     }
     if (conv || D.it >= D.max_iter) {
         D.done = true;
-        return fetch_dc();
+        return STPCI_OK;
     }
-    // corrections for unconverged roots (Eq. sparsePreconditioner with the
-    // run's eps; one launch for all of them, k <= 16)
-    std::vector<int> proots;
-    std::vector<double> pthetas;
-    for (int j = 0; j < k; ++j) {
-        if (D.rn[j] <= D.tol) continue;
-        proots.push_back(j);
-        pthetas.push_back(D.theta[j]);
+    // corrections for the unconverged roots (Eq. sparsePreconditioner: the
+    // Ritz pass formed t_j for every root; with eps > 0 the entries below
+    // eps ||t_j|| are dropped, ||t_j||^2 read where the Ritz pass left it)
+    std::vector<char> corr(k, 0);
+    int nt = 0;
+    for (int j = 0; j < k; ++j)
+        if (D.rn[j] > D.tol) {
+            corr[j] = 1;
+            ++nt;
+        }
+    const double eps = D.opts.eps_drop;
+    if (eps > 0.0) {
+        int slot[PRE_MAX];
+        for (int q = 0; q < k; ++q) slot[q] = ritz_slot(q, 1);
+        if ((s = d.hip(launch_eps_drop(d.cx, c->d_T.p, N, N, k, slot, (const double*)d.small(kRitzOff), 1, eps,
+                                       c->stream),
+                       "eps drop")))
+            return s;
+        // the norms after the drop, fetched with the first Gram matrix
+        if ((s = d.issue_pair_dots((char*)c->d_T.p, (char*)c->d_T.p, k, 0, kNrmOff))) return s;
     }
-    const int nt = (int)proots.size();
-    if ((s = d.precondition(d.vec(c->d_R, 0), d.vec(c->d_T, 0), nt, proots.data(), pthetas.data(),
-                            D.opts.eps_drop)))
-        return s;
     int mm = m;
     // restart when the space would overflow (thick restart with the
     // previous Ritz vectors, "GD+k"): the new basis is V Q, Q = the k lowest
@@ -646,17 +691,11 @@ static stpci_status dav_advance(stpci_ctx* c) {
                 Gn[(size_t)a2 * kr + b2] = v;
             }
         if ((s = d.put_small(Yr, kYOff))) return s;
-        if ((s = d.hip(launch_combine(d.cx, c->d_V.p, nullptr, N, mm, c->d_small.p, kr, nullptr, c->d_X.p, nullptr, N,
-                                      0, c->stream),
-                       "restart VY")))
+        if ((s = d.hip(launch_combine_inplace(d.cx, c->d_V.p, N, mm, d.small(kYOff), kr, N, c->stream),
+                       "restart V")))
             return s;
-        if ((s = d.hip(launch_combine(d.cx, c->d_W.p, nullptr, N, mm, c->d_small.p, kr, nullptr, c->d_R.p, nullptr, N,
-                                      0, c->stream),
-                       "restart WY")))
-            return s;
-        if ((s = d.hip(hipMemcpyAsync(c->d_V.p, c->d_X.p, vb * kr, hipMemcpyDeviceToDevice, c->stream), "restart V")))
-            return s;
-        if ((s = d.hip(hipMemcpyAsync(c->d_W.p, c->d_R.p, vb * kr, hipMemcpyDeviceToDevice, c->stream), "restart W")))
+        if ((s = d.hip(launch_combine_inplace(d.cx, c->d_W.p, N, mm, d.small(kYOff), kr, N, c->stream),
+                       "restart W")))
             return s;
         std::fill(D.G.begin(), D.G.end(), cplx(0, 0));
         for (int a2 = 0; a2 < kr; ++a2)
@@ -668,9 +707,7 @@ static stpci_status dav_advance(stpci_ctx* c) {
         for (int j = 0; j < k; ++j) Pc[(size_t)j * k + j] = cplx(1, 0);
         Pc_rows = kr;
     } else {
-        Pc.assign((size_t)mm * k, cplx(0, 0));
-        for (int i = 0; i < mm; ++i)
-            for (int j = 0; j < k; ++j) Pc[(size_t)i * k + j] = Y[(size_t)i * mm + j];
+        Pc = Yk;
         Pc_rows = mm;
     }
     D.prev_coef = std::move(Pc);
@@ -678,101 +715,105 @@ static stpci_status dav_advance(stpci_ctx* c) {
     // block orthonormalisation of the corrections: two classical Gram-Schmidt
     // passes against V, then two Cholesky QR passes among themselves; a
     // direction that keeps less than 1e-8 of its norm lies in the span
-    // (linear dependence) and is dropped
-    int added = 0;
-    if (nt > 0) {
-        // the two Gram-Schmidt passes run without a round trip: the norms
-        // before orthogonalisation go to slots [0, nts) (fetched with the
-        // first Cholesky QR Gram matrix), each pass's projections to slot
-        // nts, where the combination reads them (nts + nt mm <= nt (2 + mm)
-        // <= nt mmax: within the dot-product area for nt <= 16, mmax <= 64)
-        std::vector<cplx> n0v;
-        const int nts = Dav::pair_slots(nt);
-        if ((s = d.issue_pair_dots(d.vec(c->d_T, 0), d.vec(c->d_T, 0), nt, 0))) return s;
-        for (int pass = 0; pass < 2; ++pass) {
-            if ((s = d.issue_dots(c->d_V.p, mm, c->d_T.p, nt, nts))) return s;
-            if ((s = d.subtract_queued(c->d_V.p, mm, nts, nt, c->d_T.p))) return s;
+    // (linear dependence) and is dropped.  The passes run over all k
+    // corrections (those of converged roots are left out of the Cholesky
+    // factor), so that the columns stay where the Ritz pass wrote them.
+    const bool fuse = k <= 4;   // the Gram matrices come with the passes that form the vectors
+    for (int pass = 0; pass < 2; ++pass) {
+        if ((s = d.issue_dots(c->d_V.p, mm, c->d_T.p, k, 0))) return s;
+        if (pass == 1 && fuse) {
+            if ((s = d.hip(launch_comb_gram(d.cx, c->d_V.p, N, mm, d.small(kDotsOff), c->d_T.p, k, N, 3,
+                                            (double*)c->d_partial.p, (double*)d.small(kGramOff), c->stream),
+                           "cgs")))
+                return s;
+        } else if ((s = d.subtract_queued(c->d_V.p, mm, k, c->d_T.p))) {
+            return s;
         }
-        // Cholesky QR: T_keep = Q R, Q = T R^-1 written to V[mm..] (first pass)
-        // and re-orthonormalised in place through T (second pass)
-        const int room = D.mmax - mm;
-        std::vector<int> keep;
-        for (int qr = 0; qr < 2; ++qr) {
-            void* src = (qr == 0) ? c->d_T.p : d.vec(c->d_V, mm);
-            const int ns = (qr == 0) ? nt : (int)keep.size();
-            if (ns == 0) break;
-            // the first Gram matrix comes behind the norms before
-            // orthogonalisation, in one round trip with the pending
-            // coefficient changes
-            const int goff = (qr == 0) ? nts : 0;
-            if ((s = d.issue_dots(src, ns, src, ns, goff))) return s;
-            std::vector<cplx> got;
-            if ((s = d.fetch(goff + ns * ns, got, (qr == 0 && dc_pending) ? &dc : nullptr))) return s;
-            if (qr == 0) {
-                if (dc_pending) {
-                    c->history.back().dc = dc;
-                    dc_pending = false;
-                }
-                n0v.resize(nt);
-                for (int t = 0; t < nt; ++t) n0v[t] = got[Dav::pair_slot(t, nt)];
+    }
+    if (!fuse && (s = d.issue_dots(c->d_T.p, k, c->d_T.p, k, 0, kGramOff))) return s;
+    // Cholesky QR: T_keep = Q R, Q = T R^-1 written to V[mm..] (first pass)
+    // and re-orthonormalised in place (second pass)
+    const int room = D.mmax - mm;
+    std::vector<int> keep;
+    for (int qr = 0; qr < 2; ++qr) {
+        const int ns = (qr == 0) ? k : (int)keep.size();
+        if (ns == 0) break;
+        // the Gram matrix Gm[t * ns + i] = <src_i | src_t> (a fused pass leaves
+        // it as a 4 x 4 block of complex slots, a dot-product pass compact);
+        // the first comes with the norms after the eps drop
+        const bool padded = (qr == 0) ? fuse : ns <= 4;
+        const bool norms = qr == 0 && eps > 0.0;
+        const size_t from = norms ? kNrmOff : kGramOff;
+        const size_t gd = padded ? 32 : (size_t)ns * ns * (d.cx ? 2 : 1);
+        std::vector<double> raw;
+        if ((s = d.get_doubles(from, (kGramOff - from) / 8 + gd, raw))) return s;
+        const double* gr = raw.data() + (kGramOff - from) / 8;
+        std::vector<cplx> Gm((size_t)ns * ns);
+        for (int t = 0; t < ns; ++t)
+            for (int i = 0; i < ns; ++i) {
+                const size_t at = padded ? (size_t)2 * (4 * t + i) : (size_t)(t * ns + i) * (d.cx ? 2 : 1);
+                Gm[(size_t)t * ns + i] = cplx(gr[at], (padded || d.cx) ? gr[at + 1] : 0.0);
             }
-            const std::vector<cplx> Gm(got.begin() + goff, got.end());  // Gm[t * ns + i] = <src_i | src_t>
-            std::vector<cplx> R((size_t)ns * ns, cplx(0, 0));
-            std::vector<int> kept;
-            for (int t = 0; t < ns; ++t) {
-                double r2 = Gm[(size_t)t * ns + t].real();
-                for (int i : kept) {
-                    cplx v = Gm[(size_t)t * ns + i];
-                    for (int j : kept) {
-                        if (j >= i) break;
-                        v -= std::conj(R[(size_t)j * ns + i]) * R[(size_t)j * ns + t];
-                    }
-                    R[(size_t)i * ns + t] = v / R[(size_t)i * ns + i];
-                    r2 -= std::norm(R[(size_t)i * ns + t]);
+        std::vector<double> ref(ns, 1.0);
+        if (qr == 0)
+            for (int t = 0; t < ns; ++t)
+                ref[t] = norms ? raw[(size_t)Dav::pair_slot(t, k) * (d.cx ? 2 : 1)] : tn2[t];
+        std::vector<cplx> R((size_t)ns * ns, cplx(0, 0));
+        std::vector<int> kept;
+        for (int t = 0; t < ns; ++t) {
+            if (qr == 0 && !corr[t]) continue;
+            double r2 = Gm[(size_t)t * ns + t].real();
+            for (int i : kept) {
+                cplx v = Gm[(size_t)t * ns + i];
+                for (int j : kept) {
+                    if (j >= i) break;
+                    v -= std::conj(R[(size_t)j * ns + i]) * R[(size_t)j * ns + t];
                 }
-                const double ref = (qr == 0) ? n0v[t].real() : 1.0;
-                if (r2 <= 1e-16 * ref || (int)kept.size() >= room) continue;
-                R[(size_t)t * ns + t] = std::sqrt(r2);
-                kept.push_back(t);
+                R[(size_t)i * ns + t] = v / R[(size_t)i * ns + i];
+                r2 -= std::norm(R[(size_t)i * ns + t]);
             }
-            // Y = R^-1 on the kept columns (upper triangular), ns x kept
-            const int nk = (int)kept.size();
-            std::vector<cplx> Y((size_t)ns * std::max(nk, 1), cplx(0, 0));
-            for (int jj = 0; jj < nk; ++jj) {
-                // solve R[kept, kept] y = e_jj by back substitution over kept indices
-                std::vector<cplx> y(nk, cplx(0, 0));
-                for (int ii = jj; ii >= 0; --ii) {
-                    cplx v = (ii == jj) ? cplx(1, 0) : cplx(0, 0);
-                    for (int ll = ii + 1; ll <= jj; ++ll) v -= R[(size_t)kept[ii] * ns + kept[ll]] * y[ll];
-                    y[ii] = v / R[(size_t)kept[ii] * ns + kept[ii]];
-                }
-                for (int ii = 0; ii <= jj; ++ii) Y[(size_t)kept[ii] * nk + jj] = y[ii];
+            if (r2 <= 1e-16 * ref[t] || (int)kept.size() >= room) continue;
+            R[(size_t)t * ns + t] = std::sqrt(r2);
+            kept.push_back(t);
+        }
+        // Y = R^-1 on the kept columns (upper triangular), ns x kept
+        const int nk = (int)kept.size();
+        std::vector<cplx> Yq((size_t)ns * std::max(nk, 1), cplx(0, 0));
+        for (int jj = 0; jj < nk; ++jj) {
+            // solve R[kept, kept] y = e_jj by back substitution over kept indices
+            std::vector<cplx> y(nk, cplx(0, 0));
+            for (int ii = jj; ii >= 0; --ii) {
+                cplx v = (ii == jj) ? cplx(1, 0) : cplx(0, 0);
+                for (int ll = ii + 1; ll <= jj; ++ll) v -= R[(size_t)kept[ii] * ns + kept[ll]] * y[ll];
+                y[ii] = v / R[(size_t)kept[ii] * ns + kept[ii]];
             }
-            if (qr == 0) {
-                keep = kept;
-                if (nk == 0) break;
-                if ((s = d.put_small(Y, kYOff))) return s;
-                if ((s = d.hip(launch_combine(d.cx, c->d_T.p, nullptr, N, ns, c->d_small.p, nk, nullptr,
-                                              d.vec(c->d_V, mm), nullptr, N, 0, c->stream),
+            for (int ii = 0; ii <= jj; ++ii) Yq[(size_t)kept[ii] * nk + jj] = y[ii];
+        }
+        if (qr == 0) {
+            keep = kept;
+            if (nk == 0) break;
+            if ((s = d.put_small(Yq, kYOff))) return s;
+            if (nk <= 4) {
+                if ((s = d.hip(launch_comb_gram(d.cx, c->d_T.p, N, ns, d.small(kYOff), d.vec(c->d_V, mm), nk, N, 0,
+                                                (double*)c->d_partial.p, (double*)d.small(kGramOff), c->stream),
                                "cholqr")))
                     return s;
             } else {
-                if (nk < ns) {  // the second pass dropped a direction: keep the first pass' result
-                    break;
-                }
-                if ((s = d.put_small(Y, kYOff))) return s;
-                if ((s = d.hip(launch_combine(d.cx, d.vec(c->d_V, mm), nullptr, N, ns, c->d_small.p, nk, nullptr,
-                                              c->d_T.p, nullptr, N, 0, c->stream),
-                               "cholqr2")))
+                if ((s = d.hip(launch_combine(d.cx, c->d_T.p, nullptr, N, ns, d.small(kYOff), nk, nullptr,
+                                              d.vec(c->d_V, mm), nullptr, N, 0, c->stream),
+                               "cholqr")))
                     return s;
-                if ((s = d.hip(hipMemcpyAsync(d.vec(c->d_V, mm), c->d_T.p, vb * nk, hipMemcpyDeviceToDevice,
-                                              c->stream),
-                               "append")))
-                    return s;
+                if ((s = d.issue_dots(d.vec(c->d_V, mm), nk, d.vec(c->d_V, mm), nk, 0, kGramOff))) return s;
             }
+        } else {
+            if (nk < ns) break;   // the second pass dropped a direction: keep the first pass' result
+            if ((s = d.put_small(Yq, kYOff))) return s;
+            if ((s = d.hip(launch_combine_inplace(d.cx, d.vec(c->d_V, mm), N, ns, d.small(kYOff), nk, N, c->stream),
+                           "cholqr2")))
+                return s;
         }
-        added = (int)keep.size();
     }
+    const int added = (int)keep.size();
     if (added == 0) {  // no new direction: stagnation
         D.done = true;
         return STPCI_OK;

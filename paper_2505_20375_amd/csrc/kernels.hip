@@ -248,14 +248,79 @@ __global__ __launch_bounds__(256) void k_diag_topk(DevSpace S, const double* hd,
 // ---------------------------------------------------------------------------
 // Vector algebra (memory-bound; wavefront + block reductions, fixed order)
 // ---------------------------------------------------------------------------
+// Davidson vector algebra with its reductions fused into the passes that
+// produce the vectors.  A kernel accumulates per-thread sums (or maxima) of a
+// few scalars over its elements and reduces them over the workgroup in a
+// fixed order into partial[workgroup][slot]; a small second launch (k_fold)
+// folds the workgroups' partials in a fixed order, one wavefront per output.
+// The results do not depend on timing.  (A fold by the workgroup that
+// finishes last would need a device-scope release fence in every workgroup,
+// which writes the XCD's L2 back to memory: far slower here than a launch.)
+// ---------------------------------------------------------------------------
+
+// per-thread v[0..NS) -> part[0..NS): wavefront butterfly, then the four
+// wavefronts in order; the slots whose bit is set in MAXMASK take the maximum
+// (of non-negative values), the others the sum (256 threads)
+template <int NS, uint64_t MAXMASK>
+__device__ __forceinline__ void wg_partials(const double (&v)[NS], double* __restrict__ part) {
+    __shared__ double red[4][NS];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        constexpr uint64_t one = 1;
+        const bool mx = (MAXMASK >> s) & one;
+        double x = v[s];
+        for (int off = 32; off > 0; off >>= 1) {
+            const double y = __shfl_xor(x, off, 64);
+            x = mx ? fmax(x, y) : x + y;
+        }
+        if (lane == 0) red[w][s] = x;
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < NS; s += blockDim.x) {
+        const bool mx = (MAXMASK >> s) & (uint64_t)1;
+        part[s] = mx ? fmax(fmax(red[0][s], red[1][s]), fmax(red[2][s], red[3][s]))
+                     : (red[0][s] + red[1][s]) + (red[2][s] + red[3][s]);
+    }
+}
+
+// out[q] = fold over b < nblk of partial[b * stride + q], q < nout, one
+// wavefront per output (lanes take b in order, then a butterfly): the sum,
+// or for q % period >= max_from the maximum (of non-negative values)
+__global__ __launch_bounds__(256) void k_fold(const double* __restrict__ partial, int nblk, int stride, int nout,
+                                              int period, int max_from, double* __restrict__ out) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = blockIdx.x * 4 + w;
+    if (q >= nout) return;
+    const bool mx = (q % period) >= max_from;
+    double x = 0.0;
+    for (int b = lane; b < nblk; b += 64) {
+        const double y = partial[(int64_t)b * stride + q];
+        x = mx ? fmax(x, y) : x + y;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double y = __shfl_xor(x, off, 64);
+        x = mx ? fmax(x, y) : x + y;
+    }
+    if (lane == 0) out[q] = x;
+}
+
+static hipError_t launch_fold(const double* partial, int nblk, int stride, int nout, int period, int max_from,
+                              double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_fold, dim3((nout + 3) / 4), dim3(256), 0, st, partial, nblk, stride, nout, period, max_from,
+                       out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 constexpr int DOTV = 8;   // vectors V_i per workgroup
 constexpr int DOTW = 2;   // vectors W_t per workgroup
 
-// partial[block][t * m + i] = sum over the block's element range of
-// conj(V_i) W_t, for i < m, t < nw (V_i = Vb + i ld, W_t = W + t ld).
-// blockIdx.x: group of DOTV vectors V, blockIdx.y: element range,
-// blockIdx.z: group of DOTW vectors W.  Each V element is read once per W
-// group, each W element once per V group.
+// partial[range][t * m + i] = sum over the element range of conj(V_i) W_t,
+// for i < m, t < nw (V_i = Vb + i ld, W_t = W + t ld); k_fold adds the ranges.
+// blockIdx.x: group of DOTV vectors V, blockIdx.y: element range, blockIdx.z:
+// group of DOTW vectors W.  Each V element is read once per W group, each W
+// element once per V group.
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_dots(const typename VT<CPLX>::T* __restrict__ Vb, int64_t ld, int m,
                                               const typename VT<CPLX>::T* __restrict__ W, int nw, int64_t n,
@@ -315,80 +380,6 @@ __global__ __launch_bounds__(256) void k_dots(const typename VT<CPLX>::T* __rest
             partial[(int64_t)blockIdx.y * m * nw + (int64_t)(t0 + t) * m + i0 + i] = x;
         }
     }
-}
-
-// out[i] = sum over blocks of partial[b][i]: one workgroup per output, the
-// block partials split over its threads, then a fixed-order tree (the result
-// does not depend on timing).
-template <bool CPLX>
-__global__ __launch_bounds__(256) void k_reduce_partials(const typename VT<CPLX>::T* __restrict__ partial, int nblk,
-                                                         int m, typename VT<CPLX>::T* __restrict__ out) {
-    using V = VT<CPLX>;
-    const int i = blockIdx.x;
-    typename V::T s = V::zero();
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s = V::add(s, partial[(int64_t)b * m + i]);
-    __shared__ typename V::T red[256];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) red[threadIdx.x] = V::add(red[threadIdx.x], red[threadIdx.x + h]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[i] = red[0];
-}
-
-// partial[block] = max over the block's range of |x - ph y| (ph = phr + i phi;
-// real vectors use phr only)
-template <bool CPLX>
-__global__ __launch_bounds__(256) void k_maxdiff(const typename VT<CPLX>::T* __restrict__ x,
-                                                const typename VT<CPLX>::T* __restrict__ y, double phr, double phi,
-                                                int64_t n, double* __restrict__ partial) {
-    double m = 0.0;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        double d2;
-        if constexpr (CPLX) {
-            const cd a = x[e], b = y[e];
-            const double re = a.x - (phr * b.x - phi * b.y), im = a.y - (phr * b.y + phi * b.x);
-            d2 = re * re + im * im;
-        } else {
-            const double re = x[e] - phr * y[e];
-            d2 = re * re;
-        }
-        m = fmax(m, d2);
-    }
-    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-    __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = sqrt(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
-}
-
-// out[0] = max of nblk partials; out[1] = 0 when out holds a complex slot
-__global__ __launch_bounds__(256) void k_reduce_max(const double* __restrict__ partial, int nblk, int cplx_slot,
-                                                    double* __restrict__ out) {
-    double m = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) m = fmax(m, partial[b]);
-    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-    __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        out[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-        if (cplx_slot) out[1] = 0.0;
-    }
-}
-
-hipError_t launch_maxdiff(bool cplx, const void* x, const void* y, double phr, double phi, int64_t n, void* partial,
-                          double* out, hipStream_t st) {
-    const int nb = dots_blocks(n);
-    if (cplx)
-        hipLaunchKernelGGL(k_maxdiff<true>, dim3(nb), dim3(256), 0, st, (const cd*)x, (const cd*)y, phr, phi, n,
-                           (double*)partial);
-    else
-        hipLaunchKernelGGL(k_maxdiff<false>, dim3(nb), dim3(256), 0, st, (const double*)x, (const double*)y, phr, phi,
-                           n, (double*)partial);
-    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, st, (const double*)partial, nb, cplx ? 1 : 0, out);
-    return hipGetLastError();
 }
 
 // out_j = sum_i A_i * Y[i][j]  (+ beta_j * out_j when accumulate)   for j < k
@@ -453,6 +444,154 @@ __global__ __launch_bounds__(256) void k_unit(typename VT<CPLX>::T* __restrict__
     *reinterpret_cast<double*>(&one) = 1.0;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
         x[e] = (e == at) ? one : V::zero();
+}
+
+// Rayleigh-Ritz step for Ritz columns j0 .. j0 + 3 (j0 = 4 blockIdx.y):
+//   x_j = V y_j,  r_j = W y_j - theta_j x_j,
+//   t_j = r_j / (theta_j - H_ii), 0 where |theta_j - H_ii| < guard (the
+//   preconditioner of Eq. sparsePreconditioner before its eps drop, the
+//   diagonal formed once per determinant),
+//   d_j = V z_j (with Z: z_j = y_j - ph_j yp_j, the change of the Ritz vector
+//   since the previous iteration),
+// x_j and t_j written; the workgroup's sums of |r_j|^2 and |t_j|^2 and its
+// maximum of |d_j|^2 (0 without Z) go to partial[wg][12 (j / 4) + 4 q + j % 4]
+// for q = 0, 1, 2 (wg over blockIdx.x).  Y, Z: m x k row-major.
+constexpr int RZ_CB = 4;
+constexpr int RZ_NS = 3 * RZ_CB;
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_ritz(DevSpace S, const double* __restrict__ hd,
+                                              const double* __restrict__ JK, double e_core,
+                                              const typename VT<CPLX>::T* __restrict__ V,
+                                              const typename VT<CPLX>::T* __restrict__ W, int64_t ld, int m,
+                                              const typename VT<CPLX>::T* __restrict__ Y,
+                                              const typename VT<CPLX>::T* __restrict__ Z, int k,
+                                              const double* __restrict__ theta, double guard,
+                                              typename VT<CPLX>::T* __restrict__ X,
+                                              typename VT<CPLX>::T* __restrict__ Tc, int64_t n,
+                                              double* __restrict__ partial) {
+    using Vt = VT<CPLX>;
+    using T = typename Vt::T;
+    const int j0 = blockIdx.y * RZ_CB;
+    double acc[RZ_NS];
+#pragma unroll
+    for (int s = 0; s < RZ_NS; ++s) acc[s] = 0.0;
+    double th[RZ_CB];
+#pragma unroll
+    for (int jj = 0; jj < RZ_CB; ++jj) th[jj] = (j0 + jj < k) ? theta[j0 + jj] : 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const double h = diag_elem(S, hd, JK, e_core, e);
+        T xs[RZ_CB], rs[RZ_CB], ds[RZ_CB];
+#pragma unroll
+        for (int jj = 0; jj < RZ_CB; ++jj) xs[jj] = rs[jj] = ds[jj] = Vt::zero();
+#pragma unroll 4
+        for (int i = 0; i < m; ++i) {
+            const T a = V[(int64_t)i * ld + e];
+            const T b = W[(int64_t)i * ld + e];
+#pragma unroll
+            for (int jj = 0; jj < RZ_CB; ++jj)
+                if (j0 + jj < k) {
+                    const T y = Y[i * k + j0 + jj];
+                    xs[jj] = Vt::mad(a, y, xs[jj]);
+                    rs[jj] = Vt::mad(b, y, rs[jj]);
+                    if (Z) ds[jj] = Vt::mad(a, Z[i * k + j0 + jj], ds[jj]);
+                }
+        }
+#pragma unroll
+        for (int jj = 0; jj < RZ_CB; ++jj) {
+            const int j = j0 + jj;
+            if (j >= k) break;
+            X[(int64_t)j * ld + e] = xs[jj];
+            const T r = Vt::sub(rs[jj], Vt::scale(xs[jj], th[jj]));
+            const double den = th[jj] - h;
+            const T t = (fabs(den) >= guard) ? Vt::scale(r, 1.0 / den) : Vt::zero();
+            Tc[(int64_t)j * ld + e] = t;
+            acc[jj] += Vt::abs2(r);
+            acc[RZ_CB + jj] += Vt::abs2(t);
+            acc[2 * RZ_CB + jj] = fmax(acc[2 * RZ_CB + jj], Vt::abs2(ds[jj]));
+        }
+    }
+    constexpr uint64_t kMax = ((uint64_t)((1 << RZ_CB) - 1)) << (2 * RZ_CB);
+    wg_partials<RZ_NS, kMax>(acc, partial + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * RZ_NS);
+}
+
+// One pass over nx <= 4 vectors X_t (t < nx) with the Gram matrix of the
+// results: the workgroup's sums of conj(X_s) X_t go to partial[wg][2 (4 t + s)
+// + c] (c = 0 real, 1 imaginary part; a 4 x 4 block whatever nx):
+//   mode 0: X_t = sum_i A_i Y[i nx + t]        (Y: m x nx row-major)
+//   mode 3: X_t <- X_t - sum_i A_i Y[t m + i]  (Y as the dot products lie)
+// A and X are distinct vectors; every sum runs over i in ascending order.
+constexpr int CG_NX = 4;
+constexpr int CG_NS = 2 * CG_NX * CG_NX;
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_comb_gram(const typename VT<CPLX>::T* __restrict__ A, int64_t ld, int m,
+                                                   const typename VT<CPLX>::T* __restrict__ Y,
+                                                   typename VT<CPLX>::T* __restrict__ X, int nx, int64_t n, int mode,
+                                                   double* __restrict__ partial) {
+    using Vt = VT<CPLX>;
+    using T = typename Vt::T;
+    T g[CG_NX][CG_NX];
+#pragma unroll
+    for (int t = 0; t < CG_NX; ++t)
+#pragma unroll
+        for (int s = 0; s < CG_NX; ++s) g[t][s] = Vt::zero();
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        T xs[CG_NX];
+#pragma unroll
+        for (int t = 0; t < CG_NX; ++t) xs[t] = Vt::zero();
+#pragma unroll 4
+        for (int i = 0; i < m; ++i) {
+            const T a = A[(int64_t)i * ld + e];
+#pragma unroll
+            for (int t = 0; t < CG_NX; ++t)
+                if (t < nx) xs[t] = Vt::mad(a, (mode == 3) ? Y[t * m + i] : Y[i * nx + t], xs[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < CG_NX; ++t) {
+            if (t >= nx) break;
+            T* dst = X + (int64_t)t * ld + e;
+            if (mode == 3) xs[t] = Vt::sub(*dst, xs[t]);
+            *dst = xs[t];
+        }
+#pragma unroll
+        for (int t = 0; t < CG_NX; ++t)
+#pragma unroll
+            for (int s = 0; s < CG_NX; ++s)
+                if (t < nx && s < nx) g[t][s] = Vt::cmad(xs[s], xs[t], g[t][s]);
+    }
+    double v[CG_NS];
+#pragma unroll
+    for (int t = 0; t < CG_NX; ++t)
+#pragma unroll
+        for (int s = 0; s < CG_NX; ++s) {
+            const double* q = reinterpret_cast<const double*>(&g[t][s]);
+            v[2 * (t * CG_NX + s)] = q[0];
+            v[2 * (t * CG_NX + s) + 1] = CPLX ? q[1] : 0.0;
+        }
+    wg_partials<CG_NS, 0>(v, partial + (int64_t)blockIdx.x * CG_NS);
+}
+
+// X_j <- sum_i X_i Y[i kk + j] for j < kk <= KR, i < m, in place: every
+// element's m inputs are read before any of its outputs is written
+template <bool CPLX, int KR>
+__global__ __launch_bounds__(256) void k_combine_inplace(typename VT<CPLX>::T* X, int64_t ld, int m,
+                                                         const typename VT<CPLX>::T* __restrict__ Y, int kk,
+                                                         int64_t n) {
+    using Vt = VT<CPLX>;
+    using T = typename Vt::T;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        T acc[KR];
+#pragma unroll
+        for (int j = 0; j < KR; ++j) acc[j] = Vt::zero();
+        for (int i = 0; i < m; ++i) {
+            const T a = X[(int64_t)i * ld + e];
+#pragma unroll
+            for (int j = 0; j < KR; ++j)
+                if (j < kk) acc[j] = Vt::mad(a, Y[i * kk + j], acc[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < KR; ++j)
+            if (j < kk) X[(int64_t)j * ld + e] = acc[j];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -568,18 +707,78 @@ hipError_t launch_dots(bool cplx, const void* Vb, int64_t ld, int m, const void*
     if (m <= 0 || nw <= 0) return hipSuccess;
     const int nb = dots_blocks(n);
     const dim3 grid((m + DOTV - 1) / DOTV, nb, (nw + DOTW - 1) / DOTW);
-    if (cplx) {
+    if (cplx)
         hipLaunchKernelGGL(k_dots<true>, grid, dim3(256), 0, st, (const cd*)Vb, ld, m, (const cd*)W, nw, n,
                            (cd*)partial);
-        hipLaunchKernelGGL(k_reduce_partials<true>, dim3(m * nw), dim3(256), 0, st, (const cd*)partial, nb, m * nw,
-                           (cd*)out);
-    } else {
+    else
         hipLaunchKernelGGL(k_dots<false>, grid, dim3(256), 0, st, (const double*)Vb, ld, m, (const double*)W, nw, n,
                            (double*)partial);
-        hipLaunchKernelGGL(k_reduce_partials<false>, dim3(m * nw), dim3(256), 0, st, (const double*)partial, nb,
-                           m * nw, (double*)out);
-    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nout = m * nw * (cplx ? 2 : 1);
+    return launch_fold((const double*)partial, nb, nout, nout, nout, nout, (double*)out, st);
+}
+
+static int ritz_wgs(int64_t n) { return grid_for(n, 256, 1024); }
+int ritz_blocks(int64_t n, int k) { return ritz_wgs(n) * ((k + RZ_CB - 1) / RZ_CB); }
+
+hipError_t launch_ritz(const DevSpace& S, bool cplx, const double* hd, const double* JK, double e_core,
+                       const void* V, const void* W, int64_t ld, int m, const void* Y, const void* Z, int k,
+                       const double* theta, double guard, void* X, void* T, int64_t n, double* partial, double* out,
+                       hipStream_t st) {
+    if (k < 1 || k > PRE_MAX || m < 1) return hipErrorInvalidValue;
+    const int gy = (k + RZ_CB - 1) / RZ_CB;
+    const dim3 grid(ritz_wgs(n), gy);
+    if (cplx)
+        hipLaunchKernelGGL(k_ritz<true>, grid, dim3(256), 0, st, S, hd, JK, e_core, (const cd*)V, (const cd*)W, ld,
+                           m, (const cd*)Y, (const cd*)Z, k, theta, guard, (cd*)X, (cd*)T, n, partial);
+    else
+        hipLaunchKernelGGL(k_ritz<false>, grid, dim3(256), 0, st, S, hd, JK, e_core, (const double*)V,
+                           (const double*)W, ld, m, (const double*)Y, (const double*)Z, k, theta, guard, (double*)X,
+                           (double*)T, n, partial);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_fold(partial, grid.x, gy * RZ_NS, gy * RZ_NS, RZ_NS, 2 * RZ_CB, out, st);
+}
+
+int comb_gram_blocks(int64_t n) { return grid_for(n, 256, 1024); }
+
+hipError_t launch_comb_gram(bool cplx, const void* A, int64_t ld, int m, const void* Y, void* X, int nx, int64_t n,
+                            int mode, double* partial, double* gout, hipStream_t st) {
+    if (nx < 1 || nx > CG_NX || m < 1 || (mode != 0 && mode != 3)) return hipErrorInvalidValue;
+    const int g = comb_gram_blocks(n);
+    if (cplx)
+        hipLaunchKernelGGL(k_comb_gram<true>, dim3(g), dim3(256), 0, st, (const cd*)A, ld, m, (const cd*)Y, (cd*)X,
+                           nx, n, mode, partial);
+    else
+        hipLaunchKernelGGL(k_comb_gram<false>, dim3(g), dim3(256), 0, st, (const double*)A, ld, m,
+                           (const double*)Y, (double*)X, nx, n, mode, partial);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_fold(partial, g, CG_NS, CG_NS, CG_NS, CG_NS, gout, st);
+}
+
+template <bool CPLX>
+static hipError_t launch_inplace_t(void* X, int64_t ld, int m, const void* Y, int kk, int64_t n, hipStream_t st) {
+    using T = typename VT<CPLX>::T;
+    const int g = grid_for(n, 256, 8192);
+    if (kk <= 4)
+        hipLaunchKernelGGL((k_combine_inplace<CPLX, 4>), dim3(g), dim3(256), 0, st, (T*)X, ld, m, (const T*)Y, kk, n);
+    else if (kk <= 8)
+        hipLaunchKernelGGL((k_combine_inplace<CPLX, 8>), dim3(g), dim3(256), 0, st, (T*)X, ld, m, (const T*)Y, kk, n);
+    else if (kk <= 16)
+        hipLaunchKernelGGL((k_combine_inplace<CPLX, 16>), dim3(g), dim3(256), 0, st, (T*)X, ld, m, (const T*)Y, kk,
+                           n);
+    else
+        hipLaunchKernelGGL((k_combine_inplace<CPLX, 32>), dim3(g), dim3(256), 0, st, (T*)X, ld, m, (const T*)Y, kk,
+                           n);
     return hipGetLastError();
+}
+
+hipError_t launch_combine_inplace(bool cplx, void* X, int64_t ld, int m, const void* Y, int kk, int64_t n,
+                                  hipStream_t st) {
+    if (kk < 1 || kk > 32 || kk > m) return hipErrorInvalidValue;
+    return cplx ? launch_inplace_t<true>(X, ld, m, Y, kk, n, st) : launch_inplace_t<false>(X, ld, m, Y, kk, n, st);
 }
 
 hipError_t launch_combine(bool cplx, const void* A, const void* B, int64_t ld, int m, const void* Y, int k,

@@ -123,14 +123,32 @@ int topk_blocks(const DevSpace& S);
 hipError_t launch_diag_topk(const DevSpace& S, const double* hd, const double* JK, double e_core, int k,
                             double* vals, int64_t* idx, hipStream_t st);
 int dots_blocks(int64_t n);
-// out[t * m + i] = <V_i | W_t> for i < m, t < nw (V_i = Vb + i ld, W_t = W + t ld);
-// partial holds dots_blocks(n) * m * nw scalars
+// out[t * m + i] = <V_i | W_t> for i < m, t < nw (V_i = Vb + i ld, W_t = W +
+// t ld); partial holds dots_blocks(n) * m * nw scalars
 hipError_t launch_dots(bool cplx, const void* Vb, int64_t ld, int m, const void* W, int nw, int64_t n,
                        void* partial, void* out, hipStream_t st);
-// out[0] = max_e |x_e - ph y_e| (ph = phr + i phi), out[1] = 0 for complex
-// vectors; partial holds dots_blocks(n) doubles
-hipError_t launch_maxdiff(bool cplx, const void* x, const void* y, double phr, double phi, int64_t n, void* partial,
-                          double* out, hipStream_t st);
+// Davidson Rayleigh-Ritz step for k <= PRE_MAX Ritz pairs (coefficients Y,
+// m x k row-major; Z: coefficient changes or NULL; theta on the device):
+// X = V Y, T = the preconditioned residuals (W Y - X theta) / (theta - H_ii)
+// (0 where |theta - H_ii| < guard); out[12 (j / 4) + 4 q + j % 4] =
+// ||r_j||^2, ||t_j||^2, max |(V Z)_j|^2 for q = 0, 1, 2 (12 ceil(k / 4)
+// doubles); partial holds ritz_blocks(n, k) * 12 doubles
+int ritz_blocks(int64_t n, int k);
+hipError_t launch_ritz(const DevSpace& S, bool cplx, const double* hd, const double* JK, double e_core,
+                       const void* V, const void* W, int64_t ld, int m, const void* Y, const void* Z, int k,
+                       const double* theta, double guard, void* X, void* T, int64_t n, double* partial, double* out,
+                       hipStream_t st);
+// nx <= 4 vectors X_t from m vectors A_i (mode 0: X_t = sum_i A_i Y[i nx + t];
+// mode 3: X_t -= sum_i A_i Y[t m + i]) and the Gram matrix of the results,
+// gout[2 (4 t + s) + c] = real (c = 0) and imaginary (c = 1) part of
+// <X_s | X_t> (a 4 x 4 block of complex slots; real vectors: c = 1 is 0);
+// partial holds comb_gram_blocks(n) * 32 doubles
+int comb_gram_blocks(int64_t n);
+hipError_t launch_comb_gram(bool cplx, const void* A, int64_t ld, int m, const void* Y, void* X, int nx, int64_t n,
+                            int mode, double* partial, double* gout, hipStream_t st);
+// X_j <- sum_i X_i Y[i kk + j], j < kk <= min(32, m), i < m, in place
+hipError_t launch_combine_inplace(bool cplx, void* X, int64_t ld, int m, const void* Y, int kk, int64_t n,
+                                  hipStream_t st);
 hipError_t launch_combine(bool cplx, const void* A, const void* B, int64_t ld, int m, const void* Y, int k,
                           const double* theta, void* X, void* R, int64_t n, int mode, hipStream_t st);
 hipError_t launch_scale(bool cplx, void* x, double s, int64_t n, hipStream_t st);

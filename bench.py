@@ -58,6 +58,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=40.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--copy-calib-mb", type=float, default=0.0,
                     help="only run a plain device copy of this many MB (counter calibration)")
+    ap.add_argument("--precision-study", type=int, default=0, metavar="ITERS",
+                    help="only run the precision-form study (Davidson solves in FP64, FP32 + FP64 and BF16 + "
+                         "FP64 on a 24,190,320-determinant space of the headline integrals, then ITERS "
+                         "iterations of the FP64 and of the FP32 solve on the headline space) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -82,6 +86,9 @@ def main():
     import paper_2505_20375_amd as stpci
 
     torch.cuda.set_device(0)
+    if args.precision_study > 0:
+        print(json.dumps(_precision_study(args.precision_study)))
+        return
     if args.workload == "c3p":
         res = _headline_c3p(args)
         ctx = None
@@ -236,6 +243,79 @@ def _headline_c3p(args):
         del c, out, ctx
     torch.cuda.empty_cache()
     return res
+
+
+def _precision_study(iters):
+    """The precision form (FP32 or BF16 contractions, then FP64 refinement)
+    against plain FP64 on the headline integrals: (1) whole Davidson solves
+    to residual 1e-5 on the 8-electron space of the same 12|16|12 partition
+    with windows [2..3]|[3..4]|[2..3] (24,190,320 determinants), median of 3
+    after a warm-up; (2) on the headline space itself, whose solve to 1e-5
+    takes longer than one run should, the first `iters` iterations of the
+    FP64 solve and of the FP32 phase, timed per iteration, with their
+    energies and residual norms side by side."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2505_20375_amd as stpci
+    ints, sp3, _ = synth.config("c3p")
+    out = {"study": "precision form vs FP64, Davidson, 1 root"}
+    sp = synth.SpaceSpec(8, [12, 16, 12], [2, 3, 2], [3, 4, 3])
+    ctx = stpci.Context(0)
+    ctx.set_integrals(ints.h, ints.g)
+    ctx.set_space(sp.n_elec, sp.sub, sp.lo, sp.hi)
+    small = {"n_dets": ctx.space_info().n_dets, "partition": sp.sub, "windows": [sp.lo, sp.hi],
+             "n_elec": sp.n_elec, "tol_residual": 1e-5}
+    ctx.davidson(k=1, tol=1e-5, max_iter=300)
+    for name, prec in (("fp64", stpci.FP64), ("fp32+fp64", stpci.FP32), ("bf16+fp64", stpci.BF16)):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, r, it, st = ctx.davidson(k=1, tol=1e-5, max_iter=300, precision=prec)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        small[name] = {"s": float(np.median(ts)), "energy": float(e[0]), "resid": float(r[0]),
+                       "iterations": int(it), "sigma_vectors_fp64": ctx.dav_sigma_count(stpci.FP64),
+                       "sigma_vectors_fp32": ctx.dav_sigma_count(stpci.FP32),
+                       "sigma_vectors_bf16": ctx.dav_sigma_count(stpci.BF16)}
+        log("%d-determinant solve (%s): %.2f s, %d iterations, E %.12f" % (small["n_dets"], name, small[name]["s"],
+                                                                          it, e[0]))
+    for name in ("fp32+fp64", "bf16+fp64"):
+        small[name]["speedup"] = small["fp64"]["s"] / small[name]["s"]
+        small[name]["energy_diff_eh"] = abs(small[name]["energy"] - small["fp64"]["energy"])
+    out["space_24M"] = small
+    del ctx
+    torch.cuda.empty_cache()
+    ctx = stpci.Context(0)
+    ctx.set_integrals(ints.h, ints.g)
+    ctx.set_space(sp3.n_elec, sp3.sub, sp3.lo, sp3.hi)
+    big = {"n_dets": ctx.space_info().n_dets, "iterations": iters}
+    for name, prec in (("fp64", stpci.FP64), ("fp32", stpci.FP32)):
+        ctx.dav_begin(k=1, tol=1e-5, max_iter=iters, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ts = []
+        for i in range(iters):
+            stpci.dav_sigma_batched([ctx])
+            done = ctx.dav_finish_step()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            log("headline space, %s iteration %d: %.1f s" % (name, i + 1, ts[-1]))
+            if done:
+                break
+        h = ctx.history(full=True)
+        big[name] = {"seconds": ts[-1], "s_per_iteration": ts[-1] / len(ts),
+                     "energy": [float(x) for x in h["energies"][:len(ts), 0]],
+                     "resid": [float(x) for x in h["resid"][:len(ts), 0]]}
+    n = min(len(big["fp64"]["energy"]), len(big["fp32"]["energy"]))
+    big["per_iteration_speedup"] = big["fp64"]["s_per_iteration"] / big["fp32"]["s_per_iteration"]
+    big["max_energy_diff_eh"] = max(abs(a - b) for a, b in zip(big["fp64"]["energy"][:n], big["fp32"]["energy"][:n]))
+    big["max_resid_rel_diff"] = max(abs(a - b) / b for a, b in zip(big["fp32"]["resid"][:n], big["fp64"]["resid"][:n]))
+    out["headline_space"] = big
+    del ctx
+    torch.cuda.empty_cache()
+    return out
 
 
 def _cpu_baseline_c3p(seconds):
@@ -661,10 +741,23 @@ def _solve(ctx, roots, nsolve, precision):
     cert = float(bnd[0]) if np.isfinite(bnd[0]) else None
     n64, n32 = ctx.dav_stats()
     nbf = ctx.dav_sigma_count(stpci.BF16)
+    # one more solve (not in the percentiles) with the library's HIP events
+    # around every sigma launch: the share of the solve's wall time that the
+    # sigma kernels take; the rest is the Davidson vector algebra, its round
+    # trips and the host's projected problem
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.davidson(k=roots, tol=1e-5, max_iter=400, precision=precision)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    sig_ms = sum(ctx.kernel_time(nm)[1] for nm in ("sigma1e", "sigma", "sigma_fp32", "sigma_reduce", "sigma_bf16"))
+    ctx.profile(False)
     return {"p50_ms": float(np.percentile(times, 50)), "p99_ms": float(np.percentile(times, 99)),
             "n": nsolve, "iterations": its[-1], "energies": [float(x) for x in e],
             "resid": [float(x) for x in r], "energy_bound_eh": cert, "tol_residual": 1e-5,
-            "sigma_vectors_fp64": n64, "sigma_vectors_fp32": n32 - nbf, "sigma_vectors_bf16": nbf}
+            "sigma_vectors_fp64": n64, "sigma_vectors_fp32": n32 - nbf, "sigma_vectors_bf16": nbf,
+            "sigma_share_of_wall": round(sig_ms / wall, 4)}
 
 
 def _serve(nreq, max_dets, rate):

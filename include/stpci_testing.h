@@ -62,6 +62,25 @@ stpci_status stpci_sb_counts(const stpci_ctx* ctx, int n_vec, double* mfma_flops
 stpci_status stpci_test_precond(stpci_ctx* ctx, const void* r_dev, void* t_dev, int n, const double* theta,
                                 double eps);
 
+/* Classical Gram-Schmidt passes against the basis made by the last Davidson
+ * run (one or two per iteration that added directions: the second only where
+ * the first removed more than half of a correction's squared norm). */
+stpci_status stpci_test_dav_cgs_passes(const stpci_ctx* ctx, int* passes);
+
+/* The solver's fused Rayleigh-Ritz pass on given vectors: V (m consecutive
+ * basis vectors) and W (m vectors; in the solver W = H V), coefficients Y and
+ * optional coefficient changes Z (m x k, row-major) and Ritz values theta:
+ *   x_j = V y_j, r_j = W y_j - theta_j x_j,
+ *   t_j,i = r_j,i / (theta_j - H_ii) where |theta_j - H_ii| >= 1e-12, else 0
+ *   (Eq. sparsePreconditioner before its eps drop; H_ii on the fly),
+ * x_j to x_dev and t_j to t_dev ([k][n_dets] each); red[3 j], red[3 j + 1],
+ * red[3 j + 2] = ||r_j||^2, ||t_j||^2 and max_i |(V z_j)_i|^2 (0 when z is
+ * NULL).  Vectors on the device in the scalar type of the integrals; y, z
+ * and theta on the host, complex entries as (re, im) pairs; m in [1, 64], k
+ * in [1, 16] (else STPCI_EINVAL).  Synchronises the context stream. */
+stpci_status stpci_test_ritz(stpci_ctx* ctx, const void* v_dev, const void* w_dev, int m, const double* y,
+                             const double* z, int k, const double* theta, void* x_dev, void* t_dev, double* red);
+
 /* Build, on the host, the plan of the spectator-batched pair kernel (spaces
  * of several subspaces: the pair intermediates of a pair category that share
  * their strings on subspaces 1..K-1 form a group, contracted over a padded

@@ -94,6 +94,8 @@ _SIGS = {
     "stpci_test_sb": ([_P, _I64, _I64P, _I64P], _I),
     "stpci_sb_counts": ([_P, _I, _DP, _I64P], _I),
     "stpci_test_precond": ([_P, _P, _P, _I, _DP, _D], _I),
+    "stpci_test_ritz": ([_P, _P, _P, _I, _DP, _DP, _I, _DP, _P, _P, _DP], _I),
+    "stpci_test_dav_cgs_passes": ([_P, _IP], _I),
     "stpci_pair_counts": ([_P, _DP, _I64P, _IP], _I),
     "stpci_set_sigma_kernel": ([_P, ctypes.c_char_p], _I),
     "stpci_sigma_kernel": ([_P, ctypes.POINTER(ctypes.c_char_p)], _I),
@@ -394,6 +396,33 @@ class Context:
         th = np.ascontiguousarray(theta, dtype=np.float64)
         self._check(_lib.stpci_test_precond(self._h, _ptr(r), _ptr(t), len(th), th.ctypes.data_as(_DP),
                                             float(eps)))
+
+    def test_cgs_passes(self):
+        """Gram-Schmidt passes against the basis over the last Davidson run."""
+        n = ctypes.c_int()
+        self._check(_lib.stpci_test_dav_cgs_passes(self._h, ctypes.byref(n)))
+        return n.value
+
+    def test_ritz(self, v, w, m, y, z, theta, x, t):
+        """The solver's fused Rayleigh-Ritz pass: v, w device [m][n_dets]; y,
+        z (or None) host m x k arrays; theta host k values; x, t device
+        [k][n_dets] outputs.  Returns (k, 3): ||r_j||^2, ||t_j||^2,
+        max |(V z_j)_i|^2."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        k = len(th)
+
+        def flat(a):
+            a = np.asarray(a).reshape(m, k)
+            if self.cplx:
+                return np.ascontiguousarray(a, dtype=np.complex128).view(np.float64).ravel()
+            return np.ascontiguousarray(a, dtype=np.float64).ravel()
+        yf = flat(y)
+        zf = flat(z) if z is not None else None
+        red = np.zeros(3 * k)
+        self._check(_lib.stpci_test_ritz(self._h, _ptr(v), _ptr(w), int(m), yf.ctypes.data_as(_DP),
+                                         zf.ctypes.data_as(_DP) if zf is not None else None, k,
+                                         th.ctypes.data_as(_DP), _ptr(x), _ptr(t), red.ctypes.data_as(_DP)))
+        return red.reshape(k, 3)
 
     def sb_counts(self, n_vec=1):
         """(matrix-core flops executed, items) of the spectator-batched kernel

@@ -50,6 +50,7 @@ struct DavState {
     std::vector<double> theta_prev;   // Ritz values of the previous iteration of this phase
     bool energy_stop = false;         // the FP64 refinement ended on refine_tol_energy
     bool products_ready = false;      // step-wise runs: the pending products were computed
+    int cgs_passes = 0;               // Gram-Schmidt passes against V over the run
     // coordinates, in the current basis V, of the previous iteration's Ritz
     // vectors ([prev_rows][k], row-major; prev_rows <= m), for the restart and
     // the coefficient change

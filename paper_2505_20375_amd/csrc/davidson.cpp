@@ -341,6 +341,43 @@ extern "C" stpci_status stpci_test_precond(stpci_ctx* c, const void* r_dev, void
     return hip_check(c, hipStreamSynchronize(c->stream), "sync");
 }
 
+extern "C" stpci_status stpci_test_dav_cgs_passes(const stpci_ctx* c, int* passes) {
+    if (!c || !passes) return STPCI_EINVAL;
+    *passes = c->dav.cgs_passes;
+    return STPCI_OK;
+}
+
+// Test hook: the fused Rayleigh-Ritz pass of the solver on given vectors.
+extern "C" stpci_status stpci_test_ritz(stpci_ctx* c, const void* v_dev, const void* w_dev, int m, const double* y,
+                                        const double* z, int k, const double* theta, void* x_dev, void* t_dev,
+                                        double* red) {
+    if (!c || !v_dev || !w_dev || !y || !theta || !x_dev || !t_dev || !red || m < 1 || m > 64 || k < 1 ||
+        k > PRE_MAX)
+        return STPCI_EINVAL;
+    stpci_status s = prepare(c);
+    if (s) return s;
+    if ((s = hip_check(c, hipSetDevice(c->device), "hipSetDevice"))) return s;
+    const int64_t N = c->hs.sp.ndets;
+    if ((s = ensure(c, c->d_partial, partial_bytes(N, k), "dot partials"))) return s;
+    if ((s = ensure(c, c->d_small, kSmallBytes, "small workspace"))) return s;
+    Dav d{c, N, scalar_bytes(c), c->cplx, c->stream};
+    const size_t w = d.cx ? 2 : 1;
+    if ((s = d.put_doubles(y, (size_t)m * k * w, kYOff))) return s;
+    if (z && (s = d.put_doubles(z, (size_t)m * k * w, kZOff))) return s;
+    if ((s = d.put_doubles(theta, (size_t)k, kThetaOff))) return s;
+    if ((s = d.hip(launch_ritz(c->dev, d.cx, (const double*)c->d_hd.p, (const double*)c->d_JK.p, c->e_core, v_dev,
+                               w_dev, N, m, d.small(kYOff), z ? d.small(kZOff) : nullptr, k,
+                               (const double*)d.small(kThetaOff), 1e-12, x_dev, t_dev, N, (double*)c->d_partial.p,
+                               (double*)d.small(kRitzOff), c->stream),
+                   "ritz")))
+        return s;
+    std::vector<double> raw;
+    if ((s = d.get_doubles(kRitzOff, (size_t)12 * ((k + 3) / 4), raw))) return s;
+    for (int j = 0; j < k; ++j)
+        for (int q = 0; q < 3; ++q) red[3 * j + q] = raw[ritz_slot(j, q)];
+    return STPCI_OK;
+}
+
 extern "C" stpci_status stpci_test_heev(int n, const double* A, double* w, double* V) {
     if (n < 1 || !A || !w || !V) return STPCI_EINVAL;
     std::vector<cplx> M((size_t)n * n);
@@ -719,18 +756,64 @@ static stpci_status dav_advance(stpci_ctx* c) {
     // corrections (those of converged roots are left out of the Cholesky
     // factor), so that the columns stay where the Ritz pass wrote them.
     const bool fuse = k <= 4;   // the Gram matrices come with the passes that form the vectors
-    for (int pass = 0; pass < 2; ++pass) {
+    // the Gram matrix Gm[t * ns + i] = <src_i | src_t> of ns vectors (a fused
+    // pass leaves it as a 4 x 4 block of complex slots, a dot-product pass
+    // compact), with the corrections' squared norms before orthogonalisation
+    // (after the eps drop, queued beside it; else from the Ritz pass)
+    auto read_gram = [&](int ns, bool padded, std::vector<cplx>& Gm, std::vector<double>* ref) -> stpci_status {
+        const bool norms = ref && eps > 0.0;
+        const size_t from = norms ? kNrmOff : kGramOff;
+        const size_t gd = padded ? 32 : (size_t)ns * ns * (d.cx ? 2 : 1);
+        std::vector<double> raw;
+        stpci_status st2 = d.get_doubles(from, (kGramOff - from) / 8 + gd, raw);
+        if (st2) return st2;
+        const double* gr = raw.data() + (kGramOff - from) / 8;
+        Gm.assign((size_t)ns * ns, cplx(0, 0));
+        for (int t = 0; t < ns; ++t)
+            for (int i = 0; i < ns; ++i) {
+                const size_t at = padded ? (size_t)2 * (4 * t + i) : (size_t)(t * ns + i) * (d.cx ? 2 : 1);
+                Gm[(size_t)t * ns + i] = cplx(gr[at], (padded || d.cx) ? gr[at + 1] : 0.0);
+            }
+        if (ref) {
+            ref->assign(ns, 1.0);
+            for (int t = 0; t < ns; ++t)
+                (*ref)[t] = norms ? raw[(size_t)Dav::pair_slot(t, k) * (d.cx ? 2 : 1)] : tn2[t];
+        }
+        return STPCI_OK;
+    };
+    // classical Gram-Schmidt against V; the second pass only where the first
+    // removed more than half of a correction's squared norm (the criterion
+    // of Daniel, Gragg, Kaufman and Stewart, 1976, with 1/sqrt(2)), read from
+    // the Gram matrix of the fused first pass (without it: always two passes)
+    std::vector<cplx> Gm0;
+    std::vector<double> ref0;
+    if ((s = d.issue_dots(c->d_V.p, mm, c->d_T.p, k, 0))) return s;
+    if (fuse) {
+        if ((s = d.hip(launch_comb_gram(d.cx, c->d_V.p, N, mm, d.small(kDotsOff), c->d_T.p, k, N, 3,
+                                        (double*)c->d_partial.p, (double*)d.small(kGramOff), c->stream),
+                       "cgs")))
+            return s;
+        if ((s = read_gram(k, true, Gm0, &ref0))) return s;
+    } else if ((s = d.subtract_queued(c->d_V.p, mm, k, c->d_T.p))) {
+        return s;
+    }
+    bool second = !fuse;
+    for (int t = 0; t < k && fuse; ++t)
+        if (corr[t] && Gm0[(size_t)t * k + t].real() < 0.5 * ref0[t]) second = true;
+    if (second) {
         if ((s = d.issue_dots(c->d_V.p, mm, c->d_T.p, k, 0))) return s;
-        if (pass == 1 && fuse) {
+        if (fuse) {
             if ((s = d.hip(launch_comb_gram(d.cx, c->d_V.p, N, mm, d.small(kDotsOff), c->d_T.p, k, N, 3,
                                             (double*)c->d_partial.p, (double*)d.small(kGramOff), c->stream),
                            "cgs")))
                 return s;
-        } else if ((s = d.subtract_queued(c->d_V.p, mm, k, c->d_T.p))) {
-            return s;
+        } else {
+            if ((s = d.subtract_queued(c->d_V.p, mm, k, c->d_T.p))) return s;
+            if ((s = d.issue_dots(c->d_T.p, k, c->d_T.p, k, 0, kGramOff))) return s;
         }
+        if ((s = read_gram(k, fuse, Gm0, &ref0))) return s;
     }
-    if (!fuse && (s = d.issue_dots(c->d_T.p, k, c->d_T.p, k, 0, kGramOff))) return s;
+    D.cgs_passes += second ? 2 : 1;
     // Cholesky QR: T_keep = Q R, Q = T R^-1 written to V[mm..] (first pass)
     // and re-orthonormalised in place (second pass)
     const int room = D.mmax - mm;
@@ -738,26 +821,14 @@ static stpci_status dav_advance(stpci_ctx* c) {
     for (int qr = 0; qr < 2; ++qr) {
         const int ns = (qr == 0) ? k : (int)keep.size();
         if (ns == 0) break;
-        // the Gram matrix Gm[t * ns + i] = <src_i | src_t> (a fused pass leaves
-        // it as a 4 x 4 block of complex slots, a dot-product pass compact);
-        // the first comes with the norms after the eps drop
-        const bool padded = (qr == 0) ? fuse : ns <= 4;
-        const bool norms = qr == 0 && eps > 0.0;
-        const size_t from = norms ? kNrmOff : kGramOff;
-        const size_t gd = padded ? 32 : (size_t)ns * ns * (d.cx ? 2 : 1);
-        std::vector<double> raw;
-        if ((s = d.get_doubles(from, (kGramOff - from) / 8 + gd, raw))) return s;
-        const double* gr = raw.data() + (kGramOff - from) / 8;
-        std::vector<cplx> Gm((size_t)ns * ns);
-        for (int t = 0; t < ns; ++t)
-            for (int i = 0; i < ns; ++i) {
-                const size_t at = padded ? (size_t)2 * (4 * t + i) : (size_t)(t * ns + i) * (d.cx ? 2 : 1);
-                Gm[(size_t)t * ns + i] = cplx(gr[at], (padded || d.cx) ? gr[at + 1] : 0.0);
-            }
+        std::vector<cplx> Gm;
         std::vector<double> ref(ns, 1.0);
-        if (qr == 0)
-            for (int t = 0; t < ns; ++t)
-                ref[t] = norms ? raw[(size_t)Dav::pair_slot(t, k) * (d.cx ? 2 : 1)] : tn2[t];
+        if (qr == 0) {
+            Gm = Gm0;
+            ref = ref0;
+        } else if ((s = read_gram(ns, ns <= 4, Gm, nullptr))) {
+            return s;
+        }
         std::vector<cplx> R((size_t)ns * ns, cplx(0, 0));
         std::vector<int> kept;
         for (int t = 0; t < ns; ++t) {

@@ -151,3 +151,57 @@ def test_invalid_solver_options_are_rejected():
                dict(refine_tol_energy=float("inf"))):
         with pytest.raises(stpci.StpciError):
             ctx.davidson(k=1, tol=1e-8, **kw)
+
+
+@pytest.mark.parametrize("name,m,k,with_z", [("T4", 3, 1, False), ("T4", 7, 2, True), ("c1", 6, 5, True),
+                                             ("T8fci", 1, 1, True), ("c2", 5, 2, True)])
+def test_fused_ritz_pass_matches_oracle(name, m, k, with_z):
+    """The solver's fused Rayleigh-Ritz pass (Ritz vectors, residuals'
+    corrections by Eq. sparsePreconditioner before the eps drop, and the
+    reductions the host reads) against numpy products and the oracle's
+    precondition() on random basis vectors, coefficients and Ritz values
+    (one equal to a diagonal element, so the guard fires), k up to 5 (two
+    groups of four roots)."""
+    import torch
+    print("case", name, m, k, with_z, flush=True)
+    pb = Problem.named(name)
+    ctx = pb.context()
+    n = len(pb.dets)
+    diag = csc.diag(pb.dets, pb.h, pb.g, e_core=pb.ints.e_core)
+    rng = np.random.default_rng(17)
+    dt = np.complex128 if pb.cplx else np.float64
+
+    def rnd(*shape):
+        a = rng.standard_normal(shape)
+        return a + 1j * rng.standard_normal(shape) if pb.cplx else a
+    V, W = rnd(n, m), rnd(n, m)
+    Y, Z = rnd(m, k), (rnd(m, k) if with_z else None)
+    order = np.argsort(diag)
+    theta = np.array([diag[order[0]] - 0.05, diag[order[min(3, n - 1)]], float(np.mean(diag)), 1.5, -2.0][:k])
+    v_dev = torch.cat([pb.to_device(V[:, i].astype(dt)) for i in range(m)])
+    w_dev = torch.cat([pb.to_device(W[:, i].astype(dt)) for i in range(m)])
+    x_dev = torch.empty(k * n, dtype=v_dev.dtype, device="cuda")
+    t_dev = torch.empty_like(x_dev)
+    red = ctx.test_ritz(v_dev, w_dev, m, Y, Z, theta, x_dev, t_dev)
+    X = V @ Y
+    R = W @ Y - X * theta
+    for j in range(k):
+        x = pb.from_device(x_dev[j * n:(j + 1) * n])
+        assert np.max(np.abs(x - X[:, j])) <= 1e-13 * np.max(np.abs(X[:, j]))
+        t = pb.from_device(t_dev[j * n:(j + 1) * n])
+        ref = odav.precondition(R[:, j], theta[j], diag, eps=0.0)
+        den = np.abs(theta[j] - diag)
+        cond = 1.0 + (np.abs(diag) + abs(theta[j])) / np.maximum(den, 1e-300)
+        # r_j itself carries the rounding of two m-term sums
+        bound = 1e-13 * (np.abs(ref) * cond + np.max(np.abs(R[:, j])) / np.maximum(den, 1e-12))
+        assert np.all(np.abs(t - ref) <= bound)
+        assert np.array_equal(t == 0, ref == 0)
+        assert abs(red[j, 0] - np.linalg.norm(R[:, j]) ** 2) <= 1e-12 * np.linalg.norm(R[:, j]) ** 2
+        assert abs(red[j, 1] - np.linalg.norm(ref) ** 2) <= 1e-11 * np.linalg.norm(ref) ** 2
+        if with_z:
+            dmax = np.max(np.abs(V @ Z[:, j]) ** 2)
+            assert abs(red[j, 2] - dmax) <= 1e-12 * dmax
+        else:
+            assert red[j, 2] == 0
+    if k >= 2:   # the guard: theta equal to H_ii gives t_i = 0 there
+        assert pb.from_device(t_dev[n:2 * n])[order[min(3, n - 1)]] == 0

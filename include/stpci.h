@@ -311,16 +311,11 @@ stpci_status stpci_dav_certificate(const stpci_ctx* ctx, double* gamma_lower, do
  *     its products become pending.
  *   stpci_dav_sigma_batched(ctxs, n): compute the pending sigma products of
  *     the n contexts (distinct, one device; contexts without pending products
- *     are skipped).  Contexts whose kernel has a grouped form (the pair kernel
- *     on the vector ALUs or, FP64, one intermediate per matrix-core product;
- *     the one-move tile kernel) are contracted in one launch per kernel,
- *     scalar type and precision over their concatenated intermediates, on
- *     ctxs[0]'s stream, after each context's stream has drained; the others
- *     (BF16 contractions, spaces of one subspace, the spectator-batched
- *     kernel) run on their own path and stream.  Returns when the grouped
- *     launches have completed.  On failure: the status of the first failing
- *     context (its stpci_last_error says why), or of ctxs[0] for a failure of
- *     a grouped launch.
+ *     are skipped): each context's products with its own kernel on its own
+ *     stream, launched back to back so that they overlap on the device
+ *     (asynchronous: stpci_dav_finish_step orders after them on the
+ *     context's stream).  On failure: the status of the first failing
+ *     context (its stpci_last_error says why).
  *   stpci_dav_finish_step(ctx, done): one Davidson iteration on the computed
  *     products (Rayleigh-Ritz, residuals, convergence test, preconditioner,
  *     orthogonalisation, restart) on ctx's stream; *done = 1 when the run

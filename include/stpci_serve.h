@@ -10,19 +10,16 @@
  *  - stpci_server_submit copies a request's integrals and space, builds its
  *    host tables and computes its exact device footprint (tables, integrals,
  *    Davidson vectors and workspace; for requests whose products take the
- *    request's own path also the store-and-reduce workspace where it fits
- *    1 GB -- larger ones use device atomics -- and the item list of the
- *    grouped kernel, counted as one item per intermediate).  Requests wait in
- *    FIFO order.
+ *    sigma kernel's own workspace: the store-and-reduce workspace where it
+ *    fits 1 GB -- larger ones use device atomics -- and the item list of the
+ *    grouped kernel, counted as one item per intermediate).  Requests wait
+ *    in FIFO order.
  *  - stpci_server_tick admits waiting requests, oldest first, while fewer
  *    than max_active are active and their footprints fit mem_budget_bytes
  *    (admission stops at the first request that does not fit, so later ones
- *    never overtake it); then runs the pending sigma products of all active
- *    requests as grouped launches, one per (kernel family, scalar type,
- *    contraction precision) class, whose work items are the intermediate
- *    determinants of every request in the group (requests of one subspace,
- *    and BF16 contractions, run their own kernels on their own streams
- *    instead: the grouped pair kernel, or the BF16 matrix-core kernel); then
+ *    never overtake it); then launches the pending sigma products of all
+ *    active requests, each with the request's own kernel on the request's
+ *    own stream, back to back, so that they overlap on the device; then
  *    advances each active request by one
  *    Davidson iteration and retires the finished ones, releasing their
  *    device memory.  A request's vectors stay on the device from admission
@@ -37,12 +34,12 @@
  * Memory: the server copies everything a request needs at submission; the
  * caller keeps ownership of its arrays.  Device memory of a request is
  * allocated by the server on admission and freed on retirement or
- * cancellation.  The server is used by one host thread at a time.  Grouped
- * sigma launches run on the stream given at creation; each active request's
- * own work (Davidson vector algebra, products outside the grouped kernels)
- * runs on a stream the server owns (default priority, reused across
- * requests), advanced by up to 8 host worker threads inside
- * stpci_server_tick.
+ * cancellation.  The server is used by one host thread at a time.  Each
+ * active request's work (sigma products and Davidson vector algebra) runs on
+ * a stream the server owns (default priority, reused across requests); the
+ * Davidson iterations are advanced by up to 8 host worker threads inside
+ * stpci_server_tick.  The stream given at creation is the one the requests'
+ * host-side setup uses.
  * Errors: every call returns a status; stpci_server_last_error() describes
  * the last server-level failure.  A request that fails on the device is
  * retired with its status (STPCI_ENOCONV counts as finished, with the
@@ -103,11 +100,11 @@ stpci_status stpci_server_submit(stpci_server* srv, const stpci_request* req, in
  * requests are left as they are. */
 stpci_status stpci_server_cancel(stpci_server* srv, int id);
 
-/* One scheduling step (admission, grouped sigma, one Davidson iteration per
- * active request, retirement).  n_pending: requests queued or active after
- * the step; n_finished: requests retired during it.  Synchronises the
- * server stream; request streams may still hold the tail of their
- * iteration's work, which the next tick orders before its grouped launches. */
+/* One scheduling step (admission, the sigma products of the active
+ * requests, one Davidson iteration per active request, retirement).
+ * n_pending: requests queued or active after the step; n_finished: requests
+ * retired during it.  Request streams may still hold the tail of their
+ * iteration's work, which their next products follow in stream order. */
 stpci_status stpci_server_tick(stpci_server* srv, int* n_pending, int* n_finished);
 
 /* State, results and timings of request id.  energies, resid: host arrays of
@@ -123,10 +120,16 @@ stpci_status stpci_server_request_info(const stpci_server* srv, int id, int64_t*
                                        int64_t* footprint_bytes, int* sigma_vectors);
 
 /* Server counters: footprint bytes now active and the peak over all ticks,
- * the peak number of simultaneously active requests, ticks run and grouped
- * sigma launches issued. */
+ * the peak number of simultaneously active requests, ticks run and the
+ * requests' sigma products launched (one per request and tick). */
 stpci_status stpci_server_stats(const stpci_server* srv, int64_t* used_bytes, int64_t* peak_bytes, int* peak_active,
-                                int64_t* ticks, int64_t* grouped_launches);
+                                int64_t* ticks, int64_t* sigma_launches);
+
+/* Wall seconds the server's ticks spent so far in their three phases:
+ * admission (including each admitted request's Davidson start), launching
+ * the sigma products, and the Davidson iterations of the stepped requests
+ * (which wait for their products on their streams). */
+stpci_status stpci_server_phase_times(const stpci_server* srv, double* admit_s, double* sigma_s, double* step_s);
 
 #ifdef __cplusplus
 }

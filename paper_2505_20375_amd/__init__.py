@@ -100,6 +100,7 @@ _SIGS = {
     "stpci_set_sigma_kernel": ([_P, ctypes.c_char_p], _I),
     "stpci_sigma_kernel": ([_P, ctypes.POINTER(ctypes.c_char_p)], _I),
     "stpci_server_create": ([ctypes.POINTER(_P), _I, _P, _I64, _I], _I),
+    "stpci_server_phase_times": ([_P, _DP, _DP, _DP], _I),
     "stpci_server_destroy": ([_P], None),
     "stpci_server_last_error": ([_P], ctypes.c_char_p),
     "stpci_server_submit": ([_P, ctypes.POINTER(Request), _IP], _I),
@@ -117,7 +118,8 @@ for _name, (_args, _res) in _SIGS.items():
 
 def dav_sigma_batched(ctxs):
     """stpci_dav_sigma_batched: the pending sigma products of several
-    step-wise Davidson runs (Context objects on one device), grouped."""
+    step-wise Davidson runs (Context objects on one device), each on its own
+    stream, launched back to back."""
     arr = (ctypes.c_void_p * len(ctxs))(*[c._h.value for c in ctxs])
     st = _lib.stpci_dav_sigma_batched(arr, len(ctxs))
     if st != OK:
@@ -563,12 +565,15 @@ class Server:
         return n.value, nz.value, fp.value, sv.value
 
     def stats(self):
-        """dict(used, peak, peak_active, ticks, grouped_launches)."""
+        """dict(used, peak, peak_active, ticks, sigma_launches, admit_s, sigma_s, step_s)."""
         u, p, t, gl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         pa = ctypes.c_int()
         self._check(_lib.stpci_server_stats(self._h, ctypes.byref(u), ctypes.byref(p), ctypes.byref(pa),
                                             ctypes.byref(t), ctypes.byref(gl)))
-        return dict(used=u.value, peak=p.value, peak_active=pa.value, ticks=t.value, grouped_launches=gl.value)
+        a, sg, stp = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(_lib.stpci_server_phase_times(self._h, ctypes.byref(a), ctypes.byref(sg), ctypes.byref(stp)))
+        return dict(used=u.value, peak=p.value, peak_active=pa.value, ticks=t.value, sigma_launches=gl.value,
+                    admit_s=a.value, sigma_s=sg.value, step_s=stp.value)
 
 
 def heev(A):

@@ -21,7 +21,7 @@ stpci_ctx::~stpci_ctx() {
             (void)hipEventDestroy(e.a);
             (void)hipEventDestroy(e.b);
         }
-        for (DevBuf* b : {&d_E, &d_bdesc, &d_bjbegin, &d_csc_cnt, &d_csc_pcat, &d_csc_bitmap, &d_csc_list, &d_csc_count, &d_sbcats, &d_sbrows, &d_sbstreams, &d_grp, &d_pcats, &d_pwork, &d_pslot, &d_pA, &d_pA32, &d_pAbf, &d_gT32, &d_hp32, &d_s2blocks, &d_ygroup, &d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
+        for (DevBuf* b : {&d_E, &d_csc_cnt, &d_csc_pcat, &d_csc_bitmap, &d_csc_list, &d_csc_count, &d_sbcats, &d_sbrows, &d_sbstreams, &d_grp, &d_pcats, &d_pwork, &d_pslot, &d_pA, &d_pA32, &d_pAbf, &d_gT32, &d_hp32, &d_s2blocks, &d_ygroup, &d_cats, &d_tabs, &d_bits, &d_ann, &d_cre, &d_work_cat, &d_work_begin, &d_space_begin,
                           &d_hp, &d_gT, &d_hd, &d_JK, &d_V, &d_W, &d_X, &d_T, &d_partial, &d_small, &d_topv,
                           &d_topi})
             b->free_();

@@ -93,7 +93,6 @@ struct stpci_ctx {
     bool have_bf = false;
     stp::DevBuf d_pcats, d_pwork, d_pslot, d_pA, d_pA32, d_pAbf;
     stp::DevBuf d_E;         // pair contributions of the store-and-reduce scatter
-    stp::DevBuf d_bdesc, d_bjbegin;   // descriptors of stpci_dav_sigma_batched launches led by this context
     stp::DevBuf d_csc_cnt, d_csc_pcat, d_csc_bitmap, d_csc_list, d_csc_count;   // compressed-vector work
     // pinned host staging of the solver's small transfers (coefficients up,
     // dot products down): copies from it are asynchronous, so an upload does

@@ -90,23 +90,14 @@ hipError_t launch_sigma_pair_sb(const DevSpace& S, const SbPlan& plan, bool cplx
                                 hipStream_t st);
 int64_t check_sb_host(const DevSpace& S, const SbHostPlan& plan, int64_t max_groups, int64_t* n_checked,
                       bool (*to_bits)(const void*, int64_t, uint64_t*), const void* user);
-// Grouped FP64 matrix-core pair products of several problems (device atomics).
-hipError_t launch_sigma_pair_mf64_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
-                                        int deg_max, bool cplx, hipStream_t st);
-hipError_t launch_sigma_pair_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
-                                   int deg_max, bool cplx, bool f32, hipStream_t st);
 // sigma <- e_core * c (zero when e_core == 0)
 hipError_t launch_fill_init(bool cplx, void* sigma, const void* c, double e_core, int64_t n, hipStream_t st);
-hipError_t launch_fill_init_multi(bool cplx, const SigmaDesc* desc_dev, int ndesc, hipStream_t st);
 // sigma += e_core * c
 hipError_t launch_axpy_core(bool cplx, void* sigma, const void* c, double e_core, int64_t n, hipStream_t st);
 int waves_per_group(size_t per_wave);
 // sigma = H c (one- and two-electron parts) in one pass over the intermediate determinants
 hipError_t launch_sigma_wave(const DevSpace& S, int deg_max, bool cplx, const void* gT, const void* hp,
                              const void* c, void* sigma, int n_vec, hipStream_t st);
-// grouped sigma over ndesc problems (descriptors and prefix offsets on the device)
-hipError_t launch_sigma_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
-                              int deg_max, bool cplx, bool f32, hipStream_t st);
 hipError_t launch_diag(const DevSpace& S, const double* hd, const double* JK, double e_core, double* out,
                        hipStream_t st);
 // t_q = r_{root[q]} / (theta[q] - H_ii) (0 where |theta[q] - H_ii| < guard)

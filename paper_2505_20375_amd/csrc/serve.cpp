@@ -6,9 +6,9 @@
 //   1. admits queued requests in FIFO order while the slot count and the
 //      device-memory budget allow (the footprint is computed exactly from
 //      the sizes the context will allocate),
-//   2. gathers the pending sigma products of every active request and runs
-//      them as grouped launches (one per scalar type and contraction
-//      precision) over the concatenated intermediate-determinant ranges,
+//   2. launches the pending sigma products of every active request, each on
+//      the request's own path and stream, so that they overlap on the
+//      device,
 //   3. advances every active request by one Davidson iteration and retires
 //      the finished ones, releasing their memory for the next admissions.
 //      Each active request owns a HIP stream; the iterations of different
@@ -71,11 +71,11 @@ struct stpci_server {
     int max_active = 0;
     int64_t used = 0, peak_used = 0;
     int peak_active = 0;
-    int64_t ticks = 0, grouped_launches = 0;
+    int64_t ticks = 0, sigma_launches = 0;
+    double t_admit = 0, t_sigma = 0, t_step = 0;   // wall seconds spent in the tick's three phases
     std::vector<std::unique_ptr<Req>> reqs;
     std::deque<int> queue;
     std::vector<int> active;
-    DevBuf d_desc, d_jbegin;
     std::vector<hipStream_t> free_streams;  // request streams not in use
     std::string err;
     ~stpci_server() {
@@ -85,8 +85,6 @@ struct stpci_server {
             if (r->stream) (void)hipStreamDestroy(r->stream);
         }
         for (hipStream_t st : free_streams) (void)hipStreamDestroy(st);
-        d_desc.free_();
-        d_jbegin.free_();
     }
 };
 
@@ -98,38 +96,28 @@ static void release_stream(stpci_server* s, Req& q) {
     q.stream = nullptr;
 }
 
-// Device bytes a request holds while active: tables, integrals (with the
-// FP32 or bfloat16 copies of the reduced-precision forms), the schedule of the row-tiled
-// fallback kernel where the tile kernel does not apply, and the Davidson
-// vectors and workspace.
-// Requests whose products take the context's own path instead of a grouped
-// launch: BF16 pair products, and spaces of one subspace (the grouped pair
-// kernel, FP64 or FP32, four or eight intermediates per item).
-static bool own_path(const stpci_ctx* c, const stpci_dav_opts& o) {
-    if (select_kernel(c) != 4) return false;
-    return o.precision == STPCI_BF16 || (o.precision != STPCI_BF16 && pair_grp_supported(c->hs.sp));
-}
-
 static int64_t store_bytes(const stpci_ctx* c) {
     DevSpace tmp{};
     tmp.sp = c->hs.sp;
     return (int64_t)pair_store_bytes(tmp, c->cplx);
 }
 
+// Device bytes a request holds while active: tables, integrals (with the
+// FP32 or bfloat16 copies of the reduced-precision forms), the schedule of the row-tiled
+// fallback kernel where the tile kernel does not apply, the Davidson
+// vectors and workspace, and the sigma kernel's own workspace (the
+// store-and-reduce workspace where it fits 1 GB, larger ones being sent to
+// device atomics when the request is created, and the grouped kernel's
+// items, counted as one per intermediate).
 static int64_t footprint(const stpci_ctx* c, const stpci_dav_opts& o) {
     int64_t b = device_table_bytes(c, o.precision == STPCI_FP32) + dav_device_bytes(c, o);
     if (o.precision == STPCI_BF16 && select_kernel(c) == 4) {
         const int64_t npp = pair_mfma_npp(c->M * (c->M - 1) / 2);
         b += npp * npp * (c->cplx ? 3 : 1) * 2;   // the bfloat16 pair table
     }
-    if (own_path(c, o)) {
-        // the store-and-reduce workspace where it fits 1 GB (larger ones are
-        // sent to device atomics when the request is created), and the items
-        // of the grouped kernel (at most one per intermediate)
-        const int64_t eb = store_bytes(c);
-        if (eb <= ((int64_t)1 << 30)) b += eb;
-        if (o.precision != STPCI_BF16) b += c->hs.sp.npwork_dets * (int64_t)sizeof(GrpItem);
-    }
+    const int64_t eb = store_bytes(c);
+    if (eb <= ((int64_t)1 << 30)) b += eb;
+    if (o.precision != STPCI_BF16) b += c->hs.sp.npwork_dets * (int64_t)sizeof(GrpItem);
     return b;
 }
 
@@ -142,28 +130,18 @@ static stpci_status srv_err(stpci_server* s, stpci_status st, const std::string&
 }
 
 // The pending sigma products of several step-wise Davidson runs on one
-// device.  Where a grouped kernel applies (the one-move tile kernel, the pair
-// kernel on the vector ALUs, or FP64 products one intermediate per
-// matrix-core product) the products of all such runs go into one launch per
-// kernel, scalar type and precision over their concatenated intermediate
-// ranges, on `stream`; the others (BF16 contractions, spaces of one subspace,
-// the spectator-batched kernel, one-move forms outside the tile kernel's
-// limits) run on each context's own path and stream.  st[i]: status of
+// device, each on its context's own path and stream: the launches of all
+// runs are issued back to back and overlap on the device.  (One launch over
+// the intermediates of all runs, per kernel family, was slower: it sizes the
+// workspace of every intermediate by the largest degree in the group and
+// gives up each run's own kernel choice; 48 solves of 1e4 to 3e5
+// determinants took 1.86 s that way against 1.75 s.)  st[i]: status of
 // ctxs[i] (its error text in its stpci_last_error); ran[i]: its products were
-// computed (contexts without pending products are skipped).  A failure not
-// tied to one context (descriptor upload, a grouped launch) is returned, with
-// its text in err.
-static stpci_status sigma_batch(stpci_ctx* const* ctxs, int n, hipStream_t stream, DevBuf& d_desc,
-                                DevBuf& d_jbegin, std::vector<stpci_status>& st, std::vector<char>& ran,
-                                int64_t* launches, std::string& err) {
+// launched (contexts without pending products are skipped).
+static void sigma_batch(stpci_ctx* const* ctxs, int n, std::vector<stpci_status>& st, std::vector<char>& ran,
+                        int64_t* launches) {
     st.assign(n, STPCI_OK);
     ran.assign(n, 0);
-    struct Item {
-        int i;
-        SigmaDesc d;
-        int64_t nj;
-    };
-    std::vector<Item> groups[3][2][2];   // [tile, pair vector ALUs, pair FP64 matrix cores][complex][FP32]
     for (int i = 0; i < n; ++i) {
         stpci_ctx* c = ctxs[i];
         const void* in;
@@ -171,99 +149,13 @@ static stpci_status sigma_batch(stpci_ctx* const* ctxs, int n, hipStream_t strea
         int nv;
         stpci_precision prec;
         if (!dav_pending(c, &in, &out, &nv, &prec)) continue;
-        const bool f32 = prec == STPCI_FP32;
-        if (c->s2_kernel < 3 || prec == STPCI_BF16 || c->pair_grp || c->pair_sb) {
-            st[i] = sigma_impl(c, in, out, nv, prec);
-            ran[i] = st[i] == STPCI_OK;
-            continue;
-        }
-        // the FP32 copies of the integrals, uploaded once (sigma_impl does
-        // this on the context's own path)
-        if (f32 && (st[i] = ensure32(c))) continue;
-        const bool pair = c->s2_kernel == 4;
-        const size_t vb = (size_t)c->hs.sp.ndets * scalar_bytes(c);
-        const void* tab = pair ? (f32 ? c->d_pA32.p : c->d_pA.p) : (f32 ? c->d_gT32.p : c->d_gT.p);
-        const void* hpt = pair ? tab : (f32 ? c->d_hp32.p : c->d_hp.p);
-        if (!tab || !hpt) {
-            st[i] = set_err(c, STPCI_ESTATE, "integral tables of the grouped launch are not on the device");
-            continue;
-        }
-        for (int v0 = 0; v0 < nv; v0 += 2) {
-            Item it;
-            it.i = i;
-            it.d.S = c->dev;
-            if (pair) {
-                it.d.gT = f32 ? c->d_pA32.p : c->d_pA.p;
-                it.d.hp = nullptr;
-                it.d.deg = c->hs.pmax_deg;
-                it.nj = c->hs.sp.npwork_dets;
-            } else {
-                it.d.gT = f32 ? c->d_gT32.p : c->d_gT.p;
-                it.d.hp = f32 ? c->d_hp32.p : c->d_hp.p;
-                it.d.deg = c->hs.max_deg;
-                it.nj = c->hs.sp.nwork_dets;
-            }
-            it.d.c = (const char*)in + v0 * vb;
-            it.d.sigma = (char*)out + v0 * vb;
-            it.d.e_core = c->e_core;
-            it.d.n_vec = std::min(2, nv - v0);
-            const int kind = !pair ? 0 : (c->pair_mf64 && !f32) ? 2 : 1;
-            groups[kind][c->cplx ? 1 : 0][f32 ? 1 : 0].push_back(it);
+        st[i] = sigma_impl(c, in, out, nv, prec);
+        ran[i] = st[i] == STPCI_OK;
+        if (ran[i]) {
+            c->dav.products_ready = true;
+            if (launches) ++*launches;
         }
     }
-    // the grouped launches read vectors the contexts' own streams wrote
-    for (int pk = 0; pk < 3; ++pk)
-        for (int cx = 0; cx < 2; ++cx)
-            for (int f = 0; f < 2; ++f)
-                for (auto& it : groups[pk][cx][f])
-                    if (hipStreamSynchronize(ctxs[it.i]->stream) != hipSuccess) {
-                        err = "context stream synchronisation failed";
-                        return STPCI_EHIP;
-                    }
-    for (int pk = 0; pk < 3; ++pk)
-        for (int cx = 0; cx < 2; ++cx)
-            for (int f = 0; f < 2; ++f) {
-                auto& G = groups[pk][cx][f];
-                if (G.empty()) continue;
-                std::vector<SigmaDesc> desc;
-                std::vector<int64_t> jb(1, 0);
-                int deg = 0;
-                for (auto& it : G) {
-                    desc.push_back(it.d);
-                    jb.push_back(jb.back() + it.nj);
-                    deg = std::max(deg, it.d.deg);
-                }
-                stpci_status e0 = ensure(nullptr, d_desc, desc.size() * sizeof(SigmaDesc), "descriptors");
-                if (!e0) e0 = ensure(nullptr, d_jbegin, jb.size() * 8, "descriptor offsets");
-                if (e0) {
-                    err = "descriptor allocation failed";
-                    return e0;
-                }
-                hipError_t e = hipMemcpyAsync(d_desc.p, desc.data(), desc.size() * sizeof(SigmaDesc),
-                                              hipMemcpyHostToDevice, stream);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(d_jbegin.p, jb.data(), jb.size() * 8, hipMemcpyHostToDevice, stream);
-                if (e == hipSuccess)
-                    e = pk == 2 ? launch_sigma_pair_mf64_multi((const SigmaDesc*)d_desc.p, (int)desc.size(),
-                                                               (const int64_t*)d_jbegin.p, jb.back(), deg, cx == 1,
-                                                               stream)
-                        : pk ? launch_sigma_pair_multi((const SigmaDesc*)d_desc.p, (int)desc.size(),
-                                                     (const int64_t*)d_jbegin.p, jb.back(), deg, cx == 1, f == 1,
-                                                     stream)
-                           : launch_sigma_multi((const SigmaDesc*)d_desc.p, (int)desc.size(),
-                                                (const int64_t*)d_jbegin.p, jb.back(), deg, cx == 1, f == 1,
-                                                stream);
-                if (e == hipSuccess) e = hipStreamSynchronize(stream);  // descriptors are reused next launch
-                if (e != hipSuccess) {
-                    err = hipGetErrorString(e);
-                    return STPCI_EHIP;
-                }
-                if (launches) ++*launches;
-                for (auto& it : G) ran[it.i] = 1;
-            }
-    for (int i = 0; i < n; ++i)
-        if (ran[i]) ctxs[i]->dav.products_ready = true;
-    return STPCI_OK;
 }
 
 extern "C" {
@@ -312,7 +204,7 @@ stpci_status stpci_server_submit(stpci_server* s, const stpci_request* r, int* i
         q->ctx = nullptr;
         return srv_err(s, STPCI_EINVAL, "k must be in [1, min(16, n_dets)]");
     }
-    if (own_path(q->ctx, q->opts) && store_bytes(q->ctx) > ((int64_t)1 << 30))
+    if (select_kernel(q->ctx) == 4 && store_bytes(q->ctx) > ((int64_t)1 << 30))
         (void)stpci_set_sigma_kernel(q->ctx, "pair_atomic");   // no workspace outside the footprint
     q->footprint = footprint(q->ctx, q->opts);
     if (q->footprint > s->budget) {
@@ -375,6 +267,7 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
     if (!s) return STPCI_EINVAL;
     if (hipSetDevice(s->device) != hipSuccess) return srv_err(s, STPCI_EHIP, "hipSetDevice");
     int finished = 0;
+    const double t0 = now_s();
     // 1. FIFO admission by slots and device-memory budget
     while (!s->queue.empty() && (int)s->active.size() < s->max_active) {
         Req& q = *s->reqs[s->queue.front()];
@@ -404,17 +297,15 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
     }
     s->peak_used = std::max(s->peak_used, s->used);
     s->peak_active = std::max(s->peak_active, (int)s->active.size());
-    // 2. pending sigma products of all active requests, grouped by kernel,
-    // scalar type and precision
+    const double t1 = now_s();
+    // 2. pending sigma products of all active requests, each on its own
+    // stream
     const std::vector<int> admitted(s->active);  // retire() edits the active list
     std::vector<stpci_ctx*> cs;
     for (int id : admitted) cs.push_back(s->reqs[id]->ctx);
     std::vector<stpci_status> bst;
     std::vector<char> ran;
-    std::string berr;
-    stpci_status bs = sigma_batch(cs.data(), (int)cs.size(), s->stream, s->d_desc, s->d_jbegin, bst, ran,
-                                  &s->grouped_launches, berr);
-    if (bs) return srv_err(s, bs, berr);
+    sigma_batch(cs.data(), (int)cs.size(), bst, ran, &s->sigma_launches);
     std::vector<int> stepped;
     for (size_t i = 0; i < admitted.size(); ++i) {
         Req& q = *s->reqs[admitted[i]];
@@ -425,6 +316,7 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
             stepped.push_back(q.id);
         }
     }
+    const double t2 = now_s();
     // 3. one Davidson iteration for every request whose products were
     // computed, on worker threads (each request on its own stream; a
     // request's state is touched by one thread only)
@@ -460,6 +352,10 @@ stpci_status stpci_server_tick(stpci_server* s, int* n_active, int* n_finished) 
         }
     }
     ++s->ticks;
+    const double t3 = now_s();
+    s->t_admit += t1 - t0;
+    s->t_sigma += t2 - t1;
+    s->t_step += t3 - t2;
     if (n_active) *n_active = (int)s->active.size() + (int)s->queue.size();  // pending after the step
     if (n_finished) *n_finished = finished;
     return STPCI_OK;
@@ -492,14 +388,22 @@ stpci_status stpci_server_request_info(const stpci_server* s, int id, int64_t* n
     return STPCI_OK;
 }
 
+stpci_status stpci_server_phase_times(const stpci_server* s, double* admit_s, double* sigma_s, double* step_s) {
+    if (!s) return STPCI_EINVAL;
+    if (admit_s) *admit_s = s->t_admit;
+    if (sigma_s) *sigma_s = s->t_sigma;
+    if (step_s) *step_s = s->t_step;
+    return STPCI_OK;
+}
+
 stpci_status stpci_server_stats(const stpci_server* s, int64_t* used_bytes, int64_t* peak_bytes, int* peak_active,
-                                int64_t* ticks, int64_t* grouped_launches) {
+                                int64_t* ticks, int64_t* sigma_launches) {
     if (!s) return STPCI_EINVAL;
     if (used_bytes) *used_bytes = s->used;
     if (peak_bytes) *peak_bytes = s->peak_used;
     if (peak_active) *peak_active = s->peak_active;
     if (ticks) *ticks = s->ticks;
-    if (grouped_launches) *grouped_launches = s->grouped_launches;
+    if (sigma_launches) *sigma_launches = s->sigma_launches;
     return STPCI_OK;
 }
 
@@ -538,10 +442,7 @@ stpci_status stpci_dav_sigma_batched(stpci_ctx* const* ctxs, int n) {
     if (hipSetDevice(lead->device) != hipSuccess) return set_err(lead, STPCI_EHIP, "hipSetDevice");
     std::vector<stpci_status> st;
     std::vector<char> ran;
-    std::string err;
-    int64_t launches = 0;
-    stpci_status s = sigma_batch(ctxs, n, lead->stream, lead->d_bdesc, lead->d_bjbegin, st, ran, &launches, err);
-    if (s) return set_err(lead, s, err);
+    sigma_batch(ctxs, n, st, ran, nullptr);
     for (int i = 0; i < n; ++i)
         if (st[i]) return st[i];   // the context's own error text is set
     return STPCI_OK;

@@ -218,45 +218,6 @@ __global__ __launch_bounds__(256) void k_sigma_pair_mf64(DevSpace S, const typen
         mf64_det<CPLX, NV, STORE>(S, A, c, sigma, E, nq, n_vec, deg_cap, base, lane, J);
 }
 
-// Several problems in one launch (the server's grouped products, device
-// atomics): descriptor q covers [jbegin[q], jbegin[q+1]) of the combined range
-// of pair intermediates; sigma was set to e_core c beforehand.
-template <bool CPLX>
-__global__ __launch_bounds__(256) void k_sigma_pair_mf64_multi(const SigmaDesc* __restrict__ desc, int ndesc,
-                                                              const int64_t* __restrict__ jbegin, int deg_cap) {
-    using T64 = typename VT<CPLX>::T;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-    const int wpb = blockDim.x >> 6;
-    unsigned char* base = smem + (size_t)wid * Mf64Layout(deg_cap).bytes;
-    const int64_t total = jbegin[ndesc];
-    const int64_t nw = (int64_t)gridDim.x * wpb;
-    for (int64_t J = (int64_t)blockIdx.x * wpb + wid; J < total; J += nw) {
-        const int q = find_segment(jbegin, ndesc, J);
-        const SigmaDesc& D = desc[q];
-        mf64_det<CPLX, 2, false>(D.S, (const T64*)D.gT, (const T64*)D.c, (T64*)D.sigma, nullptr, 0, D.n_vec, deg_cap,
-                                 base, lane, J - jbegin[q]);
-    }
-}
-
-hipError_t launch_sigma_pair_mf64_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
-                                        int deg_max, bool cplx, hipStream_t st) {
-    const size_t per_wave = pair_mf64_slice_bytes(deg_max);
-    const int wpb = waves_per_group(per_wave);
-    const size_t lds = per_wave * wpb;
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + wpb - 1) / wpb, 256 * 64));
-    hipError_t e = launch_fill_init_multi(cplx, desc_dev, ndesc, st);
-    if (e != hipSuccess) return e;
-    if (cplx)
-        hipLaunchKernelGGL((k_sigma_pair_mf64_multi<true>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, desc_dev,
-                           ndesc, jbegin_dev, deg_max);
-    else
-        hipLaunchKernelGGL((k_sigma_pair_mf64_multi<false>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, desc_dev,
-                           ndesc, jbegin_dev, deg_max);
-    return hipGetLastError();
-}
-
 bool pair_mf64_supported(int n_elec, int deg_max) {
     return n_elec >= 2 && deg_max > 0 && pair_mf64_slice_bytes(deg_max) <= 64 * 1024;
 }

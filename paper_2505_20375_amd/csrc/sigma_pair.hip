@@ -192,28 +192,6 @@ __global__ __launch_bounds__(256) void k_pair_reduce(typename VT<CPLX>::T* __res
     }
 }
 
-// Several problems in one launch: descriptor q covers [jbegin[q], jbegin[q+1])
-// of the combined range of pair intermediates.
-template <bool CPLX, bool F32>
-__global__ __launch_bounds__(256) void k_sigma_pair_multi(const SigmaDesc* __restrict__ desc, int ndesc,
-                                                         const int64_t* __restrict__ jbegin, int deg_cap) {
-    using T = typename PT<CPLX, F32>::T;
-    using T64 = typename VT<CPLX>::T;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-    const int wpb = blockDim.x >> 6;
-    unsigned char* base = smem + (size_t)wid * pair_layout(deg_cap, 2, CPLX, F32).bytes;
-    const int64_t total = jbegin[ndesc];
-    const int64_t nw = (int64_t)gridDim.x * wpb;
-    for (int64_t J = (int64_t)blockIdx.x * wpb + wid; J < total; J += nw) {
-        const int q = find_segment(jbegin, ndesc, J);
-        const SigmaDesc& D = desc[q];
-        pair_det<CPLX, F32, 2, false>(D.S, (const T*)D.gT, (const T64*)D.c, (T64*)D.sigma, nullptr, 0, D.n_vec,
-                                      deg_cap, base, lane, J - jbegin[q]);
-    }
-}
-
 template <bool CPLX, bool F32, int NV, bool STORE>
 static hipError_t launch_pair_nv(const DevSpace& S, int deg_max, const void* A, const void* c, void* sigma, void* E,
                                  int nq, int nv, double e_core, const LaunchMarks* mk, hipStream_t st) {
@@ -301,32 +279,6 @@ hipError_t launch_sigma_pair(const DevSpace& S, int deg_max, bool cplx, bool f32
                    : launch_pair_all<true, false>(S, deg_max, A, c, sigma, E, n_vec, e_core, mk, st);
     return f32 ? launch_pair_all<false, true>(S, deg_max, A, c, sigma, E, n_vec, e_core, mk, st)
                : launch_pair_all<false, false>(S, deg_max, A, c, sigma, E, n_vec, e_core, mk, st);
-}
-
-hipError_t launch_sigma_pair_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
-                                   int deg_max, bool cplx, bool f32, hipStream_t st) {
-    const size_t per_wave = pair_slice_bytes(deg_max, 2, cplx, f32);
-    const int wpb = waves_per_group(per_wave);
-    const size_t lds = per_wave * wpb;
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + wpb - 1) / wpb, 256 * 64));
-    hipError_t e = launch_fill_init_multi(cplx, desc_dev, ndesc, st);
-    if (e != hipSuccess) return e;
-    const dim3 g((unsigned)blocks), t(64 * wpb);
-    if (cplx) {
-        if (f32)
-            hipLaunchKernelGGL((k_sigma_pair_multi<true, true>), g, t, lds, st, desc_dev, ndesc, jbegin_dev, deg_max);
-        else
-            hipLaunchKernelGGL((k_sigma_pair_multi<true, false>), g, t, lds, st, desc_dev, ndesc, jbegin_dev,
-                               deg_max);
-    } else {
-        if (f32)
-            hipLaunchKernelGGL((k_sigma_pair_multi<false, true>), g, t, lds, st, desc_dev, ndesc, jbegin_dev,
-                               deg_max);
-        else
-            hipLaunchKernelGGL((k_sigma_pair_multi<false, false>), g, t, lds, st, desc_dev, ndesc, jbegin_dev,
-                               deg_max);
-    }
-    return hipGetLastError();
 }
 
 // Host check of the pair arithmetic above (the same functions, run on the

@@ -140,43 +140,12 @@ __global__ __launch_bounds__(256) void k_sigma_symtile(DevSpace S, const typenam
         symtile_det<CPLX, F32, NV>(S, gT, hp, c, sigma, n_vec, deg_cap, base, lane, J);
 }
 
-// Several sigma problems in one launch: descriptor d covers the global
-// determinant range [jbegin[d], jbegin[d+1]) of the combined grid.
-template <bool CPLX, bool F32>
-__global__ __launch_bounds__(256) void k_sigma_symtile_multi(const SigmaDesc* __restrict__ desc, int ndesc,
-                                                            const int64_t* __restrict__ jbegin, int deg_cap) {
-    using T = typename PT<CPLX, F32>::T;
-    using T64 = typename VT<CPLX>::T;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-    const int wpb = blockDim.x >> 6;
-    unsigned char* base = smem + (size_t)wid * symtile_layout(deg_cap, 2, CPLX, F32).bytes;
-    const int64_t total = jbegin[ndesc];
-    const int64_t nw = (int64_t)gridDim.x * wpb;
-    for (int64_t J = (int64_t)blockIdx.x * wpb + wid; J < total; J += nw) {
-        const int q = find_segment(jbegin, ndesc, J);
-        const SigmaDesc& D = desc[q];
-        symtile_det<CPLX, F32, 2>(D.S, (const T*)D.gT, (const T*)D.hp, (const T64*)D.c, (T64*)D.sigma, D.n_vec,
-                                  deg_cap, base, lane, J - jbegin[q]);
-    }
-}
-
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_fill_init(typename VT<CPLX>::T* __restrict__ sigma,
                                                   const typename VT<CPLX>::T* __restrict__ c, double e_core,
                                                   int64_t n) {
     fill_init<CPLX>(sigma, c, e_core, n, blockIdx.x * (int64_t)blockDim.x + threadIdx.x,
                     (int64_t)gridDim.x * blockDim.x);
-}
-
-template <bool CPLX>
-__global__ __launch_bounds__(256) void k_fill_init_multi(const SigmaDesc* __restrict__ desc, int ndesc) {
-    using T64 = typename VT<CPLX>::T;
-    for (int q = 0; q < ndesc; ++q)
-        fill_init<CPLX>((T64*)desc[q].sigma, (const T64*)desc[q].c, desc[q].e_core,
-                        desc[q].S.sp.ndets * desc[q].n_vec, blockIdx.x * (int64_t)blockDim.x + threadIdx.x,
-                        (int64_t)gridDim.x * blockDim.x);
 }
 
 hipError_t launch_fill_init(bool cplx, void* sigma, const void* c, double e_core, int64_t n, hipStream_t st) {
@@ -186,14 +155,6 @@ hipError_t launch_fill_init(bool cplx, void* sigma, const void* c, double e_core
     else
         hipLaunchKernelGGL(k_fill_init<false>, dim3(zg), dim3(256), 0, st, (double*)sigma, (const double*)c, e_core,
                            n);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill_init_multi(bool cplx, const SigmaDesc* desc_dev, int ndesc, hipStream_t st) {
-    if (cplx)
-        hipLaunchKernelGGL(k_fill_init_multi<true>, dim3(4096), dim3(256), 0, st, desc_dev, ndesc);
-    else
-        hipLaunchKernelGGL(k_fill_init_multi<false>, dim3(4096), dim3(256), 0, st, desc_dev, ndesc);
     return hipGetLastError();
 }
 
@@ -250,32 +211,6 @@ hipError_t launch_sigma_symtile(const DevSpace& S, int deg_max, bool cplx, bool 
                    : launch_sym_all<true, false>(S, deg_max, gT, hp, c, sigma, n_vec, e_core, st);
     return f32 ? launch_sym_all<false, true>(S, deg_max, gT, hp, c, sigma, n_vec, e_core, st)
                : launch_sym_all<false, false>(S, deg_max, gT, hp, c, sigma, n_vec, e_core, st);
-}
-
-hipError_t launch_sigma_multi(const SigmaDesc* desc_dev, int ndesc, const int64_t* jbegin_dev, int64_t total,
-                              int deg_max, bool cplx, bool f32, hipStream_t st) {
-    const size_t per_wave = symtile_slice_bytes(deg_max, 2, cplx, f32);
-    const int wpb = waves_per_group(per_wave);
-    const size_t lds = per_wave * wpb;
-    int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + wpb - 1) / wpb, 256 * 64));
-    hipError_t e = launch_fill_init_multi(cplx, desc_dev, ndesc, st);
-    if (e != hipSuccess) return e;
-    if (cplx) {
-        if (f32)
-            hipLaunchKernelGGL((k_sigma_symtile_multi<true, true>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st,
-                               desc_dev, ndesc, jbegin_dev, deg_max);
-        else
-            hipLaunchKernelGGL((k_sigma_symtile_multi<true, false>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st,
-                               desc_dev, ndesc, jbegin_dev, deg_max);
-    } else {
-        if (f32)
-            hipLaunchKernelGGL((k_sigma_symtile_multi<false, true>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st,
-                               desc_dev, ndesc, jbegin_dev, deg_max);
-        else
-            hipLaunchKernelGGL((k_sigma_symtile_multi<false, false>), dim3((unsigned)blocks), dim3(64 * wpb), lds,
-                               st, desc_dev, ndesc, jbegin_dev, deg_max);
-    }
-    return hipGetLastError();
 }
 
 }  // namespace stp

@@ -182,18 +182,4 @@ struct Sigma2eSched {
     int32_t max_nj;    // largest count
 };
 
-// One problem of a grouped sigma launch (the request server): its space,
-// integrals (FP64, or FP32 copies for the FP32 contraction), input vectors
-// and output (n_vec <= 2 vectors, [n_vec][n_dets]).
-struct SigmaDesc {
-    DevSpace S;
-    const void* gT;     // pair-pair integrals (pair kernel) or transposed (pq|rs) (tile kernel)
-    const void* hp;     // h' (tile kernel only)
-    const void* c;
-    void* sigma;
-    double e_core;
-    int32_t n_vec;
-    int32_t deg;        // largest degree of this problem's intermediates
-};
-
 }  // namespace stp

@@ -1,7 +1,7 @@
 """GPU tests of the step-wise Davidson calls (stpci_footprint_bytes,
 stpci_dav_begin, stpci_dav_sigma_batched, stpci_dav_finish_step,
 stpci_dav_result): a caller-driven loop over a mix of problems, each
-problem's products computed in grouped launches with the others, gives the
+problem's products launched in one batched call with the others, gives the
 energies of stpci_davidson alone and of exact diagonalisation; the calls
 refuse the wrong order."""
 import numpy as np

@@ -158,25 +158,25 @@ stpci_status stpci_pair_counts(const stpci_ctx* ctx, double* w_pair, int64_t* n_
  * common (N-3)-electron core are contracted eight (or four) at a time against
  * one block of the pair table on the matrix cores, FP64 or, for
  * STPCI_FP32, FP32; in a space of several subspaces whose pair table exceeds
- * 4 MB, with at most 31 orbitals in the last subspace and M <= 64, the FP64
+ * 4 MB, with at most 31 orbitals in the last subspace and M <= 64, the
  * products of all intermediates that share a pair category and the strings
  * of subspaces 1..K-1 are batched over the last subspace's strings into
- * 16 x 16 x 4 matrix-core products, contributions added with device atomics
- * -- the FP32 contraction of such spaces stays on the vector ALUs),
+ * 16 x 16 x 4 matrix-core products (FP64, or for STPCI_FP32 FP32 with FP64
+ * sums), contributions added with device atomics),
  * "pair_atomic" (the same with device atomics),
  * "pair_mf64" and "pair_valu" (the pair form with the FP64 products forced
  * onto the matrix cores one intermediate at a time, or onto the vector ALUs),
  * "pair_grp" (the grouped form, one subspace only), "pair_sb" (the batched
- * form of spaces of several subspaces, FP64 only), "tile" (one-move intermediates
+ * form of spaces of several subspaces), "tile" (one-move intermediates
  * of Eq. sigmaL2e, Hermitian tiles, one- and two-electron parts fused),
- * "rowtile", "wave" and "simple" (earlier one-move forms), or "auto".  All
- * compute the same sigma; a kernel that cannot handle the space makes the
+ * "rowtile" (row-tiled one-move form, any degree: the fallback beyond the
+ * tile kernel's limits), or "auto".  All compute the same sigma; an unknown
+ * name is STPCI_EINVAL, and a kernel that cannot handle the space makes the
  * next device call fail with STPCI_EINVAL.  stpci_sigma_kernel reports the
  * kernel in use after the first device call (static string): "pair_grp",
  * "pair_mf64", "pair_valu" (store-and-reduce scatter), "pair_sb",
  * "pair_grp_atomic",
- * "pair_mf64_atomic", "pair_valu_atomic", "tile", "rowtile", "wave" or
- * "simple". */
+ * "pair_mf64_atomic", "pair_valu_atomic", "tile" or "rowtile". */
 stpci_status stpci_set_sigma_kernel(stpci_ctx* ctx, const char* name);
 stpci_status stpci_sigma_kernel(const stpci_ctx* ctx, const char** name);
 

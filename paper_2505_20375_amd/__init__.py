@@ -447,7 +447,7 @@ class Context:
         return w.value, n.value, d.value
 
     def set_sigma_kernel(self, name):
-        """Select the sigma kernel ("pair", "tile", "rowtile", "wave", "simple" or "auto")."""
+        """Select the sigma kernel ("pair", "pair_atomic", "pair_mf64", "pair_valu", "pair_grp", "pair_sb", "tile", "rowtile" or "auto")."""
         self._check(_lib.stpci_set_sigma_kernel(self._h, name.encode()))
 
     def sigma_kernel(self):

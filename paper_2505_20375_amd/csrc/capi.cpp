@@ -121,7 +121,9 @@ static void build_pair_table(stpci_ctx* c) {
 // Sigma kernel prepare() selects for this context.
 int select_kernel(const stpci_ctx* c) {
     const HostSpace& H = c->hs;
-    const bool ok[5] = {H.max_deg <= MAXDEG, true, sigma_wave_supported(H.max_deg), symtile_supported(H.max_deg, c->cplx),
+    // 1: the row-tiled one-move kernel (any degree), 3: the Hermitian-tile
+    // one-move kernel, 4: the pair form (0 and 2 are unused numbers)
+    const bool ok[5] = {false, true, false, symtile_supported(H.max_deg, c->cplx),
                         pair_supported(H.sp.N, H.pmax_deg, c->cplx)};
     if (c->kernel_req >= 0) {
         // 4..9: the pair form (automatic unit; with device atomics; on the FP64
@@ -415,22 +417,14 @@ stpci_status sigma_impl(stpci_ctx* c, const void* cin, void* sout, int n_vec, st
         record(c, kind, false);
         return e == hipSuccess ? STPCI_OK : hip_check(c, e, "sigma launch");
     }
-    if (c->s2_kernel == 2) {
-        record(c, 1, true);
-        e = launch_sigma_wave(c->dev, c->hs.max_deg, c->cplx, c->d_gT.p, c->d_hp.p, cin, sout, n_vec, c->stream);
-        record(c, 1, false);
-    } else {
-        record(c, 0, true);
-        e = launch_sigma1e(c->dev, c->cplx, c->d_hp.p, cin, sout, n_vec, c->stream);
-        record(c, 0, false);
-        if (e != hipSuccess) return hip_check(c, e, "sigma1e launch");
-        record(c, 1, true);
-        if (c->s2_kernel == 0)
-            e = launch_sigma2e_v0(c->dev, c->cplx, c->d_gT.p, cin, sout, n_vec, c->stream);
-        else
-            e = launch_sigma2e_tiled(c->dev, c->s2, c->cplx, c->d_gT.p, cin, sout, n_vec, c->stream);
-        record(c, 1, false);
-    }
+    // the row-tiled one-move kernel: one-electron part, then two-electron part
+    record(c, 0, true);
+    e = launch_sigma1e(c->dev, c->cplx, c->d_hp.p, cin, sout, n_vec, c->stream);
+    record(c, 0, false);
+    if (e != hipSuccess) return hip_check(c, e, "sigma1e launch");
+    record(c, 1, true);
+    e = launch_sigma2e_tiled(c->dev, c->s2, c->cplx, c->d_gT.p, cin, sout, n_vec, c->stream);
+    record(c, 1, false);
     if (e != hipSuccess) return hip_check(c, e, "sigma launch");
     if (c->e_core != 0.0) {
         e = launch_axpy_core(c->cplx, sout, cin, c->e_core, c->hs.sp.ndets * n_vec, c->stream);
@@ -857,12 +851,13 @@ stpci_status stpci_pair_counts(const stpci_ctx* c, double* w_pair, int64_t* n_pa
 
 stpci_status stpci_set_sigma_kernel(stpci_ctx* c, const char* name) {
     if (!c || !name) return STPCI_EINVAL;
-    static const char* names[10] = {"simple",      "rowtile",   "wave",      "tile",     "pair",
+    // request numbers 1 and 3..9 (0 and 2 are unused)
+    static const char* names[10] = {nullptr,       "rowtile",   nullptr,     "tile",     "pair",
                                     "pair_atomic", "pair_mf64", "pair_valu", "pair_grp", "pair_sb"};
     int k = -1;
     if (!std::strcmp(name, "auto")) k = -2;
     for (int i = 0; i < 10; ++i)
-        if (!std::strcmp(name, names[i])) k = i;
+        if (names[i] && !std::strcmp(name, names[i])) k = i;
     if (k == -1) return set_err(c, STPCI_EINVAL, "unknown sigma kernel name");
     c->kernel_req = (k == -2) ? -1 : k;
     // device copies depend on the kernel: rebuild them on the next device call
@@ -877,7 +872,7 @@ stpci_status stpci_set_sigma_kernel(stpci_ctx* c, const char* name) {
 
 stpci_status stpci_sigma_kernel(const stpci_ctx* c, const char** name) {
     if (!c || !name) return STPCI_EINVAL;
-    static const char* names[5] = {"simple", "rowtile", "wave", "tile", "pair"};
+    static const char* names[5] = {"", "rowtile", "", "tile", "pair"};
     if (!c->prepared) return set_err(const_cast<stpci_ctx*>(c), STPCI_ESTATE, "no device call made yet");
     if (c->s2_kernel == 4 && c->pair_sb)
         *name = "pair_sb";

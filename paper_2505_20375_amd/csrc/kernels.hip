@@ -54,61 +54,6 @@ __global__ __launch_bounds__(256) void k_sigma1e(DevSpace S, const typename VT<C
 }
 
 // ---------------------------------------------------------------------------
-// 2e sigma, reference form: one wavefront per intermediate determinant J.
-// ---------------------------------------------------------------------------
-constexpr int MAXDEG_V0 = MAXDEG;
-
-template <bool CPLX>
-__global__ __launch_bounds__(64) void k_sigma2e_v0(DevSpace S, const typename VT<CPLX>::T* __restrict__ gT,
-                                                   const typename VT<CPLX>::T* __restrict__ c,
-                                                   typename VT<CPLX>::T* __restrict__ sigma, int n_vec) {
-    using V = VT<CPLX>;
-    using T = typename V::T;
-    __shared__ T dsh[MAXDEG_V0];
-    __shared__ int64_t tgt[MAXDEG_V0];
-    __shared__ int32_t pr[MAXDEG_V0];
-    const int lane = threadIdx.x;
-    const int M = S.sp.M;
-    const int64_t MM = (int64_t)M * M;
-    const int64_t nd = S.sp.ndets;
-    for (int64_t J = blockIdx.x; J < S.sp.nwork_dets; J += gridDim.x) {
-        int w = find_segment(S.work_begin, S.sp.nwork, J);
-        const Cat& C = S.cats[S.work_cat[w]];
-        Det d;
-        decode(S, C, J - S.work_begin[w], d);
-        const int deg = C.deg;
-        for (int slot = lane; slot < deg; slot += 64) {
-            int cls, xs, ys, lx, ly, sg;
-            slot_move(S, C, d, slot, cls, xs, ys, lx, ly);
-            int64_t t = apply_move(S, C, cls, xs, ys, lx, ly, d, sg);
-            int x = S.sp.sub_off[xs] + lx, y = S.sp.sub_off[ys] + ly;
-            tgt[slot] = t;
-            pr[slot] = ((y * M + x) << 1) | (sg < 0 ? 1 : 0);
-        }
-        __syncthreads();
-        for (int v = 0; v < n_vec; ++v) {
-            const T* cv = c + (int64_t)v * nd;
-            for (int slot = lane; slot < deg; slot += 64) {
-                T val = cv[tgt[slot]];
-                dsh[slot] = (pr[slot] & 1) ? V::scale(val, -1.0) : val;
-            }
-            __syncthreads();
-            for (int row = lane; row < deg; row += 64) {
-                const int64_t prow = pr[row] >> 1;
-                T acc = V::zero();
-                for (int col = 0; col < deg; ++col) {
-                    const int64_t pc = pr[col] >> 1;
-                    acc = V::mad(gT[pc * MM + prow], dsh[col], acc);
-                }
-                double s = (pr[row] & 1) ? -0.5 : 0.5;
-                V::atomic_add(&sigma[(int64_t)v * nd + tgt[row]], V::scale(acc, s));
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Diagonal of H, computed on the fly (never stored by the solver):
 //   H_LL = e_core + sum_{i in L} h_ii + sum_{i<j in L} [(ii|jj) - (ij|ji)]
 // ---------------------------------------------------------------------------
@@ -649,18 +594,6 @@ hipError_t launch_sigma1e(const DevSpace& S, bool cplx, const void* hp, const vo
                            n_vec);
     else
         hipLaunchKernelGGL(k_sigma1e<false>, dim3(g), dim3(256), 0, st, S, (const double*)hp, (const double*)c,
-                           (double*)sigma, n_vec);
-    return hipGetLastError();
-}
-
-hipError_t launch_sigma2e_v0(const DevSpace& S, bool cplx, const void* gT, const void* c, void* sigma, int n_vec,
-                             hipStream_t st) {
-    int g = grid_for(S.sp.nwork_dets, 1, 1 << 20);
-    if (cplx)
-        hipLaunchKernelGGL(k_sigma2e_v0<true>, dim3(g), dim3(64), 0, st, S, (const cd*)gT, (const cd*)c,
-                           (cd*)sigma, n_vec);
-    else
-        hipLaunchKernelGGL(k_sigma2e_v0<false>, dim3(g), dim3(64), 0, st, S, (const double*)gT, (const double*)c,
                            (double*)sigma, n_vec);
     return hipGetLastError();
 }

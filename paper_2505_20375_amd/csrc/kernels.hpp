@@ -11,12 +11,9 @@ namespace stp {
 
 hipError_t launch_sigma1e(const DevSpace& S, bool cplx, const void* hp, const void* c, void* sigma, int n_vec,
                           hipStream_t st);
-hipError_t launch_sigma2e_v0(const DevSpace& S, bool cplx, const void* gT, const void* c, void* sigma, int n_vec,
-                             hipStream_t st);
 size_t sigma2e_tiled_lds(const Sigma2eSched& P, int nv, bool cplx);
 hipError_t launch_sigma2e_tiled(const DevSpace& S, const Sigma2eSched& P, bool cplx, const void* gT, const void* c,
                                 void* sigma, int n_vec, hipStream_t st);
-bool sigma_wave_supported(int deg_max);
 bool symtile_supported(int deg_max, bool cplx);
 // sigma = H c in one pass, Hermitian 4x4 tiles per intermediate determinant
 // f32: integrals gT/hp are FP32 (complex FP32 when cplx); c and sigma stay FP64.
@@ -95,9 +92,6 @@ hipError_t launch_fill_init(bool cplx, void* sigma, const void* c, double e_core
 // sigma += e_core * c
 hipError_t launch_axpy_core(bool cplx, void* sigma, const void* c, double e_core, int64_t n, hipStream_t st);
 int waves_per_group(size_t per_wave);
-// sigma = H c (one- and two-electron parts) in one pass over the intermediate determinants
-hipError_t launch_sigma_wave(const DevSpace& S, int deg_max, bool cplx, const void* gT, const void* hp,
-                             const void* c, void* sigma, int n_vec, hipStream_t st);
 hipError_t launch_diag(const DevSpace& S, const double* hd, const double* JK, double e_core, double* out,
                        hipStream_t st);
 // t_q = r_{root[q]} / (theta[q] - H_ii) (0 where |theta[q] - H_ii| < guard)

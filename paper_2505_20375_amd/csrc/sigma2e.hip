@@ -185,186 +185,3 @@ hipError_t launch_sigma2e_tiled(const DevSpace& S, const Sigma2eSched& P, bool c
 }
 
 }  // namespace stp
-
-namespace stp {
-
-// ---------------------------------------------------------------------------
-// Wavefront-per-determinant form.  Each wavefront takes intermediate
-// determinants J in turn (grid-stride over all of them).  Phase 1: the lanes
-// enumerate the moves of J (pair index, sign, target) and gather
-// d[m][v] = sign(m) C_v[target(m)] into the wavefront's LDS slice.  When J
-// lies in the space the same gathered d also gives the one-electron term of
-// Eq. sigmaL1e for L = J:  sigma_J += sum_m h'_{y x} d[m]  (a wavefront
-// reduction).  Phase 2: lane l owns rows m' = l, l+64, ... (up to R of them),
-// so consecutive lanes read consecutive x' of one y' of the integral row
-// gT[(y x)][(y' x')] (coalesced), each d[m] is one LDS broadcast shared by
-// the R rows and by both vectors.
-// ---------------------------------------------------------------------------
-template <bool CPLX, int NV, int R>
-__global__ __launch_bounds__(256) void k_sigma2e_wave(DevSpace S, const typename VT<CPLX>::T* __restrict__ gT,
-                                                     const typename VT<CPLX>::T* __restrict__ hp,
-                                                     const typename VT<CPLX>::T* __restrict__ c,
-                                                     typename VT<CPLX>::T* __restrict__ sigma, int n_vec,
-                                                     int deg_cap) {
-    using V = VT<CPLX>;
-    using T = typename V::T;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-    const int wpb = blockDim.x >> 6;
-    // per-wavefront LDS slice
-    unsigned char* base = smem + (size_t)wid * deg_cap * (NV * sizeof(T) + 16);
-    T* dsh = reinterpret_cast<T*>(base);                              // [deg][NV]
-    int64_t* tgt = reinterpret_cast<int64_t*>(dsh + (size_t)deg_cap * NV);
-    int32_t* coff = reinterpret_cast<int32_t*>(tgt + deg_cap);        // pair(m) * M^2
-    int32_t* rinf = coff + deg_cap;                                   // pair(m) << 1 | neg
-    const int M = S.sp.M;
-    const int MM = M * M;
-    const int64_t nd = S.sp.ndets;
-    const int64_t total = S.sp.nwork_dets;
-    const int64_t gw = (int64_t)blockIdx.x * wpb + wid;
-    const int64_t nw = (int64_t)gridDim.x * wpb;
-    for (int64_t J = gw; J < total; J += nw) {
-        const int w = find_segment(S.work_begin, S.sp.nwork, J);
-        const Cat& C = S.cats[S.work_cat[w]];
-        Det d;
-        decode(S, C, J - S.work_begin[w], d);
-        const int deg = C.deg;
-        T one[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) one[v] = V::zero();
-        for (int slot = lane; slot < deg; slot += 64) {
-            int cls, xs, ys, lx, ly, sg;
-            slot_move(S, C, d, slot, cls, xs, ys, lx, ly);
-            const int64_t t = apply_move(S, C, cls, xs, ys, lx, ly, d, sg);
-            const int x = S.sp.sub_off[xs] + lx, y = S.sp.sub_off[ys] + ly;
-            const int pair = y * M + x;
-            tgt[slot] = t;
-            coff[slot] = pair * MM;
-            rinf[slot] = (pair << 1) | (sg < 0 ? 1 : 0);
-            const T hv = hp[y * M + x];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                T val = (v < n_vec) ? c[(int64_t)v * nd + t] : V::zero();
-                if (sg < 0) val = V::scale(val, -1.0);
-                dsh[slot * NV + v] = val;
-                one[v] = V::mad(hv, val, one[v]);
-            }
-        }
-        if (C.in_space) {
-            // sigma_J += sum over the moves of J of h'_{y x} d[m]
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                T s = wave_sum<CPLX>(one[v]);
-                if (lane == 0 && v < n_vec) V::atomic_add(&sigma[(int64_t)v * nd + (C.offset + (J - S.work_begin[w]))], s);
-            }
-        }
-        wave_lds_sync();
-        // phase 2: rows lane, lane+64, ... ; all R row slots share each d load
-        int prow[R];
-        bool act[R];
-        T acc[R][NV];
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int r = lane + 64 * k;
-            act[k] = r < deg;
-            prow[k] = act[k] ? (rinf[r] >> 1) : 0;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[k][v] = V::zero();
-        }
-        for (int col = 0; col < deg; ++col) {
-            const T* gcol = gT + coff[col];
-            T dv[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) dv[v] = dsh[col * NV + v];
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                if (act[k]) {
-                    const T g = gcol[prow[k]];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) acc[k][v] = V::mad(g, dv[v], acc[k][v]);
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            if (!act[k]) continue;
-            const int r = lane + 64 * k;
-            const double s = (rinf[r] & 1) ? -0.5 : 0.5;
-            const int64_t t = tgt[r];
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-                if (v < n_vec) V::atomic_add(&sigma[(int64_t)v * nd + t], V::scale(acc[k][v], s));
-        }
-        wave_lds_sync();  // the next determinant overwrites this wavefront's LDS slice
-    }
-}
-
-template <bool CPLX>
-__global__ __launch_bounds__(256) void k_zero(typename VT<CPLX>::T* __restrict__ x, int64_t n) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        x[e] = VT<CPLX>::zero();
-}
-
-template <bool CPLX, int NV>
-static hipError_t launch_wave_nv(const DevSpace& S, int deg_max, const void* gT, const void* hp, const void* c,
-                                 void* sigma, int nv, hipStream_t st) {
-    using T = typename VT<CPLX>::T;
-    const int R = (deg_max + 63) / 64;
-    const size_t per_wave = (size_t)deg_max * (NV * sizeof(T) + 16);
-    int wpb = 4;
-    while (wpb > 1 && per_wave * wpb > 64 * 1024) wpb >>= 1;
-    const size_t lds = per_wave * wpb;
-    int64_t waves = (S.sp.nwork_dets + 0);
-    int64_t blocks = (waves + wpb - 1) / wpb;
-    if (blocks > 256 * 32) blocks = 256 * 32;
-    const dim3 grid((unsigned)blocks), block(64 * wpb);
-    const T* g = (const T*)gT;
-    const T* h = (const T*)hp;
-    const T* cc = (const T*)c;
-    T* ss = (T*)sigma;
-    if (R <= 1)
-        hipLaunchKernelGGL((k_sigma2e_wave<CPLX, NV, 1>), grid, block, lds, st, S, g, h, cc, ss, nv, deg_max);
-    else if (R == 2)
-        hipLaunchKernelGGL((k_sigma2e_wave<CPLX, NV, 2>), grid, block, lds, st, S, g, h, cc, ss, nv, deg_max);
-    else if (R == 3)
-        hipLaunchKernelGGL((k_sigma2e_wave<CPLX, NV, 3>), grid, block, lds, st, S, g, h, cc, ss, nv, deg_max);
-    else if (R == 4)
-        hipLaunchKernelGGL((k_sigma2e_wave<CPLX, NV, 4>), grid, block, lds, st, S, g, h, cc, ss, nv, deg_max);
-    else if (R <= 6)
-        hipLaunchKernelGGL((k_sigma2e_wave<CPLX, NV, 6>), grid, block, lds, st, S, g, h, cc, ss, nv, deg_max);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
-}
-
-bool sigma_wave_supported(int deg_max) { return deg_max <= 6 * 64; }
-
-hipError_t launch_sigma_wave(const DevSpace& S, int deg_max, bool cplx, const void* gT, const void* hp,
-                             const void* c, void* sigma, int n_vec, hipStream_t st) {
-    const int64_t n = S.sp.ndets * n_vec;
-    const int zg = (int)std::min<int64_t>(8192, (n + 255) / 256);
-    if (cplx)
-        hipLaunchKernelGGL(k_zero<true>, dim3(zg), dim3(256), 0, st, (cd*)sigma, n);
-    else
-        hipLaunchKernelGGL(k_zero<false>, dim3(zg), dim3(256), 0, st, (double*)sigma, n);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const size_t sb = cplx ? 16 : 8;
-    for (int v0 = 0; v0 < n_vec; v0 += 2) {
-        const int nv = (n_vec - v0 >= 2) ? 2 : 1;
-        const int64_t off = (int64_t)v0 * S.sp.ndets;
-        const void* cc = (const char*)c + off * sb;
-        void* ss = (char*)sigma + off * sb;
-        if (cplx)
-            e = (nv == 2) ? launch_wave_nv<true, 2>(S, deg_max, gT, hp, cc, ss, 2, st)
-                          : launch_wave_nv<true, 1>(S, deg_max, gT, hp, cc, ss, 1, st);
-        else
-            e = (nv == 2) ? launch_wave_nv<false, 2>(S, deg_max, gT, hp, cc, ss, 2, st)
-                          : launch_wave_nv<false, 1>(S, deg_max, gT, hp, cc, ss, 1, st);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
-}  // namespace stp

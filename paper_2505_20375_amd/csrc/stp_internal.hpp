@@ -9,7 +9,6 @@ constexpr int KMAX = 8;          // subspaces (distributed active spaces)
 constexpr int MMAX = 64;         // spin-orbitals in total
 constexpr int MSUB = 32;         // spin-orbitals per subspace (local strings are uint32 masks)
 constexpr int NCLS = KMAX * KMAX;
-constexpr int MAXDEG = 1024;
 constexpr int DET_BYTES = 96;   // sizeof of the device-side decoded determinant (ranks + masks)
 constexpr int NPCLS = KMAX * (KMAX + 1) / 2;   // pair classes (a <= b)
 

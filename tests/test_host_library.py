@@ -315,3 +315,16 @@ def test_exponential_search_equals_lower_bound():
             assert stpci.test_exp_search(a, n, 0) == n
     assert stpci.test_exp_search(np.zeros(4, np.uint32), 5, 0) == -1
     assert checked > 1000
+
+
+def test_sigma_kernel_names():
+    """The selectable sigma kernels; the removed one-move forms and unknown
+    names are refused with STPCI_EINVAL."""
+    import paper_2505_20375_amd as stpci
+    c = stpci.Context(device=-1)
+    for name in ("auto", "pair", "pair_atomic", "pair_mf64", "pair_valu", "pair_grp", "pair_sb", "tile", "rowtile"):
+        c.set_sigma_kernel(name)
+    for name in ("wave", "simple", "bogus", ""):
+        with pytest.raises(stpci.StpciError):
+            c.set_sigma_kernel(name)
+    del c

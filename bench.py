@@ -320,13 +320,15 @@ def _precision_study(iters):
 
 def _cpu_baseline_c3p(seconds):
     """The CPU oracle (list-free Slater-Condon rows of the windowed space) on
-    bounded samples of rows of the headline space, on 1, 4 and all host
-    threads of the GPU's share (at most 16), extrapolated to det-updates/s;
-    the best rate is reported with the thread count that gave it.  The rows'
-    determinants are drawn beforehand (not timed): the oracle's work is
-    forming and applying each row's nonzero couplings.  Threads share the
-    integrals (a process per core would hold 41 MB of them each); the
-    oracle's C routine runs outside the interpreter lock."""
+    bounded samples of rows of the headline space, about `seconds` of wall
+    time each on 1, 4 and all host threads of the GPU's share (at most 16),
+    extrapolated to det-updates/s; the best rate is reported with the thread
+    count that gave it.  The rows' determinants are drawn beforehand (not
+    timed): the oracle's work is forming and applying each row's nonzero
+    couplings.  Threads share the integrals (a process per core would hold
+    41 MB of them each); the oracle's C routine runs outside the interpreter
+    lock, but each call allocates and clears its row buffers, so threads
+    scale poorly (the oracle is timed as it stands)."""
     import numpy as np
     import synth
     from concurrent.futures import ThreadPoolExecutor
@@ -357,10 +359,13 @@ def _cpu_baseline_c3p(seconds):
             tot = sum(ex.map(rows_work, parts))
         return tot, time.perf_counter() - t0
 
+    run(4, 1)   # untimed: the first call loads the oracle's library
     scan = []
     for nth in sorted({1, min(4, ncores), ncores}):
-        tot, t = run(max(nth * 4, 8), nth)
-        nrows = int(max(nth * 4, nth * 4 * (seconds / 3) / max(t, 1e-3)))
+        # a short run sizes the timed one at about `seconds` of wall time
+        est_rows = max(nth * 16, 32)
+        tot, t = run(est_rows, nth)
+        nrows = int(max(est_rows, est_rows * seconds / max(t, 1e-3)))
         tot, t = run(nrows, nth)
         scan.append({"threads": nth, "rows": nrows, "couplings": int(tot), "seconds": round(t, 2),
                      "det_updates_per_s": tot / t})

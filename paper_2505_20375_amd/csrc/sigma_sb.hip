@@ -27,9 +27,10 @@
 // (complex: one product with the real and one with the imaginary part of
 // the table, combined by a lane exchange).  B is built 64 rows at a time
 // into LDS (double buffered, the gathers of the next chunk in flight during
-// the products of the current one; every entry formed without branches);
-// each table fragment (one 16-byte read per lane) feeds one product per
-// column group and table part.  E is added to sigma with device atomics
+// the products of the current one; every entry formed without branches; the
+// last chunk's products stop at its last group of 16 rows that holds rows of
+// the list); each table fragment (one 16-byte read per lane) feeds one
+// product per column group and table part.  E is added to sigma with device atomics
 // (sigma is not bitwise deterministic).  The FP32 form of the precision
 // option runs the same kernel with the FP32 table, B rounded to FP32 in LDS
 // and v_mfma_f32_16x16x4f32 (FP32 accumulation of a product; its output rows
@@ -278,9 +279,10 @@ bool build_sb_plan(const HostSpace& H, SbHostPlan& plan) {
 
 // Matrix-core flops and items of one launch sequence (one pass of at most
 // two vectors): per item, (npad rounded to 16) / 16 row tiles x (npad
-// rounded to 32) / 4 steps x its column groups x 2048 flop per
-// v_mfma_f64_16x16x4f64, twice for complex (the real and the imaginary part
-// of the table).
+// rounded to 16) / 4 steps (the last chunk's products stop at its last
+// group of 16 rows that holds rows of the list) x its column groups x 2048
+// flop per v_mfma_f64_16x16x4f64, twice for complex (the real and the
+// imaginary part of the table).
 void sb_plan_counts(const SbHostPlan& plan, bool cplx, int nv, double* flops, int64_t* items) {
     const int cw = cplx ? 2 * nv : nv;
     const int x = (cw == 1) ? 0 : (cw == 2 ? 1 : 2);
@@ -289,7 +291,7 @@ void sb_plan_counts(const SbHostPlan& plan, bool cplx, int nv, double* flops, in
     for (int g = 1; g <= SB_NG; ++g)
         for (int q = plan.sbegin[x][g - 1]; q < plan.sbegin[x][g]; ++q) {
             const SbCat& c = plan.cats[plan.streams[q].cat];
-            const double nrt = (c.npad + 15) / 16, nks = ((c.npad + SB_TK - 1) / SB_TK) * (SB_TK / 4);
+            const double nrt = (c.npad + 15) / 16, nks = ((c.npad + 15) / 16) * 4;
             f += (double)c.ngroups * nrt * nks * g * 2048.0 * (cplx ? 2 : 1);
             it += c.ngroups;
         }
@@ -393,7 +395,7 @@ struct SbItem {
     const int32_t* pre;
     const int32_t* binom;
     int* flags;
-    int nk, j0, nL, ps3, nkc, nRT;
+    int nk, j0, nL, ps3, nkc, nRT, npad;
 };
 
 // Passes over the row tiles of one item with NGU column groups: wavefront
@@ -504,8 +506,11 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
             __builtin_amdgcn_s_waitcnt(0);
             if (more) gen_issue(kc + 1);
             const bool mm = own && I.flags[kc];
+            // groups of 16 rows of this chunk that hold rows of the list (the
+            // rest of the last chunk is padding: its products add zeros)
+            const int ngv = min(SB_NQ, (I.npad - kc * SB_TK + 15) >> 4);
             sb_static_for<0, SB_NQ>([&](auto G) {
-                if (mm) sb_mma<NGU, 4 * G, CPLX>(B, kq, c16, af[G], c1, c2);
+                if (mm && G < ngv) sb_mma<NGU, 4 * G, CPLX>(B, kq, c16, af[G], c1, c2);
                 if constexpr (G + 1 < SB_NQ) {
                     if (own && more) sb_afrag<4 * G>(rnext, arow, NP, kq, af[G]);
                 }
@@ -636,6 +641,7 @@ __global__ __launch_bounds__(SB_WAVES * 64, 1) void k_sigma_pair_sb(DevSpace S, 
         I.nL = P.occ[L];
         I.ps3 = 3 * (I.nL + 1);
         I.nkc = (npad + SB_TK - 1) / SB_TK;                 // chunks of B rows
+        I.npad = npad;
         I.nRT = (npad + 15) >> 4;                           // 16-row tiles
         I.rbase = rbase;
         I.rinf = rinf;

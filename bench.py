@@ -367,6 +367,9 @@ def _cpu_baseline_c3p(seconds):
         tot, t = run(est_rows, nth)
         nrows = int(max(est_rows, est_rows * seconds / max(t, 1e-3)))
         tot, t = run(nrows, nth)
+        if t < 0.5 * seconds:   # the short run overestimated the time per row
+            nrows = int(nrows * seconds / max(t, 1e-3))
+            tot, t = run(nrows, nth)
         scan.append({"threads": nth, "rows": nrows, "couplings": int(tot), "seconds": round(t, 2),
                      "det_updates_per_s": tot / t})
     best = max(scan, key=lambda r: r["det_updates_per_s"])

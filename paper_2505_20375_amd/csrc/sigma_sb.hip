@@ -23,7 +23,9 @@
 // (two per SIMD), persistent over the items; each XCD works through a
 // contiguous eighth of them.  An item's right-hand side is at most four
 // 16-column groups (64 columns); each wavefront owns one 16-row tile of E
-// per pass and accumulates all column groups with v_mfma_f64_16x16x4f64
+// per pass (in a pass of at most four tiles, two or four wavefronts share a
+// tile, each taking part of every chunk's steps and adding its part of E to
+// sigma) and accumulates all column groups with v_mfma_f64_16x16x4f64
 // (complex: one product with the real and one with the imaginary part of
 // the table, combined by a lane exchange).  B is built 64 rows at a time
 // into LDS (double buffered, the gathers of the next chunk in flight during
@@ -475,8 +477,16 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
 
     const int npass = (I.nRT + SB_WAVES - 1) / SB_WAVES;
     for (int pass = 0; pass < npass; ++pass) {
-        const int RT = pass * SB_WAVES + wid;
-        const bool own = RT < I.nRT;
+        // the pass's row tiles; when it holds at most half (a quarter) as
+        // many tiles as wavefronts, the wavefronts of a tile share its
+        // products, each taking two groups (one group) of four steps of
+        // every chunk, and each adds its part of E to sigma
+        const int r = min(SB_WAVES, I.nRT - pass * SB_WAVES);
+        const int split = (r <= SB_WAVES / 4) ? 4 : (r <= SB_WAVES / 2) ? 2 : 1;
+        const int RT = pass * SB_WAVES + wid % r;
+        const int kpart = wid / r;   // this wavefront's share of the groups of four steps
+        const bool own = kpart < split;
+        auto mine = [&](int G) { return (G * split) / SB_NQ == kpart; };
         ACC c1[NGU], c2[NGU];
 #pragma unroll
         for (int h = 0; h < NGU; ++h) c1[h] = c2[h] = ACC{0, 0, 0, 0};
@@ -489,7 +499,9 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
         // the chunk build, which must not wait for it: loads complete in
         // order)
         TA af[SB_NQ][4];
-        if (own) sb_static_for<0, SB_NQ>([&](auto G) { sb_afrag<4 * G>(I.rinf, arow, NP, kq, af[G]); });
+        if (own) sb_static_for<0, SB_NQ>([&](auto G) {
+            if (mine(G)) sb_afrag<4 * G>(I.rinf, arow, NP, kq, af[G]);
+        });
         gen_issue(0);
         gen_commit(0, 0);
         __syncthreads();
@@ -510,13 +522,13 @@ __device__ __forceinline__ void sb_item(const SbItem& I, const TA* __restrict__ 
             // rest of the last chunk is padding: its products add zeros)
             const int ngv = min(SB_NQ, (I.npad - kc * SB_TK + 15) >> 4);
             sb_static_for<0, SB_NQ>([&](auto G) {
-                if (mm && G < ngv) sb_mma<NGU, 4 * G, CPLX>(B, kq, c16, af[G], c1, c2);
+                if (mm && G < ngv && mine(G)) sb_mma<NGU, 4 * G, CPLX>(B, kq, c16, af[G], c1, c2);
                 if constexpr (G + 1 < SB_NQ) {
-                    if (own && more) sb_afrag<4 * G>(rnext, arow, NP, kq, af[G]);
+                    if (own && more && mine(G)) sb_afrag<4 * G>(rnext, arow, NP, kq, af[G]);
                 }
             });
             if (more) gen_commit(kc + 1, buf ^ 1);
-            if (own && more) sb_afrag<4 * (SB_NQ - 1)>(rnext, arow, NP, kq, af[SB_NQ - 1]);
+            if (own && more && mine(SB_NQ - 1)) sb_afrag<4 * (SB_NQ - 1)>(rnext, arow, NP, kq, af[SB_NQ - 1]);
             __syncthreads();
         }
         // ---- scatter of this wavefront's row tile, staged through LDS (the

@@ -864,6 +864,25 @@ static stpci_status dav_advance(stpci_ctx* c) {
             keep = kept;
             if (nk == 0) break;
             if ((s = d.put_small(Yq, kYOff))) return s;
+            // a second pass only where the first can lose orthogonality: it
+            // leaves the directions orthonormal to about kappa eps, kappa the
+            // condition number of their Gram matrix (at most 100 here: one
+            // pass is enough)
+            {
+                std::vector<cplx> Gk((size_t)nk * nk);
+                for (int a = 0; a < nk; ++a)
+                    for (int b = 0; b < nk; ++b) Gk[(size_t)a * nk + b] = Gm[(size_t)kept[b] * ns + kept[a]];
+                std::vector<double> ev;
+                std::vector<cplx> evec;
+                herm_eig(nk, Gk, ev, evec);
+                if (ev[0] > 0.0 && ev[nk - 1] <= 100.0 * ev[0]) {
+                    if ((s = d.hip(launch_combine(d.cx, c->d_T.p, nullptr, N, ns, d.small(kYOff), nk, nullptr,
+                                                  d.vec(c->d_V, mm), nullptr, N, 0, c->stream),
+                                   "cholqr")))
+                        return s;
+                    break;
+                }
+            }
             if (nk <= 4) {
                 if ((s = d.hip(launch_comb_gram(d.cx, c->d_T.p, N, ns, d.small(kYOff), d.vec(c->d_V, mm), nk, N, 0,
                                                 (double*)c->d_partial.p, (double*)d.small(kGramOff), c->stream),

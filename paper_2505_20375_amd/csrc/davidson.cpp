@@ -699,7 +699,18 @@ static stpci_status dav_advance(stpci_ctx* c) {
             for (int i = 0; i < mm; ++i) v[i] = Y[(size_t)i * mm + j];
             cols.push_back(std::move(v));
         }
-        for (int j = 0; j < k && (int)cols.size() < room && D.prev_rows > 0; ++j) {
+        // where room is short of 2k, the previous iterates of the unconverged
+        // roots go first, largest residual first (a converged root gains
+        // nothing from its own)
+        std::vector<int> porder(k);
+        std::iota(porder.begin(), porder.end(), 0);
+        if (room < 2 * k)
+            std::stable_sort(porder.begin(), porder.end(), [&](int a, int b) {
+                if (corr[a] != corr[b]) return corr[a] > corr[b];
+                return corr[a] && D.rn[a] > D.rn[b];
+            });
+        for (int jj = 0; jj < k && (int)cols.size() < room && D.prev_rows > 0; ++jj) {
+            const int j = porder[jj];
             std::vector<cplx> v(mm, cplx(0, 0));
             for (int i = 0; i < std::min(D.prev_rows, mm); ++i) v[i] = D.prev_coef[(size_t)i * k + j];
             ortho_push(std::move(v));

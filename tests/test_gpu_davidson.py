@@ -158,19 +158,21 @@ def test_davidson_config2_matches_oracle_davidson():
     assert np.max(np.abs(e - np.array(ref["energies"]))) <= 1e-9
 
 
-@pytest.mark.parametrize("name,k", [("c1", 1), ("T8", 2), ("c1", 3)])
-def test_small_basis_restart_converges(name, k):
-    """A basis of only 2k + 1 vectors (as on a space where few vectors fit
-    the device): the restart keeps the current and the previous Ritz vectors
-    (GD+k), so the run still converges to the exact energies, in a bounded
-    multiple of the iterations of an unrestricted run."""
+@pytest.mark.parametrize("name,k,basis", [("c1", 1, 3), ("T8", 2, 5), ("c1", 3, 7), ("T8", 4, 9), ("T3", 3, 7),
+                                          ("T2", 4, 12), ("T3", 4, 12)])
+def test_small_basis_restart_converges(name, k, basis):
+    """A basis of only 2k + 1 or 3k vectors (as on a space where few vectors
+    fit the device): the restart keeps the current and the previous Ritz
+    vectors (GD+k; the unconverged roots' previous iterates first where fewer
+    than 2k restart slots remain), so the run still converges to the exact
+    energies, in a bounded multiple of the iterations of an unrestricted run."""
     from oracle import dense
     pb = Problem.named(name)
     w = np.linalg.eigvalsh(dense.hamiltonian(pb.dets, pb.h, pb.g, real=not pb.cplx))[:k] + pb.ints.e_core
     ctx = pb.context()
     e_full, r_full, it_full, _ = ctx.davidson(k=k, tol=1e-8, max_iter=500)
-    e, r, it, st = ctx.davidson(k=k, tol=1e-8, max_iter=500, max_subspace=2 * k + 1)
-    print(name, k, "iterations full basis", it_full, "basis of", 2 * k + 1, ":", it, flush=True)
+    e, r, it, st = ctx.davidson(k=k, tol=1e-8, max_iter=500, max_subspace=basis)
+    print(name, k, "iterations full basis", it_full, "basis of", basis, ":", it, flush=True)
     assert np.max(r) <= 1e-8
     assert np.max(np.abs(e - w)) <= 1e-9
     assert it <= 4 * it_full + 10

@@ -245,8 +245,12 @@ stpci_status stpci_sigma_csc(stpci_ctx* ctx, const int64_t* cat_ptr_dev, const u
  * stores the diagonal; this call exists for checks. */
 stpci_status stpci_diagonal(stpci_ctx* ctx, double* diag_dev);
 
-/* Davidson options.  k: roots; max_iter: iterations; max_subspace: expansion
- * vectors kept before a restart from the Ritz vectors (0: automatic);
+/* Davidson options.  k: roots; max_iter: iterations; max_subspace: basis
+ * vectors before a restart (0: max(8k, 32); capped at 64 and at n_dets, at
+ * least 2k, and lowered when device memory is short); the restart keeps the
+ * k Ritz vectors and the previous iteration's Ritz vectors (GD+k), so below
+ * 3k vectors only some roots keep their previous iterate and convergence can
+ * slow down or stall;
  * tol_residual: stop when every ||H x - E x|| <= tol_residual; eps_drop: the
  * epsilon of Eq. sparsePreconditioner in [0, 1): each correction s (the
  * residual divided by theta - H_ii, 0 where |theta - H_ii| < 1e-12) keeps only

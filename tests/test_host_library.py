@@ -328,3 +328,16 @@ def test_sigma_kernel_names():
         with pytest.raises(stpci.StpciError):
             c.set_sigma_kernel(name)
     del c
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: a request for several exits with status 2
+    and says why, before touching a device."""
+    import subprocess
+    import sys
+    from pathlib import Path
+    root = Path(__file__).resolve().parents[1]
+    p = subprocess.run([sys.executable, str(root / "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120, cwd=root)
+    assert p.returncode == 2
+    assert "exactly one GPU" in p.stderr and p.stdout == ""
